@@ -1,0 +1,153 @@
+/*
+ * lbsd -- C ABI of the semi-discrete compressible lattice Boltzmann step
+ * (tau = 1) of Komeili, Mirzaei and Shabouei, "Performance of 1-D and 2-D
+ * Lattice Boltzmann (LB) in Solution of the Shock Tube Problem"
+ * (arXiv 1602.02675), on AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the paper's own statement of the problem (Sec. V.A): set
+ * the initial flow parameters (density, velocity, energy), advance the
+ * migration step, read the moments back.
+ *
+ * Conventions
+ *  - Every call returns an int status (LB_OK = 0, negative on error) unless
+ *    stated otherwise; out-parameters are written only on LB_OK; nothing
+ *    throws across the ABI.  lb_last_error() gives a message for the calling
+ *    thread's last failed call.
+ *  - Device memory is owned by the caller: lb_state_bytes() says how much,
+ *    lb_bind() hands over a device pointer (e.g. a PyTorch tensor's
+ *    data_ptr()) and a HIP stream.  The caller keeps that memory alive until
+ *    lb_destroy().  The library owns the handle.
+ *  - Device work is stream-ordered on the bound stream.  lb_step() returns
+ *    as soon as the launches are queued; errors detected on the device
+ *    (LB_EREACH, LB_ESTATE) are reported by the next call that synchronises
+ *    (lb_sync, lb_moments, lb_totals, lb_step_timed).
+ *  - One handle is not thread-safe; different handles on different streams
+ *    may run concurrently.
+ *  - Units: the caller speaks physical units.  Inside, the lattice spacing
+ *    and time step are 1 and lambda = dt/dx scales velocity (x lambda) and
+ *    energy per unit mass (x lambda^2).
+ */
+#ifndef LBSD_H
+#define LBSD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define LB_OK 0
+#define LB_EINVAL (-1)  /* bad argument: size, gamma outside (1, 1 + 2/D], delta0 outside [0, 1), n < 0 ... */
+#define LB_ENOMEM (-2)  /* bound buffer too small / host allocation failed */
+#define LB_EDEVICE (-3) /* a HIP call failed */
+#define LB_ESTATE (-4)  /* rho <= 0, p < 0 or a non-finite value in a state */
+#define LB_EREACH (-5)  /* a packet would move further than the halo (LB_HALO nodes) in one step */
+
+/* ---- enumerations ---- */
+#define LB_BC_TRANSMISSIVE 0 /* ghost nodes copy the edge node every step; packets leaving are dropped (Sec. V.B) */
+#define LB_BC_PERIODIC 1     /* the lateral direction of the 2-D lattice (Sec. V.B); also allowed along x */
+
+#define LB_LATTICE_D1_TRIPLE 1       /* 1-D triple-level set (Sec. IV.A): c' in {0, +-c'_1, +-c'_2}, b0=1, b1=b2=2 */
+#define LB_LATTICE_D2_SQUARE_DUAL 2  /* square dual-level set (Sec. IV.B): +-c'_1, +-c'_2 along x and y, d0=0, b1=b2=4 */
+
+#define LB_FP64 0 /* FP64 storage and arithmetic */
+#define LB_FP32 1 /* FP32 storage and arithmetic, FP64 conservation totals */
+
+#define LB_HALO 5 /* largest per-axis displacement a packet may have in one step */
+
+typedef struct lb_solver lb_solver; /* opaque */
+
+/* Grid: dim 1 -> ny must be 1.  Nodes are cell centres x_i = x_lo + (i + 1/2) dx,
+ * dx = (x_hi - x_lo) / nx; the square lattice has dy = dx. */
+typedef struct {
+    int32_t dim;
+    int64_t nx, ny;
+    double x_lo, x_hi;
+    int32_t bc_x, bc_y;
+} lb_grid;
+
+/* Velocity set: lattice (must match dim) and d0_frac = d_0 / rho, the rest
+ * weight of the 1-D triple-level set (the paper picks 0.4 .. 0.55; 0.5 is the
+ * usual choice); must be 0 for the square dual-level set. */
+typedef struct {
+    int32_t lattice;
+    double d0_frac;
+} lb_velset;
+
+/* Primitive state in physical units; v is ignored in 1-D. */
+typedef struct {
+    double rho, u, v, p;
+} lb_prim;
+
+/* Create a solver for one grid (Sec. III-IV).  gamma must lie in (1, 1 + 2/D]
+ * so that the non-translational energy phi of eq. 15 is non-negative.
+ * precision: LB_FP64 or LB_FP32.  *out receives the handle. */
+int lb_create(const lb_grid* grid, double gamma, const lb_velset* velset, int32_t precision,
+              lb_solver** out);
+
+/* Bytes of device memory the solver needs (two ping-pong SoA moment sets,
+ * export staging, control block, per-block partials). */
+size_t lb_state_bytes(const lb_solver* s);
+
+/* Hand over device memory (>= lb_state_bytes, 256-byte aligned) and the HIP
+ * stream (hipStream_t, NULL = default stream) all later work is queued on. */
+int lb_bind(lb_solver* s, void* dev_ptr, size_t bytes, void* hip_stream);
+
+/* lambda = dt/dx used by the next lb_init_* call.  lb_set_lambda fixes it
+ * (> 0); lb_set_cfl (> 0, default 1) makes lb_init_riemann take
+ * lambda = cfl / max(|u| + sqrt(gamma p / rho)) over the two states. */
+int lb_set_lambda(lb_solver* s, double lambda);
+int lb_set_cfl(lb_solver* s, double cfl);
+
+/* Riemann problem (Sec. V.C): node i gets `left` when x_i < x_diaphragm, else
+ * `right`; rho E = p/(gamma - 1) + rho |u|^2 / 2 (eq. 27).  Resets the step
+ * count and any pending error.  LB_ESTATE for rho <= 0, p < 0, non-finite. */
+int lb_init_riemann(lb_solver* s, double x_diaphragm, const lb_prim* left, const lb_prim* right);
+
+/* General initial state: host_Y is FP64 SoA [nf][ny][nx] of the conserved
+ * moments rho, rho u, (rho v), rho E in physical units (nf = dim + 2), and
+ * lambda > 0 the time-step ratio to use.  Copied synchronously. */
+int lb_init_moments(lb_solver* s, const double* host_Y, double lambda);
+
+/* Queue n >= 0 steps (eq. 10 / eq. 30 with tau = 1, Sec. V.A).  Each step is
+ * one kernel that also forms the interior conservation totals and checks the
+ * reach.  If a step fails, it and every later queued step leave the state at
+ * the last good step; the error is reported at the next synchronising call. */
+int lb_step(lb_solver* s, int64_t n);
+
+/* As lb_step, bracketed by HIP events on the bound stream; waits and writes
+ * the elapsed milliseconds of the n steps to *ms. */
+int lb_step_timed(lb_solver* s, int64_t n, float* ms);
+
+/* Wait for queued work; returns LB_EREACH / LB_ESTATE if a step failed. */
+int lb_sync(lb_solver* s);
+
+/* Current moments as FP64 SoA [nf][ny][nx] in physical units, into `out`
+ * (host memory, or device memory when out_on_device != 0).  Synchronises. */
+int lb_moments(lb_solver* s, double* out, int32_t out_on_device);
+
+/* Interior sums of rho, rho u, rho v (0 in 1-D), rho E of the current state
+ * in physical units per node (multiply by dx for integrals).  The step
+ * kernels form them in FP64 with a fixed reduction order.  Synchronises. */
+int lb_totals(lb_solver* s, double out[4]);
+
+double lb_lambda(const lb_solver* s);         /* lambda of the current state (0 before init) */
+double lb_dt(const lb_solver* s);             /* physical time step lambda * dx */
+int64_t lb_steps_done(const lb_solver* s);    /* good steps since the last init */
+int32_t lb_max_reach(lb_solver* s);           /* largest reach of the latest step (synchronises) */
+
+/* Per-node floor(v_x), floor(v_y) (0 in 1-D) and c'_1 (eq. 26) of the current
+ * state, computed by the same device function the step uses; host int32
+ * arrays of nx*ny entries.  Synchronises. */
+int lb_debug_lanes(lb_solver* s, int32_t* floor_x, int32_t* floor_y, int32_t* c1);
+
+void lb_destroy(lb_solver* s);
+const char* lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBSD_H */

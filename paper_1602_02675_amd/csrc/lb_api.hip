@@ -1,0 +1,485 @@
+// Host runtime behind include/lbsd.h: validation, device-memory layout
+// inside the caller's buffer, launches on the caller's stream, error
+// recovery to the last good step.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <climits>
+#include <string>
+#include <vector>
+
+#include "lb_kernels.hpp"
+#include "lbsd.h"
+
+using namespace lbsd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(LB_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct lb_solver {
+    lb_grid grid;
+    Grid g;
+    int dim, nf, precision;
+    double gamma;
+    lb_velset vs;
+    Consts k;
+    int64_t nn;
+    size_t elem;
+    // layout inside the bound buffer
+    size_t off_buf[2], off_export, off_ctl, off_partials, total;
+    int64_t nblocks;
+    char* base;
+    hipStream_t stream;
+    bool bound, initialized;
+    double lambda_set, cfl, lambda;
+    int cur;               // buffer holding the state after `steps_done` steps
+    int64_t steps_done;    // steps queued since init (optimistic until synced)
+    int pending_err;       // error already known on the host
+    hipEvent_t ev0, ev1;
+    bool events;
+};
+
+static void* buf_ptr(lb_solver* s, int i) { return s->base + s->off_buf[i]; }
+static StepCtl* ctl_ptr(lb_solver* s) { return (StepCtl*)(s->base + s->off_ctl); }
+static double* partials_ptr(lb_solver* s) { return (double*)(s->base + s->off_partials); }
+static double* export_ptr(lb_solver* s) { return (double*)(s->base + s->off_export); }
+
+extern "C" {
+
+const char* lb_last_error(void) { return g_last_error.c_str(); }
+
+int lb_create(const lb_grid* grid, double gamma, const lb_velset* vs, int32_t precision,
+              lb_solver** out)
+{
+    if (!grid || !vs || !out) return fail(LB_EINVAL, "null argument");
+    const int dim = grid->dim;
+    if (dim != 1 && dim != 2) return fail(LB_EINVAL, "dim must be 1 or 2 (got %d)", dim);
+    if (grid->nx < 1 || grid->ny < 1) return fail(LB_EINVAL, "nx, ny must be >= 1");
+    if (dim == 1 && grid->ny != 1) return fail(LB_EINVAL, "ny must be 1 in 1-D");
+    if (grid->nx > (int64_t)1 << 40 || grid->ny > (int64_t)1 << 40 ||
+        grid->nx * grid->ny > (int64_t)1 << 36)
+        return fail(LB_EINVAL, "grid too large");
+    if (!(grid->x_hi > grid->x_lo) || !isfinite(grid->x_lo) || !isfinite(grid->x_hi))
+        return fail(LB_EINVAL, "need x_lo < x_hi");
+    for (int b : {grid->bc_x, grid->bc_y})
+        if (b != LB_BC_TRANSMISSIVE && b != LB_BC_PERIODIC)
+            return fail(LB_EINVAL, "unknown boundary condition %d", b);
+    if (!(gamma > 1.0) || !(gamma <= 1.0 + 2.0 / dim))
+        return fail(LB_EINVAL, "gamma must lie in (1, 1 + 2/D] (phi >= 0, eq. 15); got %g", gamma);
+    if ((dim == 1 && vs->lattice != LB_LATTICE_D1_TRIPLE) ||
+        (dim == 2 && vs->lattice != LB_LATTICE_D2_SQUARE_DUAL))
+        return fail(LB_EINVAL, "lattice %d does not match dim %d", vs->lattice, dim);
+    if (dim == 1 && !(vs->d0_frac >= 0.0 && vs->d0_frac < 1.0))
+        return fail(LB_EINVAL, "d0_frac must lie in [0, 1); got %g", vs->d0_frac);
+    if (dim == 2 && vs->d0_frac != 0.0)
+        return fail(LB_EINVAL, "the square dual-level set has d0 = 0");
+    if (precision != LB_FP64 && precision != LB_FP32)
+        return fail(LB_EINVAL, "precision must be LB_FP64 or LB_FP32");
+
+    lb_solver* s = new (std::nothrow) lb_solver();
+    if (!s) return fail(LB_ENOMEM, "host allocation failed");
+    s->grid = *grid;
+    s->g = Grid{grid->nx, grid->ny, grid->bc_x, grid->bc_y};
+    s->dim = dim;
+    s->nf = dim + 2;
+    s->precision = precision;
+    s->gamma = gamma;
+    s->vs = *vs;
+    s->k.Dg1 = (double)dim * (gamma - 1.0);
+    s->k.phi_coef = 1.0 - ((double)dim / 2.0) * (gamma - 1.0);
+    s->k.delta0 = dim == 1 ? vs->d0_frac : 0.0;
+    s->k.b0 = dim == 1 ? 1.0 : 0.0;
+    s->k.inv_b1 = dim == 1 ? 0.5 : 0.25;
+    s->nn = grid->nx * grid->ny;
+    s->elem = precision == LB_FP64 ? 8 : 4;
+    const size_t field_bytes = align256((size_t)s->nf * (size_t)s->nn * s->elem);
+    s->nblocks = dim == 1 ? step_blocks_1d(s->g) : step_blocks_2d(s->g);
+    s->off_buf[0] = 0;
+    s->off_buf[1] = field_bytes;
+    s->off_export = 2 * field_bytes;
+    s->off_ctl = s->off_export + align256((size_t)s->nf * (size_t)s->nn * 8);
+    s->off_partials = s->off_ctl + align256(sizeof(StepCtl));
+    s->total = s->off_partials + align256((size_t)s->nblocks * kPartialStride * 8);
+    s->cfl = 1.0;
+    s->lambda_set = 0.0;
+    *out = s;
+    return LB_OK;
+}
+
+size_t lb_state_bytes(const lb_solver* s) { return s ? s->total : 0; }
+
+int lb_bind(lb_solver* s, void* dev_ptr, size_t bytes, void* hip_stream)
+{
+    if (!s || !dev_ptr) return fail(LB_EINVAL, "null argument");
+    if (bytes < s->total) return fail(LB_ENOMEM, "buffer of %zu bytes < %zu needed", bytes, s->total);
+    if ((uintptr_t)dev_ptr % 256 != 0) return fail(LB_EINVAL, "device buffer must be 256-byte aligned");
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, dev_ptr);
+    if (e != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return fail(LB_EINVAL, "pointer is not device memory");
+    }
+    s->base = (char*)dev_ptr;
+    s->stream = (hipStream_t)hip_stream;
+    if (!s->events) {
+        if ((e = hipEventCreate(&s->ev0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+        if ((e = hipEventCreate(&s->ev1)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+        s->events = true;
+    }
+    s->bound = true;
+    s->initialized = false;
+    if ((e = launch_reset_ctl(ctl_ptr(s), s->stream)) != hipSuccess) return hip_fail(e, "reset");
+    return LB_OK;
+}
+
+int lb_set_lambda(lb_solver* s, double lambda)
+{
+    if (!s || !(lambda > 0.0) || !isfinite(lambda)) return fail(LB_EINVAL, "lambda must be > 0");
+    s->lambda_set = lambda;
+    return LB_OK;
+}
+
+int lb_set_cfl(lb_solver* s, double cfl)
+{
+    if (!s || !(cfl > 0.0) || !isfinite(cfl)) return fail(LB_EINVAL, "cfl must be > 0");
+    s->cfl = cfl;
+    s->lambda_set = 0.0;
+    return LB_OK;
+}
+
+static bool prim_ok(const lb_prim* p)
+{
+    return p && p->rho > 0.0 && p->p >= 0.0 && isfinite(p->rho) && isfinite(p->u) &&
+           isfinite(p->v) && isfinite(p->p);
+}
+
+static int start_state(lb_solver* s)
+{
+    s->cur = 0;
+    s->steps_done = 0;
+    s->pending_err = 0;
+    s->initialized = true;
+    hipError_t e = launch_reset_ctl(ctl_ptr(s), s->stream);
+    return e == hipSuccess ? LB_OK : hip_fail(e, "reset");
+}
+
+int lb_init_riemann(lb_solver* s, double x_d, const lb_prim* L, const lb_prim* R)
+{
+    if (!s || !s->bound) return fail(LB_EINVAL, "solver not bound");
+    if (!isfinite(x_d)) return fail(LB_EINVAL, "diaphragm position must be finite");
+    if (!prim_ok(L) || !prim_ok(R)) return fail(LB_ESTATE, "need rho > 0, p >= 0, finite values");
+    const double g = s->gamma;
+    double lam = s->lambda_set;
+    if (!(lam > 0.0)) {
+        double smax = 0.0;
+        for (const lb_prim* q : {L, R}) {
+            const double uu = s->dim == 2 ? sqrt(q->u * q->u + q->v * q->v) : fabs(q->u);
+            const double c = uu + sqrt(g * q->p / q->rho);
+            smax = c > smax ? c : smax;
+        }
+        if (!(smax > 0.0)) return fail(LB_ESTATE, "both states have zero signal speed; set lambda");
+        lam = s->cfl / smax;
+    }
+    double side[2][4];
+    const lb_prim* P[2] = {L, R};
+    const double lam2 = lam * lam;
+    for (int i = 0; i < 2; ++i) {
+        const double rho = P[i]->rho, u = P[i]->u, v = s->dim == 2 ? P[i]->v : 0.0, p = P[i]->p;
+        const double rE = p / (g - 1.0) + 0.5 * rho * (u * u + v * v);
+        side[i][0] = rho;
+        side[i][1] = (rho * u) * lam;
+        if (s->dim == 2) {
+            side[i][2] = (rho * v) * lam;
+            side[i][3] = rE * lam2;
+        } else {
+            side[i][2] = rE * lam2;
+            side[i][3] = 0.0;
+        }
+    }
+    s->lambda = lam;
+    const double dx = (s->grid.x_hi - s->grid.x_lo) / (double)s->grid.nx;
+    hipError_t e;
+    if (s->precision == LB_FP64)
+        e = launch_init_riemann<double>((double*)buf_ptr(s, 0), s->g, s->nf, s->grid.x_lo, dx, x_d,
+                                        side[0], side[1], s->stream);
+    else
+        e = launch_init_riemann<float>((float*)buf_ptr(s, 0), s->g, s->nf, s->grid.x_lo, dx, x_d,
+                                       side[0], side[1], s->stream);
+    if (e != hipSuccess) return hip_fail(e, "init kernel");
+    return start_state(s);
+}
+
+int lb_init_moments(lb_solver* s, const double* Y, double lambda)
+{
+    if (!s || !s->bound) return fail(LB_EINVAL, "solver not bound");
+    if (!Y) return fail(LB_EINVAL, "null moments");
+    if (!(lambda > 0.0) || !isfinite(lambda)) return fail(LB_EINVAL, "lambda must be > 0");
+    const int64_t nn = s->nn;
+    const int nf = s->nf;
+    for (int64_t q = 0; q < nn; ++q)
+        if (!(Y[q] > 0.0)) return fail(LB_ESTATE, "rho <= 0 at node %lld", (long long)q);
+    for (int64_t q = 0; q < (int64_t)nf * nn; ++q)
+        if (!isfinite(Y[q])) return fail(LB_ESTATE, "non-finite moment at %lld", (long long)q);
+    const double lam2 = lambda * lambda;
+    std::vector<double> tmp;
+    std::vector<float> tmpf;
+    try {
+        if (s->precision == LB_FP64) tmp.resize((size_t)nf * nn);
+        else tmpf.resize((size_t)nf * nn);
+    } catch (...) {
+        return fail(LB_ENOMEM, "host staging allocation failed");
+    }
+    for (int f = 0; f < nf; ++f) {
+        const double sc = f == 0 ? 0.0 : (f == nf - 1 ? lam2 : lambda);
+        for (int64_t q = 0; q < nn; ++q) {
+            const double y = Y[(int64_t)f * nn + q];
+            const double v = f == 0 ? y : y * sc;
+            if (s->precision == LB_FP64) tmp[(size_t)f * nn + q] = v;
+            else tmpf[(size_t)f * nn + q] = (float)v;
+        }
+    }
+    hipError_t e = s->precision == LB_FP64
+        ? hipMemcpyAsync(buf_ptr(s, 0), tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice, s->stream)
+        : hipMemcpyAsync(buf_ptr(s, 0), tmpf.data(), tmpf.size() * 4, hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return hip_fail(e, "sync");
+    s->lambda = lambda;
+    return start_state(s);
+}
+
+static int queue_steps(lb_solver* s, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        const int in = s->cur, out = s->cur ^ 1;
+        const long long step = (long long)(s->steps_done + 1);
+        hipError_t e;
+        if (s->dim == 1) {
+            if (s->precision == LB_FP64)
+                e = launch_step1d<double>((const double*)buf_ptr(s, in), (double*)buf_ptr(s, out), s->g,
+                                          s->k, ctl_ptr(s), partials_ptr(s), step, s->stream);
+            else
+                e = launch_step1d<float>((const float*)buf_ptr(s, in), (float*)buf_ptr(s, out), s->g,
+                                         s->k, ctl_ptr(s), partials_ptr(s), step, s->stream);
+        } else {
+            if (s->precision == LB_FP64)
+                e = launch_step2d<double>((const double*)buf_ptr(s, in), (double*)buf_ptr(s, out), s->g,
+                                          s->k, ctl_ptr(s), partials_ptr(s), step, s->stream);
+            else
+                e = launch_step2d<float>((const float*)buf_ptr(s, in), (float*)buf_ptr(s, out), s->g,
+                                         s->k, ctl_ptr(s), partials_ptr(s), step, s->stream);
+        }
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        s->cur = out;
+        s->steps_done += 1;
+    }
+    return LB_OK;
+}
+
+int lb_step(lb_solver* s, int64_t n)
+{
+    if (!s || !s->initialized) return fail(LB_EINVAL, "solver not initialised");
+    if (n < 0) return fail(LB_EINVAL, "n must be >= 0");
+    if (s->pending_err) return fail(s->pending_err, "an earlier step failed; re-initialise");
+    return queue_steps(s, n);
+}
+
+// Wait, then roll the host view back to the last good step if one failed.
+int lb_sync(lb_solver* s)
+{
+    if (!s || !s->bound) return fail(LB_EINVAL, "solver not bound");
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "sync");
+    if (s->pending_err) return fail(s->pending_err, "an earlier step failed; re-initialise");
+    if (!s->initialized) return LB_OK;
+    StepCtl c;
+    if ((e = hipMemcpy(&c, ctl_ptr(s), sizeof c, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "read control block");
+    if (c.err_code) {
+        // step err_step (1-based since init) failed; its input, the state
+        // after err_step - 1 steps, sits in buffer (err_step - 1) & 1.
+        const int64_t good = (int64_t)c.err_step - 1;
+        s->steps_done = good;
+        s->cur = (int)(good & 1);
+        s->pending_err = (c.err_code & kErrState) ? LB_ESTATE : LB_EREACH;
+        return fail(s->pending_err, "step %lld failed: %s", (long long)c.err_step,
+                    (c.err_code & kErrState) ? "rho <= 0 or non-finite moment"
+                                             : "a packet moves further than the halo");
+    }
+    return LB_OK;
+}
+
+int lb_step_timed(lb_solver* s, int64_t n, float* ms)
+{
+    if (!s || !ms) return fail(LB_EINVAL, "null argument");
+    if (!s->initialized) return fail(LB_EINVAL, "solver not initialised");
+    if (n < 0) return fail(LB_EINVAL, "n must be >= 0");
+    if (s->pending_err) return fail(s->pending_err, "an earlier step failed; re-initialise");
+    hipError_t e;
+    if ((e = hipEventRecord(s->ev0, s->stream)) != hipSuccess) return hip_fail(e, "event");
+    int rc = queue_steps(s, n);
+    if (rc != LB_OK) return rc;
+    if ((e = hipEventRecord(s->ev1, s->stream)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipEventSynchronize(s->ev1)) != hipSuccess) return hip_fail(e, "event sync");
+    float t = 0.f;
+    if ((e = hipEventElapsedTime(&t, s->ev0, s->ev1)) != hipSuccess) return hip_fail(e, "elapsed");
+    rc = lb_sync(s);
+    if (rc != LB_OK) return rc;
+    *ms = t;
+    return LB_OK;
+}
+
+static void field_scales(const lb_solver* s, double sc[4])
+{
+    const double lam = s->lambda, lam2 = lam * lam;
+    sc[0] = 1.0;
+    for (int f = 1; f < 4; ++f) sc[f] = 1.0;
+    for (int f = 1; f < s->nf - 1; ++f) sc[f] = lam;
+    sc[s->nf - 1] = lam2;
+}
+
+int lb_moments(lb_solver* s, double* out, int32_t on_device)
+{
+    if (!s || !out) return fail(LB_EINVAL, "null argument");
+    if (!s->initialized) return fail(LB_EINVAL, "solver not initialised");
+    int rc = lb_sync(s);
+    if (rc != LB_OK && rc != LB_EREACH && rc != LB_ESTATE) return rc;
+    // After a failed step the state is the last good one; exporting it is allowed.
+    double sc[4];
+    field_scales(s, sc);
+    double* dst = on_device ? out : export_ptr(s);
+    hipError_t e = s->precision == LB_FP64
+        ? launch_export<double>((const double*)buf_ptr(s, s->cur), dst, s->nn, s->nf, sc, s->stream)
+        : launch_export<float>((const float*)buf_ptr(s, s->cur), dst, s->nn, s->nf, sc, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "export kernel");
+    if (!on_device) {
+        e = hipMemcpyAsync(out, dst, (size_t)s->nf * s->nn * 8, hipMemcpyDeviceToHost, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "copy out");
+    }
+    if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return hip_fail(e, "sync");
+    if (rc != LB_OK) return fail(rc, "%s", "state is the last good step; an earlier step failed");
+    return LB_OK;
+}
+
+int lb_totals(lb_solver* s, double out[4])
+{
+    if (!s || !out) return fail(LB_EINVAL, "null argument");
+    if (!s->initialized) return fail(LB_EINVAL, "solver not initialised");
+    int rc = lb_sync(s);
+    if (rc != LB_OK) return rc;
+    StepCtl c;
+    hipError_t e = hipMemcpy(&c, ctl_ptr(s), sizeof c, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read control block");
+    double sc[4];
+    field_scales(s, sc);
+    double t[4] = {0, 0, 0, 0};
+    if (c.totals_step == (long long)s->steps_done && s->steps_done > 0) {
+        for (int f = 0; f < 4; ++f) t[f] = c.totals[f];
+    } else {
+        // no step since init: sum the exported state on the host (index order)
+        std::vector<double> y;
+        try { y.resize((size_t)s->nf * s->nn); } catch (...) { return fail(LB_ENOMEM, "host alloc"); }
+        double sc1[4] = {1, 1, 1, 1};
+        e = s->precision == LB_FP64
+            ? launch_export<double>((const double*)buf_ptr(s, s->cur), export_ptr(s), s->nn, s->nf, sc1, s->stream)
+            : launch_export<float>((const float*)buf_ptr(s, s->cur), export_ptr(s), s->nn, s->nf, sc1, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "export kernel");
+        e = hipMemcpyAsync(y.data(), export_ptr(s), y.size() * 8, hipMemcpyDeviceToHost, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "copy out");
+        if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return hip_fail(e, "sync");
+        for (int f = 0; f < s->nf; ++f) {
+            double a = 0.0;
+            for (int64_t q = 0; q < s->nn; ++q) a += y[(size_t)f * s->nn + q];
+            t[f] = a;
+        }
+    }
+    // field order on the device: rho, rho u, (rho v), rho E -> out[0..3]
+    double o[4] = {0, 0, 0, 0};
+    o[0] = t[0] / sc[0];
+    o[1] = t[1] / sc[1];
+    if (s->dim == 2) {
+        o[2] = t[2] / sc[2];
+        o[3] = t[3] / sc[3];
+    } else {
+        o[3] = t[2] / sc[2];
+    }
+    for (int f = 0; f < 4; ++f) out[f] = o[f];
+    return LB_OK;
+}
+
+double lb_lambda(const lb_solver* s) { return s ? s->lambda : 0.0; }
+
+double lb_dt(const lb_solver* s)
+{
+    return s ? s->lambda * (s->grid.x_hi - s->grid.x_lo) / (double)s->grid.nx : 0.0;
+}
+
+int64_t lb_steps_done(const lb_solver* s) { return s ? s->steps_done : 0; }
+
+int32_t lb_max_reach(lb_solver* s)
+{
+    if (!s || !s->bound) return -1;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return -1;
+    StepCtl c;
+    if (hipMemcpy(&c, ctl_ptr(s), sizeof c, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+    return c.max_reach;
+}
+
+int lb_debug_lanes(lb_solver* s, int32_t* fx, int32_t* fy, int32_t* c1)
+{
+    if (!s || !fx || !fy || !c1) return fail(LB_EINVAL, "null argument");
+    if (!s->initialized) return fail(LB_EINVAL, "solver not initialised");
+    int rc = lb_sync(s);
+    if (rc != LB_OK && rc != LB_EREACH && rc != LB_ESTATE) return rc;
+    int32_t* d = (int32_t*)export_ptr(s);  // 3 nn int32 fit in the nf nn FP64 staging area
+    hipError_t e = s->precision == LB_FP64
+        ? launch_lanes<double>((const double*)buf_ptr(s, s->cur), s->g, s->dim, s->k, d, d + s->nn,
+                               d + 2 * s->nn, s->stream)
+        : launch_lanes<float>((const float*)buf_ptr(s, s->cur), s->g, s->dim, s->k, d, d + s->nn,
+                              d + 2 * s->nn, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "lanes kernel");
+    int32_t* outs[3] = {fx, fy, c1};
+    for (int i = 0; i < 3; ++i) {
+        e = hipMemcpyAsync(outs[i], d + (size_t)i * s->nn, (size_t)s->nn * 4, hipMemcpyDeviceToHost,
+                           s->stream);
+        if (e != hipSuccess) return hip_fail(e, "copy out");
+    }
+    if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return hip_fail(e, "sync");
+    return LB_OK;
+}
+
+void lb_destroy(lb_solver* s)
+{
+    if (!s) return;
+    if (s->bound) (void)hipStreamSynchronize(s->stream);
+    if (s->events) {
+        (void)hipEventDestroy(s->ev0);
+        (void)hipEventDestroy(s->ev1);
+    }
+    delete s;
+}
+
+}  // extern "C"

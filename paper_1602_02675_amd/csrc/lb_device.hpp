@@ -1,0 +1,218 @@
+// Device-side building blocks of the tau = 1 semi-discrete LB step on gfx950.
+//
+// One node's equilibrium (Sec. III.B of Komeili, Mirzaei, Shabouei,
+// arXiv 1602.02675) is reduced to the handful of numbers a destination needs
+// to rebuild every packet the node emits:
+//   f      floor of the flow velocity per axis (corner 0 of eq. 28/29)
+//   r      v - f per axis: the interpolation fraction (alpha_1 = r, alpha_0 = 1 - r)
+//   c1     c'_1 of eq. 26 (c'_2 = c1 + 1)
+//   d0..d2 level weights (eq. 24-25 and d_0 = delta0 rho)
+//   K      |v|^2 / 2 + phi, so that a packet on lane c' carries
+//          zeta = K + c'.v + |c'|^2 / 2 (eq. 14, 21)
+// The integer decisions (f, c1) are taken in the same precision and with the
+// same expression order as the plain definition, with FMA contraction off, so
+// that the destination of every packet is reproducible bit for bit.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbsd {
+
+constexpr int kMaxC1 = 1000;  // caps A (any real reach check fails far earlier)
+
+// Problem constants shared by every kernel (lattice units).
+struct Consts {
+    double Dg1;       // D (gamma - 1)
+    double phi_coef;  // 1 - (D/2)(gamma - 1), eq. 15
+    double delta0;    // d_0 / rho on the 1-D triple-level set
+    double b0;        // rest-lane multiplicity b_0 (1 in 1-D, 0 on the square lattice)
+    double inv_b1;    // 1 / b_1
+};
+
+template <typename T>
+struct Src1 {   // one source node of the 1-D lattice
+    int f, c1;
+    T r, d0, d1, d2, K;
+    bool bad;   // rho <= 0 or a non-finite moment
+};
+
+template <typename T>
+struct Src2 {   // one source node of the square lattice
+    int fx, fy, c1;
+    T rx, ry, d1, d2, K;
+    bool bad;
+};
+
+template <typename T>
+__device__ __forceinline__ T dev_floor(T x) { return floor(x); }
+template <>
+__device__ __forceinline__ float dev_floor<float>(float x) { return floorf(x); }
+
+template <typename T>
+__device__ __forceinline__ T dev_sqrt(T x) { return sqrt(x); }
+template <>
+__device__ __forceinline__ float dev_sqrt<float>(float x) { return sqrtf(x); }
+
+// Largest integer c with c*c <= A, for 0 <= A <= kMaxC1^2 (eq. 26: "int" of sqrt).
+template <typename T>
+__device__ __forceinline__ int isqrt_floor(T A)
+{
+#pragma clang fp contract(off)
+    int c = (int)dev_floor<T>(dev_sqrt<T>(A));
+    if (c > 0 && (T)c * (T)c > A) --c;
+    if ((T)(c + 1) * (T)(c + 1) <= A) ++c;
+    return c;
+}
+
+// Internal energy, c'_1 and the weight split of one node.  rho > 0 required.
+//  e = E - |v|^2/2 (clamped at 0), A = D(gamma-1) e rho / (rho - b0 d0),
+//  c1 = floor(sqrt(A)); with w = (A - c1^2) / (c2^2 - c1^2) in [0, 1):
+//  b1 d2 = (rho - b0 d0) w and b1 d1 = (rho - b0 d0)(1 - w), which is eq. 24-25
+//  rewritten (both sum to rho - b0 d0 and satisfy sum b d c'^2 = D p).
+template <typename T>
+struct Levels {
+    T e, A, rest;
+    int c1;
+};
+
+template <typename T>
+__device__ __forceinline__ Levels<T> node_levels(T rho, T v2, T E, T d0, const Consts& k)
+{
+#pragma clang fp contract(off)
+    Levels<T> L;
+    T e = E - (T)0.5 * v2;
+    if (e < (T)0) e = (T)0;
+    L.e = e;
+    L.rest = rho - (T)k.b0 * d0;
+    T A = (T)k.Dg1 * e * rho / L.rest;
+    if (!(A >= (T)0)) A = (T)0;
+    if (A > (T)kMaxC1 * (T)kMaxC1) A = (T)kMaxC1 * (T)kMaxC1;
+    L.A = A;
+    L.c1 = isqrt_floor<T>(A);
+    return L;
+}
+
+template <typename T>
+__device__ __forceinline__ bool finite_val(T x) { return isfinite(x); }
+
+template <typename T>
+__device__ __forceinline__ Src1<T> make_src1(T m0, T m1, T m2, const Consts& k)
+{
+    Src1<T> s;
+    s.bad = !(m0 > (T)0) || !finite_val(m0) || !finite_val(m1) || !finite_val(m2);
+    if (s.bad || !(m0 > (T)0)) {
+        s.f = 0; s.c1 = 0;
+        s.r = (T)0; s.d0 = (T)0; s.d1 = (T)0; s.d2 = (T)0; s.K = (T)0;
+        return s;
+    }
+    T v, E, v2, d0;
+    {
+#pragma clang fp contract(off)
+        v = m1 / m0;
+        E = m2 / m0;
+        v2 = v * v;
+        d0 = (T)k.delta0 * m0;
+    }
+    Levels<T> L = node_levels<T>(m0, v2, E, d0, k);
+    T fv = dev_floor<T>(v);
+    s.f = (int)fv;
+    s.r = v - fv;
+    s.c1 = L.c1;
+    const T c1s = (T)(L.c1 * L.c1);
+    const T w0 = (L.A - c1s) / (T)(2 * L.c1 + 1);
+    const T w = w0 < (T)0 ? (T)0 : (w0 > (T)1 ? (T)1 : w0);
+    const T per = L.rest * (T)k.inv_b1;
+    s.d2 = per * w;
+    s.d1 = per - s.d2;
+    s.d0 = d0;
+    const T phi = (T)k.phi_coef * L.e;
+    s.K = (T)0.5 * v2 + phi;
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ Src2<T> make_src2(T m0, T m1, T m2, T m3, const Consts& k)
+{
+    Src2<T> s;
+    s.bad = !(m0 > (T)0) || !finite_val(m0) || !finite_val(m1) || !finite_val(m2) || !finite_val(m3);
+    if (s.bad) {
+        s.fx = 0; s.fy = 0; s.c1 = 0;
+        s.rx = (T)0; s.ry = (T)0; s.d1 = (T)0; s.d2 = (T)0; s.K = (T)0;
+        return s;
+    }
+    T vx, vy, E, v2;
+    {
+#pragma clang fp contract(off)
+        vx = m1 / m0;
+        vy = m2 / m0;
+        E = m3 / m0;
+        v2 = vx * vx + vy * vy;
+    }
+    Levels<T> L = node_levels<T>(m0, v2, E, (T)0, k);
+    const T fvx = dev_floor<T>(vx), fvy = dev_floor<T>(vy);
+    s.fx = (int)fvx;
+    s.fy = (int)fvy;
+    s.rx = vx - fvx;
+    s.ry = vy - fvy;
+    s.c1 = L.c1;
+    const T c1s = (T)(L.c1 * L.c1);
+    const T w0 = (L.A - c1s) / (T)(2 * L.c1 + 1);
+    const T w = w0 < (T)0 ? (T)0 : (w0 > (T)1 ? (T)1 : w0);
+    const T per = L.rest * (T)k.inv_b1;
+    s.d2 = per * w;
+    s.d1 = per - s.d2;
+    const T phi = (T)k.phi_coef * L.e;
+    s.K = (T)0.5 * v2 + phi;
+    return s;
+}
+
+// Reach of a node: the largest |displacement| of any of its packets along one
+// axis, max(f + 1 + c'_2, c'_2 - f).
+__device__ __forceinline__ int axis_reach(int f, int c1)
+{
+    const int c2 = c1 + 1;
+    const int a = f + 1 + c2, b = c2 - f;
+    return a > b ? a : b;
+}
+
+// Wavefront (64-lane) reductions.
+template <typename V>
+__device__ __forceinline__ V wave_sum(V x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+__device__ __forceinline__ int wave_max(int x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) { int y = __shfl_xor(x, o, 64); x = y > x ? y : x; }
+    return x;
+}
+__device__ __forceinline__ int wave_min(int x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) { int y = __shfl_xor(x, o, 64); x = y < x ? y : x; }
+    return x;
+}
+
+__device__ __forceinline__ int64_t wrap_idx(int64_t i, int64_t n)
+{
+    int64_t r = i % n;
+    return r < 0 ? r + n : r;
+}
+// Periodic index for i within a few periods of [0, n): the full modulo runs
+// only for the (halo) indices that are out of range.
+__device__ __forceinline__ int64_t wrap_near(int64_t i, int64_t n)
+{
+    if (i >= 0 && i < n) return i;
+    if (i < 0 && i + n >= 0) return i + n;
+    if (i >= n && i - n < n) return i - n;
+    return wrap_idx(i, n);
+}
+__device__ __forceinline__ int64_t clamp_idx(int64_t i, int64_t n)
+{
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+}  // namespace lbsd

@@ -1,0 +1,569 @@
+// The tau = 1 step of the semi-discrete compressible LB method as one fused
+// gather kernel per step (1-D triple-level lattice and square dual-level
+// lattice of Komeili, Mirzaei, Shabouei, arXiv 1602.02675, Sec. III-V).
+//
+// With tau = 1 the distribution after a step is the migrated equilibrium
+// (eq. 10, eq. 30), and the equilibrium depends on the node moments only, so
+// the whole state is the SoA moment field Y = (rho, rho v, rho E) (eq. 7) and a
+// step maps Y to Y'.  Every node (source) emits packets m (1, v + c', zeta) to
+// x + floor(v) + k + c' (eq. 11-13, 21, 23); Y' at a node is the sum of what
+// lands there (Sec. V.A).
+//
+// GPU formulation (deterministic gather, no atomics on field data):
+//   1. a block stages the sources of its destination tile plus a halo of H
+//      nodes in LDS, reduced to (f, r, c'_1, d_v, K) per source
+//      (lb_device.hpp);
+//   2. every destination rebuilds each packet class (lane, corner) from the
+//      source that class maps onto it.  In a tile where floor(v) and c'_1 are
+//      the same for every staged source (the integer parts of the migration
+//      vectors are piecewise constant), each class has exactly one source at
+//      a compile-time offset, and the 10 (1-D) or 32 (2-D) packets are fully
+//      unrolled; otherwise every candidate displacement in the tile's range
+//      is tested against the source's own displacement;
+//   3. the interior sums of the new moments are reduced per block with
+//      wavefront shuffles, and the last block to finish adds the per-block
+//      partials in a fixed order (deterministic totals), along with the
+//      reach (halo overflow) and state checks.
+#include <climits>
+
+#include "lb_kernels.hpp"
+
+namespace lbsd {
+
+namespace {
+
+__device__ __forceinline__ int pack_lane(int fx, int fy, int c1)
+{
+    fx = fx < -127 ? -127 : (fx > 127 ? 127 : fx);
+    fy = fy < -127 ? -127 : (fy > 127 ? 127 : fy);
+    c1 = c1 > 255 ? 255 : c1;
+    return (fx + 128) | ((fy + 128) << 8) | (c1 << 16);
+}
+__device__ __forceinline__ int lane_fx(int p) { return (p & 255) - 128; }
+__device__ __forceinline__ int lane_fy(int p) { return ((p >> 8) & 255) - 128; }
+__device__ __forceinline__ int lane_c1(int p) { return (p >> 16) & 255; }
+
+// Integer summary of the staged sources of one block.
+struct TileInfo {
+    int fxmin, fxmax, fymin, fymax, cmin, cmax, reach, bad;
+};
+
+template <int NW>
+__device__ __forceinline__ TileInfo block_tile_info(TileInfo t, int (*s_red)[8])
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    t.fxmin = wave_min(t.fxmin); t.fxmax = wave_max(t.fxmax);
+    t.fymin = wave_min(t.fymin); t.fymax = wave_max(t.fymax);
+    t.cmin = wave_min(t.cmin);   t.cmax = wave_max(t.cmax);
+    t.reach = wave_max(t.reach); t.bad = wave_max(t.bad);
+    if (lane == 0) {
+        s_red[wid][0] = t.fxmin; s_red[wid][1] = t.fxmax;
+        s_red[wid][2] = t.fymin; s_red[wid][3] = t.fymax;
+        s_red[wid][4] = t.cmin;  s_red[wid][5] = t.cmax;
+        s_red[wid][6] = t.reach; s_red[wid][7] = t.bad;
+    }
+    __syncthreads();
+    TileInfo r = {s_red[0][0], s_red[0][1], s_red[0][2], s_red[0][3],
+                  s_red[0][4], s_red[0][5], s_red[0][6], s_red[0][7]};
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+        r.fxmin = min(r.fxmin, s_red[w][0]); r.fxmax = max(r.fxmax, s_red[w][1]);
+        r.fymin = min(r.fymin, s_red[w][2]); r.fymax = max(r.fymax, s_red[w][3]);
+        r.cmin = min(r.cmin, s_red[w][4]);   r.cmax = max(r.cmax, s_red[w][5]);
+        r.reach = max(r.reach, s_red[w][6]); r.bad = max(r.bad, s_red[w][7]);
+    }
+    return r;
+}
+
+// Epilogue: per-block field sums and checks -> one row of `partials`.  No
+// atomics or device-scope fences here: the reduction over blocks is a separate
+// single-block kernel (finalize_kernel), so the kernel boundary orders it.
+template <int NW, int NF>
+__device__ void finish_step(double (&acc)[NF], const TileInfo& ti, double* __restrict__ partials,
+                            int H)
+{
+    __shared__ double s_sum[NW][4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t bid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] = wave_sum(acc[f]);
+    if (lane == 0) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) s_sum[wid][f] = acc[f];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double* p = partials + bid * kPartialStride;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            double s = s_sum[0][f];
+            for (int w = 1; w < NW; ++w) s += s_sum[w][f];
+            p[f] = s;
+        }
+        for (int f = NF; f < 4; ++f) p[f] = 0.0;
+        p[4] = (double)ti.reach;
+        p[5] = (double)((ti.reach > H ? kErrReach : 0) | (ti.bad ? kErrState : 0));
+    }
+}
+
+// Sum the per-block partials of one step in a fixed order (deterministic),
+// record the totals, the largest reach and the first failed step.
+constexpr int kFinTPB = 256;
+__global__ void __launch_bounds__(kFinTPB)
+finalize_kernel(const double* __restrict__ partials, int64_t nb, StepCtl* __restrict__ ctl,
+                long long step, int H)
+{
+    __shared__ double s_sum[kFinTPB / 64][4];
+    __shared__ int s_ir[kFinTPB / 64][2];
+    if (ctl->err_step < step) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    int reach = 0, err = 0;
+    for (int64_t b = tid; b < nb; b += kFinTPB) {
+        const double* p = partials + b * kPartialStride;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) s[f] += p[f];
+        reach = max(reach, (int)p[4]);
+        err |= (int)p[5];
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) s[f] = wave_sum(s[f]);
+    reach = wave_max(reach);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) err |= __shfl_xor(err, o, 64);
+    if (lane == 0) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) s_sum[wid][f] = s[f];
+        s_ir[wid][0] = reach;
+        s_ir[wid][1] = err;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int f = 0; f < 4; ++f) {
+            double t = s_sum[0][f];
+            for (int w = 1; w < kFinTPB / 64; ++w) t += s_sum[w][f];
+            ctl->totals[f] = t;
+        }
+        int r = s_ir[0][0], e = s_ir[0][1];
+        for (int w = 1; w < kFinTPB / 64; ++w) { r = max(r, s_ir[w][0]); e |= s_ir[w][1]; }
+        ctl->max_reach = r;
+        ctl->totals_step = step;
+        if (e) {
+            ctl->err_code = e;
+            ctl->err_step = step;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ 1-D ----
+
+template <typename T>
+struct Tile1 {
+    int* pk;
+    T *r, *d0, *d1, *d2, *K;
+};
+
+// One packet of a 1-D source s at displacement k + c' from its floor node:
+// mass alpha_k d, momentum m (v + c'), energy m (K + c' v + c'^2/2).
+template <typename T>
+__device__ __forceinline__ void add_packet1(const Tile1<T>& tl, int s, int f, int k, int lane_c,
+                                            int lev, T& R, T& P, T& En)
+{
+    const T r = tl.r[s];
+    const T a = k ? r : (T)1 - r;
+    const T d = lev == 0 ? tl.d0[s] : (lev == 1 ? tl.d1[s] : tl.d2[s]);
+    const T m = a * d;
+    const T v = (T)f + r;
+    const T c = (T)lane_c;
+    const T xi = v + c;
+    const T zeta = tl.K[s] + c * v + (T)0.5 * c * c;
+    R += m;
+    P += m * xi;
+    En += m * zeta;
+}
+
+// Lane l of the 1-D set: 0 rest (d0), 1/2 +-c1 (d1), 3/4 +-c2 (d2).
+__device__ __forceinline__ constexpr int lane_level1(int l) { return l == 0 ? 0 : (l <= 2 ? 1 : 2); }
+__device__ __forceinline__ constexpr int lane_sign1(int l) { return l == 0 ? 0 : ((l & 1) ? 1 : -1); }
+
+template <typename T, int H, int TPB, int J, int C1>
+__device__ __forceinline__ void gather1_uniform(const Tile1<T>& tl, int f, int64_t x0, int64_t nx,
+                                                T* __restrict__ Yn, double (&acc)[3])
+{
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int t = j * TPB + (int)threadIdx.x;
+        const int base = t + H - f;  // source of displacement f + o is base - o
+        T R = 0, P = 0, En = 0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+#pragma unroll
+            for (int l = 0; l < 5; ++l) {
+                const int lev = lane_level1(l);
+                const int c = lane_sign1(l) * (lev == 0 ? 0 : C1 + lev - 1);
+                add_packet1<T>(tl, base - (k + c), f, k, c, lev, R, P, En);
+            }
+        }
+        const int64_t x = x0 + t;
+        if (x < nx) {
+            Yn[x] = R;
+            Yn[nx + x] = P;
+            Yn[2 * nx + x] = En;
+            acc[0] += (double)R;
+            acc[1] += (double)P;
+            acc[2] += (double)En;
+        }
+    }
+}
+
+template <typename T, int H, int TPB, int J>
+__device__ void gather1_general(const Tile1<T>& tl, const TileInfo& ti, int64_t x0, int64_t nx,
+                                T* __restrict__ Yn, double (&acc)[3])
+{
+    for (int j = 0; j < J; ++j) {
+        const int t = j * TPB + (int)threadIdx.x;
+        T R = 0, P = 0, En = 0;
+        for (int k = 0; k < 2; ++k) {
+            for (int l = 0; l < 5; ++l) {
+                const int lev = lane_level1(l), sg = lane_sign1(l);
+                int clo = 0, chi = 0;
+                if (lev > 0) {
+                    const int a = ti.cmin + lev - 1, b = ti.cmax + lev - 1;
+                    clo = sg > 0 ? a : -b;
+                    chi = sg > 0 ? b : -a;
+                }
+                const int lo = max(-H, ti.fxmin + k + clo), hi = min(H, ti.fxmax + k + chi);
+                for (int dl = lo; dl <= hi; ++dl) {
+                    const int s = t + H - dl;
+                    const int p = tl.pk[s];
+                    const int fs = lane_fx(p);
+                    const int cs = lev == 0 ? 0 : sg * (lane_c1(p) + lev - 1);
+                    if (fs + k + cs != dl) continue;
+                    add_packet1<T>(tl, s, fs, k, cs, lev, R, P, En);
+                }
+            }
+        }
+        const int64_t x = x0 + t;
+        if (x < nx) {
+            Yn[x] = R;
+            Yn[nx + x] = P;
+            Yn[2 * nx + x] = En;
+            acc[0] += (double)R;
+            acc[1] += (double)P;
+            acc[2] += (double)En;
+        }
+    }
+}
+
+template <typename T, int H, int TPB, int J>
+__global__ void __launch_bounds__(TPB)
+step1d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
+              StepCtl* __restrict__ ctl, double* __restrict__ partials, long long step)
+{
+    constexpr int TILE = TPB * J;
+    constexpr int W = TILE + 2 * H;
+    constexpr int NW = TPB / 64;
+    __shared__ int s_pk[W];
+    __shared__ T s_r[W], s_d0[W], s_d1[W], s_d2[W], s_K[W];
+    __shared__ int s_red[NW][8];
+    if (ctl->err_step < step) return;  // an earlier step failed: keep its input intact
+
+    const int64_t nx = g.nx;
+    const int64_t x0 = (int64_t)blockIdx.x * TILE;
+    TileInfo ti = {INT_MAX, INT_MIN, 0, 0, INT_MAX, INT_MIN, 0, 0};
+    constexpr int NS = (W + TPB - 1) / TPB;
+    T ld[NS][3];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const int i = (int)threadIdx.x + u * TPB;
+        if (i < W) {
+            const int64_t gx = x0 - H + i;
+            const int64_t si = g.bc_x == kBcPeriodic ? wrap_near(gx, nx) : clamp_idx(gx, nx);
+            ld[u][0] = Y[si]; ld[u][1] = Y[nx + si]; ld[u][2] = Y[2 * nx + si];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const int i = (int)threadIdx.x + u * TPB;
+        if (i >= W) break;
+        const Src1<T> s = make_src1<T>(ld[u][0], ld[u][1], ld[u][2], k);
+        s_pk[i] = pack_lane(s.f, 0, s.c1);
+        s_r[i] = s.r;
+        s_d0[i] = s.d0;
+        s_d1[i] = s.d1;
+        s_d2[i] = s.d2;
+        s_K[i] = s.K;
+        ti.fxmin = min(ti.fxmin, s.f);
+        ti.fxmax = max(ti.fxmax, s.f);
+        ti.cmin = min(ti.cmin, s.c1);
+        ti.cmax = max(ti.cmax, s.c1);
+        ti.reach = max(ti.reach, axis_reach(s.f, s.c1));
+        ti.bad |= s.bad ? 1 : 0;
+    }
+    ti = block_tile_info<NW>(ti, s_red);  // contains the barrier after staging
+    const Tile1<T> tl = {s_pk, s_r, s_d0, s_d1, s_d2, s_K};
+    double acc[3] = {0.0, 0.0, 0.0};
+    const bool uniform = ti.fxmin == ti.fxmax && ti.cmin == ti.cmax && ti.reach <= H;
+    if (uniform && ti.cmin == 0)
+        gather1_uniform<T, H, TPB, J, 0>(tl, ti.fxmin, x0, nx, Yn, acc);
+    else if (uniform && ti.cmin == 1)
+        gather1_uniform<T, H, TPB, J, 1>(tl, ti.fxmin, x0, nx, Yn, acc);
+    else if (uniform && ti.cmin == 2)
+        gather1_uniform<T, H, TPB, J, 2>(tl, ti.fxmin, x0, nx, Yn, acc);
+    else if (uniform && ti.cmin == 3)
+        gather1_uniform<T, H, TPB, J, 3>(tl, ti.fxmin, x0, nx, Yn, acc);
+    else
+        gather1_general<T, H, TPB, J>(tl, ti, x0, nx, Yn, acc);
+    finish_step<NW, 3>(acc, ti, partials, H);
+}
+
+// ------------------------------------------------------------------ 2-D ----
+
+template <typename T>
+struct Tile2 {
+    int* pk;
+    T *rx, *ry, *d1, *d2, *K;
+};
+
+// One packet of a square-lattice source s: corner (kx, ky), lane along axis
+// `ax` (0 = x, 1 = y) with signed speed c, level lev (d1 or d2).
+template <typename T>
+__device__ __forceinline__ void add_packet2(const Tile2<T>& tl, int s, int fx, int fy, int kx, int ky,
+                                            int ax, int c, int lev, T& R, T& Px, T& Py, T& En)
+{
+    const T rx = tl.rx[s], ry = tl.ry[s];
+    const T a = (kx ? rx : (T)1 - rx) * (ky ? ry : (T)1 - ry);
+    const T m = a * (lev == 1 ? tl.d1[s] : tl.d2[s]);
+    const T vx = (T)fx + rx, vy = (T)fy + ry;
+    const T cc = (T)c;
+    const T xix = ax == 0 ? vx + cc : vx;
+    const T xiy = ax == 1 ? vy + cc : vy;
+    const T zeta = tl.K[s] + cc * (ax == 0 ? vx : vy) + (T)0.5 * cc * cc;
+    R += m;
+    Px += m * xix;
+    Py += m * xiy;
+    En += m * zeta;
+}
+
+// Packet p in [0, 32): lane = p >> 2 (level 1 +x,-x,+y,-y then level 2), corner = p & 3.
+__device__ __forceinline__ constexpr int p2_lev(int p) { return (p >> 4) + 1; }
+__device__ __forceinline__ constexpr int p2_axis(int p) { return (p >> 3) & 1; }
+__device__ __forceinline__ constexpr int p2_sign(int p) { return ((p >> 2) & 1) ? -1 : 1; }
+__device__ __forceinline__ constexpr int p2_kx(int p) { return p & 1; }
+__device__ __forceinline__ constexpr int p2_ky(int p) { return (p >> 1) & 1; }
+
+template <typename T, int H, int TX, int TY, int J, int C1>
+__device__ __forceinline__ void gather2_uniform(const Tile2<T>& tl, int fx, int fy, int64_t x0,
+                                                int64_t y0, const Grid& g, T* __restrict__ Yn,
+                                                double (&acc)[4])
+{
+    constexpr int WX = TX + 2 * H;
+    const int lx = (int)threadIdx.x % TX, ly = (int)threadIdx.x / TX;
+    const int64_t nn = g.nx * g.ny;
+    const int base0 = (ly * J + H - fy) * WX + (lx + H - fx);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int base = base0 + j * WX;
+        T R = 0, Px = 0, Py = 0, En = 0;
+#pragma unroll
+        for (int p = 0; p < 32; ++p) {
+            const int lev = p2_lev(p), ax = p2_axis(p), sg = p2_sign(p);
+            const int kx = p2_kx(p), ky = p2_ky(p);
+            const int c = sg * (C1 + lev - 1);
+            const int ox = kx + (ax == 0 ? c : 0), oy = ky + (ax == 1 ? c : 0);
+            add_packet2<T>(tl, base - (oy * WX + ox), fx, fy, kx, ky, ax, c, lev, R, Px, Py, En);
+        }
+        const int64_t x = x0 + lx, y = y0 + ly * J + j;
+        if (x < g.nx && y < g.ny) {
+            const int64_t q = y * g.nx + x;
+            Yn[q] = R;
+            Yn[nn + q] = Px;
+            Yn[2 * nn + q] = Py;
+            Yn[3 * nn + q] = En;
+            acc[0] += (double)R;
+            acc[1] += (double)Px;
+            acc[2] += (double)Py;
+            acc[3] += (double)En;
+        }
+    }
+}
+
+template <typename T, int H, int TX, int TY, int J>
+__device__ void gather2_general(const Tile2<T>& tl, const TileInfo& ti, int64_t x0, int64_t y0,
+                                const Grid& g, T* __restrict__ Yn, double (&acc)[4])
+{
+    constexpr int WX = TX + 2 * H;
+    const int lx = (int)threadIdx.x % TX, ly = (int)threadIdx.x / TX;
+    const int64_t nn = g.nx * g.ny;
+    for (int j = 0; j < J; ++j) {
+        const int wx = lx + H, wy = ly * J + j + H;
+        T R = 0, Px = 0, Py = 0, En = 0;
+        for (int p = 0; p < 32; ++p) {
+            const int lev = p2_lev(p), ax = p2_axis(p), sg = p2_sign(p);
+            const int kx = p2_kx(p), ky = p2_ky(p);
+            const int a = ti.cmin + lev - 1, b = ti.cmax + lev - 1;
+            const int clo = sg > 0 ? a : -b, chi = sg > 0 ? b : -a;
+            const int xlo = max(-H, ti.fxmin + kx + (ax == 0 ? clo : 0));
+            const int xhi = min(H, ti.fxmax + kx + (ax == 0 ? chi : 0));
+            const int ylo = max(-H, ti.fymin + ky + (ax == 1 ? clo : 0));
+            const int yhi = min(H, ti.fymax + ky + (ax == 1 ? chi : 0));
+            for (int dy = ylo; dy <= yhi; ++dy) {
+                for (int dx = xlo; dx <= xhi; ++dx) {
+                    const int s = (wy - dy) * WX + (wx - dx);
+                    const int pk = tl.pk[s];
+                    const int fxs = lane_fx(pk), fys = lane_fy(pk);
+                    const int cs = sg * (lane_c1(pk) + lev - 1);
+                    if (fxs + kx + (ax == 0 ? cs : 0) != dx) continue;
+                    if (fys + ky + (ax == 1 ? cs : 0) != dy) continue;
+                    add_packet2<T>(tl, s, fxs, fys, kx, ky, ax, cs, lev, R, Px, Py, En);
+                }
+            }
+        }
+        const int64_t x = x0 + lx, y = y0 + ly * J + j;
+        if (x < g.nx && y < g.ny) {
+            const int64_t q = y * g.nx + x;
+            Yn[q] = R;
+            Yn[nn + q] = Px;
+            Yn[2 * nn + q] = Py;
+            Yn[3 * nn + q] = En;
+            acc[0] += (double)R;
+            acc[1] += (double)Px;
+            acc[2] += (double)Py;
+            acc[3] += (double)En;
+        }
+    }
+}
+
+#ifndef LB_T2_WPE
+#define LB_T2_WPE 1
+#endif
+template <typename T, int H, int TX, int TY, int J>
+__global__ void __launch_bounds__(TX * TY / J) __attribute__((amdgpu_waves_per_eu(LB_T2_WPE)))
+step2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
+              StepCtl* __restrict__ ctl, double* __restrict__ partials, long long step)
+{
+    constexpr int TPB = TX * TY / J;
+    constexpr int NW = TPB / 64;
+    constexpr int WX = TX + 2 * H, WY = TY + 2 * H, W = WX * WY;
+    __shared__ int s_pk[W];
+    __shared__ T s_rx[W], s_ry[W], s_d1[W], s_d2[W], s_K[W];
+    __shared__ int s_red[NW][8];
+    if (ctl->err_step < step) return;
+
+    const int64_t nx = g.nx, ny = g.ny, nn = nx * ny;
+    const int64_t x0 = (int64_t)blockIdx.x * TX, y0 = (int64_t)blockIdx.y * TY;
+    TileInfo ti = {INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN, 0, 0};
+    constexpr int NS = (W + TPB - 1) / TPB;
+    T ld[NS][4];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const int i = (int)threadIdx.x + u * TPB;
+        if (i < W) {
+            const int wy = i / WX, wx = i - wy * WX;
+            const int64_t gx = x0 - H + wx, gy = y0 - H + wy;
+            const int64_t si = g.bc_x == kBcPeriodic ? wrap_near(gx, nx) : clamp_idx(gx, nx);
+            const int64_t sj = g.bc_y == kBcPeriodic ? wrap_near(gy, ny) : clamp_idx(gy, ny);
+            const int64_t q = sj * nx + si;
+            ld[u][0] = Y[q]; ld[u][1] = Y[nn + q]; ld[u][2] = Y[2 * nn + q]; ld[u][3] = Y[3 * nn + q];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const int i = (int)threadIdx.x + u * TPB;
+        if (i >= W) break;
+        const Src2<T> s = make_src2<T>(ld[u][0], ld[u][1], ld[u][2], ld[u][3], k);
+        s_pk[i] = pack_lane(s.fx, s.fy, s.c1);
+        s_rx[i] = s.rx;
+        s_ry[i] = s.ry;
+        s_d1[i] = s.d1;
+        s_d2[i] = s.d2;
+        s_K[i] = s.K;
+        ti.fxmin = min(ti.fxmin, s.fx);
+        ti.fxmax = max(ti.fxmax, s.fx);
+        ti.fymin = min(ti.fymin, s.fy);
+        ti.fymax = max(ti.fymax, s.fy);
+        ti.cmin = min(ti.cmin, s.c1);
+        ti.cmax = max(ti.cmax, s.c1);
+        ti.reach = max(ti.reach, max(axis_reach(s.fx, s.c1), axis_reach(s.fy, s.c1)));
+        ti.bad |= s.bad ? 1 : 0;
+    }
+    ti = block_tile_info<NW>(ti, s_red);
+    const Tile2<T> tl = {s_pk, s_rx, s_ry, s_d1, s_d2, s_K};
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool uniform = ti.fxmin == ti.fxmax && ti.fymin == ti.fymax && ti.cmin == ti.cmax &&
+                         ti.reach <= H;
+    if (uniform && ti.cmin == 0)
+        gather2_uniform<T, H, TX, TY, J, 0>(tl, ti.fxmin, ti.fymin, x0, y0, g, Yn, acc);
+    else if (uniform && ti.cmin == 1)
+        gather2_uniform<T, H, TX, TY, J, 1>(tl, ti.fxmin, ti.fymin, x0, y0, g, Yn, acc);
+    else if (uniform && ti.cmin == 2)
+        gather2_uniform<T, H, TX, TY, J, 2>(tl, ti.fxmin, ti.fymin, x0, y0, g, Yn, acc);
+    else if (uniform && ti.cmin == 3)
+        gather2_uniform<T, H, TX, TY, J, 3>(tl, ti.fxmin, ti.fymin, x0, y0, g, Yn, acc);
+    else
+        gather2_general<T, H, TX, TY, J>(tl, ti, x0, y0, g, Yn, acc);
+    finish_step<NW, 4>(acc, ti, partials, H);
+}
+
+#ifndef LB_T1_TPB
+#define LB_T1_TPB 256
+#endif
+#ifndef LB_T1_J
+#define LB_T1_J 4
+#endif
+#ifndef LB_T2_TX
+#define LB_T2_TX 32
+#endif
+#ifndef LB_T2_TY
+#define LB_T2_TY 16
+#endif
+#ifndef LB_T2_J
+#define LB_T2_J 4
+#endif
+constexpr int k1TPB = LB_T1_TPB, k1J = LB_T1_J;
+constexpr int k2TX = LB_T2_TX, k2TY = LB_T2_TY, k2J = LB_T2_J;
+
+}  // namespace
+
+int64_t step_blocks_1d(const Grid& g)
+{
+    const int64_t tile = (int64_t)k1TPB * k1J;
+    return (g.nx + tile - 1) / tile;
+}
+
+int64_t step_blocks_2d(const Grid& g)
+{
+    return ((g.nx + k2TX - 1) / k2TX) * ((g.ny + k2TY - 1) / k2TY);
+}
+
+template <typename T>
+hipError_t launch_step1d(const T* Y, T* Yn, const Grid& g, const Consts& k, StepCtl* ctl,
+                         double* partials, long long step, hipStream_t stream)
+{
+    const dim3 grid((unsigned)step_blocks_1d(g));
+    step1d_kernel<T, kHalo, k1TPB, k1J><<<grid, k1TPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step);
+    finalize_kernel<<<1, kFinTPB, 0, stream>>>(partials, (int64_t)grid.x, ctl, step, kHalo);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step2d(const T* Y, T* Yn, const Grid& g, const Consts& k, StepCtl* ctl,
+                         double* partials, long long step, hipStream_t stream)
+{
+    const dim3 grid((unsigned)((g.nx + k2TX - 1) / k2TX), (unsigned)((g.ny + k2TY - 1) / k2TY));
+    step2d_kernel<T, kHalo, k2TX, k2TY, k2J>
+        <<<grid, k2TX * k2TY / k2J, 0, stream>>>(Y, Yn, g, k, ctl, partials, step);
+    finalize_kernel<<<1, kFinTPB, 0, stream>>>(partials, (int64_t)grid.x * grid.y, ctl, step, kHalo);
+    return hipGetLastError();
+}
+
+template hipError_t launch_step1d<double>(const double*, double*, const Grid&, const Consts&,
+                                          StepCtl*, double*, long long, hipStream_t);
+template hipError_t launch_step1d<float>(const float*, float*, const Grid&, const Consts&,
+                                         StepCtl*, double*, long long, hipStream_t);
+template hipError_t launch_step2d<double>(const double*, double*, const Grid&, const Consts&,
+                                          StepCtl*, double*, long long, hipStream_t);
+template hipError_t launch_step2d<float>(const float*, float*, const Grid&, const Consts&,
+                                         StepCtl*, double*, long long, hipStream_t);
+
+}  // namespace lbsd

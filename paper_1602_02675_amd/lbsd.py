@@ -1,0 +1,216 @@
+"""Python binding of the lbsd C ABI (include/lbsd.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of ``liblbsd.so``; PyTorch
+provides the device memory (one uint8 tensor per solver) and the stream.  If
+the library has not been built, importing this module raises: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("LBSD_LIBRARY") or os.path.join(_PKG, "liblbsd.so")
+
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ESTATE, LB_EREACH = 0, -1, -2, -3, -4, -5
+LB_BC_TRANSMISSIVE, LB_BC_PERIODIC = 0, 1
+LB_LATTICE_D1_TRIPLE, LB_LATTICE_D2_SQUARE_DUAL = 1, 2
+LB_FP64, LB_FP32 = 0, 1
+LB_HALO = 5
+
+_ERR_NAMES = {LB_EINVAL: "LB_EINVAL", LB_ENOMEM: "LB_ENOMEM", LB_EDEVICE: "LB_EDEVICE",
+              LB_ESTATE: "LB_ESTATE", LB_EREACH: "LB_EREACH"}
+
+EXPORTED = ["lb_create", "lb_state_bytes", "lb_bind", "lb_set_lambda", "lb_set_cfl",
+            "lb_init_riemann", "lb_init_moments", "lb_step", "lb_step_timed", "lb_sync",
+            "lb_moments", "lb_totals", "lb_lambda", "lb_dt", "lb_steps_done", "lb_max_reach",
+            "lb_debug_lanes", "lb_destroy", "lb_last_error"]
+
+
+class LBError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class lb_grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("x_lo", ctypes.c_double), ("x_hi", ctypes.c_double),
+                ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32)]
+
+
+class lb_velset(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int32), ("d0_frac", ctypes.c_double)]
+
+
+class lb_prim(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_double), ("u", ctypes.c_double), ("v", ctypes.c_double),
+                ("p", ctypes.c_double)]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1602_02675_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    D, I32P = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "lb_create": (ctypes.c_int, [ctypes.POINTER(lb_grid), dbl, ctypes.POINTER(lb_velset), i32,
+                                     ctypes.POINTER(vp)]),
+        "lb_state_bytes": (ctypes.c_size_t, [vp]),
+        "lb_bind": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+        "lb_set_lambda": (ctypes.c_int, [vp, dbl]),
+        "lb_set_cfl": (ctypes.c_int, [vp, dbl]),
+        "lb_init_riemann": (ctypes.c_int, [vp, dbl, ctypes.POINTER(lb_prim), ctypes.POINTER(lb_prim)]),
+        "lb_init_moments": (ctypes.c_int, [vp, D, dbl]),
+        "lb_step": (ctypes.c_int, [vp, i64]),
+        "lb_step_timed": (ctypes.c_int, [vp, i64, ctypes.POINTER(ctypes.c_float)]),
+        "lb_sync": (ctypes.c_int, [vp]),
+        "lb_moments": (ctypes.c_int, [vp, vp, i32]),
+        "lb_totals": (ctypes.c_int, [vp, D]),
+        "lb_lambda": (dbl, [vp]),
+        "lb_dt": (dbl, [vp]),
+        "lb_steps_done": (i64, [vp]),
+        "lb_max_reach": (i32, [vp]),
+        "lb_debug_lanes": (ctypes.c_int, [vp, I32P, I32P, I32P]),
+        "lb_destroy": (None, [vp]),
+        "lb_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = load_library()
+
+
+def _check(rc: int):
+    if rc != LB_OK:
+        raise LBError(rc, _lib.lb_last_error().decode())
+
+
+def _bc(v) -> int:
+    if isinstance(v, str):
+        return {"transmissive": LB_BC_TRANSMISSIVE, "periodic": LB_BC_PERIODIC}[v]
+    return int(v)
+
+
+class Solver:
+    """One grid on one GPU.  State = SoA moments (rho, rho u, (rho v), rho E)."""
+
+    def __init__(self, dim: int, nx: int, ny: int = 1, *, gamma: float = 1.4, d0_frac=None,
+                 precision: str = "fp64", bc_x="transmissive", bc_y="periodic", x_lo: float = 0.0,
+                 x_hi: float = 1.0, device=None, stream=None):
+        import torch
+
+        if d0_frac is None:
+            d0_frac = 0.5 if dim == 1 else 0.0
+        self.dim, self.nx, self.ny = dim, int(nx), int(ny if dim == 2 else 1)
+        self.nf = dim + 2
+        self.precision = precision
+        g = lb_grid(dim, self.nx, self.ny, x_lo, x_hi, _bc(bc_x), _bc(bc_y))
+        vs = lb_velset(LB_LATTICE_D1_TRIPLE if dim == 1 else LB_LATTICE_D2_SQUARE_DUAL, d0_frac)
+        prec = {"fp64": LB_FP64, "fp32": LB_FP32}[precision]
+        h = ctypes.c_void_p()
+        _check(_lib.lb_create(ctypes.byref(g), gamma, ctypes.byref(vs), prec, ctypes.byref(h)))
+        self._h = h
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        nbytes = int(_lib.lb_state_bytes(h))
+        self._buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        _check(_lib.lb_bind(h, ctypes.c_void_p(self._buf.data_ptr()), nbytes,
+                            ctypes.c_void_p(self.stream.cuda_stream)))
+
+    # -- lifecycle -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def state_bytes(self) -> int:
+        return int(_lib.lb_state_bytes(self._h))
+
+    # -- initial states --------------------------------------------------------
+    def set_lambda(self, lam: float):
+        _check(_lib.lb_set_lambda(self._h, float(lam)))
+
+    def set_cfl(self, cfl: float):
+        _check(_lib.lb_set_cfl(self._h, float(cfl)))
+
+    def init_riemann(self, x_d: float, left, right, lam: float | None = None):
+        """left/right = (rho, u, v, p) in physical units."""
+        if lam is not None:
+            self.set_lambda(lam)
+        L, R = lb_prim(*map(float, left)), lb_prim(*map(float, right))
+        _check(_lib.lb_init_riemann(self._h, float(x_d), ctypes.byref(L), ctypes.byref(R)))
+
+    def init_moments(self, Y, lam: float):
+        """Y: FP64 [nf, ny, nx] conserved moments, physical units."""
+        Y = np.ascontiguousarray(Y, dtype=np.float64).reshape(self.nf, self.ny, self.nx)
+        _check(_lib.lb_init_moments(self._h, Y.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    float(lam)))
+
+    # -- stepping --------------------------------------------------------------
+    def step(self, n: int = 1):
+        _check(_lib.lb_step(self._h, int(n)))
+
+    def step_timed(self, n: int) -> float:
+        ms = ctypes.c_float(0.0)
+        _check(_lib.lb_step_timed(self._h, int(n), ctypes.byref(ms)))
+        return float(ms.value)
+
+    def sync(self):
+        _check(_lib.lb_sync(self._h))
+
+    # -- outputs ---------------------------------------------------------------
+    def moments(self) -> np.ndarray:
+        out = np.empty((self.nf, self.ny, self.nx), dtype=np.float64)
+        _check(_lib.lb_moments(self._h, ctypes.c_void_p(out.ctypes.data), 0))
+        return out
+
+    def moments_device(self):
+        import torch
+
+        out = torch.empty((self.nf, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        _check(_lib.lb_moments(self._h, ctypes.c_void_p(out.data_ptr()), 1))
+        return out
+
+    def totals(self) -> np.ndarray:
+        out = np.zeros(4, dtype=np.float64)
+        _check(_lib.lb_totals(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def lanes(self):
+        n = self.nx * self.ny
+        fx, fy, c1 = (np.zeros(n, dtype=np.int32) for _ in range(3))
+        p = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        _check(_lib.lb_debug_lanes(self._h, p(fx), p(fy), p(c1)))
+        shp = (self.ny, self.nx)
+        return fx.reshape(shp), fy.reshape(shp), c1.reshape(shp)
+
+    @property
+    def lam(self) -> float:
+        return float(_lib.lb_lambda(self._h))
+
+    @property
+    def dt(self) -> float:
+        return float(_lib.lb_dt(self._h))
+
+    @property
+    def steps_done(self) -> int:
+        return int(_lib.lb_steps_done(self._h))
+
+    def max_reach(self) -> int:
+        return int(_lib.lb_max_reach(self._h))

@@ -1,0 +1,72 @@
+"""The C ABI library: it loads, exports every symbol include/lbsd.h declares,
+and rejects bad arguments on the host (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbsd.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    from paper_1602_02675_amd import lbsd
+
+    names = _declared()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(lbsd.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in lbsd.h but not exported"
+    assert set(lbsd.EXPORTED) <= set(names)
+
+
+def _create(lbsd, **kw):
+    g = lbsd.lb_grid(kw.get("dim", 1), kw.get("nx", 100), kw.get("ny", 1), kw.get("x_lo", 0.0),
+                     kw.get("x_hi", 1.0), kw.get("bc_x", 0), kw.get("bc_y", 1))
+    vs = lbsd.lb_velset(kw.get("lattice", 1), kw.get("d0", 0.5))
+    h = ctypes.c_void_p()
+    rc = lbsd._lib.lb_create(ctypes.byref(g), kw.get("gamma", 1.4), ctypes.byref(vs),
+                             kw.get("prec", 0), ctypes.byref(h))
+    return rc, h
+
+
+def test_create_validation():
+    from paper_1602_02675_amd import lbsd
+
+    rc, h = _create(lbsd)
+    assert rc == lbsd.LB_OK
+    assert lbsd._lib.lb_state_bytes(h) >= 2 * 3 * 100 * 8
+    lbsd._lib.lb_destroy(h)
+    bad = [dict(gamma=1.0), dict(gamma=3.5), dict(dim=2, lattice=2, d0=0.0, gamma=2.5),
+           dict(d0=1.0), dict(d0=-0.1), dict(dim=3), dict(nx=0), dict(ny=2),
+           dict(dim=2, lattice=1, d0=0.0), dict(dim=2, lattice=2, d0=0.5),
+           dict(bc_x=7), dict(x_hi=0.0), dict(prec=5)]
+    for kw in bad:
+        rc, h = _create(lbsd, **kw)
+        assert rc == lbsd.LB_EINVAL, kw
+        assert lbsd._lib.lb_last_error()
+    rc, h = _create(lbsd, dim=2, lattice=2, d0=0.0, nx=64, ny=32, prec=1)
+    assert rc == lbsd.LB_OK
+    # 2 FP32 buffers of 4 fields + FP64 staging
+    assert lbsd._lib.lb_state_bytes(h) >= 2 * 4 * 64 * 32 * 4 + 4 * 64 * 32 * 8
+    lbsd._lib.lb_destroy(h)
+
+
+def test_calls_on_unbound_solver_fail_cleanly():
+    from paper_1602_02675_amd import lbsd
+
+    rc, h = _create(lbsd)
+    assert lbsd._lib.lb_step(h, 1) == lbsd.LB_EINVAL
+    out = (ctypes.c_double * 4)()
+    assert lbsd._lib.lb_totals(h, out) == lbsd.LB_EINVAL
+    assert lbsd._lib.lb_set_lambda(h, -1.0) == lbsd.LB_EINVAL
+    assert lbsd._lib.lb_set_cfl(h, 0.0) == lbsd.LB_EINVAL
+    assert lbsd._lib.lb_bind(h, None, 0, None) == lbsd.LB_EINVAL
+    lbsd._lib.lb_destroy(h)

@@ -1,0 +1,293 @@
+"""GPU parity: the HIP step (through the C ABI) against the FP64 oracle.
+
+Bar: packet destinations (floor v, c'_1 per node) bit-exact on identical input
+states; FP64 fields within 1e-12 normwise per field (|a - b| <= 1e-12 * max|b|,
+the momentum components sharing one scale since a component can be zero in
+exact arithmetic); the oracle sums packets in source order, the GPU in packet-
+class order, so only rounding differs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1602_02675_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def lbsd():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_1602_02675_amd import lbsd as m
+
+    return m
+
+
+def normwise_err(got, ref, dim):
+    got = np.asarray(got).reshape(ref.shape)
+    errs = []
+    mom = max(np.max(np.abs(ref[1:1 + dim])), 1e-300)
+    for f in range(ref.shape[0]):
+        scale = mom if 1 <= f <= dim else max(np.max(np.abs(ref[f])), 1e-300)
+        errs.append(np.max(np.abs(got[f] - ref[f])) / scale)
+    return max(errs)
+
+
+def run_pair(lbsd, dim, Y_phys, lam, n, *, nx, ny=1, bcx=0, bcy=1, delta0=None, prec="fp64"):
+    P = oracle.Problem(dim, nx, ny, bc_x=bcx, bc_y=bcy, delta0=delta0)
+    ref, st, reach = oracle.run(P, oracle.to_lattice(P, Y_phys, lam), n)
+    assert st == 0 and reach <= 5
+    s = lbsd.Solver(dim, nx, ny, bc_x=bcx, bc_y=bcy, d0_frac=delta0, precision=prec)
+    s.init_moments(Y_phys, lam)
+    s.step(n)
+    got = s.moments()
+    return P, oracle.from_lattice(P, ref, lam), got, s
+
+
+def test_sod_1d_config0(lbsd):
+    """1-D Sod, 1000 nodes to t = 0.2 (237 steps), transmissive ends."""
+    nx = 1000
+    n, lam = inputs.steps_and_lambda(0.2, 1.0 / nx, [inputs.SOD_LEFT, inputs.SOD_RIGHT])
+    P = oracle.Problem(1, nx)
+    Y0 = oracle.riemann_moments(P, inputs.node_x(nx), inputs.SOD_LEFT, inputs.SOD_RIGHT, 0.5)
+    ref, st, _ = oracle.run(P, oracle.to_lattice(P, Y0, lam), n)
+    ref = oracle.from_lattice(P, ref, lam)
+    s = lbsd.Solver(1, nx)
+    s.init_riemann(0.5, inputs.SOD_LEFT, inputs.SOD_RIGHT, lam=lam)
+    assert s.lam == lam
+    s.step(n)
+    got = s.moments()
+    assert normwise_err(got, ref, 1) <= TOL64
+    tot = s.totals()
+    otot = oracle.totals(P, ref)
+    assert tot[0] == pytest.approx(otot[0], rel=1e-13)
+    assert tot[1] == pytest.approx(otot[1], rel=1e-12)
+    assert tot[3] == pytest.approx(otot[2], rel=1e-13)
+    assert s.steps_done == n
+
+
+def test_sod_2d_config1_rows(lbsd):
+    """2-D Sod on 800 x 200 (190 steps, periodic y): every row against the
+    oracle on 800 x 4 (planar data: all rows evolve alike)."""
+    nx, ny = 800, 200
+    n, lam = inputs.steps_and_lambda(0.2, 1.0 / nx, [inputs.SOD_LEFT, inputs.SOD_RIGHT])
+    assert n == 190
+    P = oracle.Problem(2, nx, 4)
+    Y0 = oracle.riemann_moments(P, inputs.node_x(nx), inputs.SOD_LEFT, inputs.SOD_RIGHT, 0.5)
+    ref, st, _ = oracle.run(P, oracle.to_lattice(P, Y0, lam), n)
+    ref = oracle.from_lattice(P, ref, lam)
+    s = lbsd.Solver(2, nx, ny)
+    s.init_riemann(0.5, inputs.SOD_LEFT, inputs.SOD_RIGHT, lam=lam)
+    s.step(n)
+    got = s.moments()
+    assert np.all(got == got[:, :1, :]), "planar rows must stay bit-identical"
+    assert normwise_err(got[:, :4, :], ref, 2) <= TOL64
+
+
+@pytest.mark.parametrize("nx", [1, 7, 1023, 1025, 3001])
+@pytest.mark.parametrize("bcx", [0, 1])
+def test_random_1d(lbsd, nx, bcx):
+    for smooth, seed in ((9, 1), (0, 2)):
+        Y = inputs.random_state(seed, 1, nx, vel=(-1.3, 1.3), e=(0.0, 1.5), smooth=smooth if nx > 9 else 0)
+        P, ref, got, _ = run_pair(lbsd, 1, Y, 1.0, 6, nx=nx, bcx=bcx)
+        assert normwise_err(got, ref, 1) <= TOL64, (nx, bcx, smooth)
+
+
+@pytest.mark.parametrize("delta0", [0.4, 0.55])
+def test_random_1d_delta0(lbsd, delta0):
+    Y = inputs.random_state(4, 1, 2100, vel=(-1.3, 1.3), e=(0.0, 1.5), smooth=5)
+    P, ref, got, _ = run_pair(lbsd, 1, Y, 1.0, 5, nx=2100, bcx=1, delta0=delta0)
+    assert normwise_err(got, ref, 1) <= TOL64
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (33, 17), (70, 37), (129, 65)])
+@pytest.mark.parametrize("bcs", [(0, 1), (1, 1), (0, 0), (1, 0)])
+def test_random_2d(lbsd, shape, bcs):
+    nx, ny = shape
+    for smooth, seed in ((5, 3), (0, 4)):
+        Y = inputs.random_state(seed, 2, nx, ny, vel=(-1.1, 1.1), e=(0.0, 1.2),
+                                smooth=smooth if nx > 5 else 0)
+        P, ref, got, _ = run_pair(lbsd, 2, Y, 1.0, 4, nx=nx, ny=ny, bcx=bcs[0], bcy=bcs[1])
+        assert normwise_err(got, ref, 2) <= TOL64, (shape, bcs, smooth)
+
+
+def _adversarial(dim, nx, ny, seed):
+    """Random states with integer velocities and perfect-square A mixed in."""
+    rng = np.random.default_rng(seed)
+    Y = inputs.random_state(seed, dim, nx, ny, vel=(-1.5, 1.5), e=(0.0, 3.0))
+    rho = Y[0]
+    pick = rng.random(rho.shape) < 0.3
+    for a in range(dim):
+        v = np.round(Y[1 + a] / rho)
+        Y[1 + a] = np.where(pick, rho * v, Y[1 + a])
+    pick2 = rng.random(rho.shape) < 0.3
+    # e with D (gamma - 1) e / (1 - b0 delta0) = k^2 in real arithmetic
+    k = rng.integers(0, 3, size=rho.shape)
+    e = k * k * (0.5 if dim == 1 else 1.0) / (dim * 0.4)
+    v2 = sum((Y[1 + a] / rho) ** 2 for a in range(dim))
+    Y[-1] = np.where(pick2, rho * (e + 0.5 * v2), Y[-1])
+    return Y
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_lanes_bit_exact(lbsd, dim):
+    nx, ny = (4099, 1) if dim == 1 else (97, 61)
+    for seed in (0, 1, 2):
+        for Y in (inputs.random_state(seed, dim, nx, ny, vel=(-2.5, 2.5), e=(0.0, 6.0)),
+                  _adversarial(dim, nx, ny, seed)):
+            P = oracle.Problem(dim, nx, ny)
+            s = lbsd.Solver(dim, nx, ny)
+            s.init_moments(Y, 1.0)
+            fx, fy, c1 = s.lanes()
+            ofx, ofy, oc1 = oracle.lanes(P, Y)
+            assert np.array_equal(fx, ofx) and np.array_equal(fy, ofy) and np.array_equal(c1, oc1)
+
+
+def test_adversarial_fields(lbsd):
+    for dim, nx, ny in ((1, 2049, 1), (2, 65, 47)):
+        Y = _adversarial(dim, nx, ny, 9)
+        P, ref, got, _ = run_pair(lbsd, dim, Y, 1.0, 1, nx=nx, ny=ny, bcx=1)
+        assert normwise_err(got, ref, dim) <= TOL64
+
+
+def test_totals_track_oracle(lbsd):
+    nx, ny = 90, 50
+    Y = inputs.random_state(7, 2, nx, ny, vel=(-1.0, 1.0), e=(0.1, 1.5), smooth=5)
+    P, ref, got, s = run_pair(lbsd, 2, Y, 0.9, 5, nx=nx, ny=ny, bcx=1, bcy=1)
+    tot = s.totals()
+    otot = oracle.totals(P, ref)
+    assert tot[0] == pytest.approx(otot[0], rel=1e-13)
+    assert tot[3] == pytest.approx(otot[3], rel=1e-13)
+    mom = np.sum(np.abs(ref[1:3]))
+    assert abs(tot[1] - otot[1]) <= 1e-13 * mom and abs(tot[2] - otot[2]) <= 1e-13 * mom
+    # periodic: conserved since the start
+    t0 = oracle.totals(P, Y)
+    assert tot[0] == pytest.approx(t0[0], rel=1e-13)
+    assert tot[3] == pytest.approx(t0[3], rel=1e-13)
+
+
+def test_determinism(lbsd):
+    nx, ny = 300, 140
+    Y = inputs.random_state(11, 2, nx, ny, vel=(-1.0, 1.0), e=(0.0, 1.5), smooth=3)
+    outs = []
+    for _ in range(2):
+        s = lbsd.Solver(2, nx, ny, bc_x=1)
+        s.init_moments(Y, 1.0)
+        s.step(7)
+        outs.append((s.moments(), s.totals()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_uniform_state_bit_identical_nodes(lbsd):
+    for dim, nx, ny in ((1, 100003, 1), (2, 517, 263)):
+        node = [0.7, 0.7 * 0.37] + ([0.7 * -0.61] if dim == 2 else []) + [0.7 * 1.9]
+        Y = np.broadcast_to(np.array(node)[:, None, None], (dim + 2, ny, nx)).copy()
+        for bcx in (0, 1):
+            s = lbsd.Solver(dim, nx, ny, bc_x=bcx)
+            s.init_moments(Y, 1.0)
+            s.step(5)
+            got = s.moments()
+            assert np.all(got == got[:, :1, :1])
+            assert np.allclose(got, Y, rtol=1e-14, atol=1e-15)
+
+
+def test_reach_error_rolls_back(lbsd):
+    """A step whose packets would move further than LB_HALO fails with
+    LB_EREACH; the state stays at the last good step and later steps are refused."""
+    nx = 400
+    P = oracle.Problem(1, nx)
+    # expansion into near-vacuum: the front accelerates past 4 nodes per step
+    left, right = (1.0, 0.0, 0.0, 1.0), (1e-4, 0.0, 0.0, 1e-8)
+    lam = 0.8 / np.sqrt(1.4)
+    Y0 = oracle.riemann_moments(P, inputs.node_x(nx), left, right, 0.5)
+    Yl = oracle.to_lattice(P, Y0, lam)
+    # find the first step whose sources reach further than 5 nodes
+    k, Y, good = 0, Yl, None
+    while k < 200:
+        Yn, st, r = oracle.step(P, Y)
+        k += 1
+        if r > 5:
+            break
+        good, Y = Yn, Yn
+    assert 1 < k < 200
+    s = lbsd.Solver(1, nx)
+    s.init_riemann(0.5, left, right, lam=lam)
+    s.step(k + 3)
+    with pytest.raises(lbsd.LBError) as ei:
+        s.sync()
+    assert ei.value.code == lbsd.LB_EREACH
+    assert s.steps_done == k - 1
+    with pytest.raises(lbsd.LBError):
+        s.step(1)
+    with pytest.raises(lbsd.LBError) as ei:
+        s.moments()
+    # moments() still exports the last good state before raising; read it
+    out = np.empty((3, 1, nx))
+    import ctypes
+    rc = lbsd._lib.lb_moments(s._h, ctypes.c_void_p(out.ctypes.data), 0)
+    assert rc == lbsd.LB_EREACH
+    assert normwise_err(out, oracle.from_lattice(P, good, lam), 1) <= TOL64
+    # re-initialising clears the error
+    s.init_riemann(0.5, inputs.SOD_LEFT, inputs.SOD_RIGHT, lam=0.8)
+    s.step(2)
+    s.sync()
+    assert s.steps_done == 2
+
+
+def test_state_errors(lbsd):
+    s = lbsd.Solver(1, 50)
+    Y = inputs.random_state(0, 1, 50)
+    Y[0, 0, 3] = 0.0
+    with pytest.raises(lbsd.LBError) as ei:
+        s.init_moments(Y, 1.0)
+    assert ei.value.code == lbsd.LB_ESTATE
+    with pytest.raises(lbsd.LBError) as ei:
+        s.init_riemann(0.5, (1.0, 0.0, 0.0, -1.0), inputs.SOD_RIGHT)
+    assert ei.value.code == lbsd.LB_ESTATE
+    Y = inputs.random_state(0, 1, 50)
+    Y[2, 0, 7] = np.nan
+    with pytest.raises(lbsd.LBError) as ei:
+        s.init_moments(Y, 1.0)
+    assert ei.value.code == lbsd.LB_ESTATE
+    with pytest.raises(lbsd.LBError) as ei:
+        s.step(-1)
+
+
+def test_full_size_2d_planar(lbsd):
+    """4096 x 4096 seeded planar tube (the headline workload) in the launch
+    configuration the benchmark times: 3 steps against the oracle on a
+    4096 x 4 strip, and bit-identical rows."""
+    nx = ny = 4096
+    left, right, xd = inputs.riemann_instance(0)
+    lam = inputs.cfl_lambda([left, right])
+    P = oracle.Problem(2, nx, 4)
+    Y0 = oracle.riemann_moments(P, inputs.node_x(nx), left, right, xd)
+    ref, st, _ = oracle.run(P, oracle.to_lattice(P, Y0, lam), 3)
+    ref = oracle.from_lattice(P, ref, lam)
+    s = lbsd.Solver(2, nx, ny)
+    s.init_riemann(xd, left, right, lam=lam)
+    s.step(3)
+    got = s.moments_device()
+    rows = got[:, ::509, :].cpu().numpy()
+    assert np.all(rows == rows[:, :1, :])
+    assert normwise_err(rows[:, :4, :], ref, 2) <= TOL64
+
+
+def test_fp32_against_oracle(lbsd):
+    """FP32 form: relative L1 density error against the FP64 oracle."""
+    nx = 1000
+    n, lam = inputs.steps_and_lambda(0.2, 1.0 / nx, [inputs.SOD_LEFT, inputs.SOD_RIGHT])
+    P = oracle.Problem(1, nx)
+    Y0 = oracle.riemann_moments(P, inputs.node_x(nx), inputs.SOD_LEFT, inputs.SOD_RIGHT, 0.5)
+    ref, _, _ = oracle.run(P, oracle.to_lattice(P, Y0, lam), n)
+    ref = oracle.from_lattice(P, ref, lam)
+    s = lbsd.Solver(1, nx, precision="fp32")
+    s.init_riemann(0.5, inputs.SOD_LEFT, inputs.SOD_RIGHT, lam=lam)
+    s.step(n)
+    got = s.moments()
+    rel_l1 = np.sum(np.abs(got[0] - ref[0])) / np.sum(np.abs(ref[0]))
+    assert rel_l1 <= 1e-5, rel_l1
