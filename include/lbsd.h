@@ -121,6 +121,11 @@ int lb_step(lb_solver* s, int64_t n);
  * the elapsed milliseconds of the n steps to *ms. */
 int lb_step_timed(lb_solver* s, int64_t n, float* ms);
 
+/* As lb_step_timed, with HIP events also around each step kernel (not its
+ * small totals-reduction kernel): *kernel_ms gets the summed duration of the
+ * n step kernels, *total_ms the elapsed time of the whole sequence.  n <= 100000. */
+int lb_step_profiled(lb_solver* s, int64_t n, float* kernel_ms, float* total_ms);
+
 /* Wait for queued work; returns LB_EREACH / LB_ESTATE if a step failed. */
 int lb_sync(lb_solver* s);
 

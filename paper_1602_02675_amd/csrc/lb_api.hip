@@ -51,7 +51,9 @@ struct lb_solver {
     size_t elem;
     // layout inside the bound buffer
     size_t off_buf[2], off_export, off_ctl, off_partials, total;
-    int64_t nblocks;
+    int64_t nblocks;      // step-kernel blocks (rows of partials used per step)
+    MarchGeom march;      // square lattice launch geometry (set at bind)
+    bool march_full;      // square lattice: launch only the full-FIFO kernel
     char* base;
     hipStream_t stream;
     bool bound, initialized;
@@ -117,7 +119,7 @@ int lb_create(const lb_grid* grid, double gamma, const lb_velset* vs, int32_t pr
     s->nn = grid->nx * grid->ny;
     s->elem = precision == LB_FP64 ? 8 : 4;
     const size_t field_bytes = align256((size_t)s->nf * (size_t)s->nn * s->elem);
-    s->nblocks = dim == 1 ? step_blocks_1d(s->g) : step_blocks_2d(s->g);
+    s->nblocks = dim == 1 ? step_blocks_1d(s->g) : march2d_max_blocks(s->g);
     s->off_buf[0] = 0;
     s->off_buf[1] = field_bytes;
     s->off_export = 2 * field_bytes;
@@ -150,6 +152,16 @@ int lb_bind(lb_solver* s, void* dev_ptr, size_t bytes, void* hip_stream)
         if ((e = hipEventCreate(&s->ev1)) != hipSuccess) return hip_fail(e, "hipEventCreate");
         s->events = true;
     }
+    if (s->dim == 2) {
+        int dev = 0, cus = 0;
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+            return hip_fail(e, "hipDeviceGetAttribute");
+        const int per_cu = s->precision == LB_FP64 ? march2d_blocks_per_cu<double>()
+                                                   : march2d_blocks_per_cu<float>();
+        s->march = march2d_geometry(s->g, cus * per_cu);
+        s->nblocks = s->march.blocks();
+    }
     s->bound = true;
     s->initialized = false;
     if ((e = launch_reset_ctl(ctl_ptr(s), s->stream)) != hipSuccess) return hip_fail(e, "reset");
@@ -179,6 +191,7 @@ static bool prim_ok(const lb_prim* p)
 
 static int start_state(lb_solver* s)
 {
+    s->march_full = false;
     s->cur = 0;
     s->steps_done = 0;
     s->pending_err = 0;
@@ -271,12 +284,15 @@ int lb_init_moments(lb_solver* s, const double* Y, double lambda)
     return start_state(s);
 }
 
-static int queue_steps(lb_solver* s, int64_t n)
+// Queue n steps: step kernel + finalize kernel each.  With ev != NULL,
+// ev[2i] / ev[2i+1] are recorded right before / after step i's step kernel.
+static int queue_steps(lb_solver* s, int64_t n, hipEvent_t* ev = nullptr)
 {
     for (int64_t i = 0; i < n; ++i) {
         const int in = s->cur, out = s->cur ^ 1;
         const long long step = (long long)(s->steps_done + 1);
         hipError_t e;
+        if (ev && (e = hipEventRecord(ev[2 * i], s->stream)) != hipSuccess) return hip_fail(e, "event");
         if (s->dim == 1) {
             if (s->precision == LB_FP64)
                 e = launch_step1d<double>((const double*)buf_ptr(s, in), (double*)buf_ptr(s, out), s->g,
@@ -286,13 +302,18 @@ static int queue_steps(lb_solver* s, int64_t n)
                                          s->k, ctl_ptr(s), partials_ptr(s), step, s->stream);
         } else {
             if (s->precision == LB_FP64)
-                e = launch_step2d<double>((const double*)buf_ptr(s, in), (double*)buf_ptr(s, out), s->g,
-                                          s->k, ctl_ptr(s), partials_ptr(s), step, s->stream);
+                e = launch_march2d<double>((const double*)buf_ptr(s, in), (double*)buf_ptr(s, out), s->g,
+                                           s->march, s->k, ctl_ptr(s), partials_ptr(s), step,
+                                           s->march_full, s->stream);
             else
-                e = launch_step2d<float>((const float*)buf_ptr(s, in), (float*)buf_ptr(s, out), s->g,
-                                         s->k, ctl_ptr(s), partials_ptr(s), step, s->stream);
+                e = launch_march2d<float>((const float*)buf_ptr(s, in), (float*)buf_ptr(s, out), s->g,
+                                          s->march, s->k, ctl_ptr(s), partials_ptr(s), step,
+                                          s->march_full, s->stream);
         }
         if (e != hipSuccess) return hip_fail(e, "step launch");
+        if (ev && (e = hipEventRecord(ev[2 * i + 1], s->stream)) != hipSuccess) return hip_fail(e, "event");
+        e = launch_finalize(partials_ptr(s), s->nblocks, ctl_ptr(s), step, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "finalize launch");
         s->cur = out;
         s->steps_done += 1;
     }
@@ -318,6 +339,7 @@ int lb_sync(lb_solver* s)
     StepCtl c;
     if ((e = hipMemcpy(&c, ctl_ptr(s), sizeof c, hipMemcpyDeviceToHost)) != hipSuccess)
         return hip_fail(e, "read control block");
+    if (c.redo_count > 0) s->march_full = true;  // the short FIFO no longer covers the flow
     if (c.err_code) {
         // step err_step (1-based since init) failed; its input, the state
         // after err_step - 1 steps, sits in buffer (err_step - 1) & 1.
@@ -349,6 +371,39 @@ int lb_step_timed(lb_solver* s, int64_t n, float* ms)
     rc = lb_sync(s);
     if (rc != LB_OK) return rc;
     *ms = t;
+    return LB_OK;
+}
+
+int lb_step_profiled(lb_solver* s, int64_t n, float* kernel_ms, float* total_ms)
+{
+    if (!s || !kernel_ms || !total_ms) return fail(LB_EINVAL, "null argument");
+    if (!s->initialized) return fail(LB_EINVAL, "solver not initialised");
+    if (n < 0 || n > 100000) return fail(LB_EINVAL, "n must be in [0, 100000]");
+    if (s->pending_err) return fail(s->pending_err, "an earlier step failed; re-initialise");
+    std::vector<hipEvent_t> ev;
+    try { ev.resize((size_t)(2 * n)); } catch (...) { return fail(LB_ENOMEM, "host alloc"); }
+    hipError_t e;
+    int rc = LB_OK;
+    size_t made = 0;
+    for (; made < ev.size(); ++made)
+        if ((e = hipEventCreate(&ev[made])) != hipSuccess) { rc = hip_fail(e, "hipEventCreate"); break; }
+    if (rc == LB_OK && (e = hipEventRecord(s->ev0, s->stream)) != hipSuccess) rc = hip_fail(e, "event");
+    if (rc == LB_OK) rc = queue_steps(s, n, ev.data());
+    if (rc == LB_OK && (e = hipEventRecord(s->ev1, s->stream)) != hipSuccess) rc = hip_fail(e, "event");
+    if (rc == LB_OK && (e = hipEventSynchronize(s->ev1)) != hipSuccess) rc = hip_fail(e, "event sync");
+    float kt = 0.f, tt = 0.f;
+    for (int64_t i = 0; rc == LB_OK && i < n; ++i) {
+        float t = 0.f;
+        if ((e = hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1])) != hipSuccess) rc = hip_fail(e, "elapsed");
+        kt += t;
+    }
+    if (rc == LB_OK && (e = hipEventElapsedTime(&tt, s->ev0, s->ev1)) != hipSuccess) rc = hip_fail(e, "elapsed");
+    for (size_t i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+    if (rc != LB_OK) return rc;
+    rc = lb_sync(s);
+    if (rc != LB_OK) return rc;
+    *kernel_ms = kt;
+    *total_ms = tt;
     return LB_OK;
 }
 

@@ -15,13 +15,15 @@ constexpr int kErrState = 2;  // rho <= 0 or a non-finite moment
 
 // Per-solver control block in device memory (written by the step kernels).
 struct StepCtl {
-    unsigned int counter;   // blocks of the running step that are done
+    unsigned int counter;   // unused (kept for layout)
     int err_code;           // kErr* bits of the first failed step
     long long err_step;     // first failed step (LLONG_MAX if none)
     long long totals_step;  // step whose totals are in `totals`
     double totals[4];       // interior sums of the moment fields (lattice units)
     int max_reach;          // largest reach seen in the latest step
-    int pad[7];
+    int redo_count;         // steps the square-lattice kernel had to redo with its full FIFO
+    long long redo_step;    // step whose short-FIFO pass found a y-reach beyond its FIFO
+    int pad[4];
 };
 
 // Per-block partial results: 4 field sums, reach, error bits.
@@ -32,9 +34,10 @@ struct Grid {
     int bc_x, bc_y;
 };
 
-// Launch one step of a 1-D / 2-D problem (async on `stream`).  Y and Yn are
-// SoA [nf][ny][nx] arrays of T; partials holds one kPartialStride row per
-// block (step_blocks_* gives the count).
+// Launch the step kernel of a 1-D / 2-D problem (async on `stream`).  Y and
+// Yn are SoA [nf][ny][nx] arrays of T; partials receives one kPartialStride
+// row per block (step_blocks_1d / march2d_blocks give the count), which
+// launch_finalize then reduces.
 template <typename T>
 hipError_t launch_step1d(const T* Y, T* Yn, const Grid& g, const Consts& k, StepCtl* ctl,
                          double* partials, long long step, hipStream_t stream);
@@ -43,6 +46,29 @@ hipError_t launch_step2d(const T* Y, T* Yn, const Grid& g, const Consts& k, Step
                          double* partials, long long step, hipStream_t stream);
 int64_t step_blocks_1d(const Grid& g);
 int64_t step_blocks_2d(const Grid& g);
+
+// Square lattice, column-march kernel (lb_march2d.hip).  The launch
+// geometry (strip height, blocks) is chosen per device so that one wave of
+// resident blocks covers the grid.
+struct MarchGeom {
+    int sy;                   // destination rows per block
+    int64_t grid_x, grid_y;   // blocks along x (column strips) and y (row chunks)
+    int64_t blocks() const { return grid_x * grid_y; }
+};
+MarchGeom march2d_geometry(const Grid& g, int target_blocks);
+int64_t march2d_max_blocks(const Grid& g);
+template <typename T>
+int march2d_blocks_per_cu();
+// full_only: launch only the full-FIFO kernel; otherwise the short-FIFO
+// kernel runs and the full one redoes the step only if it had to.
+template <typename T>
+hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
+                          StepCtl* ctl, double* partials, long long step, bool full_only,
+                          hipStream_t stream);
+
+// Reduce nb per-block partial rows of one step into ctl (fixed order).
+hipError_t launch_finalize(const double* partials, int64_t nb, StepCtl* ctl, long long step,
+                           hipStream_t stream);
 constexpr int kHalo = 5;
 
 // Riemann initial state: node i (cell centre x_lo + (i + 1/2) dx) takes the

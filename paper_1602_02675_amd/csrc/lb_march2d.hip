@@ -1,0 +1,569 @@
+// Square-lattice step as a column march (Sec. IV.B and V.A of Komeili,
+// Mirzaei, Shabouei, arXiv 1602.02675; tau = 1 so a step is the migration of
+// the equilibrium, eq. 10 / eq. 30).
+//
+// Every packet moves along x by floor(v_x) + k_x (+ c' for x-lanes) and along y
+// by floor(v_y) + k_y (+ c' for y-lanes).  The kernel splits the two:
+//   - a block of 256 threads owns 256 consecutive source columns (the middle
+//     256 - 2H of them are its destination columns) and marches down a strip
+//     of rows;
+//   - per source row, each thread turns its node's moments into
+//     (floor v, r, c'_1, d_1, d_2, K) once and stages them in an LDS row
+//     buffer (double-buffered: one barrier per row);
+//   - each destination thread gathers the packets that move into its column
+//     from the staged row (the x part of the migration) and adds each to a
+//     register FIFO of pending destination rows, indexed by the y
+//     displacement o = floor(v_y) + k_y (+ c' for y-lanes), o in [-H, H]
+//     (the y part); after source row sy the FIFO slot of row sy - H can
+//     receive nothing more and is written out.
+// Where the staged sources around a wavefront share floor(v) and c'_1 (the
+// integer parts of the migration vectors are piecewise constant), the 32
+// packet classes have compile-time column offsets and FIFO slots; elsewhere
+// every source within the halo is examined and slots are chosen at run time.
+// The same packets are summed either way; only the summation order differs
+// from the scatter definition.
+#include <climits>
+
+#include "lb_kernels.hpp"
+
+namespace lbsd {
+
+namespace {
+
+constexpr int kMTPB = 256;        // threads (= staged source columns) per block
+constexpr int kMNW = kMTPB / 64;  // wavefronts per block
+constexpr int kMH = kHalo;        // x halo (largest displacement per axis)
+// The FIFO covers y displacements o in [-L, L] (2L + 1 slots).  L = H covers
+// every packet; L = 3 covers every source with c'_1 <= 1 and |floor(v_y)|
+// small (y-reach <= 3), and leaves registers for two wavefronts per SIMD.
+constexpr int kLFull = kMH, kLSmall = 3;
+constexpr int kMinRows = 16;      // smallest strip height (bounds the y-halo overhead)
+
+// FIFO values per slot.  The y-momentum is kept as two parts: what packets
+// carry as m v_y, and the m c' of the y-lanes, summed in double-length
+// (TwoSum) arithmetic.  A y-lane packet and its mirror (opposite sign) reach a
+// destination from two different source rows, after other terms; the
+// double-length sum makes them cancel exactly when those rows are equal, so a
+// planar flow keeps v_y = 0 exactly and floor(v_y) stays uniform.
+enum { kR = 0, kPx = 1, kPyv = 2, kGh = 3, kGl = 4, kE = 5, kNV = 6 };
+
+// (h, l) += x with the rounding error of h + x carried into l (TwoSum).
+template <typename T>
+__device__ __forceinline__ void dd_add(T& h, T& l, T x)
+{
+#pragma clang fp contract(off)
+    const T s = h + x;
+    const T bp = s - h;
+    const T e = (h - (s - bp)) + (x - bp);
+    h = s;
+    l = l + e;
+}
+
+__device__ __forceinline__ int mpack(int fx, int fy, int c1)
+{
+    fx = fx < -127 ? -127 : (fx > 127 ? 127 : fx);
+    fy = fy < -127 ? -127 : (fy > 127 ? 127 : fy);
+    c1 = c1 > 255 ? 255 : c1;
+    return (fx + 128) | ((fy + 128) << 8) | (c1 << 16);
+}
+__device__ __forceinline__ int mfx(int p) { return (p & 255) - 128; }
+__device__ __forceinline__ int mfy(int p) { return ((p >> 8) & 255) - 128; }
+__device__ __forceinline__ int mc1(int p) { return (p >> 16) & 255; }
+
+template <typename T>
+struct MRow {  // one staged source row
+    T rx[kMTPB], ry[kMTPB], d1[kMTPB], d2[kMTPB], K[kMTPB];
+    int pk[kMTPB];
+};
+
+struct WaveInfo {  // per wavefront and staged row: ranges over its 64 sources
+    int fxmin, fxmax, fymin, fymax, c1min, c1max;
+};
+
+template <typename T, int L>
+struct Fifo {
+    static constexpr int NS = 2 * L + 1;
+    T a[NS][kNV];  // slot o + L: destination row (current source row) + o
+};
+
+// Add to the FIFO slot `slot` (differs between lanes) for slots in the
+// wavefront-uniform range [lo, hi]: each slot in range takes a select, so the
+// FIFO keeps compile-time indices (registers).  Slots out of range occur only
+// with reach > H (reported).
+template <typename T, int L>
+__device__ __forceinline__ void fifo_add_sel(Fifo<T, L>& f, int slot, int lo, int hi, T r, T px, T pyv, T e)
+{
+#pragma unroll
+    for (int o = 0; o < 2 * L + 1; ++o) {
+        if (o < lo || o > hi) continue;
+        const bool h = slot == o;
+        f.a[o][kR] += h ? r : (T)0;
+        f.a[o][kPx] += h ? px : (T)0;
+        f.a[o][kPyv] += h ? pyv : (T)0;
+        f.a[o][kE] += h ? e : (T)0;
+    }
+}
+
+template <typename T, int L>
+__device__ __forceinline__ void fifo_add_g(Fifo<T, L>& f, int slot, int lo, int hi, T v)
+{
+#pragma unroll
+    for (int o = 0; o < 2 * L + 1; ++o) {
+        if (o < lo || o > hi) continue;
+        dd_add<T>(f.a[o][kGh], f.a[o][kGl], slot == o ? v : (T)0);
+    }
+}
+
+// Rows where every source seen by this wavefront has floor(v_y) = FY: the
+// FIFO slot of every packet is known at compile time up to c'_1, which is
+// taken from its (short) range [clo, chi] in unrolled branches; floor(v_x)
+// and c'_1 may vary along the row.  Each packet class (level, sign, k_x) is
+// matched against its candidate sources: in a window where floor(v_x) and
+// c'_1 are uniform there is exactly one candidate per class.
+//  - x-lanes are taken in +-c pairs, and y-lanes summed over k_x before they
+//    meet the FIFO: in uniform and planar regions the mirrored terms cancel
+//    exactly (noise-free zero velocities keep floor(v) uniform);
+//  - a class with no matching candidate adds zero mass.
+template <typename T>
+__device__ __forceinline__ T prod_nc(T a, T b)
+{
+#pragma clang fp contract(off)
+    return a * b;
+}
+
+// Window where every source has floor(v) = (fx, FY) and c'_1 = C1: every
+// packet class has a compile-time column offset and FIFO slot.
+template <typename T, int L, int FY, int C1>
+__device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, Fifo<T, L>& f)
+{
+    const int base = lane - fx;  // staged column of x displacement fx + a is base - a
+    const T fxT = (T)fx;
+#pragma unroll
+    for (int lev = 1; lev <= 2; ++lev) {
+        const int c = C1 + lev - 1;
+        const T cc = (T)c, hc2 = (T)(0.5 * c * c);
+        // x-lanes: destination row FY + ky, source columns base - (kx +- c)
+#pragma unroll
+        for (int kx = 0; kx < 2; ++kx) {
+            const int sp = base - (kx + c), sm = base - (kx - c);
+            const T rxp = R.rx[sp], ryp = R.ry[sp], rxm = R.rx[sm], rym = R.ry[sm];
+            const T dp = lev == 1 ? R.d1[sp] : R.d2[sp];
+            const T dm = lev == 1 ? R.d1[sm] : R.d2[sm];
+            const T bp = (kx ? rxp : (T)1 - rxp) * dp, bm = (kx ? rxm : (T)1 - rxm) * dm;
+            const T vxp = fxT + rxp, vxm = fxT + rxm, vyp = (T)FY + ryp, vym = (T)FY + rym;
+            const T zp = R.K[sp] + hc2 + cc * vxp, zm = R.K[sm] + hc2 - cc * vxm;
+#pragma unroll
+            for (int ky = 0; ky < 2; ++ky) {
+                const int o = FY + ky + L;
+                const T mp = bp * (ky ? ryp : (T)1 - ryp), mm = bm * (ky ? rym : (T)1 - rym);
+                f.a[o][kR] += mp + mm;
+                f.a[o][kPx] += (mp * vxp + mm * vxm) + (mp - mm) * cc;
+                f.a[o][kPyv] += mp * vyp + mm * vym;
+                f.a[o][kE] += mp * zp + mm * zm;
+            }
+        }
+        // y-lanes: source columns base (kx = 0) and base - 1 (kx = 1)
+        {
+            const int s0 = base, s1 = base - 1;
+            const T rx0 = R.rx[s0], ry0 = R.ry[s0], rx1 = R.rx[s1], ry1 = R.ry[s1];
+            const T b0 = ((T)1 - rx0) * (lev == 1 ? R.d1[s0] : R.d2[s0]);
+            const T b1 = rx1 * (lev == 1 ? R.d1[s1] : R.d2[s1]);
+            const T vx0 = fxT + rx0, vx1 = fxT + rx1, vy0 = (T)FY + ry0, vy1 = (T)FY + ry1;
+            const T k0 = R.K[s0] + hc2, k1 = R.K[s1] + hc2;
+#pragma unroll
+            for (int ky = 0; ky < 2; ++ky) {
+                const T m0 = b0 * (ky ? ry0 : (T)1 - ry0), m1 = b1 * (ky ? ry1 : (T)1 - ry1);
+                const T gm = (m0 + m1) * cc;
+#pragma unroll
+                for (int sg = -1; sg <= 1; sg += 2) {
+                    const int o = FY + ky + sg * c + L;
+                    f.a[o][kR] += m0 + m1;
+                    f.a[o][kPx] += m0 * vx0 + m1 * vx1;
+                    f.a[o][kPyv] += m0 * vy0 + m1 * vy1;
+                    dd_add<T>(f.a[o][kGh], f.a[o][kGl], sg > 0 ? gm : -gm);
+                    f.a[o][kE] += m0 * (k0 + (T)sg * cc * vy0) + m1 * (k1 + (T)sg * cc * vy1);
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int L, int FY>
+__device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<T, L>& f, int fxlo, int fxhi,
+                                            int clo, int chi)
+{
+    const int nfx = fxhi - fxlo;  // extra candidates from floor(v_x) variation
+#pragma unroll
+    for (int lev = 1; lev <= 2; ++lev) {
+        const int cl = clo + lev - 1, ch = chi + lev - 1;
+        const int ncand = nfx + (ch - cl) + 1;
+        // x-lanes: destination row FY + ky; +c from a = kx + fx + c, -c from a = kx + fx - c
+#pragma unroll
+        for (int kx = 0; kx < 2; ++kx) {
+            for (int i = 0; i < ncand; ++i) {
+                const int ap = kx + fxlo + cl + i, am = kx + fxhi - cl - i;
+                const int sp = lane - ap, sm = lane - am;
+                const int pkp = R.pk[sp], pkm = R.pk[sm];
+                const int fxp = mfx(pkp), fxm = mfx(pkm);
+                const int cp = ap - kx - fxp, cm = kx + fxm - am;  // speed this source would need
+                const bool okp = cp == mc1(pkp) + lev - 1, okm = cm == mc1(pkm) + lev - 1;
+                const T rxp = R.rx[sp], ryp = R.ry[sp], rxm = R.rx[sm], rym = R.ry[sm];
+                const T dp = lev == 1 ? R.d1[sp] : R.d2[sp];
+                const T dm = lev == 1 ? R.d1[sm] : R.d2[sm];
+                const T bp = okp ? (kx ? rxp : (T)1 - rxp) * dp : (T)0;
+                const T bm = okm ? (kx ? rxm : (T)1 - rxm) * dm : (T)0;
+                const T ccp = (T)cp, ccm = (T)cm;
+                const T vxp = (T)fxp + rxp, vxm = (T)fxm + rxm, vyp = (T)FY + ryp, vym = (T)FY + rym;
+                const T zp = R.K[sp] + (T)0.5 * ccp * ccp + ccp * vxp;
+                const T zm = R.K[sm] + (T)0.5 * ccm * ccm - ccm * vxm;
+#pragma unroll
+                for (int ky = 0; ky < 2; ++ky) {
+                    const int o = FY + ky + L;
+                    const T mp = bp * (ky ? ryp : (T)1 - ryp), mm = bm * (ky ? rym : (T)1 - rym);
+                    f.a[o][kR] += mp + mm;
+                    f.a[o][kPx] += (mp * vxp + mm * vxm) + (prod_nc(mp, ccp) - prod_nc(mm, ccm));
+                    f.a[o][kPyv] += mp * vyp + mm * vym;
+                    f.a[o][kE] += mp * zp + mm * zm;
+                }
+            }
+        }
+        // y-lanes: a = fx + kx; kx = 0 and kx = 1 candidates taken together
+        for (int i = 0; i <= nfx; ++i) {
+            const int a0 = fxlo + i, a1 = fxlo + 1 + i;
+            const int s0 = lane - a0, s1 = lane - a1;
+            const int pk0 = R.pk[s0], pk1 = R.pk[s1];
+            const bool ok0 = mfx(pk0) == a0, ok1 = mfx(pk1) + 1 == a1;
+            const int c0 = mc1(pk0) + lev - 1, c1 = mc1(pk1) + lev - 1;
+            const T rx0 = R.rx[s0], ry0 = R.ry[s0], rx1 = R.rx[s1], ry1 = R.ry[s1];
+            const T b0 = ok0 ? ((T)1 - rx0) * (lev == 1 ? R.d1[s0] : R.d2[s0]) : (T)0;
+            const T b1 = ok1 ? rx1 * (lev == 1 ? R.d1[s1] : R.d2[s1]) : (T)0;
+            const T vx0 = (T)mfx(pk0) + rx0, vx1 = (T)mfx(pk1) + rx1;
+            const T vy0 = (T)FY + ry0, vy1 = (T)FY + ry1;
+            const T K0 = R.K[s0], K1 = R.K[s1];
+#pragma unroll
+            for (int C = 0; C <= 3 + 1; ++C) {  // speed of this level, static
+                if (C < cl || C > ch) continue;
+                const T w0 = c0 == C ? b0 : (T)0, w1 = c1 == C ? b1 : (T)0;
+                const T cc = (T)C, hc2 = (T)(0.5 * C * C);
+#pragma unroll
+                for (int ky = 0; ky < 2; ++ky) {
+                    const T m0 = w0 * (ky ? ry0 : (T)1 - ry0), m1 = w1 * (ky ? ry1 : (T)1 - ry1);
+                    const T gm = (m0 + m1) * cc;
+#pragma unroll
+                    for (int sg = -1; sg <= 1; sg += 2) {
+                        const int o = FY + ky + sg * C + L;
+                        if (o < 0 || o > 2 * L) continue;  // out of the FIFO: the step is redone / reported
+                        f.a[o][kR] += m0 + m1;
+                        f.a[o][kPx] += m0 * vx0 + m1 * vx1;
+                        f.a[o][kPyv] += m0 * vy0 + m1 * vy1;
+                        dd_add<T>(f.a[o][kGh], f.a[o][kGl], sg > 0 ? gm : -gm);
+                        f.a[o][kE] += m0 * (K0 + hc2 + (T)sg * cc * vy0) + m1 * (K1 + hc2 + (T)sg * cc * vy1);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Any mix of floor(v) and c'_1 around the destination (floor(v_y) varies
+// across the wavefront, i.e. the flow is not planar here): examine all 2H + 1
+// staged sources of the row and every packet that reaches this column.
+// [xlo, xhi] / [ylo, yhi] bound the FIFO slots x- / y-lane packets of the
+// wavefront's sources can reach.
+template <typename T, int L>
+__device__ void gather_general(const MRow<T>& R, int lane, Fifo<T, L>& f, int xlo, int xhi, int ylo, int yhi)
+{
+#pragma unroll 1
+    for (int a = -kMH; a <= kMH; ++a) {
+        const int s = lane - a;
+        const int pk = R.pk[s];
+        const int fx = mfx(pk), fy = mfy(pk), c1 = mc1(pk), c2 = c1 + 1;
+        const T rx = R.rx[s], ry = R.ry[s], d1 = R.d1[s], d2 = R.d2[s], K = R.K[s];
+        const T vx = (T)fx + rx, vy = (T)fy + ry;
+#pragma unroll 1
+        for (int kx = 0; kx < 2; ++kx) {
+            const int cx = a - fx - kx;  // x-lane speed needed to land here
+            const T axw = kx ? rx : (T)1 - rx;
+            // x-lanes with c' = cx: +-c1 (both when c1 = 0) and +-c2
+            const int n1 = (cx == c1 || cx == -c1) ? (c1 == 0 ? 2 : 1) : 0;
+            const int n2 = (cx == c2 || cx == -c2) ? 1 : 0;
+            if (n1 + n2 > 0) {
+                const T w = axw * ((T)n1 * d1 + (T)n2 * d2);
+                const T cc = (T)cx;
+                const T zx = K + cc * vx + (T)0.5 * cc * cc;
+#pragma unroll 1
+                for (int ky = 0; ky < 2; ++ky) {
+                    const T m = w * (ky ? ry : (T)1 - ry);
+                    fifo_add_sel<T, L>(f, fy + ky + L, xlo, xhi, m, m * (vx + cc), m * vy, m * zx);
+                }
+            }
+            if (cx == 0) {  // y-lanes move in x by fx + kx only
+#pragma unroll 1
+                for (int lev = 1; lev <= 2; ++lev) {
+                    const int c = lev == 1 ? c1 : c2;
+                    const T d = lev == 1 ? d1 : d2;
+#pragma unroll 1
+                    for (int sg = -1; sg <= 1; sg += 2) {
+                        const T cc = (T)(sg * c);
+                        const T zy = K + cc * vy + (T)0.5 * cc * cc;
+#pragma unroll 1
+                        for (int ky = 0; ky < 2; ++ky) {
+                            const T m = axw * (ky ? ry : (T)1 - ry) * d;
+                            const int slot = fy + ky + sg * c + L;
+                            fifo_add_sel<T, L>(f, slot, ylo, yhi, m, m * vx, m * vy, m * zy);
+                            fifo_add_g<T, L>(f, slot, ylo, yhi, m * cc);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_node(const T* __restrict__ Y, int64_t nn, int64_t q, T (&m)[4])
+{
+    m[0] = Y[q];
+    m[1] = Y[nn + q];
+    m[2] = Y[2 * nn + q];
+    m[3] = Y[3 * nn + q];
+}
+
+#ifndef LB_MARCH_WPE
+#define LB_MARCH_WPE 2
+#endif
+// L = kLSmall: the short-FIFO pass; a source whose y-reach exceeds L marks the
+// step for a redo.  L = kLFull with redo_only: runs only if the short pass of
+// this step asked for it (and then recomputes every block, bit-identically:
+// the summation order does not depend on L).
+template <typename T, int L>
+__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? LB_MARCH_WPE : 1)))
+march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
+               StepCtl* __restrict__ ctl, double* __restrict__ partials, long long step, int sy,
+               int redo_only)
+{
+    __shared__ MRow<T> s_row[2];
+    __shared__ WaveInfo s_w[2][kMNW];
+    if (ctl->err_step < step) return;
+    if (redo_only && ctl->redo_step != step) return;
+
+    const int tid = threadIdx.x, lane64 = tid & 63, wid = tid >> 6;
+    const int64_t nx = g.nx, ny = g.ny, nn = nx * ny;
+    const int64_t X0 = (int64_t)blockIdx.x * (kMTPB - 2 * kMH);  // first destination column
+    const int64_t Y0 = (int64_t)blockIdx.y * sy;                 // first destination row
+    const int64_t gx = X0 - kMH + tid;                           // this thread's source column
+    const int64_t sx = g.bc_x == kBcPeriodic ? wrap_near(gx, nx) : clamp_idx(gx, nx);
+    const bool dest = tid >= kMH && tid < kMTPB - kMH && gx < nx;
+    const int64_t ylast = min(Y0 + (int64_t)sy, ny);  // destination rows [Y0, ylast)
+    const int nrows = Y0 < ny ? (int)(ylast - Y0) + 2 * L : 0;
+    constexpr int NS = 2 * L + 1;
+
+    Fifo<T, L> f;
+#pragma unroll
+    for (int o = 0; o < NS; ++o)
+#pragma unroll
+        for (int c = 0; c < kNV; ++c) f.a[o][c] = (T)0;
+    double tot[4] = {0.0, 0.0, 0.0, 0.0};
+    int reach = 0, bad = 0, yfar = 0;
+
+    auto row_index = [&](int64_t gy) -> int64_t {
+        const int64_t yy = g.bc_y == kBcPeriodic ? wrap_near(gy, ny) : clamp_idx(gy, ny);
+        return yy * nx + sx;
+    };
+    T cur[4], nxt[4];
+    if (nrows > 0) load_node<T>(Y, nn, row_index(Y0 - L), cur);
+
+    for (int r = 0; r < nrows; ++r) {
+        const int b = r & 1;
+        if (r + 1 < nrows) load_node<T>(Y, nn, row_index(Y0 - L + r + 1), nxt);
+        // stage this source row
+        const Src2<T> s = make_src2<T>(cur[0], cur[1], cur[2], cur[3], k);
+        const int pk = mpack(s.fx, s.fy, s.c1);
+        s_row[b].rx[tid] = s.rx;
+        s_row[b].ry[tid] = s.ry;
+        s_row[b].d1[tid] = s.d1;
+        s_row[b].d2[tid] = s.d2;
+        s_row[b].K[tid] = s.K;
+        s_row[b].pk[tid] = pk;
+        const int yr = axis_reach(s.fy, s.c1);
+        reach = max(reach, max(axis_reach(s.fx, s.c1), yr));
+        yfar |= yr > L ? 1 : 0;
+        bad |= s.bad ? 1 : 0;
+        {
+            const WaveInfo wi{wave_min(s.fx), wave_max(s.fx), wave_min(s.fy), wave_max(s.fy),
+                              wave_min(s.c1), wave_max(s.c1)};
+            if (lane64 == 0) s_w[b][wid] = wi;
+        }
+        __syncthreads();
+
+        // gather this row's packets into the FIFO
+        WaveInfo w = s_w[b][wid];
+        if (wid > 0) {
+            const WaveInfo l = s_w[b][wid - 1];
+            w = WaveInfo{min(w.fxmin, l.fxmin), max(w.fxmax, l.fxmax), min(w.fymin, l.fymin),
+                         max(w.fymax, l.fymax), min(w.c1min, l.c1min), max(w.c1max, l.c1max)};
+        }
+        if (wid + 1 < kMNW) {
+            const WaveInfo r2 = s_w[b][wid + 1];
+            w = WaveInfo{min(w.fxmin, r2.fxmin), max(w.fxmax, r2.fxmax), min(w.fymin, r2.fymin),
+                         max(w.fymax, r2.fymax), min(w.c1min, r2.c1min), max(w.c1max, r2.c1max)};
+        }
+        // the fast and row paths need every packet of the window inside the
+        // FIFO (y) and the staged row (x); the general path takes any window
+        // whose sources each reach <= H.  A short FIFO that cannot hold the
+        // window's y displacements marks the step for a redo.
+        const int c2max = w.c1max + 1;
+        const bool fits_y = w.fymin - c2max >= -L && w.fymax + 1 + c2max <= L;
+        const bool fits_x = w.fxmin - c2max >= -kMH && w.fxmax + 1 + c2max <= kMH;
+        if (L < kLFull && !fits_y) yfar = 1;
+        const bool rows_ok = fits_x && fits_y && w.fymin == w.fymax && (w.fymin == 0 || w.fymin == -1) &&
+                             w.c1max <= 3 && w.fxmax - w.fxmin <= 2;
+        const bool uni = rows_ok && w.fxmin == w.fxmax && w.c1min == w.c1max;
+        if (dest && (fits_y || L == kLFull)) {
+            if (uni) {
+                const MRow<T>& R = s_row[b];
+                if (w.fymin == 0) {
+                    switch (w.c1min) {
+                        case 0: gather_fast<T, L, 0, 0>(R, tid, w.fxmin, f); break;
+                        case 1: gather_fast<T, L, 0, 1>(R, tid, w.fxmin, f); break;
+                        case 2: if (L >= 4) gather_fast<T, L, 0, (L >= 4 ? 2 : 0)>(R, tid, w.fxmin, f); break;
+                        default: if (L >= 5) gather_fast<T, L, 0, (L >= 5 ? 3 : 0)>(R, tid, w.fxmin, f); break;
+                    }
+                } else {
+                    switch (w.c1min) {
+                        case 0: gather_fast<T, L, -1, 0>(R, tid, w.fxmin, f); break;
+                        case 1: if (L >= 3) gather_fast<T, L, -1, (L >= 3 ? 1 : 0)>(R, tid, w.fxmin, f); break;
+                        case 2: if (L >= 4) gather_fast<T, L, -1, (L >= 4 ? 2 : 0)>(R, tid, w.fxmin, f); break;
+                        default: if (L >= 5) gather_fast<T, L, -1, (L >= 5 ? 3 : 0)>(R, tid, w.fxmin, f); break;
+                    }
+                }
+            } else if (rows_ok) {
+                if (w.fymin == 0)
+                    gather_rows<T, L, 0>(s_row[b], tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max);
+                else
+                    gather_rows<T, L, -1>(s_row[b], tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max);
+            } else {
+                gather_general<T, L>(s_row[b], tid, f, w.fymin + L, w.fymax + 1 + L,
+                                     w.fymin - c2max + L, w.fymax + 1 + c2max + L);
+            }
+        }
+        // destination row (source row) - L is complete
+        if (r >= 2 * L && dest) {
+            const int64_t ty = Y0 + r - 2 * L;
+            const int64_t q = ty * nx + gx;
+            const T py = f.a[0][kPyv] + (f.a[0][kGh] + f.a[0][kGl]);
+            Yn[q] = f.a[0][kR];
+            Yn[nn + q] = f.a[0][kPx];
+            Yn[2 * nn + q] = py;
+            Yn[3 * nn + q] = f.a[0][kE];
+            tot[0] += (double)f.a[0][kR];
+            tot[1] += (double)f.a[0][kPx];
+            tot[2] += (double)py;
+            tot[3] += (double)f.a[0][kE];
+        }
+#pragma unroll
+        for (int o = 0; o + 1 < NS; ++o)
+#pragma unroll
+            for (int c = 0; c < kNV; ++c) f.a[o][c] = f.a[o + 1][c];
+#pragma unroll
+        for (int c = 0; c < kNV; ++c) f.a[NS - 1][c] = (T)0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cur[c] = nxt[c];
+    }
+    if (L < kLFull) {
+        // a packet of this block's sources needs a wider FIFO: redo the step
+        if (__any(yfar) && lane64 == 0) ctl->redo_step = step;
+    } else if (redo_only && blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
+        ctl->redo_count += 1;
+    }
+
+    // per-block partials: field sums, reach, error bits
+    __shared__ double s_sum[kMNW][4];
+    __shared__ int s_ir[kMNW][2];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) tot[c] = wave_sum(tot[c]);
+    reach = wave_max(reach);
+    bad = wave_max(bad);
+    if (lane64 == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s_sum[wid][c] = tot[c];
+        s_ir[wid][0] = reach;
+        s_ir[wid][1] = bad;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int64_t bid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        double* p = partials + bid * kPartialStride;
+        int rr = 0, bb = 0;
+        for (int c = 0; c < 4; ++c) {
+            double t = s_sum[0][c];
+            for (int w = 1; w < kMNW; ++w) t += s_sum[w][c];
+            p[c] = t;
+        }
+        for (int w = 0; w < kMNW; ++w) {
+            rr = max(rr, s_ir[w][0]);
+            bb |= s_ir[w][1];
+        }
+        p[4] = (double)rr;
+        p[5] = (double)((rr > kMH ? kErrReach : 0) | (bb ? kErrState : 0));
+    }
+}
+
+int64_t x_strips(const Grid& g) { return (g.nx + (kMTPB - 2 * kMH) - 1) / (kMTPB - 2 * kMH); }
+
+}  // namespace
+
+MarchGeom march2d_geometry(const Grid& g, int target_blocks)
+{
+    MarchGeom m;
+    const int64_t xs = x_strips(g);
+    int64_t chunks = target_blocks > 0 ? (target_blocks + xs - 1) / xs : 1;
+    if (chunks < 1) chunks = 1;
+    int64_t sy = (g.ny + chunks - 1) / chunks;
+    if (sy < kMinRows) sy = kMinRows;
+    m.sy = (int)sy;
+    m.grid_x = xs;
+    m.grid_y = (g.ny + sy - 1) / sy;
+    return m;
+}
+
+int64_t march2d_max_blocks(const Grid& g)
+{
+    return x_strips(g) * ((g.ny + kMinRows - 1) / kMinRows);
+}
+
+template <typename T>
+int march2d_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, march2d_kernel<T, kLSmall>, kMTPB, 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+template <typename T>
+hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
+                          StepCtl* ctl, double* partials, long long step, bool full_only,
+                          hipStream_t stream)
+{
+    const dim3 grid((unsigned)m.grid_x, (unsigned)m.grid_y);
+    if (!full_only) {
+        march2d_kernel<T, kLSmall><<<grid, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step, m.sy, 0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    march2d_kernel<T, kLFull><<<grid, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step, m.sy,
+                                                          full_only ? 0 : 1);
+    return hipGetLastError();
+}
+
+template int march2d_blocks_per_cu<double>();
+template int march2d_blocks_per_cu<float>();
+template hipError_t launch_march2d<double>(const double*, double*, const Grid&, const MarchGeom&,
+                                           const Consts&, StepCtl*, double*, long long, bool,
+                                           hipStream_t);
+template hipError_t launch_march2d<float>(const float*, float*, const Grid&, const MarchGeom&,
+                                          const Consts&, StepCtl*, double*, long long, bool,
+                                          hipStream_t);
+
+}  // namespace lbsd

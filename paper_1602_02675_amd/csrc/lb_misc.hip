@@ -62,6 +62,8 @@ __global__ void reset_ctl_kernel(StepCtl* ctl)
         ctl->totals_step = -1;
         for (int f = 0; f < 4; ++f) ctl->totals[f] = 0.0;
         ctl->max_reach = 0;
+        ctl->redo_count = 0;
+        ctl->redo_step = -1;
     }
 }
 

@@ -542,7 +542,6 @@ hipError_t launch_step1d(const T* Y, T* Yn, const Grid& g, const Consts& k, Step
 {
     const dim3 grid((unsigned)step_blocks_1d(g));
     step1d_kernel<T, kHalo, k1TPB, k1J><<<grid, k1TPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step);
-    finalize_kernel<<<1, kFinTPB, 0, stream>>>(partials, (int64_t)grid.x, ctl, step, kHalo);
     return hipGetLastError();
 }
 
@@ -553,7 +552,13 @@ hipError_t launch_step2d(const T* Y, T* Yn, const Grid& g, const Consts& k, Step
     const dim3 grid((unsigned)((g.nx + k2TX - 1) / k2TX), (unsigned)((g.ny + k2TY - 1) / k2TY));
     step2d_kernel<T, kHalo, k2TX, k2TY, k2J>
         <<<grid, k2TX * k2TY / k2J, 0, stream>>>(Y, Yn, g, k, ctl, partials, step);
-    finalize_kernel<<<1, kFinTPB, 0, stream>>>(partials, (int64_t)grid.x * grid.y, ctl, step, kHalo);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* partials, int64_t nb, StepCtl* ctl, long long step,
+                           hipStream_t stream)
+{
+    finalize_kernel<<<1, kFinTPB, 0, stream>>>(partials, nb, ctl, step, kHalo);
     return hipGetLastError();
 }
 

@@ -12,6 +12,11 @@ import os
 
 import numpy as np
 
+# torch first: its bundled HIP runtime must be the one liblbsd.so binds to
+# (the library's libamdhip64.so.7 dependency then resolves to that copy), so
+# that torch's device pointers and streams are valid in the library.
+import torch  # noqa: F401
+
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBSD_LIBRARY") or os.path.join(_PKG, "liblbsd.so")
 
@@ -25,7 +30,7 @@ _ERR_NAMES = {LB_EINVAL: "LB_EINVAL", LB_ENOMEM: "LB_ENOMEM", LB_EDEVICE: "LB_ED
               LB_ESTATE: "LB_ESTATE", LB_EREACH: "LB_EREACH"}
 
 EXPORTED = ["lb_create", "lb_state_bytes", "lb_bind", "lb_set_lambda", "lb_set_cfl",
-            "lb_init_riemann", "lb_init_moments", "lb_step", "lb_step_timed", "lb_sync",
+            "lb_init_riemann", "lb_init_moments", "lb_step", "lb_step_timed", "lb_step_profiled", "lb_sync",
             "lb_moments", "lb_totals", "lb_lambda", "lb_dt", "lb_steps_done", "lb_max_reach",
             "lb_debug_lanes", "lb_destroy", "lb_last_error"]
 
@@ -68,6 +73,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lb_init_moments": (ctypes.c_int, [vp, D, dbl]),
         "lb_step": (ctypes.c_int, [vp, i64]),
         "lb_step_timed": (ctypes.c_int, [vp, i64, ctypes.POINTER(ctypes.c_float)]),
+        "lb_step_profiled": (ctypes.c_int, [vp, i64, ctypes.POINTER(ctypes.c_float),
+                                            ctypes.POINTER(ctypes.c_float)]),
         "lb_sync": (ctypes.c_int, [vp]),
         "lb_moments": (ctypes.c_int, [vp, vp, i32]),
         "lb_totals": (ctypes.c_int, [vp, D]),
@@ -170,6 +177,12 @@ class Solver:
         ms = ctypes.c_float(0.0)
         _check(_lib.lb_step_timed(self._h, int(n), ctypes.byref(ms)))
         return float(ms.value)
+
+    def step_profiled(self, n: int):
+        """(summed step-kernel ms, total ms) of n steps, from HIP events."""
+        k, t = ctypes.c_float(0.0), ctypes.c_float(0.0)
+        _check(_lib.lb_step_profiled(self._h, int(n), ctypes.byref(k), ctypes.byref(t)))
+        return float(k.value), float(t.value)
 
     def sync(self):
         _check(_lib.lb_sync(self._h))

@@ -162,3 +162,26 @@ def test_reach_reported():
     Y0[0, 0, 5] = -1.0
     _, st, _ = oracle.step(P, Y0)
     assert st == -4
+
+
+def test_square_lattice_transverse_growth():
+    """Characterisation (not a pin): on the square dual-level lattice (d_0 = 0)
+    a gas at rest with c'_1 = 1 amplifies small perturbations, while the 1-D
+    triple-level set and c'_1 = 0 damp them.  Planar runs therefore have to
+    keep their rows identical bit for bit to stay planar."""
+    rng = np.random.default_rng(0)
+    lam2 = 0.8439 ** 2
+
+    def growth(dim, e):
+        nx, ny = (48, 48) if dim == 2 else (256, 1)
+        P = oracle.Problem(dim, nx, ny, bc_x=oracle.PERIODIC, bc_y=oracle.PERIODIC)
+        Y = np.zeros(P.shape)
+        Y[0] = 1.0 + 1e-8 * rng.standard_normal((ny, nx))
+        Y[-1] = Y[0] * e * lam2
+        s0 = np.std(Y[0])
+        Y, st, _ = oracle.run(P, Y, 40)
+        return np.std(Y[0]) / s0
+
+    assert growth(2, 2.5) > 100.0          # A = 1.42: c'_1 = 1, unstable
+    assert growth(2, 0.25 * 2.5 / 0.8) < 1.0  # A = 0.45: c'_1 = 0, damped
+    assert growth(1, 2.5) < 1.0            # 1-D, rest particle d_0 = rho/2: damped
