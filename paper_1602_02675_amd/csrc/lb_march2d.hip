@@ -78,7 +78,16 @@ struct MRow {  // one staged source row
 
 struct WaveInfo {  // per wavefront and staged row: ranges over its 64 sources
     int fxmin, fxmax, fymin, fymax, c1min, c1max;
+    int ry0;       // 1 if every source has v_y integral (r_y = 0)
+    int pad;
 };
+
+__device__ __forceinline__ WaveInfo merge(const WaveInfo& a, const WaveInfo& b)
+{
+    return WaveInfo{min(a.fxmin, b.fxmin), max(a.fxmax, b.fxmax), min(a.fymin, b.fymin),
+                    max(a.fymax, b.fymax), min(a.c1min, b.c1min), max(a.c1max, b.c1max),
+                    a.ry0 & b.ry0, 0};
+}
 
 template <typename T, int L>
 struct Fifo {
@@ -114,6 +123,80 @@ __device__ __forceinline__ void fifo_add_g(Fifo<T, L>& f, int slot, int lo, int 
     }
 }
 
+// Window where every source has floor(v) = (fx, FY) and c'_1 in
+// {S0, S0 + NSP - 2}: the lanes of the window have speeds S0 .. S0 + NSP - 1,
+// four per speed (+-x, +-y), and a source puts its level-1 weight d_1 on speed
+// c'_1 and d_2 on c'_1 + 1 (zero on the others).  Every packet class then has
+// a compile-time column offset and FIFO slot.  NSP = 2 (UNI) is the window of
+// uniform c'_1; NSP = 3 covers a window where c'_1 takes two adjacent values.
+// RY0: every source has r_y = 0, so the corners k_y = 1 carry no mass (eq. 29)
+// and are skipped; with FY = 0 also v_y = 0 and the m v_y terms vanish.  The
+// sums are the same, term for term.
+template <typename T, int L, int FY, int S0, int NSP, bool RY0>
+__device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, Fifo<T, L>& f)
+{
+    constexpr bool UNI = NSP == 2;
+    const int base = lane - fx;  // staged column of x displacement fx + a is base - a
+    const T fxT = (T)fx;
+    // weight of speed S0 + j for the source in column s
+    auto wgt = [&](int s, int j) -> T {
+        if (UNI) return j == 0 ? R.d1[s] : R.d2[s];
+        const int lev = S0 + j - mc1(R.pk[s]) + 1;  // 1, 2 or out of range
+        return lev == 1 ? R.d1[s] : (lev == 2 ? R.d2[s] : (T)0);
+    };
+#pragma unroll
+    for (int j = 0; j < NSP; ++j) {
+        const int c = S0 + j;
+        const T cc = (T)c, hc2 = (T)(0.5 * c * c);
+        // x-lanes: destination row FY + ky, source columns base - (kx +- c)
+#pragma unroll
+        for (int kx = 0; kx < 2; ++kx) {
+            const int sp = base - (kx + c), sm = base - (kx - c);
+            const T rxp = R.rx[sp], ryp = R.ry[sp], rxm = R.rx[sm], rym = R.ry[sm];
+            const T bp = (kx ? rxp : (T)1 - rxp) * wgt(sp, j), bm = (kx ? rxm : (T)1 - rxm) * wgt(sm, j);
+            const T vxp = fxT + rxp, vxm = fxT + rxm, vyp = (T)FY + ryp, vym = (T)FY + rym;
+            const T zp = R.K[sp] + hc2 + cc * vxp, zm = R.K[sm] + hc2 - cc * vxm;
+#pragma unroll
+            for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
+                const int o = FY + ky + L;
+                const T mp = RY0 ? bp : bp * (ky ? ryp : (T)1 - ryp);
+                const T mm = RY0 ? bm : bm * (ky ? rym : (T)1 - rym);
+                f.a[o][kR] += mp + mm;
+                f.a[o][kPx] += (mp * vxp + mm * vxm) + (mp - mm) * cc;
+                if (!(RY0 && FY == 0)) f.a[o][kPyv] += mp * vyp + mm * vym;
+                f.a[o][kE] += mp * zp + mm * zm;
+            }
+        }
+        // y-lanes: source columns base (kx = 0) and base - 1 (kx = 1)
+        {
+            const int s0 = base, s1 = base - 1;
+            const T rx0 = R.rx[s0], ry0 = R.ry[s0], rx1 = R.rx[s1], ry1 = R.ry[s1];
+            const T b0 = ((T)1 - rx0) * wgt(s0, j);
+            const T b1 = rx1 * wgt(s1, j);
+            const T vx0 = fxT + rx0, vx1 = fxT + rx1, vy0 = (T)FY + ry0, vy1 = (T)FY + ry1;
+            const T k0 = R.K[s0] + hc2, k1 = R.K[s1] + hc2;
+#pragma unroll
+            for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
+                const T m0 = RY0 ? b0 : b0 * (ky ? ry0 : (T)1 - ry0);
+                const T m1 = RY0 ? b1 : b1 * (ky ? ry1 : (T)1 - ry1);
+                const T gm = (m0 + m1) * cc;
+#pragma unroll
+                for (int sg = -1; sg <= 1; sg += 2) {
+                    const int o = FY + ky + sg * c + L;
+                    f.a[o][kR] += m0 + m1;
+                    f.a[o][kPx] += m0 * vx0 + m1 * vx1;
+                    if (!(RY0 && FY == 0)) f.a[o][kPyv] += m0 * vy0 + m1 * vy1;
+                    if (c != 0) dd_add<T>(f.a[o][kGh], f.a[o][kGl], sg > 0 ? gm : -gm);
+                    if (RY0 && FY == 0)
+                        f.a[o][kE] += m0 * k0 + m1 * k1;
+                    else
+                        f.a[o][kE] += m0 * (k0 + (T)sg * cc * vy0) + m1 * (k1 + (T)sg * cc * vy1);
+                }
+            }
+        }
+    }
+}
+
 // Rows where every source seen by this wavefront has floor(v_y) = FY: the
 // FIFO slot of every packet is known at compile time up to c'_1, which is
 // taken from its (short) range [clo, chi] in unrolled branches; floor(v_x)
@@ -131,63 +214,6 @@ __device__ __forceinline__ T prod_nc(T a, T b)
     return a * b;
 }
 
-// Window where every source has floor(v) = (fx, FY) and c'_1 = C1: every
-// packet class has a compile-time column offset and FIFO slot.
-template <typename T, int L, int FY, int C1>
-__device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, Fifo<T, L>& f)
-{
-    const int base = lane - fx;  // staged column of x displacement fx + a is base - a
-    const T fxT = (T)fx;
-#pragma unroll
-    for (int lev = 1; lev <= 2; ++lev) {
-        const int c = C1 + lev - 1;
-        const T cc = (T)c, hc2 = (T)(0.5 * c * c);
-        // x-lanes: destination row FY + ky, source columns base - (kx +- c)
-#pragma unroll
-        for (int kx = 0; kx < 2; ++kx) {
-            const int sp = base - (kx + c), sm = base - (kx - c);
-            const T rxp = R.rx[sp], ryp = R.ry[sp], rxm = R.rx[sm], rym = R.ry[sm];
-            const T dp = lev == 1 ? R.d1[sp] : R.d2[sp];
-            const T dm = lev == 1 ? R.d1[sm] : R.d2[sm];
-            const T bp = (kx ? rxp : (T)1 - rxp) * dp, bm = (kx ? rxm : (T)1 - rxm) * dm;
-            const T vxp = fxT + rxp, vxm = fxT + rxm, vyp = (T)FY + ryp, vym = (T)FY + rym;
-            const T zp = R.K[sp] + hc2 + cc * vxp, zm = R.K[sm] + hc2 - cc * vxm;
-#pragma unroll
-            for (int ky = 0; ky < 2; ++ky) {
-                const int o = FY + ky + L;
-                const T mp = bp * (ky ? ryp : (T)1 - ryp), mm = bm * (ky ? rym : (T)1 - rym);
-                f.a[o][kR] += mp + mm;
-                f.a[o][kPx] += (mp * vxp + mm * vxm) + (mp - mm) * cc;
-                f.a[o][kPyv] += mp * vyp + mm * vym;
-                f.a[o][kE] += mp * zp + mm * zm;
-            }
-        }
-        // y-lanes: source columns base (kx = 0) and base - 1 (kx = 1)
-        {
-            const int s0 = base, s1 = base - 1;
-            const T rx0 = R.rx[s0], ry0 = R.ry[s0], rx1 = R.rx[s1], ry1 = R.ry[s1];
-            const T b0 = ((T)1 - rx0) * (lev == 1 ? R.d1[s0] : R.d2[s0]);
-            const T b1 = rx1 * (lev == 1 ? R.d1[s1] : R.d2[s1]);
-            const T vx0 = fxT + rx0, vx1 = fxT + rx1, vy0 = (T)FY + ry0, vy1 = (T)FY + ry1;
-            const T k0 = R.K[s0] + hc2, k1 = R.K[s1] + hc2;
-#pragma unroll
-            for (int ky = 0; ky < 2; ++ky) {
-                const T m0 = b0 * (ky ? ry0 : (T)1 - ry0), m1 = b1 * (ky ? ry1 : (T)1 - ry1);
-                const T gm = (m0 + m1) * cc;
-#pragma unroll
-                for (int sg = -1; sg <= 1; sg += 2) {
-                    const int o = FY + ky + sg * c + L;
-                    f.a[o][kR] += m0 + m1;
-                    f.a[o][kPx] += m0 * vx0 + m1 * vx1;
-                    f.a[o][kPyv] += m0 * vy0 + m1 * vy1;
-                    dd_add<T>(f.a[o][kGh], f.a[o][kGl], sg > 0 ? gm : -gm);
-                    f.a[o][kE] += m0 * (k0 + (T)sg * cc * vy0) + m1 * (k1 + (T)sg * cc * vy1);
-                }
-            }
-        }
-    }
-}
-
 template <typename T, int L, int FY>
 __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<T, L>& f, int fxlo, int fxhi,
                                             int clo, int chi)
@@ -200,6 +226,10 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<T, 
         // x-lanes: destination row FY + ky; +c from a = kx + fx + c, -c from a = kx + fx - c
 #pragma unroll
         for (int kx = 0; kx < 2; ++kx) {
+            // the lane momenta m c' of the candidates are summed per (k_x, k_y)
+            // before they meet the FIFO, so a +c packet and its -c mirror found
+            // at different candidates still cancel exactly
+            T sx[2] = {(T)0, (T)0}, vxs[2] = {(T)0, (T)0};
             for (int i = 0; i < ncand; ++i) {
                 const int ap = kx + fxlo + cl + i, am = kx + fxhi - cl - i;
                 const int sp = lane - ap, sm = lane - am;
@@ -221,11 +251,14 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<T, 
                     const int o = FY + ky + L;
                     const T mp = bp * (ky ? ryp : (T)1 - ryp), mm = bm * (ky ? rym : (T)1 - rym);
                     f.a[o][kR] += mp + mm;
-                    f.a[o][kPx] += (mp * vxp + mm * vxm) + (prod_nc(mp, ccp) - prod_nc(mm, ccm));
+                    vxs[ky] += mp * vxp + mm * vxm;
+                    sx[ky] += prod_nc(mp, ccp) - prod_nc(mm, ccm);
                     f.a[o][kPyv] += mp * vyp + mm * vym;
                     f.a[o][kE] += mp * zp + mm * zm;
                 }
             }
+#pragma unroll
+            for (int ky = 0; ky < 2; ++ky) f.a[FY + ky + L][kPx] += vxs[ky] + sx[ky];
         }
         // y-lanes: a = fx + kx; kx = 0 and kx = 1 candidates taken together
         for (int i = 0; i <= nfx; ++i) {
@@ -390,24 +423,23 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
         yfar |= yr > L ? 1 : 0;
         bad |= s.bad ? 1 : 0;
         {
-            const WaveInfo wi{wave_min(s.fx), wave_max(s.fx), wave_min(s.fy), wave_max(s.fy),
-                              wave_min(s.c1), wave_max(s.c1)};
+            const int ry0 = __all(s.ry == (T)0) ? 1 : 0;
+            const int pk0 = __builtin_amdgcn_readfirstlane(pk);
+            WaveInfo wi;
+            if (__all(pk == pk0)) {  // the common case: one ballot instead of six reductions
+                wi = WaveInfo{mfx(pk0), mfx(pk0), mfy(pk0), mfy(pk0), mc1(pk0), mc1(pk0), ry0, 0};
+            } else {
+                wi = WaveInfo{wave_min(s.fx), wave_max(s.fx), wave_min(s.fy), wave_max(s.fy),
+                              wave_min(s.c1), wave_max(s.c1), ry0, 0};
+            }
             if (lane64 == 0) s_w[b][wid] = wi;
         }
         __syncthreads();
 
         // gather this row's packets into the FIFO
         WaveInfo w = s_w[b][wid];
-        if (wid > 0) {
-            const WaveInfo l = s_w[b][wid - 1];
-            w = WaveInfo{min(w.fxmin, l.fxmin), max(w.fxmax, l.fxmax), min(w.fymin, l.fymin),
-                         max(w.fymax, l.fymax), min(w.c1min, l.c1min), max(w.c1max, l.c1max)};
-        }
-        if (wid + 1 < kMNW) {
-            const WaveInfo r2 = s_w[b][wid + 1];
-            w = WaveInfo{min(w.fxmin, r2.fxmin), max(w.fxmax, r2.fxmax), min(w.fymin, r2.fymin),
-                         max(w.fymax, r2.fymax), min(w.c1min, r2.c1min), max(w.c1max, r2.c1max)};
-        }
+        if (wid > 0) w = merge(w, s_w[b][wid - 1]);
+        if (wid + 1 < kMNW) w = merge(w, s_w[b][wid + 1]);
         // the fast and row paths need every packet of the window inside the
         // FIFO (y) and the staged row (x); the general path takes any window
         // whose sources each reach <= H.  A short FIFO that cannot hold the
@@ -420,22 +452,28 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
                              w.c1max <= 3 && w.fxmax - w.fxmin <= 2;
         const bool uni = rows_ok && w.fxmin == w.fxmax && w.c1min == w.c1max;
         if (dest && (fits_y || L == kLFull)) {
-            if (uni) {
+            const bool mix2 = rows_ok && !uni && w.fxmin == w.fxmax && w.c1max == w.c1min + 1;
+            if (uni || mix2) {
                 const MRow<T>& R = s_row[b];
-                if (w.fymin == 0) {
-                    switch (w.c1min) {
-                        case 0: gather_fast<T, L, 0, 0>(R, tid, w.fxmin, f); break;
-                        case 1: gather_fast<T, L, 0, 1>(R, tid, w.fxmin, f); break;
-                        case 2: if (L >= 4) gather_fast<T, L, 0, (L >= 4 ? 2 : 0)>(R, tid, w.fxmin, f); break;
-                        default: if (L >= 5) gather_fast<T, L, 0, (L >= 5 ? 3 : 0)>(R, tid, w.fxmin, f); break;
-                    }
-                } else {
-                    switch (w.c1min) {
-                        case 0: gather_fast<T, L, -1, 0>(R, tid, w.fxmin, f); break;
-                        case 1: if (L >= 3) gather_fast<T, L, -1, (L >= 3 ? 1 : 0)>(R, tid, w.fxmin, f); break;
-                        case 2: if (L >= 4) gather_fast<T, L, -1, (L >= 4 ? 2 : 0)>(R, tid, w.fxmin, f); break;
-                        default: if (L >= 5) gather_fast<T, L, -1, (L >= 5 ? 3 : 0)>(R, tid, w.fxmin, f); break;
-                    }
+                const int fx0 = w.fxmin;
+                const int sel = (w.fymin == 0 ? (w.ry0 ? 0 : 1) : 2) * 8 + (mix2 ? 4 : 0) + w.c1min;
+                switch (sel) {
+#define LB_FAST(S, FYV, S0, NSP, RY)                                                   \
+    case S:                                                                            \
+        if ((FYV) - (S0) - (NSP) + 1 >= -L && (FYV) + 1 + (S0) + (NSP) - 1 <= L)       \
+            gather_fast<T, L, FYV, S0, NSP, RY>(R, tid, fx0, f);                       \
+        break;
+                    LB_FAST(0, 0, 0, 2, true) LB_FAST(1, 0, 1, 2, true) LB_FAST(2, 0, 2, 2, true)
+                    LB_FAST(3, 0, 3, 2, true) LB_FAST(4, 0, 0, 3, true) LB_FAST(5, 0, 1, 3, true)
+                    LB_FAST(6, 0, 2, 3, true)
+                    LB_FAST(8, 0, 0, 2, false) LB_FAST(9, 0, 1, 2, false) LB_FAST(10, 0, 2, 2, false)
+                    LB_FAST(11, 0, 3, 2, false) LB_FAST(12, 0, 0, 3, false) LB_FAST(13, 0, 1, 3, false)
+                    LB_FAST(14, 0, 2, 3, false)
+                    LB_FAST(16, -1, 0, 2, false) LB_FAST(17, -1, 1, 2, false) LB_FAST(18, -1, 2, 2, false)
+                    LB_FAST(19, -1, 3, 2, false) LB_FAST(20, -1, 0, 3, false) LB_FAST(21, -1, 1, 3, false)
+                    LB_FAST(22, -1, 2, 3, false)
+#undef LB_FAST
+                    default: break;
                 }
             } else if (rows_ok) {
                 if (w.fymin == 0)
@@ -517,7 +555,9 @@ MarchGeom march2d_geometry(const Grid& g, int target_blocks)
 {
     MarchGeom m;
     const int64_t xs = x_strips(g);
-    int64_t chunks = target_blocks > 0 ? (target_blocks + xs - 1) / xs : 1;
+    // as many row chunks per column strip as keep every block resident at
+    // once (no second, nearly empty round of blocks)
+    int64_t chunks = target_blocks > 0 ? target_blocks / xs : 1;
     if (chunks < 1) chunks = 1;
     int64_t sy = (g.ny + chunks - 1) / chunks;
     if (sy < kMinRows) sy = kMinRows;
