@@ -123,19 +123,96 @@ __device__ __forceinline__ void fifo_add_g(Fifo<T, L>& f, int slot, int lo, int 
     }
 }
 
-// Window where every source has floor(v) = (fx, FY) and c'_1 in
-// {S0, S0 + NSP - 2}: the lanes of the window have speeds S0 .. S0 + NSP - 1,
-// four per speed (+-x, +-y), and a source puts its level-1 weight d_1 on speed
-// c'_1 and d_2 on c'_1 + 1 (zero on the others).  Every packet class then has
-// a compile-time column offset and FIFO slot.  NSP = 2 (UNI) is the window of
-// uniform c'_1; NSP = 3 covers a window where c'_1 takes two adjacent values.
+template <typename T>
+__device__ __forceinline__ T fmaT(T a, T b, T c);
+template <>
+__device__ __forceinline__ float fmaT<float>(float a, float b, float c)
+{
+    return __builtin_fmaf(a, b, c);
+}
+template <>
+__device__ __forceinline__ double fmaT<double>(double a, double b, double c)
+{
+    return __builtin_fma(a, b, c);
+}
+
+// The fast and the row paths add every packet class through the two helpers
+// below, with fixed expressions (explicit fused multiply-adds, no automatic
+// contraction).  A destination whose packets all come from sources of one
+// floor(v_x) and c'_1 then gets the same bits whichever path its wavefront
+// takes: the other classes add exact zeros.  Without this, wavefronts next to
+// a transition would round an at-rest region differently from their
+// neighbours, and the 1-ulp differences grow into momentum noise that flips
+// floor(v_x) between -1 and 0.
+//
+// One +-c pair of x-lane packets: masses mp (+c) and mm (-c) into slot o.
+// The pair's momentum m c' enters as (mp - mm) c, exactly zero for mirrored
+// packets of equal mass.
+template <typename T, int L, bool NOVY>
+__device__ __forceinline__ void add_xpair(Fifo<T, L>& f, int o, T mp, T mm, T vxp, T vxm, T vyp, T vym, T cc,
+                                          T zp, T zm)
+{
+#pragma clang fp contract(off)
+    f.a[o][kR] += mp + mm;
+    f.a[o][kPx] += fmaT(mp - mm, cc, fmaT(mp, vxp, mm * vxm));
+    if (!NOVY) f.a[o][kPyv] += fmaT(mp, vyp, mm * vym);
+    f.a[o][kE] += fmaT(mp, zp, mm * zm);
+}
+
+// The +-c y-lane packets of NQ x-corner sources (masses m[q], kk = K + c^2/2)
+// into slots op (+c) and om (-c); summed over the corners first, in order.
+template <typename T, int L, int NQ, bool NOVY>
+__device__ __forceinline__ void add_ylanes(Fifo<T, L>& f, int op, int om, const T (&m)[NQ], const T (&vx)[NQ],
+                                           const T (&vy)[NQ], const T (&kk)[NQ], T cc)
+{
+#pragma clang fp contract(off)
+    T msum = m[0], pr = m[0] * vx[0], py = m[0] * vy[0];
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+        msum += m[q];
+        pr = fmaT(m[q], vx[q], pr);
+        py = fmaT(m[q], vy[q], py);
+    }
+    const T gm = msum * cc;
+#pragma unroll
+    for (int sg = -1; sg <= 1; sg += 2) {
+        const int o = sg > 0 ? op : om;
+        const T scc = sg > 0 ? cc : -cc;
+        T pe;
+        if (NOVY) {  // v_y = 0: K + c^2/2 + s c v_y is kk exactly
+            pe = m[0] * kk[0];
+#pragma unroll
+            for (int q = 1; q < NQ; ++q) pe = fmaT(m[q], kk[q], pe);
+        } else {
+            pe = m[0] * fmaT(scc, vy[0], kk[0]);
+#pragma unroll
+            for (int q = 1; q < NQ; ++q) pe = fmaT(m[q], fmaT(scc, vy[q], kk[q]), pe);
+        }
+        f.a[o][kR] += msum;
+        f.a[o][kPx] += pr;
+        if (!NOVY) f.a[o][kPyv] += py;
+        dd_add<T>(f.a[o][kGh], f.a[o][kGl], sg > 0 ? gm : -gm);
+        f.a[o][kE] += pe;
+    }
+}
+
+// Window where every source has floor(v_y) = FY, floor(v_x) in {fx - NKX + 2,
+// fx} and c'_1 in {S0, S0 + NSP - 2}: the lanes of the window have speeds
+// S0 .. S0 + NSP - 1, four per speed (+-x, +-y), and a source puts its level-1
+// weight d_1 on speed c'_1 and d_2 on c'_1 + 1 (zero on the others); its x
+// corners k_x = 0, 1 sit at x displacement floor(v_x) + k_x, i.e. at corners
+// -1 .. 1 relative to fx.  Every packet class then has a compile-time column
+// offset and FIFO slot.  NSP = 2, NKX = 2 is the uniform window.
 // RY0: every source has r_y = 0, so the corners k_y = 1 carry no mass (eq. 29)
 // and are skipped; with FY = 0 also v_y = 0 and the m v_y terms vanish.  The
 // sums are the same, term for term.
-template <typename T, int L, int FY, int S0, int NSP, bool RY0>
+template <typename T, int L, int FY, int S0, int NSP, int NKX, bool RY0>
 __device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, Fifo<T, L>& f)
 {
+#pragma clang fp contract(off)
     constexpr bool UNI = NSP == 2;
+    constexpr bool NOVY = RY0 && FY == 0;
+    constexpr int K0 = NKX == 3 ? -1 : 0;  // first x corner relative to floor(v_x) = fx
     const int base = lane - fx;  // staged column of x displacement fx + a is base - a
     const T fxT = (T)fx;
     // weight of speed S0 + j for the source in column s
@@ -144,55 +221,50 @@ __device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, 
         const int lev = S0 + j - mc1(R.pk[s]) + 1;  // 1, 2 or out of range
         return lev == 1 ? R.d1[s] : (lev == 2 ? R.d2[s] : (T)0);
     };
+    // weight of corner k (relative to fx) of the source in column s
+    auto xw = [&](int s, int k, T rx) -> T {
+        if (NKX == 2) return k == 0 ? (T)1 - rx : rx;
+        const int kk = k + fx - mfx(R.pk[s]);  // the source's own corner
+        return kk == 0 ? (T)1 - rx : (kk == 1 ? rx : (T)0);
+    };
+    auto vxof = [&](int s, T rx) -> T { return (NKX == 2 ? fxT : (T)mfx(R.pk[s])) + rx; };
 #pragma unroll
     for (int j = 0; j < NSP; ++j) {
         const int c = S0 + j;
         const T cc = (T)c, hc2 = (T)(0.5 * c * c);
         // x-lanes: destination row FY + ky, source columns base - (kx +- c)
 #pragma unroll
-        for (int kx = 0; kx < 2; ++kx) {
+        for (int kx = K0; kx < 2; ++kx) {
             const int sp = base - (kx + c), sm = base - (kx - c);
             const T rxp = R.rx[sp], ryp = R.ry[sp], rxm = R.rx[sm], rym = R.ry[sm];
-            const T bp = (kx ? rxp : (T)1 - rxp) * wgt(sp, j), bm = (kx ? rxm : (T)1 - rxm) * wgt(sm, j);
-            const T vxp = fxT + rxp, vxm = fxT + rxm, vyp = (T)FY + ryp, vym = (T)FY + rym;
-            const T zp = R.K[sp] + hc2 + cc * vxp, zm = R.K[sm] + hc2 - cc * vxm;
+            const T bp = xw(sp, kx, rxp) * wgt(sp, j), bm = xw(sm, kx, rxm) * wgt(sm, j);
+            const T vxp = vxof(sp, rxp), vxm = vxof(sm, rxm), vyp = (T)FY + ryp, vym = (T)FY + rym;
+            const T zp = fmaT(cc, vxp, R.K[sp] + hc2), zm = fmaT(-cc, vxm, R.K[sm] + hc2);
 #pragma unroll
             for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
-                const int o = FY + ky + L;
                 const T mp = RY0 ? bp : bp * (ky ? ryp : (T)1 - ryp);
                 const T mm = RY0 ? bm : bm * (ky ? rym : (T)1 - rym);
-                f.a[o][kR] += mp + mm;
-                f.a[o][kPx] += (mp * vxp + mm * vxm) + (mp - mm) * cc;
-                if (!(RY0 && FY == 0)) f.a[o][kPyv] += mp * vyp + mm * vym;
-                f.a[o][kE] += mp * zp + mm * zm;
+                add_xpair<T, L, NOVY>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm);
             }
         }
-        // y-lanes: source columns base (kx = 0) and base - 1 (kx = 1)
-        {
-            const int s0 = base, s1 = base - 1;
-            const T rx0 = R.rx[s0], ry0 = R.ry[s0], rx1 = R.rx[s1], ry1 = R.ry[s1];
-            const T b0 = ((T)1 - rx0) * wgt(s0, j);
-            const T b1 = rx1 * wgt(s1, j);
-            const T vx0 = fxT + rx0, vx1 = fxT + rx1, vy0 = (T)FY + ry0, vy1 = (T)FY + ry1;
-            const T k0 = R.K[s0] + hc2, k1 = R.K[s1] + hc2;
+        // y-lanes: source columns base - kx
+        T b[NKX], ry[NKX], vx[NKX], vy[NKX], kk[NKX];
 #pragma unroll
-            for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
-                const T m0 = RY0 ? b0 : b0 * (ky ? ry0 : (T)1 - ry0);
-                const T m1 = RY0 ? b1 : b1 * (ky ? ry1 : (T)1 - ry1);
-                const T gm = (m0 + m1) * cc;
+        for (int q = 0; q < NKX; ++q) {
+            const int kx = K0 + q, sq = base - kx;
+            const T rx = R.rx[sq];
+            ry[q] = R.ry[sq];
+            b[q] = xw(sq, kx, rx) * wgt(sq, j);
+            vx[q] = vxof(sq, rx);
+            vy[q] = (T)FY + ry[q];
+            kk[q] = R.K[sq] + hc2;
+        }
 #pragma unroll
-                for (int sg = -1; sg <= 1; sg += 2) {
-                    const int o = FY + ky + sg * c + L;
-                    f.a[o][kR] += m0 + m1;
-                    f.a[o][kPx] += m0 * vx0 + m1 * vx1;
-                    if (!(RY0 && FY == 0)) f.a[o][kPyv] += m0 * vy0 + m1 * vy1;
-                    if (c != 0) dd_add<T>(f.a[o][kGh], f.a[o][kGl], sg > 0 ? gm : -gm);
-                    if (RY0 && FY == 0)
-                        f.a[o][kE] += m0 * k0 + m1 * k1;
-                    else
-                        f.a[o][kE] += m0 * (k0 + (T)sg * cc * vy0) + m1 * (k1 + (T)sg * cc * vy1);
-                }
-            }
+        for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
+            T m[NKX];
+#pragma unroll
+            for (int q = 0; q < NKX; ++q) m[q] = RY0 ? b[q] : b[q] * (ky ? ry[q] : (T)1 - ry[q]);
+            add_ylanes<T, L, NKX, NOVY>(f, FY + ky + c + L, FY + ky - c + L, m, vx, vy, kk, cc);
         }
     }
 }
@@ -200,98 +272,69 @@ __device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, 
 // Rows where every source seen by this wavefront has floor(v_y) = FY: the
 // FIFO slot of every packet is known at compile time up to c'_1, which is
 // taken from its (short) range [clo, chi] in unrolled branches; floor(v_x)
-// and c'_1 may vary along the row.  Each packet class (level, sign, k_x) is
-// matched against its candidate sources: in a window where floor(v_x) and
-// c'_1 are uniform there is exactly one candidate per class.
-//  - x-lanes are taken in +-c pairs, and y-lanes summed over k_x before they
-//    meet the FIFO: in uniform and planar regions the mirrored terms cancel
-//    exactly (noise-free zero velocities keep floor(v) uniform);
-//  - a class with no matching candidate adds zero mass.
-template <typename T>
-__device__ __forceinline__ T prod_nc(T a, T b)
-{
-#pragma clang fp contract(off)
-    return a * b;
-}
-
+// and c'_1 may vary along the row.  Packets are taken per class (level, k_x,
+// floor(v_x) = F, speed C): the x-lane pair +-C of a class comes from the two
+// sources at x displacement k_x + F -+ C, and counts when that source has this
+// F and speed C on this level (zero mass otherwise).
 template <typename T, int L, int FY>
 __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<T, L>& f, int fxlo, int fxhi,
                                             int clo, int chi)
 {
-    const int nfx = fxhi - fxlo;  // extra candidates from floor(v_x) variation
+#pragma clang fp contract(off)
+    const int nfx = fxhi - fxlo;
 #pragma unroll
     for (int lev = 1; lev <= 2; ++lev) {
         const int cl = clo + lev - 1, ch = chi + lev - 1;
-        const int ncand = nfx + (ch - cl) + 1;
-        // x-lanes: destination row FY + ky; +c from a = kx + fx + c, -c from a = kx + fx - c
 #pragma unroll
         for (int kx = 0; kx < 2; ++kx) {
-            // the lane momenta m c' of the candidates are summed per (k_x, k_y)
-            // before they meet the FIFO, so a +c packet and its -c mirror found
-            // at different candidates still cancel exactly
-            T sx[2] = {(T)0, (T)0}, vxs[2] = {(T)0, (T)0};
-            for (int i = 0; i < ncand; ++i) {
-                const int ap = kx + fxlo + cl + i, am = kx + fxhi - cl - i;
-                const int sp = lane - ap, sm = lane - am;
-                const int pkp = R.pk[sp], pkm = R.pk[sm];
-                const int fxp = mfx(pkp), fxm = mfx(pkm);
-                const int cp = ap - kx - fxp, cm = kx + fxm - am;  // speed this source would need
-                const bool okp = cp == mc1(pkp) + lev - 1, okm = cm == mc1(pkm) + lev - 1;
-                const T rxp = R.rx[sp], ryp = R.ry[sp], rxm = R.rx[sm], rym = R.ry[sm];
-                const T dp = lev == 1 ? R.d1[sp] : R.d2[sp];
-                const T dm = lev == 1 ? R.d1[sm] : R.d2[sm];
-                const T bp = okp ? (kx ? rxp : (T)1 - rxp) * dp : (T)0;
-                const T bm = okm ? (kx ? rxm : (T)1 - rxm) * dm : (T)0;
-                const T ccp = (T)cp, ccm = (T)cm;
-                const T vxp = (T)fxp + rxp, vxm = (T)fxm + rxm, vyp = (T)FY + ryp, vym = (T)FY + rym;
-                const T zp = R.K[sp] + (T)0.5 * ccp * ccp + ccp * vxp;
-                const T zm = R.K[sm] + (T)0.5 * ccm * ccm - ccm * vxm;
+            for (int i = 0; i <= nfx; ++i) {
+                const int F = fxlo + i;
+                for (int C = cl; C <= ch; ++C) {
+                    const int sp = lane - (kx + F + C), sm = lane - (kx + F - C);
+                    const int pkp = R.pk[sp], pkm = R.pk[sm];
+                    const bool okp = mfx(pkp) == F && mc1(pkp) + lev - 1 == C;
+                    const bool okm = mfx(pkm) == F && mc1(pkm) + lev - 1 == C;
+                    const T rxp = R.rx[sp], ryp = R.ry[sp], rxm = R.rx[sm], rym = R.ry[sm];
+                    const T dp = lev == 1 ? R.d1[sp] : R.d2[sp];
+                    const T dm = lev == 1 ? R.d1[sm] : R.d2[sm];
+                    const T bp = (kx ? rxp : (T)1 - rxp) * (okp ? dp : (T)0);
+                    const T bm = (kx ? rxm : (T)1 - rxm) * (okm ? dm : (T)0);
+                    const T cc = (T)C, hc2 = (T)(0.5 * C * C);
+                    const T vxp = (T)F + rxp, vxm = (T)F + rxm, vyp = (T)FY + ryp, vym = (T)FY + rym;
+                    const T zp = fmaT(cc, vxp, R.K[sp] + hc2), zm = fmaT(-cc, vxm, R.K[sm] + hc2);
 #pragma unroll
-                for (int ky = 0; ky < 2; ++ky) {
-                    const int o = FY + ky + L;
-                    const T mp = bp * (ky ? ryp : (T)1 - ryp), mm = bm * (ky ? rym : (T)1 - rym);
-                    f.a[o][kR] += mp + mm;
-                    vxs[ky] += mp * vxp + mm * vxm;
-                    sx[ky] += prod_nc(mp, ccp) - prod_nc(mm, ccm);
-                    f.a[o][kPyv] += mp * vyp + mm * vym;
-                    f.a[o][kE] += mp * zp + mm * zm;
+                    for (int ky = 0; ky < 2; ++ky) {
+                        const T mp = bp * (ky ? ryp : (T)1 - ryp), mm = bm * (ky ? rym : (T)1 - rym);
+                        add_xpair<T, L, false>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm);
+                    }
                 }
             }
-#pragma unroll
-            for (int ky = 0; ky < 2; ++ky) f.a[FY + ky + L][kPx] += vxs[ky] + sx[ky];
         }
-        // y-lanes: a = fx + kx; kx = 0 and kx = 1 candidates taken together
+        // y-lanes: the corners k_x = 0, 1 of floor(v_x) = F sit at x
+        // displacement F and F + 1
         for (int i = 0; i <= nfx; ++i) {
-            const int a0 = fxlo + i, a1 = fxlo + 1 + i;
-            const int s0 = lane - a0, s1 = lane - a1;
+            const int F = fxlo + i;
+            const int s0 = lane - F, s1 = lane - F - 1;
             const int pk0 = R.pk[s0], pk1 = R.pk[s1];
-            const bool ok0 = mfx(pk0) == a0, ok1 = mfx(pk1) + 1 == a1;
+            const bool ok0 = mfx(pk0) == F, ok1 = mfx(pk1) == F;
             const int c0 = mc1(pk0) + lev - 1, c1 = mc1(pk1) + lev - 1;
-            const T rx0 = R.rx[s0], ry0 = R.ry[s0], rx1 = R.rx[s1], ry1 = R.ry[s1];
-            const T b0 = ok0 ? ((T)1 - rx0) * (lev == 1 ? R.d1[s0] : R.d2[s0]) : (T)0;
-            const T b1 = ok1 ? rx1 * (lev == 1 ? R.d1[s1] : R.d2[s1]) : (T)0;
-            const T vx0 = (T)mfx(pk0) + rx0, vx1 = (T)mfx(pk1) + rx1;
-            const T vy0 = (T)FY + ry0, vy1 = (T)FY + ry1;
-            const T K0 = R.K[s0], K1 = R.K[s1];
+            const T rx0 = R.rx[s0], rx1 = R.rx[s1];
+            const T ry[2] = {R.ry[s0], R.ry[s1]};
+            const T b0 = ((T)1 - rx0) * (ok0 ? (lev == 1 ? R.d1[s0] : R.d2[s0]) : (T)0);
+            const T b1 = rx1 * (ok1 ? (lev == 1 ? R.d1[s1] : R.d2[s1]) : (T)0);
+            const T vx[2] = {(T)F + rx0, (T)F + rx1};
+            const T vy[2] = {(T)FY + ry[0], (T)FY + ry[1]};
 #pragma unroll
             for (int C = 0; C <= 3 + 1; ++C) {  // speed of this level, static
                 if (C < cl || C > ch) continue;
+                if (FY + 1 + C > L || FY - C < -L) continue;  // out of the FIFO: redone / reported
                 const T w0 = c0 == C ? b0 : (T)0, w1 = c1 == C ? b1 : (T)0;
                 const T cc = (T)C, hc2 = (T)(0.5 * C * C);
+                const T kk[2] = {R.K[s0] + hc2, R.K[s1] + hc2};
 #pragma unroll
                 for (int ky = 0; ky < 2; ++ky) {
-                    const T m0 = w0 * (ky ? ry0 : (T)1 - ry0), m1 = w1 * (ky ? ry1 : (T)1 - ry1);
-                    const T gm = (m0 + m1) * cc;
-#pragma unroll
-                    for (int sg = -1; sg <= 1; sg += 2) {
-                        const int o = FY + ky + sg * C + L;
-                        if (o < 0 || o > 2 * L) continue;  // out of the FIFO: the step is redone / reported
-                        f.a[o][kR] += m0 + m1;
-                        f.a[o][kPx] += m0 * vx0 + m1 * vx1;
-                        f.a[o][kPyv] += m0 * vy0 + m1 * vy1;
-                        dd_add<T>(f.a[o][kGh], f.a[o][kGl], sg > 0 ? gm : -gm);
-                        f.a[o][kE] += m0 * (K0 + hc2 + (T)sg * cc * vy0) + m1 * (K1 + hc2 + (T)sg * cc * vy1);
-                    }
+                    const T m[2] = {w0 * (ky ? ry[0] : (T)1 - ry[0]), w1 * (ky ? ry[1] : (T)1 - ry[1])};
+                    add_ylanes<T, L, 2, false>(f, FY + ky + C + L, FY + ky - C + L, m, vx, vy, kk, cc);
                 }
             }
         }
@@ -450,30 +493,33 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
         if (L < kLFull && !fits_y) yfar = 1;
         const bool rows_ok = fits_x && fits_y && w.fymin == w.fymax && (w.fymin == 0 || w.fymin == -1) &&
                              w.c1max <= 3 && w.fxmax - w.fxmin <= 2;
-        const bool uni = rows_ok && w.fxmin == w.fxmax && w.c1min == w.c1max;
         if (dest && (fits_y || L == kLFull)) {
-            const bool mix2 = rows_ok && !uni && w.fxmin == w.fxmax && w.c1max == w.c1min + 1;
-            if (uni || mix2) {
+            // two adjacent values of c'_1 and/or of floor(v_x) keep compile-time offsets
+            const bool cmix = w.c1max == w.c1min + 1, xmix = w.fxmax == w.fxmin + 1;
+            const bool fastw = rows_ok && (w.c1max == w.c1min || cmix) && (w.fxmax == w.fxmin || xmix) &&
+                               !(cmix && xmix) && (!cmix || w.c1min <= 2) && (!xmix || w.c1min <= 1);
+            if (fastw) {
                 const MRow<T>& R = s_row[b];
-                const int fx0 = w.fxmin;
-                const int sel = (w.fymin == 0 ? (w.ry0 ? 0 : 1) : 2) * 8 + (mix2 ? 4 : 0) + w.c1min;
+                const int fx0 = w.fxmax;
+                const int sel = ((w.fymin == 0 ? (w.ry0 ? 0 : 1) : 2) * 2 + (xmix ? 1 : 0)) * 8 +
+                                (cmix ? 4 : 0) + w.c1min;
                 switch (sel) {
-#define LB_FAST(S, FYV, S0, NSP, RY)                                                   \
-    case S:                                                                            \
-        if ((FYV) - (S0) - (NSP) + 1 >= -L && (FYV) + 1 + (S0) + (NSP) - 1 <= L)       \
-            gather_fast<T, L, FYV, S0, NSP, RY>(R, tid, fx0, f);                       \
+#define LB_FAST(S, FYV, S0, NSP, NKX, RY)                                                   \
+    case S:                                                                                 \
+        if ((FYV) - (S0) - (NSP) + 1 >= -L && (FYV) + 1 + (S0) + (NSP) - 1 <= L)            \
+            gather_fast<T, L, FYV, S0, NSP, NKX, RY>(R, tid, fx0, f);                       \
         break;
-                    LB_FAST(0, 0, 0, 2, true) LB_FAST(1, 0, 1, 2, true) LB_FAST(2, 0, 2, 2, true)
-                    LB_FAST(3, 0, 3, 2, true) LB_FAST(4, 0, 0, 3, true) LB_FAST(5, 0, 1, 3, true)
-                    LB_FAST(6, 0, 2, 3, true)
-                    LB_FAST(8, 0, 0, 2, false) LB_FAST(9, 0, 1, 2, false) LB_FAST(10, 0, 2, 2, false)
-                    LB_FAST(11, 0, 3, 2, false) LB_FAST(12, 0, 0, 3, false) LB_FAST(13, 0, 1, 3, false)
-                    LB_FAST(14, 0, 2, 3, false)
-                    LB_FAST(16, -1, 0, 2, false) LB_FAST(17, -1, 1, 2, false) LB_FAST(18, -1, 2, 2, false)
-                    LB_FAST(19, -1, 3, 2, false) LB_FAST(20, -1, 0, 3, false) LB_FAST(21, -1, 1, 3, false)
-                    LB_FAST(22, -1, 2, 3, false)
+#define LB_FAST_SET(B, FYV, RY)                                                              \
+    LB_FAST(B + 0, FYV, 0, 2, 2, RY) LB_FAST(B + 1, FYV, 1, 2, 2, RY) LB_FAST(B + 2, FYV, 2, 2, 2, RY) \
+    LB_FAST(B + 3, FYV, 3, 2, 2, RY) LB_FAST(B + 4, FYV, 0, 3, 2, RY) LB_FAST(B + 5, FYV, 1, 3, 2, RY) \
+    LB_FAST(B + 6, FYV, 2, 3, 2, RY)                                                        \
+    LB_FAST(B + 8, FYV, 0, 2, 3, RY) LB_FAST(B + 9, FYV, 1, 2, 3, RY)
+                    LB_FAST_SET(0, 0, true)
+                    LB_FAST_SET(16, 0, false)
+                    LB_FAST_SET(32, -1, false)
+#undef LB_FAST_SET
 #undef LB_FAST
-                    default: break;
+                    default: break;  // not reached: fastw admits only the cases above
                 }
             } else if (rows_ok) {
                 if (w.fymin == 0)
