@@ -95,52 +95,60 @@ __device__ __forceinline__ Levels<T> node_levels(T rho, T v2, T E, T d0, const C
 template <typename T>
 __device__ __forceinline__ bool finite_val(T x) { return isfinite(x); }
 
+// Per-node primitives, level speeds, weights and interpolation split of one
+// source (eq. 15, 24-26, 28-29).  They are computed in FP64 whatever the
+// storage type T: in FP32 storage the per-node energy bookkeeping (E -> e, A,
+// the d_1 / d_2 split near a switch of c'_1) is where FP32 arithmetic would
+// lose the most, and FP64 costs the same VALU issue rate on this chip.  The
+// staged results are rounded to T.
 template <typename T>
-__device__ __forceinline__ Src1<T> make_src1(T m0, T m1, T m2, const Consts& k)
+__device__ __forceinline__ Src1<T> make_src1(T m0t, T m1t, T m2t, const Consts& k)
 {
+    const double m0 = m0t, m1 = m1t, m2 = m2t;
     Src1<T> s;
-    s.bad = !(m0 > (T)0) || !finite_val(m0) || !finite_val(m1) || !finite_val(m2);
-    if (s.bad || !(m0 > (T)0)) {
+    s.bad = !(m0 > 0.0) || !finite_val(m0) || !finite_val(m1) || !finite_val(m2);
+    if (s.bad) {
         s.f = 0; s.c1 = 0;
         s.r = (T)0; s.d0 = (T)0; s.d1 = (T)0; s.d2 = (T)0; s.K = (T)0;
         return s;
     }
-    T v, E, v2, d0;
+    double v, E, v2, d0;
     {
 #pragma clang fp contract(off)
         v = m1 / m0;
         E = m2 / m0;
         v2 = v * v;
-        d0 = (T)k.delta0 * m0;
+        d0 = k.delta0 * m0;
     }
-    Levels<T> L = node_levels<T>(m0, v2, E, d0, k);
-    T fv = dev_floor<T>(v);
+    Levels<double> L = node_levels<double>(m0, v2, E, d0, k);
+    const double fv = floor(v);
     s.f = (int)fv;
-    s.r = v - fv;
+    s.r = (T)(v - fv);
     s.c1 = L.c1;
-    const T c1s = (T)(L.c1 * L.c1);
-    const T w0 = (L.A - c1s) / (T)(2 * L.c1 + 1);
-    const T w = w0 < (T)0 ? (T)0 : (w0 > (T)1 ? (T)1 : w0);
-    const T per = L.rest * (T)k.inv_b1;
-    s.d2 = per * w;
-    s.d1 = per - s.d2;
-    s.d0 = d0;
-    const T phi = (T)k.phi_coef * L.e;
-    s.K = (T)0.5 * v2 + phi;
+    const double c1s = (double)(L.c1 * L.c1);
+    const double w0 = (L.A - c1s) / (double)(2 * L.c1 + 1);
+    const double w = w0 < 0.0 ? 0.0 : (w0 > 1.0 ? 1.0 : w0);
+    const double per = L.rest * k.inv_b1;
+    const double d2 = per * w;
+    s.d2 = (T)d2;
+    s.d1 = (T)(per - d2);
+    s.d0 = (T)d0;
+    s.K = (T)(0.5 * v2 + k.phi_coef * L.e);
     return s;
 }
 
 template <typename T>
-__device__ __forceinline__ Src2<T> make_src2(T m0, T m1, T m2, T m3, const Consts& k)
+__device__ __forceinline__ Src2<T> make_src2(T m0t, T m1t, T m2t, T m3t, const Consts& k)
 {
+    const double m0 = m0t, m1 = m1t, m2 = m2t, m3 = m3t;
     Src2<T> s;
-    s.bad = !(m0 > (T)0) || !finite_val(m0) || !finite_val(m1) || !finite_val(m2) || !finite_val(m3);
+    s.bad = !(m0 > 0.0) || !finite_val(m0) || !finite_val(m1) || !finite_val(m2) || !finite_val(m3);
     if (s.bad) {
         s.fx = 0; s.fy = 0; s.c1 = 0;
         s.rx = (T)0; s.ry = (T)0; s.d1 = (T)0; s.d2 = (T)0; s.K = (T)0;
         return s;
     }
-    T vx, vy, E, v2;
+    double vx, vy, E, v2;
     {
 #pragma clang fp contract(off)
         vx = m1 / m0;
@@ -148,21 +156,21 @@ __device__ __forceinline__ Src2<T> make_src2(T m0, T m1, T m2, T m3, const Const
         E = m3 / m0;
         v2 = vx * vx + vy * vy;
     }
-    Levels<T> L = node_levels<T>(m0, v2, E, (T)0, k);
-    const T fvx = dev_floor<T>(vx), fvy = dev_floor<T>(vy);
+    Levels<double> L = node_levels<double>(m0, v2, E, 0.0, k);
+    const double fvx = floor(vx), fvy = floor(vy);
     s.fx = (int)fvx;
     s.fy = (int)fvy;
-    s.rx = vx - fvx;
-    s.ry = vy - fvy;
+    s.rx = (T)(vx - fvx);
+    s.ry = (T)(vy - fvy);
     s.c1 = L.c1;
-    const T c1s = (T)(L.c1 * L.c1);
-    const T w0 = (L.A - c1s) / (T)(2 * L.c1 + 1);
-    const T w = w0 < (T)0 ? (T)0 : (w0 > (T)1 ? (T)1 : w0);
-    const T per = L.rest * (T)k.inv_b1;
-    s.d2 = per * w;
-    s.d1 = per - s.d2;
-    const T phi = (T)k.phi_coef * L.e;
-    s.K = (T)0.5 * v2 + phi;
+    const double c1s = (double)(L.c1 * L.c1);
+    const double w0 = (L.A - c1s) / (double)(2 * L.c1 + 1);
+    const double w = w0 < 0.0 ? 0.0 : (w0 > 1.0 ? 1.0 : w0);
+    const double per = L.rest * k.inv_b1;
+    const double d2 = per * w;
+    s.d2 = (T)d2;
+    s.d1 = (T)(per - d2);
+    s.K = (T)(0.5 * v2 + k.phi_coef * L.e);
     return s;
 }
 

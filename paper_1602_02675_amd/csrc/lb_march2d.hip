@@ -89,6 +89,12 @@ __device__ __forceinline__ WaveInfo merge(const WaveInfo& a, const WaveInfo& b)
                     a.ry0 & b.ry0, 0};
 }
 
+// Accumulator type of the FIFO for storage type T.  FP32 storage keeps FP32
+// accumulators: with the per-node primitives in FP64, FP64 accumulators did
+// not lower the FP32 form's error against FP64 on the seeded planar tubes.
+template <typename T>
+using Acc = T;
+
 template <typename T, int L>
 struct Fifo {
     static constexpr int NS = 2 * L + 1;
@@ -99,27 +105,27 @@ struct Fifo {
 // wavefront-uniform range [lo, hi]: each slot in range takes a select, so the
 // FIFO keeps compile-time indices (registers).  Slots out of range occur only
 // with reach > H (reported).
-template <typename T, int L>
-__device__ __forceinline__ void fifo_add_sel(Fifo<T, L>& f, int slot, int lo, int hi, T r, T px, T pyv, T e)
+template <typename A, typename T, int L>
+__device__ __forceinline__ void fifo_add_sel(Fifo<A, L>& f, int slot, int lo, int hi, T r, T px, T pyv, T e)
 {
 #pragma unroll
     for (int o = 0; o < 2 * L + 1; ++o) {
         if (o < lo || o > hi) continue;
         const bool h = slot == o;
-        f.a[o][kR] += h ? r : (T)0;
-        f.a[o][kPx] += h ? px : (T)0;
-        f.a[o][kPyv] += h ? pyv : (T)0;
-        f.a[o][kE] += h ? e : (T)0;
+        f.a[o][kR] += (A)(h ? r : (T)0);
+        f.a[o][kPx] += (A)(h ? px : (T)0);
+        f.a[o][kPyv] += (A)(h ? pyv : (T)0);
+        f.a[o][kE] += (A)(h ? e : (T)0);
     }
 }
 
-template <typename T, int L>
-__device__ __forceinline__ void fifo_add_g(Fifo<T, L>& f, int slot, int lo, int hi, T v)
+template <typename A, typename T, int L>
+__device__ __forceinline__ void fifo_add_g(Fifo<A, L>& f, int slot, int lo, int hi, T v)
 {
 #pragma unroll
     for (int o = 0; o < 2 * L + 1; ++o) {
         if (o < lo || o > hi) continue;
-        dd_add<T>(f.a[o][kGh], f.a[o][kGl], slot == o ? v : (T)0);
+        dd_add<A>(f.a[o][kGh], f.a[o][kGl], (A)(slot == o ? v : (T)0));
     }
 }
 
@@ -148,21 +154,21 @@ __device__ __forceinline__ double fmaT<double>(double a, double b, double c)
 // One +-c pair of x-lane packets: masses mp (+c) and mm (-c) into slot o.
 // The pair's momentum m c' enters as (mp - mm) c, exactly zero for mirrored
 // packets of equal mass.
-template <typename T, int L, bool NOVY>
-__device__ __forceinline__ void add_xpair(Fifo<T, L>& f, int o, T mp, T mm, T vxp, T vxm, T vyp, T vym, T cc,
+template <typename A, typename T, int L, bool NOVY>
+__device__ __forceinline__ void add_xpair(Fifo<A, L>& f, int o, T mp, T mm, T vxp, T vxm, T vyp, T vym, T cc,
                                           T zp, T zm)
 {
 #pragma clang fp contract(off)
-    f.a[o][kR] += mp + mm;
-    f.a[o][kPx] += fmaT(mp - mm, cc, fmaT(mp, vxp, mm * vxm));
-    if (!NOVY) f.a[o][kPyv] += fmaT(mp, vyp, mm * vym);
-    f.a[o][kE] += fmaT(mp, zp, mm * zm);
+    f.a[o][kR] += (A)(mp + mm);
+    f.a[o][kPx] += (A)fmaT(mp - mm, cc, fmaT(mp, vxp, mm * vxm));
+    if (!NOVY) f.a[o][kPyv] += (A)fmaT(mp, vyp, mm * vym);
+    f.a[o][kE] += (A)fmaT(mp, zp, mm * zm);
 }
 
 // The +-c y-lane packets of NQ x-corner sources (masses m[q], kk = K + c^2/2)
 // into slots op (+c) and om (-c); summed over the corners first, in order.
-template <typename T, int L, int NQ, bool NOVY>
-__device__ __forceinline__ void add_ylanes(Fifo<T, L>& f, int op, int om, const T (&m)[NQ], const T (&vx)[NQ],
+template <typename A, typename T, int L, int NQ, bool NOVY>
+__device__ __forceinline__ void add_ylanes(Fifo<A, L>& f, int op, int om, const T (&m)[NQ], const T (&vx)[NQ],
                                            const T (&vy)[NQ], const T (&kk)[NQ], T cc)
 {
 #pragma clang fp contract(off)
@@ -188,11 +194,11 @@ __device__ __forceinline__ void add_ylanes(Fifo<T, L>& f, int op, int om, const 
 #pragma unroll
             for (int q = 1; q < NQ; ++q) pe = fmaT(m[q], fmaT(scc, vy[q], kk[q]), pe);
         }
-        f.a[o][kR] += msum;
-        f.a[o][kPx] += pr;
-        if (!NOVY) f.a[o][kPyv] += py;
-        dd_add<T>(f.a[o][kGh], f.a[o][kGl], sg > 0 ? gm : -gm);
-        f.a[o][kE] += pe;
+        f.a[o][kR] += (A)msum;
+        f.a[o][kPx] += (A)pr;
+        if (!NOVY) f.a[o][kPyv] += (A)py;
+        dd_add<A>(f.a[o][kGh], f.a[o][kGl], (A)(sg > 0 ? gm : -gm));
+        f.a[o][kE] += (A)pe;
     }
 }
 
@@ -207,7 +213,7 @@ __device__ __forceinline__ void add_ylanes(Fifo<T, L>& f, int op, int om, const 
 // and are skipped; with FY = 0 also v_y = 0 and the m v_y terms vanish.  The
 // sums are the same, term for term.
 template <typename T, int L, int FY, int S0, int NSP, int NKX, bool RY0>
-__device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, Fifo<T, L>& f)
+__device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, Fifo<Acc<T>, L>& f)
 {
 #pragma clang fp contract(off)
     constexpr bool UNI = NSP == 2;
@@ -244,7 +250,7 @@ __device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, 
             for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
                 const T mp = RY0 ? bp : bp * (ky ? ryp : (T)1 - ryp);
                 const T mm = RY0 ? bm : bm * (ky ? rym : (T)1 - rym);
-                add_xpair<T, L, NOVY>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm);
+                add_xpair<Acc<T>, T, L, NOVY>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm);
             }
         }
         // y-lanes: source columns base - kx
@@ -264,7 +270,7 @@ __device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, 
             T m[NKX];
 #pragma unroll
             for (int q = 0; q < NKX; ++q) m[q] = RY0 ? b[q] : b[q] * (ky ? ry[q] : (T)1 - ry[q]);
-            add_ylanes<T, L, NKX, NOVY>(f, FY + ky + c + L, FY + ky - c + L, m, vx, vy, kk, cc);
+            add_ylanes<Acc<T>, T, L, NKX, NOVY>(f, FY + ky + c + L, FY + ky - c + L, m, vx, vy, kk, cc);
         }
     }
 }
@@ -277,7 +283,7 @@ __device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, 
 // sources at x displacement k_x + F -+ C, and counts when that source has this
 // F and speed C on this level (zero mass otherwise).
 template <typename T, int L, int FY>
-__device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<T, L>& f, int fxlo, int fxhi,
+__device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, int fxlo, int fxhi,
                                             int clo, int chi)
 {
 #pragma clang fp contract(off)
@@ -305,7 +311,7 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<T, 
 #pragma unroll
                     for (int ky = 0; ky < 2; ++ky) {
                         const T mp = bp * (ky ? ryp : (T)1 - ryp), mm = bm * (ky ? rym : (T)1 - rym);
-                        add_xpair<T, L, false>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm);
+                        add_xpair<Acc<T>, T, L, false>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm);
                     }
                 }
             }
@@ -334,7 +340,7 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<T, 
 #pragma unroll
                 for (int ky = 0; ky < 2; ++ky) {
                     const T m[2] = {w0 * (ky ? ry[0] : (T)1 - ry[0]), w1 * (ky ? ry[1] : (T)1 - ry[1])};
-                    add_ylanes<T, L, 2, false>(f, FY + ky + C + L, FY + ky - C + L, m, vx, vy, kk, cc);
+                    add_ylanes<Acc<T>, T, L, 2, false>(f, FY + ky + C + L, FY + ky - C + L, m, vx, vy, kk, cc);
                 }
             }
         }
@@ -347,7 +353,7 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<T, 
 // [xlo, xhi] / [ylo, yhi] bound the FIFO slots x- / y-lane packets of the
 // wavefront's sources can reach.
 template <typename T, int L>
-__device__ void gather_general(const MRow<T>& R, int lane, Fifo<T, L>& f, int xlo, int xhi, int ylo, int yhi)
+__device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, int xlo, int xhi, int ylo, int yhi)
 {
 #pragma unroll 1
     for (int a = -kMH; a <= kMH; ++a) {
@@ -370,7 +376,7 @@ __device__ void gather_general(const MRow<T>& R, int lane, Fifo<T, L>& f, int xl
 #pragma unroll 1
                 for (int ky = 0; ky < 2; ++ky) {
                     const T m = w * (ky ? ry : (T)1 - ry);
-                    fifo_add_sel<T, L>(f, fy + ky + L, xlo, xhi, m, m * (vx + cc), m * vy, m * zx);
+                    fifo_add_sel<Acc<T>, T, L>(f, fy + ky + L, xlo, xhi, m, m * (vx + cc), m * vy, m * zx);
                 }
             }
             if (cx == 0) {  // y-lanes move in x by fx + kx only
@@ -386,8 +392,8 @@ __device__ void gather_general(const MRow<T>& R, int lane, Fifo<T, L>& f, int xl
                         for (int ky = 0; ky < 2; ++ky) {
                             const T m = axw * (ky ? ry : (T)1 - ry) * d;
                             const int slot = fy + ky + sg * c + L;
-                            fifo_add_sel<T, L>(f, slot, ylo, yhi, m, m * vx, m * vy, m * zy);
-                            fifo_add_g<T, L>(f, slot, ylo, yhi, m * cc);
+                            fifo_add_sel<Acc<T>, T, L>(f, slot, ylo, yhi, m, m * vx, m * vy, m * zy);
+                            fifo_add_g<Acc<T>, T, L>(f, slot, ylo, yhi, m * cc);
                         }
                     }
                 }
@@ -434,11 +440,12 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
     const int nrows = Y0 < ny ? (int)(ylast - Y0) + 2 * L : 0;
     constexpr int NS = 2 * L + 1;
 
-    Fifo<T, L> f;
+    using A = Acc<T>;
+    Fifo<A, L> f;
 #pragma unroll
     for (int o = 0; o < NS; ++o)
 #pragma unroll
-        for (int c = 0; c < kNV; ++c) f.a[o][c] = (T)0;
+        for (int c = 0; c < kNV; ++c) f.a[o][c] = (A)0;
     double tot[4] = {0.0, 0.0, 0.0, 0.0};
     int reach = 0, bad = 0, yfar = 0;
 
@@ -494,7 +501,9 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
         const bool rows_ok = fits_x && fits_y && w.fymin == w.fymax && (w.fymin == 0 || w.fymin == -1) &&
                              w.c1max <= 3 && w.fxmax - w.fxmin <= 2;
         if (dest && (fits_y || L == kLFull)) {
-            // two adjacent values of c'_1 and/or of floor(v_x) keep compile-time offsets
+            // two adjacent values of c'_1 or of floor(v_x) keep compile-time
+            // offsets; a window mixing both (rare in planar flows) takes the
+            // row path, whose extra registers would otherwise cost occupancy
             const bool cmix = w.c1max == w.c1min + 1, xmix = w.fxmax == w.fxmin + 1;
             const bool fastw = rows_ok && (w.c1max == w.c1min || cmix) && (w.fxmax == w.fxmin || xmix) &&
                                !(cmix && xmix) && (!cmix || w.c1min <= 2) && (!xmix || w.c1min <= 1);
@@ -506,7 +515,7 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
                 switch (sel) {
 #define LB_FAST(S, FYV, S0, NSP, NKX, RY)                                                   \
     case S:                                                                                 \
-        if ((FYV) - (S0) - (NSP) + 1 >= -L && (FYV) + 1 + (S0) + (NSP) - 1 <= L)            \
+        if constexpr ((FYV) - (S0) - (NSP) + 1 >= -L && (FYV) + 1 + (S0) + (NSP) - 1 <= L)  \
             gather_fast<T, L, FYV, S0, NSP, NKX, RY>(R, tid, fx0, f);                       \
         break;
 #define LB_FAST_SET(B, FYV, RY)                                                              \
@@ -535,11 +544,11 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
         if (r >= 2 * L && dest) {
             const int64_t ty = Y0 + r - 2 * L;
             const int64_t q = ty * nx + gx;
-            const T py = f.a[0][kPyv] + (f.a[0][kGh] + f.a[0][kGl]);
-            Yn[q] = f.a[0][kR];
-            Yn[nn + q] = f.a[0][kPx];
+            const T py = (T)(f.a[0][kPyv] + (f.a[0][kGh] + f.a[0][kGl]));
+            Yn[q] = (T)f.a[0][kR];
+            Yn[nn + q] = (T)f.a[0][kPx];
             Yn[2 * nn + q] = py;
-            Yn[3 * nn + q] = f.a[0][kE];
+            Yn[3 * nn + q] = (T)f.a[0][kE];
             tot[0] += (double)f.a[0][kR];
             tot[1] += (double)f.a[0][kPx];
             tot[2] += (double)py;
@@ -550,7 +559,7 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
 #pragma unroll
             for (int c = 0; c < kNV; ++c) f.a[o][c] = f.a[o + 1][c];
 #pragma unroll
-        for (int c = 0; c < kNV; ++c) f.a[NS - 1][c] = (T)0;
+        for (int c = 0; c < kNV; ++c) f.a[NS - 1][c] = (A)0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) cur[c] = nxt[c];
     }

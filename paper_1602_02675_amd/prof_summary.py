@@ -87,6 +87,9 @@ def main():
     _, kw = _pick(write, args.kernel)
     _, cf = _pick(fetch, args.copy_kernel)
     _, cw = _pick(write, args.copy_kernel)
+    # the calibration copies are the three largest copy dispatches (1 GiB
+    # each); smaller copies of the run (staging, exports) are not used
+    cf, cw = sorted(cf)[-3:], sorted(cw)[-3:]
     f_factor = (sum(cf) / len(cf)) * 1024.0 / COPY_BYTES
     w_factor = (sum(cw) / len(cw)) * 1024.0 / COPY_BYTES
     fetch_b = (sum(kf) / len(kf)) * 1024.0 / f_factor

@@ -325,3 +325,68 @@ def test_fp32_against_oracle(lbsd):
     got = s.moments()
     rel_l1 = np.sum(np.abs(got[0] - ref[0])) / np.sum(np.abs(ref[0]))
     assert rel_l1 <= 1e-5, rel_l1
+
+
+def _planar_random(seed, nx, ny, vel, e):
+    """A random 1-D profile repeated along y, v_y = 0: every row alike."""
+    Y1 = inputs.random_state(seed, 1, nx, vel=vel, e=e, smooth=4)
+    Y = np.zeros((4, ny, nx))
+    Y[0] = Y1[0]
+    Y[1] = Y1[1]
+    Y[3] = Y1[2]
+    return Y
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("fp32", 1e-5)])
+@pytest.mark.parametrize("seed", [31, 32, 33])
+def test_planar_mixed_windows(lbsd, prec, tol, seed):
+    """Planar states whose floor(v_x) straddles 0 and whose c'_1 straddles
+    1 (or 1 and 2): wavefront windows mixing two values of either or both,
+    which take the compile-time mixed paths or the row path.  Rows stay
+    bit-identical; fields match the oracle (FP64 1e-12, FP32 1e-5 normwise)."""
+    nx, ny = 700, 24
+    e = (0.6, 1.9) if seed != 33 else (3.5, 6.5)
+    Y = _planar_random(seed, nx, ny, vel=(-0.45, 0.45), e=e)
+    P = oracle.Problem(2, nx, 4, bc_y=oracle.TRANSMISSIVE)
+    ref, st, reach = oracle.run(P, oracle.to_lattice(P, Y[:, :4, :], 1.0), 8)
+    assert st == 0
+    ref = oracle.from_lattice(P, ref, 1.0)
+    s = lbsd.Solver(2, nx, ny, precision=prec)
+    s.init_moments(Y, 1.0)
+    fx, _, c1 = s.lanes()
+    assert set(np.unique(fx)) == {-1, 0} and len(np.unique(c1)) >= 2
+    s.step(8)
+    got = s.moments()
+    assert np.all(got == got[:, :1, :]), "planar rows must stay bit-identical"
+    assert normwise_err(got[:, :4, :], ref, 2) <= tol
+
+
+@pytest.mark.parametrize("seed", [0, 5])
+def test_fp32_planar_tube_against_oracle(lbsd, seed):
+    """FP32 square-lattice planar tube of the seeded family, 300 steps: relative
+    L1 density error against the FP64 oracle, rows bit-identical, and the
+    undisturbed ends still exactly uniform (no rounding noise created there)."""
+    nx, ny = 1200, 16
+    left, right, xd = inputs.riemann_instance(seed)
+    lam = inputs.cfl_lambda([left, right])
+    P = oracle.Problem(2, nx, 4, bc_y=oracle.TRANSMISSIVE)
+    Y0 = oracle.riemann_moments(P, inputs.node_x(nx), left, right, xd)
+    n = 300
+    ref, st, _ = oracle.run(P, oracle.to_lattice(P, Y0, lam), n)
+    assert st == 0
+    ref = oracle.from_lattice(P, ref, lam)
+    s = lbsd.Solver(2, nx, ny, precision="fp32")
+    s.init_riemann(xd, left, right, lam=lam)
+    # after 60 steps no packet from the diaphragm can have moved more than
+    # 60 * 5 nodes: beyond that both ends must still be uniform, bit for bit
+    s.step(60)
+    got = s.moments()
+    i_d = int(xd * nx)
+    for end in (slice(0, i_d - 310), slice(i_d + 310, nx)):
+        blk = got[:, :, end]
+        assert np.all(blk == blk[:, :1, :1]) and np.all(blk[1:3] == 0.0)
+    s.step(n - 60)
+    got = s.moments()
+    assert np.all(got == got[:, :1, :])
+    rel_l1 = np.sum(np.abs(got[0, :4] - ref[0])) / np.sum(np.abs(ref[0]))
+    assert rel_l1 <= 1e-5, rel_l1
