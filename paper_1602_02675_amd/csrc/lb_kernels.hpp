@@ -41,11 +41,7 @@ struct Grid {
 template <typename T>
 hipError_t launch_step1d(const T* Y, T* Yn, const Grid& g, const Consts& k, StepCtl* ctl,
                          double* partials, long long step, hipStream_t stream);
-template <typename T>
-hipError_t launch_step2d(const T* Y, T* Yn, const Grid& g, const Consts& k, StepCtl* ctl,
-                         double* partials, long long step, hipStream_t stream);
 int64_t step_blocks_1d(const Grid& g);
-int64_t step_blocks_2d(const Grid& g);
 
 // Square lattice, column-march kernel (lb_march2d.hip).  The launch
 // geometry (strip height, blocks) is chosen per device so that one wave of

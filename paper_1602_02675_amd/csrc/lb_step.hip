@@ -1,6 +1,7 @@
-// The tau = 1 step of the semi-discrete compressible LB method as one fused
-// gather kernel per step (1-D triple-level lattice and square dual-level
-// lattice of Komeili, Mirzaei, Shabouei, arXiv 1602.02675, Sec. III-V).
+// The tau = 1 step of the semi-discrete compressible LB method on the 1-D
+// triple-level lattice as one fused gather kernel per step (Komeili, Mirzaei,
+// Shabouei, arXiv 1602.02675, Sec. III-V), and the per-step reduction kernel
+// shared with the square lattice (whose step kernel is in lb_march2d.hip).
 //
 // With tau = 1 the distribution after a step is the migrated equilibrium
 // (eq. 10, eq. 30), and the equilibrium depends on the node moments only, so
@@ -17,13 +18,13 @@
 //      source that class maps onto it.  In a tile where floor(v) and c'_1 are
 //      the same for every staged source (the integer parts of the migration
 //      vectors are piecewise constant), each class has exactly one source at
-//      a compile-time offset, and the 10 (1-D) or 32 (2-D) packets are fully
-//      unrolled; otherwise every candidate displacement in the tile's range
-//      is tested against the source's own displacement;
+//      a compile-time offset, and the 10 packets are fully unrolled;
+//      otherwise every candidate displacement in the tile's range is tested
+//      against the source's own displacement;
 //   3. the interior sums of the new moments are reduced per block with
-//      wavefront shuffles, and the last block to finish adds the per-block
-//      partials in a fixed order (deterministic totals), along with the
-//      reach (halo overflow) and state checks.
+//      wavefront shuffles into one row of per-block partials; a one-block
+//      kernel then adds the rows in a fixed order (deterministic totals) and
+//      records the reach (halo overflow) and state checks.
 #include <climits>
 
 #include "lb_kernels.hpp"
@@ -317,211 +318,13 @@ step1d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
     finish_step<NW, 3>(acc, ti, partials, H);
 }
 
-// ------------------------------------------------------------------ 2-D ----
-
-template <typename T>
-struct Tile2 {
-    int* pk;
-    T *rx, *ry, *d1, *d2, *K;
-};
-
-// One packet of a square-lattice source s: corner (kx, ky), lane along axis
-// `ax` (0 = x, 1 = y) with signed speed c, level lev (d1 or d2).
-template <typename T>
-__device__ __forceinline__ void add_packet2(const Tile2<T>& tl, int s, int fx, int fy, int kx, int ky,
-                                            int ax, int c, int lev, T& R, T& Px, T& Py, T& En)
-{
-    const T rx = tl.rx[s], ry = tl.ry[s];
-    const T a = (kx ? rx : (T)1 - rx) * (ky ? ry : (T)1 - ry);
-    const T m = a * (lev == 1 ? tl.d1[s] : tl.d2[s]);
-    const T vx = (T)fx + rx, vy = (T)fy + ry;
-    const T cc = (T)c;
-    const T xix = ax == 0 ? vx + cc : vx;
-    const T xiy = ax == 1 ? vy + cc : vy;
-    const T zeta = tl.K[s] + cc * (ax == 0 ? vx : vy) + (T)0.5 * cc * cc;
-    R += m;
-    Px += m * xix;
-    Py += m * xiy;
-    En += m * zeta;
-}
-
-// Packet p in [0, 32): lane = p >> 2 (level 1 +x,-x,+y,-y then level 2), corner = p & 3.
-__device__ __forceinline__ constexpr int p2_lev(int p) { return (p >> 4) + 1; }
-__device__ __forceinline__ constexpr int p2_axis(int p) { return (p >> 3) & 1; }
-__device__ __forceinline__ constexpr int p2_sign(int p) { return ((p >> 2) & 1) ? -1 : 1; }
-__device__ __forceinline__ constexpr int p2_kx(int p) { return p & 1; }
-__device__ __forceinline__ constexpr int p2_ky(int p) { return (p >> 1) & 1; }
-
-template <typename T, int H, int TX, int TY, int J, int C1>
-__device__ __forceinline__ void gather2_uniform(const Tile2<T>& tl, int fx, int fy, int64_t x0,
-                                                int64_t y0, const Grid& g, T* __restrict__ Yn,
-                                                double (&acc)[4])
-{
-    constexpr int WX = TX + 2 * H;
-    const int lx = (int)threadIdx.x % TX, ly = (int)threadIdx.x / TX;
-    const int64_t nn = g.nx * g.ny;
-    const int base0 = (ly * J + H - fy) * WX + (lx + H - fx);
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int base = base0 + j * WX;
-        T R = 0, Px = 0, Py = 0, En = 0;
-#pragma unroll
-        for (int p = 0; p < 32; ++p) {
-            const int lev = p2_lev(p), ax = p2_axis(p), sg = p2_sign(p);
-            const int kx = p2_kx(p), ky = p2_ky(p);
-            const int c = sg * (C1 + lev - 1);
-            const int ox = kx + (ax == 0 ? c : 0), oy = ky + (ax == 1 ? c : 0);
-            add_packet2<T>(tl, base - (oy * WX + ox), fx, fy, kx, ky, ax, c, lev, R, Px, Py, En);
-        }
-        const int64_t x = x0 + lx, y = y0 + ly * J + j;
-        if (x < g.nx && y < g.ny) {
-            const int64_t q = y * g.nx + x;
-            Yn[q] = R;
-            Yn[nn + q] = Px;
-            Yn[2 * nn + q] = Py;
-            Yn[3 * nn + q] = En;
-            acc[0] += (double)R;
-            acc[1] += (double)Px;
-            acc[2] += (double)Py;
-            acc[3] += (double)En;
-        }
-    }
-}
-
-template <typename T, int H, int TX, int TY, int J>
-__device__ void gather2_general(const Tile2<T>& tl, const TileInfo& ti, int64_t x0, int64_t y0,
-                                const Grid& g, T* __restrict__ Yn, double (&acc)[4])
-{
-    constexpr int WX = TX + 2 * H;
-    const int lx = (int)threadIdx.x % TX, ly = (int)threadIdx.x / TX;
-    const int64_t nn = g.nx * g.ny;
-    for (int j = 0; j < J; ++j) {
-        const int wx = lx + H, wy = ly * J + j + H;
-        T R = 0, Px = 0, Py = 0, En = 0;
-        for (int p = 0; p < 32; ++p) {
-            const int lev = p2_lev(p), ax = p2_axis(p), sg = p2_sign(p);
-            const int kx = p2_kx(p), ky = p2_ky(p);
-            const int a = ti.cmin + lev - 1, b = ti.cmax + lev - 1;
-            const int clo = sg > 0 ? a : -b, chi = sg > 0 ? b : -a;
-            const int xlo = max(-H, ti.fxmin + kx + (ax == 0 ? clo : 0));
-            const int xhi = min(H, ti.fxmax + kx + (ax == 0 ? chi : 0));
-            const int ylo = max(-H, ti.fymin + ky + (ax == 1 ? clo : 0));
-            const int yhi = min(H, ti.fymax + ky + (ax == 1 ? chi : 0));
-            for (int dy = ylo; dy <= yhi; ++dy) {
-                for (int dx = xlo; dx <= xhi; ++dx) {
-                    const int s = (wy - dy) * WX + (wx - dx);
-                    const int pk = tl.pk[s];
-                    const int fxs = lane_fx(pk), fys = lane_fy(pk);
-                    const int cs = sg * (lane_c1(pk) + lev - 1);
-                    if (fxs + kx + (ax == 0 ? cs : 0) != dx) continue;
-                    if (fys + ky + (ax == 1 ? cs : 0) != dy) continue;
-                    add_packet2<T>(tl, s, fxs, fys, kx, ky, ax, cs, lev, R, Px, Py, En);
-                }
-            }
-        }
-        const int64_t x = x0 + lx, y = y0 + ly * J + j;
-        if (x < g.nx && y < g.ny) {
-            const int64_t q = y * g.nx + x;
-            Yn[q] = R;
-            Yn[nn + q] = Px;
-            Yn[2 * nn + q] = Py;
-            Yn[3 * nn + q] = En;
-            acc[0] += (double)R;
-            acc[1] += (double)Px;
-            acc[2] += (double)Py;
-            acc[3] += (double)En;
-        }
-    }
-}
-
-#ifndef LB_T2_WPE
-#define LB_T2_WPE 1
-#endif
-template <typename T, int H, int TX, int TY, int J>
-__global__ void __launch_bounds__(TX * TY / J) __attribute__((amdgpu_waves_per_eu(LB_T2_WPE)))
-step2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
-              StepCtl* __restrict__ ctl, double* __restrict__ partials, long long step)
-{
-    constexpr int TPB = TX * TY / J;
-    constexpr int NW = TPB / 64;
-    constexpr int WX = TX + 2 * H, WY = TY + 2 * H, W = WX * WY;
-    __shared__ int s_pk[W];
-    __shared__ T s_rx[W], s_ry[W], s_d1[W], s_d2[W], s_K[W];
-    __shared__ int s_red[NW][8];
-    if (ctl->err_step < step) return;
-
-    const int64_t nx = g.nx, ny = g.ny, nn = nx * ny;
-    const int64_t x0 = (int64_t)blockIdx.x * TX, y0 = (int64_t)blockIdx.y * TY;
-    TileInfo ti = {INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN, 0, 0};
-    constexpr int NS = (W + TPB - 1) / TPB;
-    T ld[NS][4];
-#pragma unroll
-    for (int u = 0; u < NS; ++u) {
-        const int i = (int)threadIdx.x + u * TPB;
-        if (i < W) {
-            const int wy = i / WX, wx = i - wy * WX;
-            const int64_t gx = x0 - H + wx, gy = y0 - H + wy;
-            const int64_t si = g.bc_x == kBcPeriodic ? wrap_near(gx, nx) : clamp_idx(gx, nx);
-            const int64_t sj = g.bc_y == kBcPeriodic ? wrap_near(gy, ny) : clamp_idx(gy, ny);
-            const int64_t q = sj * nx + si;
-            ld[u][0] = Y[q]; ld[u][1] = Y[nn + q]; ld[u][2] = Y[2 * nn + q]; ld[u][3] = Y[3 * nn + q];
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < NS; ++u) {
-        const int i = (int)threadIdx.x + u * TPB;
-        if (i >= W) break;
-        const Src2<T> s = make_src2<T>(ld[u][0], ld[u][1], ld[u][2], ld[u][3], k);
-        s_pk[i] = pack_lane(s.fx, s.fy, s.c1);
-        s_rx[i] = s.rx;
-        s_ry[i] = s.ry;
-        s_d1[i] = s.d1;
-        s_d2[i] = s.d2;
-        s_K[i] = s.K;
-        ti.fxmin = min(ti.fxmin, s.fx);
-        ti.fxmax = max(ti.fxmax, s.fx);
-        ti.fymin = min(ti.fymin, s.fy);
-        ti.fymax = max(ti.fymax, s.fy);
-        ti.cmin = min(ti.cmin, s.c1);
-        ti.cmax = max(ti.cmax, s.c1);
-        ti.reach = max(ti.reach, max(axis_reach(s.fx, s.c1), axis_reach(s.fy, s.c1)));
-        ti.bad |= s.bad ? 1 : 0;
-    }
-    ti = block_tile_info<NW>(ti, s_red);
-    const Tile2<T> tl = {s_pk, s_rx, s_ry, s_d1, s_d2, s_K};
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const bool uniform = ti.fxmin == ti.fxmax && ti.fymin == ti.fymax && ti.cmin == ti.cmax &&
-                         ti.reach <= H;
-    if (uniform && ti.cmin == 0)
-        gather2_uniform<T, H, TX, TY, J, 0>(tl, ti.fxmin, ti.fymin, x0, y0, g, Yn, acc);
-    else if (uniform && ti.cmin == 1)
-        gather2_uniform<T, H, TX, TY, J, 1>(tl, ti.fxmin, ti.fymin, x0, y0, g, Yn, acc);
-    else if (uniform && ti.cmin == 2)
-        gather2_uniform<T, H, TX, TY, J, 2>(tl, ti.fxmin, ti.fymin, x0, y0, g, Yn, acc);
-    else if (uniform && ti.cmin == 3)
-        gather2_uniform<T, H, TX, TY, J, 3>(tl, ti.fxmin, ti.fymin, x0, y0, g, Yn, acc);
-    else
-        gather2_general<T, H, TX, TY, J>(tl, ti, x0, y0, g, Yn, acc);
-    finish_step<NW, 4>(acc, ti, partials, H);
-}
-
 #ifndef LB_T1_TPB
 #define LB_T1_TPB 256
 #endif
 #ifndef LB_T1_J
 #define LB_T1_J 4
 #endif
-#ifndef LB_T2_TX
-#define LB_T2_TX 32
-#endif
-#ifndef LB_T2_TY
-#define LB_T2_TY 16
-#endif
-#ifndef LB_T2_J
-#define LB_T2_J 4
-#endif
 constexpr int k1TPB = LB_T1_TPB, k1J = LB_T1_J;
-constexpr int k2TX = LB_T2_TX, k2TY = LB_T2_TY, k2J = LB_T2_J;
 
 }  // namespace
 
@@ -531,27 +334,12 @@ int64_t step_blocks_1d(const Grid& g)
     return (g.nx + tile - 1) / tile;
 }
 
-int64_t step_blocks_2d(const Grid& g)
-{
-    return ((g.nx + k2TX - 1) / k2TX) * ((g.ny + k2TY - 1) / k2TY);
-}
-
 template <typename T>
 hipError_t launch_step1d(const T* Y, T* Yn, const Grid& g, const Consts& k, StepCtl* ctl,
                          double* partials, long long step, hipStream_t stream)
 {
     const dim3 grid((unsigned)step_blocks_1d(g));
     step1d_kernel<T, kHalo, k1TPB, k1J><<<grid, k1TPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_step2d(const T* Y, T* Yn, const Grid& g, const Consts& k, StepCtl* ctl,
-                         double* partials, long long step, hipStream_t stream)
-{
-    const dim3 grid((unsigned)((g.nx + k2TX - 1) / k2TX), (unsigned)((g.ny + k2TY - 1) / k2TY));
-    step2d_kernel<T, kHalo, k2TX, k2TY, k2J>
-        <<<grid, k2TX * k2TY / k2J, 0, stream>>>(Y, Yn, g, k, ctl, partials, step);
     return hipGetLastError();
 }
 
@@ -565,10 +353,6 @@ hipError_t launch_finalize(const double* partials, int64_t nb, StepCtl* ctl, lon
 template hipError_t launch_step1d<double>(const double*, double*, const Grid&, const Consts&,
                                           StepCtl*, double*, long long, hipStream_t);
 template hipError_t launch_step1d<float>(const float*, float*, const Grid&, const Consts&,
-                                         StepCtl*, double*, long long, hipStream_t);
-template hipError_t launch_step2d<double>(const double*, double*, const Grid&, const Consts&,
-                                          StepCtl*, double*, long long, hipStream_t);
-template hipError_t launch_step2d<float>(const float*, float*, const Grid&, const Consts&,
                                          StepCtl*, double*, long long, hipStream_t);
 
 }  // namespace lbsd
