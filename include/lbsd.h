@@ -151,6 +151,73 @@ int lb_debug_lanes(lb_solver* s, int32_t* floor_x, int32_t* floor_y, int32_t* c1
 void lb_destroy(lb_solver* s);
 const char* lb_last_error(void);
 
+/* ---- pools: many independent problems, one persistent launch per step ----
+ *
+ * The batching and serving forms.  A pool holds up to max_slots problems of one
+ * lattice, gamma and precision (each with its own grid, lambda, boundary
+ * conditions and step target) in an arena of arena_bytes inside the caller's
+ * device memory.  One pool step is one persistent kernel launch (plus, on the
+ * square lattice, a pass that redoes the tiles whose packets reached past the
+ * short FIFO, and a per-slot reduction kernel) over a tile table in device
+ * memory; every live, unfinished slot advances by one step (eq. 10 / 30 with
+ * tau = 1, as lb_step).  Admissions and releases rewrite the tables between
+ * launches, so the launch shape and a captured HIP graph stay valid while
+ * problems come and go.  A slot's results do not depend on what else is in
+ * the pool, the tile shape or graph use: they are bit-identical to an
+ * lb_solver run of the same problem.
+ *
+ * Slot status (lb_pool_poll): 0 running, 1 reached its step target, or
+ * LB_EREACH / LB_ESTATE if one of its steps failed (it then stops at its last
+ * good step; other slots go on).  Calls that synchronise: poll, moments,
+ * totals, release, set_shape, autotune, the admit calls. */
+typedef struct lb_pool lb_pool; /* opaque */
+
+/* max_slots in [1, 2^20]; arena_bytes: device memory for the slots' moment
+ * sets (lb_pool_footprint per slot). */
+int lb_pool_create(int32_t dim, double gamma, const lb_velset* velset, int32_t precision,
+                   int32_t max_slots, size_t arena_bytes, lb_pool** out);
+size_t lb_pool_bytes(const lb_pool* p);                   /* device bytes to bind (arena + tables) */
+size_t lb_pool_footprint(const lb_pool* p, int64_t nx, int64_t ny); /* arena bytes one problem takes */
+/* As lb_bind.  A non-default stream is required for lb_pool_use_graph. */
+int lb_pool_bind(lb_pool* p, void* dev_ptr, size_t bytes, void* hip_stream);
+
+/* Admit a Riemann problem (as lb_init_riemann; lambda <= 0 takes the CFL-1
+ * rule) that stops after `steps` steps.  *slot receives its slot.  LB_ENOMEM
+ * when no slot is free or its footprint does not fit the arena now. */
+int lb_pool_admit_riemann(lb_pool* p, const lb_grid* grid, double lambda, double x_diaphragm,
+                          const lb_prim* left, const lb_prim* right, int64_t steps, int32_t* slot);
+/* Admit a general state (as lb_init_moments). */
+int lb_pool_admit_moments(lb_pool* p, const lb_grid* grid, const double* host_Y, double lambda,
+                          int64_t steps, int32_t* slot);
+/* Free a slot and its arena space (waits for queued steps first). */
+int lb_pool_release(lb_pool* p, int32_t slot);
+
+/* Queue n >= 0 pool steps (async; graph launches when lb_pool_use_graph is on). */
+int lb_pool_advance(lb_pool* p, int64_t n);
+/* As lb_pool_advance, bracketed by HIP events on the bound stream; waits and
+ * writes the elapsed milliseconds to *ms (a graph is captured before timing). */
+int lb_pool_advance_timed(lb_pool* p, int64_t n, float* ms);
+
+int lb_pool_poll(lb_pool* p, int32_t slot, int64_t* steps_done, int32_t* status);
+/* As lb_moments / lb_totals for one slot (lb_pool_totals: LB_EINVAL before its first step). */
+int lb_pool_moments(lb_pool* p, int32_t slot, double* out, int32_t out_on_device);
+int lb_pool_totals(lb_pool* p, int32_t slot, double out[4]);
+double lb_pool_lambda(const lb_pool* p, int32_t slot);
+int32_t lb_pool_live(const lb_pool* p);                  /* admitted slots */
+
+/* Tile shapes: 1-D, threads x nodes per thread in {256x1, 256x2, 256x4,
+ * 256x8, 512x4}; square lattice, strip heights {16, 32, 64, 128, 256} rows of
+ * 246 columns.  lb_pool_autotune times `trials` steps of every shape on the
+ * admitted problems without changing their states, keeps the fastest and
+ * writes its index and median milliseconds per step. */
+int32_t lb_pool_shapes(const lb_pool* p);
+int32_t lb_pool_shape(const lb_pool* p);
+int lb_pool_set_shape(lb_pool* p, int32_t shape);
+int lb_pool_autotune(lb_pool* p, int32_t trials, int32_t* best, float* ms_per_step);
+/* Capture steps_per_graph pool steps as one HIP graph (0: plain launches). */
+int lb_pool_use_graph(lb_pool* p, int32_t steps_per_graph);
+void lb_pool_destroy(lb_pool* p);
+
 #ifdef __cplusplus
 }
 #endif

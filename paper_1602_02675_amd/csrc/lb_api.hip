@@ -10,16 +10,14 @@
 #include <string>
 #include <vector>
 
-#include "lb_kernels.hpp"
-#include "lbsd.h"
+#include "lb_host.hpp"
 
 using namespace lbsd;
 
-namespace {
+namespace lbsd {
 
 thread_local std::string g_last_error;
 
-int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char* fmt, ...)
 {
     char buf[512];
@@ -38,7 +36,139 @@ int hip_fail(hipError_t e, const char* what)
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
-}  // namespace
+int check_model(int dim, double gamma, const lb_velset* vs, int precision)
+{
+    if (!vs) return fail(LB_EINVAL, "null velocity set");
+    if (dim != 1 && dim != 2) return fail(LB_EINVAL, "dim must be 1 or 2 (got %d)", dim);
+    if (!(gamma > 1.0) || !(gamma <= 1.0 + 2.0 / dim))
+        return fail(LB_EINVAL, "gamma must lie in (1, 1 + 2/D] (phi >= 0, eq. 15); got %g", gamma);
+    if ((dim == 1 && vs->lattice != LB_LATTICE_D1_TRIPLE) ||
+        (dim == 2 && vs->lattice != LB_LATTICE_D2_SQUARE_DUAL))
+        return fail(LB_EINVAL, "lattice %d does not match dim %d", vs->lattice, dim);
+    if (dim == 1 && !(vs->d0_frac >= 0.0 && vs->d0_frac < 1.0))
+        return fail(LB_EINVAL, "d0_frac must lie in [0, 1); got %g", vs->d0_frac);
+    if (dim == 2 && vs->d0_frac != 0.0)
+        return fail(LB_EINVAL, "the square dual-level set has d0 = 0");
+    if (precision != LB_FP64 && precision != LB_FP32)
+        return fail(LB_EINVAL, "precision must be LB_FP64 or LB_FP32");
+    return LB_OK;
+}
+
+int check_grid(const lb_grid* grid, int dim)
+{
+    if (!grid) return fail(LB_EINVAL, "null grid");
+    if (grid->dim != dim) return fail(LB_EINVAL, "grid dim %d, expected %d", grid->dim, dim);
+    if (grid->nx < 1 || grid->ny < 1) return fail(LB_EINVAL, "nx, ny must be >= 1");
+    if (dim == 1 && grid->ny != 1) return fail(LB_EINVAL, "ny must be 1 in 1-D");
+    if (grid->nx > (int64_t)1 << 40 || grid->ny > (int64_t)1 << 40 ||
+        grid->nx * grid->ny > (int64_t)1 << 36)
+        return fail(LB_EINVAL, "grid too large");
+    if (!(grid->x_hi > grid->x_lo) || !isfinite(grid->x_lo) || !isfinite(grid->x_hi))
+        return fail(LB_EINVAL, "need x_lo < x_hi");
+    for (int b : {grid->bc_x, grid->bc_y})
+        if (b != LB_BC_TRANSMISSIVE && b != LB_BC_PERIODIC)
+            return fail(LB_EINVAL, "unknown boundary condition %d", b);
+    return LB_OK;
+}
+
+Consts make_consts(int dim, double gamma, const lb_velset* vs)
+{
+    Consts k;
+    k.Dg1 = (double)dim * (gamma - 1.0);
+    k.phi_coef = 1.0 - ((double)dim / 2.0) * (gamma - 1.0);
+    k.delta0 = dim == 1 ? vs->d0_frac : 0.0;
+    k.b0 = dim == 1 ? 1.0 : 0.0;
+    k.inv_b1 = dim == 1 ? 0.5 : 0.25;
+    return k;
+}
+
+static bool prim_ok(const lb_prim* p)
+{
+    return p && p->rho > 0.0 && p->p >= 0.0 && isfinite(p->rho) && isfinite(p->u) &&
+           isfinite(p->v) && isfinite(p->p);
+}
+
+int riemann_sides(int dim, double gamma, double lam_set, double cfl, const lb_prim* L, const lb_prim* R,
+                  double* lam_out, double side[2][4])
+{
+    if (!prim_ok(L) || !prim_ok(R)) return fail(LB_ESTATE, "need rho > 0, p >= 0, finite values");
+    double lam = lam_set;
+    if (!(lam > 0.0)) {
+        double smax = 0.0;
+        for (const lb_prim* q : {L, R}) {
+            const double uu = dim == 2 ? sqrt(q->u * q->u + q->v * q->v) : fabs(q->u);
+            const double c = uu + sqrt(gamma * q->p / q->rho);
+            smax = c > smax ? c : smax;
+        }
+        if (!(smax > 0.0)) return fail(LB_ESTATE, "both states have zero signal speed; set lambda");
+        lam = cfl / smax;
+    }
+    const lb_prim* P[2] = {L, R};
+    const double lam2 = lam * lam;
+    for (int i = 0; i < 2; ++i) {
+        const double rho = P[i]->rho, u = P[i]->u, v = dim == 2 ? P[i]->v : 0.0, p = P[i]->p;
+        const double rE = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v);
+        side[i][0] = rho;
+        side[i][1] = (rho * u) * lam;
+        if (dim == 2) {
+            side[i][2] = (rho * v) * lam;
+            side[i][3] = rE * lam2;
+        } else {
+            side[i][2] = rE * lam2;
+            side[i][3] = 0.0;
+        }
+    }
+    *lam_out = lam;
+    return LB_OK;
+}
+
+int check_moments(const double* Y, int nf, int64_t nn)
+{
+    if (!Y) return fail(LB_EINVAL, "null moments");
+    for (int64_t q = 0; q < nn; ++q)
+        if (!(Y[q] > 0.0)) return fail(LB_ESTATE, "rho <= 0 at node %lld", (long long)q);
+    for (int64_t q = 0; q < (int64_t)nf * nn; ++q)
+        if (!isfinite(Y[q])) return fail(LB_ESTATE, "non-finite moment at %lld", (long long)q);
+    return LB_OK;
+}
+
+int upload_moments(void* dst, const double* Y, int nf, int64_t nn, double lambda, bool fp64,
+                   hipStream_t stream)
+{
+    const double lam2 = lambda * lambda;
+    std::vector<double> tmp;
+    std::vector<float> tmpf;
+    try {
+        if (fp64) tmp.resize((size_t)nf * nn);
+        else tmpf.resize((size_t)nf * nn);
+    } catch (...) {
+        return fail(LB_ENOMEM, "host staging allocation failed");
+    }
+    for (int f = 0; f < nf; ++f) {
+        const double sc = f == nf - 1 ? lam2 : lambda;
+        for (int64_t q = 0; q < nn; ++q) {
+            const double y = Y[(int64_t)f * nn + q];
+            const double v = f == 0 ? y : y * sc;
+            if (fp64) tmp[(size_t)f * nn + q] = v;
+            else tmpf[(size_t)f * nn + q] = (float)v;
+        }
+    }
+    hipError_t e = fp64 ? hipMemcpyAsync(dst, tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice, stream)
+                        : hipMemcpyAsync(dst, tmpf.data(), tmpf.size() * 4, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "sync");
+    return LB_OK;
+}
+
+void field_scales(int nf, double lambda, double sc[4])
+{
+    const double lam2 = lambda * lambda;
+    for (int f = 0; f < 4; ++f) sc[f] = 1.0;
+    for (int f = 1; f < nf - 1; ++f) sc[f] = lambda;
+    sc[nf - 1] = lam2;
+}
+
+}  // namespace lbsd
 
 struct lb_solver {
     lb_grid grid;
@@ -79,28 +209,9 @@ int lb_create(const lb_grid* grid, double gamma, const lb_velset* vs, int32_t pr
 {
     if (!grid || !vs || !out) return fail(LB_EINVAL, "null argument");
     const int dim = grid->dim;
-    if (dim != 1 && dim != 2) return fail(LB_EINVAL, "dim must be 1 or 2 (got %d)", dim);
-    if (grid->nx < 1 || grid->ny < 1) return fail(LB_EINVAL, "nx, ny must be >= 1");
-    if (dim == 1 && grid->ny != 1) return fail(LB_EINVAL, "ny must be 1 in 1-D");
-    if (grid->nx > (int64_t)1 << 40 || grid->ny > (int64_t)1 << 40 ||
-        grid->nx * grid->ny > (int64_t)1 << 36)
-        return fail(LB_EINVAL, "grid too large");
-    if (!(grid->x_hi > grid->x_lo) || !isfinite(grid->x_lo) || !isfinite(grid->x_hi))
-        return fail(LB_EINVAL, "need x_lo < x_hi");
-    for (int b : {grid->bc_x, grid->bc_y})
-        if (b != LB_BC_TRANSMISSIVE && b != LB_BC_PERIODIC)
-            return fail(LB_EINVAL, "unknown boundary condition %d", b);
-    if (!(gamma > 1.0) || !(gamma <= 1.0 + 2.0 / dim))
-        return fail(LB_EINVAL, "gamma must lie in (1, 1 + 2/D] (phi >= 0, eq. 15); got %g", gamma);
-    if ((dim == 1 && vs->lattice != LB_LATTICE_D1_TRIPLE) ||
-        (dim == 2 && vs->lattice != LB_LATTICE_D2_SQUARE_DUAL))
-        return fail(LB_EINVAL, "lattice %d does not match dim %d", vs->lattice, dim);
-    if (dim == 1 && !(vs->d0_frac >= 0.0 && vs->d0_frac < 1.0))
-        return fail(LB_EINVAL, "d0_frac must lie in [0, 1); got %g", vs->d0_frac);
-    if (dim == 2 && vs->d0_frac != 0.0)
-        return fail(LB_EINVAL, "the square dual-level set has d0 = 0");
-    if (precision != LB_FP64 && precision != LB_FP32)
-        return fail(LB_EINVAL, "precision must be LB_FP64 or LB_FP32");
+    int rc = check_model(dim, gamma, vs, precision);
+    if (rc != LB_OK) return rc;
+    if ((rc = check_grid(grid, dim)) != LB_OK) return rc;
 
     lb_solver* s = new (std::nothrow) lb_solver();
     if (!s) return fail(LB_ENOMEM, "host allocation failed");
@@ -111,11 +222,7 @@ int lb_create(const lb_grid* grid, double gamma, const lb_velset* vs, int32_t pr
     s->precision = precision;
     s->gamma = gamma;
     s->vs = *vs;
-    s->k.Dg1 = (double)dim * (gamma - 1.0);
-    s->k.phi_coef = 1.0 - ((double)dim / 2.0) * (gamma - 1.0);
-    s->k.delta0 = dim == 1 ? vs->d0_frac : 0.0;
-    s->k.b0 = dim == 1 ? 1.0 : 0.0;
-    s->k.inv_b1 = dim == 1 ? 0.5 : 0.25;
+    s->k = make_consts(dim, gamma, vs);
     s->nn = grid->nx * grid->ny;
     s->elem = precision == LB_FP64 ? 8 : 4;
     const size_t field_bytes = align256((size_t)s->nf * (size_t)s->nn * s->elem);
@@ -183,12 +290,6 @@ int lb_set_cfl(lb_solver* s, double cfl)
     return LB_OK;
 }
 
-static bool prim_ok(const lb_prim* p)
-{
-    return p && p->rho > 0.0 && p->p >= 0.0 && isfinite(p->rho) && isfinite(p->u) &&
-           isfinite(p->v) && isfinite(p->p);
-}
-
 static int start_state(lb_solver* s)
 {
     s->march_full = false;
@@ -204,35 +305,9 @@ int lb_init_riemann(lb_solver* s, double x_d, const lb_prim* L, const lb_prim* R
 {
     if (!s || !s->bound) return fail(LB_EINVAL, "solver not bound");
     if (!isfinite(x_d)) return fail(LB_EINVAL, "diaphragm position must be finite");
-    if (!prim_ok(L) || !prim_ok(R)) return fail(LB_ESTATE, "need rho > 0, p >= 0, finite values");
-    const double g = s->gamma;
-    double lam = s->lambda_set;
-    if (!(lam > 0.0)) {
-        double smax = 0.0;
-        for (const lb_prim* q : {L, R}) {
-            const double uu = s->dim == 2 ? sqrt(q->u * q->u + q->v * q->v) : fabs(q->u);
-            const double c = uu + sqrt(g * q->p / q->rho);
-            smax = c > smax ? c : smax;
-        }
-        if (!(smax > 0.0)) return fail(LB_ESTATE, "both states have zero signal speed; set lambda");
-        lam = s->cfl / smax;
-    }
-    double side[2][4];
-    const lb_prim* P[2] = {L, R};
-    const double lam2 = lam * lam;
-    for (int i = 0; i < 2; ++i) {
-        const double rho = P[i]->rho, u = P[i]->u, v = s->dim == 2 ? P[i]->v : 0.0, p = P[i]->p;
-        const double rE = p / (g - 1.0) + 0.5 * rho * (u * u + v * v);
-        side[i][0] = rho;
-        side[i][1] = (rho * u) * lam;
-        if (s->dim == 2) {
-            side[i][2] = (rho * v) * lam;
-            side[i][3] = rE * lam2;
-        } else {
-            side[i][2] = rE * lam2;
-            side[i][3] = 0.0;
-        }
-    }
+    double lam = 0.0, side[2][4];
+    const int rc = riemann_sides(s->dim, s->gamma, s->lambda_set, s->cfl, L, R, &lam, side);
+    if (rc != LB_OK) return rc;
     s->lambda = lam;
     const double dx = (s->grid.x_hi - s->grid.x_lo) / (double)s->grid.nx;
     hipError_t e;
@@ -249,37 +324,11 @@ int lb_init_riemann(lb_solver* s, double x_d, const lb_prim* L, const lb_prim* R
 int lb_init_moments(lb_solver* s, const double* Y, double lambda)
 {
     if (!s || !s->bound) return fail(LB_EINVAL, "solver not bound");
-    if (!Y) return fail(LB_EINVAL, "null moments");
     if (!(lambda > 0.0) || !isfinite(lambda)) return fail(LB_EINVAL, "lambda must be > 0");
-    const int64_t nn = s->nn;
-    const int nf = s->nf;
-    for (int64_t q = 0; q < nn; ++q)
-        if (!(Y[q] > 0.0)) return fail(LB_ESTATE, "rho <= 0 at node %lld", (long long)q);
-    for (int64_t q = 0; q < (int64_t)nf * nn; ++q)
-        if (!isfinite(Y[q])) return fail(LB_ESTATE, "non-finite moment at %lld", (long long)q);
-    const double lam2 = lambda * lambda;
-    std::vector<double> tmp;
-    std::vector<float> tmpf;
-    try {
-        if (s->precision == LB_FP64) tmp.resize((size_t)nf * nn);
-        else tmpf.resize((size_t)nf * nn);
-    } catch (...) {
-        return fail(LB_ENOMEM, "host staging allocation failed");
-    }
-    for (int f = 0; f < nf; ++f) {
-        const double sc = f == 0 ? 0.0 : (f == nf - 1 ? lam2 : lambda);
-        for (int64_t q = 0; q < nn; ++q) {
-            const double y = Y[(int64_t)f * nn + q];
-            const double v = f == 0 ? y : y * sc;
-            if (s->precision == LB_FP64) tmp[(size_t)f * nn + q] = v;
-            else tmpf[(size_t)f * nn + q] = (float)v;
-        }
-    }
-    hipError_t e = s->precision == LB_FP64
-        ? hipMemcpyAsync(buf_ptr(s, 0), tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice, s->stream)
-        : hipMemcpyAsync(buf_ptr(s, 0), tmpf.data(), tmpf.size() * 4, hipMemcpyHostToDevice, s->stream);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-    if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return hip_fail(e, "sync");
+    int rc = check_moments(Y, s->nf, s->nn);
+    if (rc != LB_OK) return rc;
+    rc = upload_moments(buf_ptr(s, 0), Y, s->nf, s->nn, lambda, s->precision == LB_FP64, s->stream);
+    if (rc != LB_OK) return rc;
     s->lambda = lambda;
     return start_state(s);
 }
@@ -407,15 +456,6 @@ int lb_step_profiled(lb_solver* s, int64_t n, float* kernel_ms, float* total_ms)
     return LB_OK;
 }
 
-static void field_scales(const lb_solver* s, double sc[4])
-{
-    const double lam = s->lambda, lam2 = lam * lam;
-    sc[0] = 1.0;
-    for (int f = 1; f < 4; ++f) sc[f] = 1.0;
-    for (int f = 1; f < s->nf - 1; ++f) sc[f] = lam;
-    sc[s->nf - 1] = lam2;
-}
-
 int lb_moments(lb_solver* s, double* out, int32_t on_device)
 {
     if (!s || !out) return fail(LB_EINVAL, "null argument");
@@ -424,7 +464,7 @@ int lb_moments(lb_solver* s, double* out, int32_t on_device)
     if (rc != LB_OK && rc != LB_EREACH && rc != LB_ESTATE) return rc;
     // After a failed step the state is the last good one; exporting it is allowed.
     double sc[4];
-    field_scales(s, sc);
+    field_scales(s->nf, s->lambda, sc);
     double* dst = on_device ? out : export_ptr(s);
     hipError_t e = s->precision == LB_FP64
         ? launch_export<double>((const double*)buf_ptr(s, s->cur), dst, s->nn, s->nf, sc, s->stream)
@@ -449,7 +489,7 @@ int lb_totals(lb_solver* s, double out[4])
     hipError_t e = hipMemcpy(&c, ctl_ptr(s), sizeof c, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "read control block");
     double sc[4];
-    field_scales(s, sc);
+    field_scales(s->nf, s->lambda, sc);
     double t[4] = {0, 0, 0, 0};
     if (c.totals_step == (long long)s->steps_done && s->steps_done > 0) {
         for (int f = 0; f < 4; ++f) t[f] = c.totals[f];

@@ -85,4 +85,65 @@ hipError_t launch_lanes(const T* Y, const Grid& g, int dim, const Consts& k, int
 
 hipError_t launch_reset_ctl(StepCtl* ctl, hipStream_t stream);
 
+// ---- pools: many independent problems advanced by one persistent launch per
+// step over a device-resident tile table (lb_pool.hip) ----
+
+struct PoolProb {       // one slot, written by the host between launches
+    int64_t off[2];     // element offsets of the two SoA moment sets in the arena
+    int64_t nx, ny;
+    int32_t bc_x, bc_y;
+    int32_t active;     // 0: free slot (it owns no tiles)
+    int32_t pad;
+    int64_t target;     // the problem stops after this many good steps
+    int64_t t0, t1;     // its tiles [t0, t1) in the tile table
+};
+
+struct PoolState {      // one slot, written by the device, read by the host after a sync
+    int64_t done;       // good steps so far: the moments are in set (done & 1)
+    int64_t err_step;   // step that failed (0: none); the problem then stops
+    int32_t err_code;   // kErr* bits
+    int32_t max_reach;  // largest reach of its latest step
+    int64_t totals_step;
+    double totals[4];   // interior sums after step totals_step (lattice units)
+};
+
+struct PoolTile {
+    int32_t prob, rows;  // slot; destination rows (square lattice; 1 in 1-D)
+    int64_t x0, y0;      // first destination column / row
+};
+
+struct PoolView {
+    const PoolProb* probs;
+    PoolState* state;
+    const PoolTile* tiles;
+    const int32_t* ntiles;  // live tiles (read by the kernels, so admissions need no new launch shape)
+    double* partials;       // kPartialStride doubles per tile
+    int32_t* flags;         // square lattice: tile needs the full-FIFO pass
+    void* arena;            // moment sets of all slots (T elements)
+};
+
+// Tile shapes of the 1-D pool kernel (threads per block, nodes per thread).
+constexpr int kPool1Shapes = 5;
+constexpr int kPool1TPB[kPool1Shapes] = {256, 256, 256, 256, 512};
+constexpr int kPool1J[kPool1Shapes] = {1, 2, 4, 8, 4};
+// Strip heights of the square-lattice pool tiles (rows per tile).
+constexpr int kPool2Shapes = 5;
+constexpr int kPool2Rows[kPool2Shapes] = {16, 32, 64, 128, 256};
+constexpr int kPool2Cols = 256 - 2 * kHalo;  // destination columns per square-lattice tile
+
+// One step of every live tile: the 1-D kernel of tile shape `shape`, or the
+// square-lattice short-FIFO pass followed by the full-FIFO pass over the tiles
+// it flagged.  nblocks persistent blocks walk the tile table.
+template <typename T>
+hipError_t launch_pool1d(const PoolView& v, const Consts& k, int shape, int nblocks, hipStream_t stream);
+template <typename T>
+int pool1d_blocks_per_cu(int shape);
+template <typename T>
+hipError_t launch_pool2d(const PoolView& v, const Consts& k, int nblocks, hipStream_t stream);
+template <typename T>
+int pool2d_blocks_per_cu();
+// Per slot: reduce its tiles' partial rows (fixed order) into its state and,
+// when commit != 0 and the step succeeded, count the step.
+hipError_t launch_pool_finalize(const PoolView& v, int nslots, int commit, hipStream_t stream);
+
 }  // namespace lbsd

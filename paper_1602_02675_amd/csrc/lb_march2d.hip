@@ -414,25 +414,21 @@ __device__ __forceinline__ void load_node(const T* __restrict__ Y, int64_t nn, i
 #ifndef LB_MARCH_WPE
 #define LB_MARCH_WPE 2
 #endif
-// L = kLSmall: the short-FIFO pass; a source whose y-reach exceeds L marks the
-// step for a redo.  L = kLFull with redo_only: runs only if the short pass of
-// this step asked for it (and then recomputes every block, bit-identically:
-// the summation order does not depend on L).
+// One tile: destination columns [X0, X0 + 256 - 2H) and rows [Y0, Y0 + sy)
+// (clipped to the grid) of grid g, marched from row Y0 - L to Y0 + sy + L - 1.
+// Writes Yn and one row of per-tile partials (field sums, reach, error bits).
+// Returns 1 (the same in every thread) when the FIFO of this L cannot hold a
+// source's y-displacement: the tile's output is then incomplete and must be
+// recomputed with L = kLFull, which sums in the same order (bit-identical).
+// Contains block-wide barriers: every thread of the block must call it.
 template <typename T, int L>
-__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? LB_MARCH_WPE : 1)))
-march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
-               StepCtl* __restrict__ ctl, double* __restrict__ partials, long long step, int sy,
-               int redo_only)
+__device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict__ Yn, const Grid& g, const Consts& k,
+                          int64_t X0, int64_t Y0, int sy, double* __restrict__ prow)
 {
     __shared__ MRow<T> s_row[2];
     __shared__ WaveInfo s_w[2][kMNW];
-    if (ctl->err_step < step) return;
-    if (redo_only && ctl->redo_step != step) return;
-
     const int tid = threadIdx.x, lane64 = tid & 63, wid = tid >> 6;
     const int64_t nx = g.nx, ny = g.ny, nn = nx * ny;
-    const int64_t X0 = (int64_t)blockIdx.x * (kMTPB - 2 * kMH);  // first destination column
-    const int64_t Y0 = (int64_t)blockIdx.y * sy;                 // first destination row
     const int64_t gx = X0 - kMH + tid;                           // this thread's source column
     const int64_t sx = g.bc_x == kBcPeriodic ? wrap_near(gx, nx) : clamp_idx(gx, nx);
     const bool dest = tid >= kMH && tid < kMTPB - kMH && gx < nx;
@@ -563,14 +559,7 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
 #pragma unroll
         for (int c = 0; c < 4; ++c) cur[c] = nxt[c];
     }
-    if (L < kLFull) {
-        // a packet of this block's sources needs a wider FIFO: redo the step
-        if (__any(yfar) && lane64 == 0) ctl->redo_step = step;
-    } else if (redo_only && blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
-        ctl->redo_count += 1;
-    }
-
-    // per-block partials: field sums, reach, error bits
+    // per-tile partials: field sums, reach, error bits
     __shared__ double s_sum[kMNW][4];
     __shared__ int s_ir[kMNW][2];
 #pragma unroll
@@ -583,22 +572,71 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
         s_ir[wid][0] = reach;
         s_ir[wid][1] = bad;
     }
-    __syncthreads();
+    const int far = __syncthreads_or(L < kLFull ? yfar : 0);
     if (tid == 0) {
-        const int64_t bid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-        double* p = partials + bid * kPartialStride;
         int rr = 0, bb = 0;
         for (int c = 0; c < 4; ++c) {
             double t = s_sum[0][c];
             for (int w = 1; w < kMNW; ++w) t += s_sum[w][c];
-            p[c] = t;
+            prow[c] = t;
         }
         for (int w = 0; w < kMNW; ++w) {
             rr = max(rr, s_ir[w][0]);
             bb |= s_ir[w][1];
         }
-        p[4] = (double)rr;
-        p[5] = (double)((rr > kMH ? kErrReach : 0) | (bb ? kErrState : 0));
+        prow[4] = (double)rr;
+        prow[5] = (double)((rr > kMH ? kErrReach : 0) | (bb ? kErrState : 0));
+    }
+    return far;
+}
+
+#ifndef LB_MARCH_WPE
+#define LB_MARCH_WPE 2
+#endif
+// L = kLSmall: the short-FIFO pass; a block whose sources reach beyond the
+// FIFO marks the step for a redo.  L = kLFull with redo_only: runs only if the
+// short pass of this step asked for it, and then recomputes every block.
+template <typename T, int L>
+__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? LB_MARCH_WPE : 1)))
+march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
+               StepCtl* __restrict__ ctl, double* __restrict__ partials, long long step, int sy,
+               int redo_only)
+{
+    if (ctl->err_step < step) return;
+    if (redo_only && ctl->redo_step != step) return;
+    const int64_t bid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const int far = march_tile<T, L>(Y, Yn, g, k, (int64_t)blockIdx.x * (kMTPB - 2 * kMH),
+                                     (int64_t)blockIdx.y * sy, sy, partials + bid * kPartialStride);
+    if (threadIdx.x == 0) {
+        if (L < kLFull) {
+            if (far) ctl->redo_step = step;
+        } else if (redo_only && bid == 0) {
+            ctl->redo_count += 1;
+        }
+    }
+}
+
+// Pool form: persistent blocks walk the tile table (see pool1d_kernel).  The
+// short-FIFO pass flags the tiles it could not complete; the full-FIFO pass
+// recomputes only those.
+template <typename T, int L>
+__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? LB_MARCH_WPE : 1)))
+pool2d_kernel(PoolView v, Consts k)
+{
+    const int nt = *v.ntiles;
+    T* arena = (T*)v.arena;
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+        if (L == kLFull && v.flags[t] == 0) continue;
+        const PoolTile tl = v.tiles[t];
+        const PoolProb& P = v.probs[tl.prob];
+        const PoolState& S = v.state[tl.prob];
+        const int64_t done = S.done;
+        if (done >= P.target || S.err_step != 0) continue;  // the same for the whole block
+        const int cur = (int)(done & 1);
+        const Grid g{P.nx, P.ny, P.bc_x, P.bc_y};
+        const int far = march_tile<T, L>(arena + P.off[cur], arena + P.off[cur ^ 1], g, k, tl.x0, tl.y0,
+                                         tl.rows, v.partials + (int64_t)t * kPartialStride);
+        if (threadIdx.x == 0) v.flags[t] = L < kLFull ? far : 0;
     }
 }
 
@@ -652,8 +690,31 @@ hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, 
     return hipGetLastError();
 }
 
+template <typename T>
+int pool2d_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pool2d_kernel<T, kLSmall>, kMTPB, 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+template <typename T>
+hipError_t launch_pool2d(const PoolView& v, const Consts& k, int nblocks, hipStream_t stream)
+{
+    pool2d_kernel<T, kLSmall><<<nblocks, kMTPB, 0, stream>>>(v, k);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    pool2d_kernel<T, kLFull><<<nblocks, kMTPB, 0, stream>>>(v, k);
+    return hipGetLastError();
+}
+
 template int march2d_blocks_per_cu<double>();
 template int march2d_blocks_per_cu<float>();
+template int pool2d_blocks_per_cu<double>();
+template int pool2d_blocks_per_cu<float>();
+template hipError_t launch_pool2d<double>(const PoolView&, const Consts&, int, hipStream_t);
+template hipError_t launch_pool2d<float>(const PoolView&, const Consts&, int, hipStream_t);
 template hipError_t launch_march2d<double>(const double*, double*, const Grid&, const MarchGeom&,
                                            const Consts&, StepCtl*, double*, long long, bool,
                                            hipStream_t);

@@ -80,12 +80,10 @@ __device__ __forceinline__ TileInfo block_tile_info(TileInfo t, int (*s_red)[8])
 // atomics or device-scope fences here: the reduction over blocks is a separate
 // single-block kernel (finalize_kernel), so the kernel boundary orders it.
 template <int NW, int NF>
-__device__ void finish_step(double (&acc)[NF], const TileInfo& ti, double* __restrict__ partials,
-                            int H)
+__device__ void finish_step(double (&acc)[NF], const TileInfo& ti, double* __restrict__ prow, int H)
 {
     __shared__ double s_sum[NW][4];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int64_t bid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
 #pragma unroll
     for (int f = 0; f < NF; ++f) acc[f] = wave_sum(acc[f]);
     if (lane == 0) {
@@ -94,16 +92,15 @@ __device__ void finish_step(double (&acc)[NF], const TileInfo& ti, double* __res
     }
     __syncthreads();
     if (tid == 0) {
-        double* p = partials + bid * kPartialStride;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             double s = s_sum[0][f];
             for (int w = 1; w < NW; ++w) s += s_sum[w][f];
-            p[f] = s;
+            prow[f] = s;
         }
-        for (int f = NF; f < 4; ++f) p[f] = 0.0;
-        p[4] = (double)ti.reach;
-        p[5] = (double)((ti.reach > H ? kErrReach : 0) | (ti.bad ? kErrState : 0));
+        for (int f = NF; f < 4; ++f) prow[f] = 0.0;
+        prow[4] = (double)ti.reach;
+        prow[5] = (double)((ti.reach > H ? kErrReach : 0) | (ti.bad ? kErrState : 0));
     }
 }
 
@@ -256,10 +253,13 @@ __device__ void gather1_general(const Tile1<T>& tl, const TileInfo& ti, int64_t 
     }
 }
 
+// One tile of TPB * J destinations starting at x0 of a tube of nx nodes:
+// stage its sources (plus a halo of H, clamped or wrapped), gather, write Yn,
+// and add the tile's new moments to acc.  Returns the tile's integer summary.
+// Contains block-wide barriers: every thread of the block must call it.
 template <typename T, int H, int TPB, int J>
-__global__ void __launch_bounds__(TPB)
-step1d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
-              StepCtl* __restrict__ ctl, double* __restrict__ partials, long long step)
+__device__ __forceinline__ TileInfo tile1d(const T* __restrict__ Y, T* __restrict__ Yn, int64_t nx, int bc, int64_t x0,
+                           const Consts& k, double (&acc)[3])
 {
     constexpr int TILE = TPB * J;
     constexpr int W = TILE + 2 * H;
@@ -267,10 +267,7 @@ step1d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
     __shared__ int s_pk[W];
     __shared__ T s_r[W], s_d0[W], s_d1[W], s_d2[W], s_K[W];
     __shared__ int s_red[NW][8];
-    if (ctl->err_step < step) return;  // an earlier step failed: keep its input intact
 
-    const int64_t nx = g.nx;
-    const int64_t x0 = (int64_t)blockIdx.x * TILE;
     TileInfo ti = {INT_MAX, INT_MIN, 0, 0, INT_MAX, INT_MIN, 0, 0};
     constexpr int NS = (W + TPB - 1) / TPB;
     T ld[NS][3];
@@ -279,7 +276,7 @@ step1d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
         const int i = (int)threadIdx.x + u * TPB;
         if (i < W) {
             const int64_t gx = x0 - H + i;
-            const int64_t si = g.bc_x == kBcPeriodic ? wrap_near(gx, nx) : clamp_idx(gx, nx);
+            const int64_t si = bc == kBcPeriodic ? wrap_near(gx, nx) : clamp_idx(gx, nx);
             ld[u][0] = Y[si]; ld[u][1] = Y[nx + si]; ld[u][2] = Y[2 * nx + si];
         }
     }
@@ -303,7 +300,6 @@ step1d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
     }
     ti = block_tile_info<NW>(ti, s_red);  // contains the barrier after staging
     const Tile1<T> tl = {s_pk, s_r, s_d0, s_d1, s_d2, s_K};
-    double acc[3] = {0.0, 0.0, 0.0};
     const bool uniform = ti.fxmin == ti.fxmax && ti.cmin == ti.cmax && ti.reach <= H;
     if (uniform && ti.cmin == 0)
         gather1_uniform<T, H, TPB, J, 0>(tl, ti.fxmin, x0, nx, Yn, acc);
@@ -315,7 +311,93 @@ step1d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
         gather1_uniform<T, H, TPB, J, 3>(tl, ti.fxmin, x0, nx, Yn, acc);
     else
         gather1_general<T, H, TPB, J>(tl, ti, x0, nx, Yn, acc);
-    finish_step<NW, 3>(acc, ti, partials, H);
+    return ti;
+}
+
+template <typename T, int H, int TPB, int J>
+__global__ void __launch_bounds__(TPB)
+step1d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
+              StepCtl* __restrict__ ctl, double* __restrict__ partials, long long step)
+{
+    if (ctl->err_step < step) return;  // an earlier step failed: keep its input intact
+    double acc[3] = {0.0, 0.0, 0.0};
+    const TileInfo ti = tile1d<T, H, TPB, J>(Y, Yn, g.nx, g.bc_x, (int64_t)blockIdx.x * (TPB * J), k, acc);
+    finish_step<TPB / 64, 3>(acc, ti, partials + (int64_t)blockIdx.x * kPartialStride, H);
+}
+
+// Pool form: persistent blocks walk the tile table; a tile belongs to one
+// slot, whose own step count picks the moment set it reads (done & 1) and
+// writes.  Finished, failed and free slots own no work.  The tile -> block
+// assignment does not change any result.
+template <typename T, int TPB, int J>
+__global__ void __launch_bounds__(TPB) pool1d_kernel(PoolView v, Consts k)
+{
+    const int nt = *v.ntiles;
+    T* arena = (T*)v.arena;
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+        const PoolTile tl = v.tiles[t];
+        const PoolProb& P = v.probs[tl.prob];
+        const PoolState& S = v.state[tl.prob];
+        const int64_t done = S.done;
+        if (done >= P.target || S.err_step != 0) continue;  // the same for the whole block
+        const int cur = (int)(done & 1);
+        double acc[3] = {0.0, 0.0, 0.0};
+        const TileInfo ti =
+            tile1d<T, kHalo, TPB, J>(arena + P.off[cur], arena + P.off[cur ^ 1], P.nx, P.bc_x, tl.x0, k, acc);
+        finish_step<TPB / 64, 3>(acc, ti, v.partials + (int64_t)t * kPartialStride, kHalo);
+    }
+}
+
+// Per slot (one block each): the same fixed-order reduction as finalize_kernel
+// over the slot's tile rows.
+__global__ void __launch_bounds__(kFinTPB) pool_finalize_kernel(PoolView v, int commit)
+{
+    __shared__ double s_sum[kFinTPB / 64][4];
+    __shared__ int s_ir[kFinTPB / 64][2];
+    const int p = blockIdx.x;
+    const PoolProb& P = v.probs[p];
+    PoolState& S = v.state[p];
+    if (!P.active || S.done >= P.target || S.err_step != 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    int reach = 0, err = 0;
+    for (int64_t b = P.t0 + tid; b < P.t1; b += kFinTPB) {
+        const double* q = v.partials + b * kPartialStride;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) s[f] += q[f];
+        reach = max(reach, (int)q[4]);
+        err |= (int)q[5];
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) s[f] = wave_sum(s[f]);
+    reach = wave_max(reach);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) err |= __shfl_xor(err, o, 64);
+    if (lane == 0) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) s_sum[wid][f] = s[f];
+        s_ir[wid][0] = reach;
+        s_ir[wid][1] = err;
+    }
+    __syncthreads();
+    if (tid == 0 && commit) {
+        const int64_t step = S.done + 1;
+        for (int f = 0; f < 4; ++f) {
+            double t = s_sum[0][f];
+            for (int w = 1; w < kFinTPB / 64; ++w) t += s_sum[w][f];
+            S.totals[f] = t;
+        }
+        int r = s_ir[0][0], e = s_ir[0][1];
+        for (int w = 1; w < kFinTPB / 64; ++w) { r = max(r, s_ir[w][0]); e |= s_ir[w][1]; }
+        S.max_reach = r;
+        S.totals_step = step;
+        if (e) {
+            S.err_code = e;
+            S.err_step = step;
+        } else {
+            S.done = step;
+        }
+    }
 }
 
 #ifndef LB_T1_TPB
@@ -343,6 +425,55 @@ hipError_t launch_step1d(const T* Y, T* Yn, const Grid& g, const Consts& k, Step
     return hipGetLastError();
 }
 
+template <typename T, int S>
+static hipError_t pool1d_launch_shape(const PoolView& v, const Consts& k, int nblocks, hipStream_t stream)
+{
+    pool1d_kernel<T, kPool1TPB[S], kPool1J[S]><<<nblocks, kPool1TPB[S], 0, stream>>>(v, k);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pool1d(const PoolView& v, const Consts& k, int shape, int nblocks, hipStream_t stream)
+{
+    switch (shape) {
+        case 0: return pool1d_launch_shape<T, 0>(v, k, nblocks, stream);
+        case 1: return pool1d_launch_shape<T, 1>(v, k, nblocks, stream);
+        case 2: return pool1d_launch_shape<T, 2>(v, k, nblocks, stream);
+        case 3: return pool1d_launch_shape<T, 3>(v, k, nblocks, stream);
+        case 4: return pool1d_launch_shape<T, 4>(v, k, nblocks, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int S>
+static int pool1d_occupancy()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pool1d_kernel<T, kPool1TPB[S], kPool1J[S]>,
+                                                     kPool1TPB[S], 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+template <typename T>
+int pool1d_blocks_per_cu(int shape)
+{
+    switch (shape) {
+        case 0: return pool1d_occupancy<T, 0>();
+        case 1: return pool1d_occupancy<T, 1>();
+        case 2: return pool1d_occupancy<T, 2>();
+        case 3: return pool1d_occupancy<T, 3>();
+        case 4: return pool1d_occupancy<T, 4>();
+        default: return 1;
+    }
+}
+
+hipError_t launch_pool_finalize(const PoolView& v, int nslots, int commit, hipStream_t stream)
+{
+    pool_finalize_kernel<<<nslots, kFinTPB, 0, stream>>>(v, commit);
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(const double* partials, int64_t nb, StepCtl* ctl, long long step,
                            hipStream_t stream)
 {
@@ -354,5 +485,10 @@ template hipError_t launch_step1d<double>(const double*, double*, const Grid&, c
                                           StepCtl*, double*, long long, hipStream_t);
 template hipError_t launch_step1d<float>(const float*, float*, const Grid&, const Consts&,
                                          StepCtl*, double*, long long, hipStream_t);
+
+template hipError_t launch_pool1d<double>(const PoolView&, const Consts&, int, int, hipStream_t);
+template hipError_t launch_pool1d<float>(const PoolView&, const Consts&, int, int, hipStream_t);
+template int pool1d_blocks_per_cu<double>(int);
+template int pool1d_blocks_per_cu<float>(int);
 
 }  // namespace lbsd

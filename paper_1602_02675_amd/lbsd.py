@@ -32,7 +32,12 @@ _ERR_NAMES = {LB_EINVAL: "LB_EINVAL", LB_ENOMEM: "LB_ENOMEM", LB_EDEVICE: "LB_ED
 EXPORTED = ["lb_create", "lb_state_bytes", "lb_bind", "lb_set_lambda", "lb_set_cfl",
             "lb_init_riemann", "lb_init_moments", "lb_step", "lb_step_timed", "lb_step_profiled", "lb_sync",
             "lb_moments", "lb_totals", "lb_lambda", "lb_dt", "lb_steps_done", "lb_max_reach",
-            "lb_debug_lanes", "lb_destroy", "lb_last_error"]
+            "lb_debug_lanes", "lb_destroy", "lb_last_error",
+            "lb_pool_create", "lb_pool_bytes", "lb_pool_footprint", "lb_pool_bind", "lb_pool_admit_riemann",
+            "lb_pool_admit_moments", "lb_pool_release", "lb_pool_advance", "lb_pool_advance_timed",
+            "lb_pool_poll", "lb_pool_moments", "lb_pool_totals", "lb_pool_lambda", "lb_pool_live",
+            "lb_pool_shapes", "lb_pool_shape", "lb_pool_set_shape", "lb_pool_autotune", "lb_pool_use_graph",
+            "lb_pool_destroy"]
 
 
 class LBError(RuntimeError):
@@ -85,6 +90,28 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lb_debug_lanes": (ctypes.c_int, [vp, I32P, I32P, I32P]),
         "lb_destroy": (None, [vp]),
         "lb_last_error": (ctypes.c_char_p, []),
+        "lb_pool_create": (ctypes.c_int, [i32, dbl, ctypes.POINTER(lb_velset), i32, i32, ctypes.c_size_t,
+                                          ctypes.POINTER(vp)]),
+        "lb_pool_bytes": (ctypes.c_size_t, [vp]),
+        "lb_pool_footprint": (ctypes.c_size_t, [vp, i64, i64]),
+        "lb_pool_bind": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+        "lb_pool_admit_riemann": (ctypes.c_int, [vp, ctypes.POINTER(lb_grid), dbl, dbl, ctypes.POINTER(lb_prim),
+                                                 ctypes.POINTER(lb_prim), i64, I32P]),
+        "lb_pool_admit_moments": (ctypes.c_int, [vp, ctypes.POINTER(lb_grid), D, dbl, i64, I32P]),
+        "lb_pool_release": (ctypes.c_int, [vp, i32]),
+        "lb_pool_advance": (ctypes.c_int, [vp, i64]),
+        "lb_pool_advance_timed": (ctypes.c_int, [vp, i64, ctypes.POINTER(ctypes.c_float)]),
+        "lb_pool_poll": (ctypes.c_int, [vp, i32, ctypes.POINTER(ctypes.c_int64), I32P]),
+        "lb_pool_moments": (ctypes.c_int, [vp, i32, vp, i32]),
+        "lb_pool_totals": (ctypes.c_int, [vp, i32, D]),
+        "lb_pool_lambda": (dbl, [vp, i32]),
+        "lb_pool_live": (i32, [vp]),
+        "lb_pool_shapes": (i32, [vp]),
+        "lb_pool_shape": (i32, [vp]),
+        "lb_pool_set_shape": (ctypes.c_int, [vp, i32]),
+        "lb_pool_autotune": (ctypes.c_int, [vp, i32, I32P, ctypes.POINTER(ctypes.c_float)]),
+        "lb_pool_use_graph": (ctypes.c_int, [vp, i32]),
+        "lb_pool_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -227,3 +254,140 @@ class Solver:
 
     def max_reach(self) -> int:
         return int(_lib.lb_max_reach(self._h))
+
+
+class Pool:
+    """Many independent problems of one lattice and precision, advanced by one
+    persistent launch per step (include/lbsd.h, lb_pool_*).  Memory: one
+    uint8 torch tensor; stream: a dedicated torch stream (graph capture needs
+    a non-default stream)."""
+
+    def __init__(self, dim: int, max_slots: int, arena_bytes: int, *, gamma: float = 1.4, d0_frac=None,
+                 precision: str = "fp32", device=None, stream=None):
+        import torch
+
+        if d0_frac is None:
+            d0_frac = 0.5 if dim == 1 else 0.0
+        self.dim, self.nf, self.precision = dim, dim + 2, precision
+        vs = lb_velset(LB_LATTICE_D1_TRIPLE if dim == 1 else LB_LATTICE_D2_SQUARE_DUAL, d0_frac)
+        prec = {"fp64": LB_FP64, "fp32": LB_FP32}[precision]
+        h = ctypes.c_void_p()
+        _check(_lib.lb_pool_create(dim, gamma, ctypes.byref(vs), prec, int(max_slots), int(arena_bytes),
+                                   ctypes.byref(h)))
+        self._h = h
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        nbytes = int(_lib.lb_pool_bytes(h))
+        self._buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(self.device) if stream is None else stream
+        torch.cuda.synchronize(self.device)  # the buffer exists before the pool's stream uses it
+        _check(_lib.lb_pool_bind(h, ctypes.c_void_p(self._buf.data_ptr()), nbytes,
+                                 ctypes.c_void_p(self.stream.cuda_stream)))
+        self._shape = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lb_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def footprint(self, nx: int, ny: int = 1) -> int:
+        return int(_lib.lb_pool_footprint(self._h, int(nx), int(ny)))
+
+    def _grid(self, nx, ny, bc_x, bc_y, x_lo, x_hi):
+        ny = int(ny) if self.dim == 2 else 1
+        return lb_grid(self.dim, int(nx), ny, float(x_lo), float(x_hi), _bc(bc_x), _bc(bc_y))
+
+    def admit_riemann(self, nx: int, x_d: float, left, right, steps: int, *, ny: int = 1, lam: float = 0.0,
+                      bc_x="transmissive", bc_y="periodic", x_lo: float = 0.0, x_hi: float = 1.0):
+        """Slot index, or None when the pool has no room now (LB_ENOMEM)."""
+        g = self._grid(nx, ny, bc_x, bc_y, x_lo, x_hi)
+        L, R = lb_prim(*map(float, left)), lb_prim(*map(float, right))
+        slot = ctypes.c_int32(-1)
+        rc = _lib.lb_pool_admit_riemann(self._h, ctypes.byref(g), float(lam), float(x_d), ctypes.byref(L),
+                                        ctypes.byref(R), int(steps), ctypes.byref(slot))
+        if rc == LB_ENOMEM:
+            return None
+        _check(rc)
+        self._shape[slot.value] = (self.nf, g.ny, g.nx)
+        return slot.value
+
+    def admit_moments(self, Y, lam: float, steps: int, *, bc_x="transmissive", bc_y="periodic",
+                      x_lo: float = 0.0, x_hi: float = 1.0):
+        Y = np.ascontiguousarray(Y, dtype=np.float64)
+        ny, nx = (Y.shape[1], Y.shape[2]) if Y.ndim == 3 else (1, Y.shape[-1])
+        g = self._grid(nx, ny, bc_x, bc_y, x_lo, x_hi)
+        slot = ctypes.c_int32(-1)
+        rc = _lib.lb_pool_admit_moments(self._h, ctypes.byref(g), Y.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        float(lam), int(steps), ctypes.byref(slot))
+        if rc == LB_ENOMEM:
+            return None
+        _check(rc)
+        self._shape[slot.value] = (self.nf, g.ny, g.nx)
+        return slot.value
+
+    def release(self, slot: int):
+        _check(_lib.lb_pool_release(self._h, int(slot)))
+        self._shape.pop(int(slot), None)
+
+    def advance(self, n: int = 1):
+        _check(_lib.lb_pool_advance(self._h, int(n)))
+
+    def advance_timed(self, n: int) -> float:
+        ms = ctypes.c_float(0.0)
+        _check(_lib.lb_pool_advance_timed(self._h, int(n), ctypes.byref(ms)))
+        return float(ms.value)
+
+    def poll(self, slot: int):
+        """(steps done, status): status 0 running, 1 finished, LB_EREACH / LB_ESTATE failed."""
+        done, st = ctypes.c_int64(0), ctypes.c_int32(0)
+        _check(_lib.lb_pool_poll(self._h, int(slot), ctypes.byref(done), ctypes.byref(st)))
+        return int(done.value), int(st.value)
+
+    def moments(self, slot: int) -> np.ndarray:
+        out = np.empty(self._shape[int(slot)], dtype=np.float64)
+        _check(_lib.lb_pool_moments(self._h, int(slot), ctypes.c_void_p(out.ctypes.data), 0))
+        return out
+
+    def moments_device(self, slot: int):
+        import torch
+
+        out = torch.empty(self._shape[int(slot)], dtype=torch.float64, device=self.device)
+        _check(_lib.lb_pool_moments(self._h, int(slot), ctypes.c_void_p(out.data_ptr()), 1))
+        return out
+
+    def totals(self, slot: int) -> np.ndarray:
+        out = np.zeros(4, dtype=np.float64)
+        _check(_lib.lb_pool_totals(self._h, int(slot), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def lam(self, slot: int) -> float:
+        return float(_lib.lb_pool_lambda(self._h, int(slot)))
+
+    @property
+    def live(self) -> int:
+        return int(_lib.lb_pool_live(self._h))
+
+    @property
+    def shapes(self) -> int:
+        return int(_lib.lb_pool_shapes(self._h))
+
+    @property
+    def shape(self) -> int:
+        return int(_lib.lb_pool_shape(self._h))
+
+    def set_shape(self, shape: int):
+        _check(_lib.lb_pool_set_shape(self._h, int(shape)))
+
+    def autotune(self, trials: int = 5):
+        """(best shape, its median ms per step)."""
+        best, ms = ctypes.c_int32(-1), ctypes.c_float(0.0)
+        _check(_lib.lb_pool_autotune(self._h, int(trials), ctypes.byref(best), ctypes.byref(ms)))
+        return int(best.value), float(ms.value)
+
+    def use_graph(self, steps_per_graph: int):
+        _check(_lib.lb_pool_use_graph(self._h, int(steps_per_graph)))

@@ -70,3 +70,38 @@ def test_calls_on_unbound_solver_fail_cleanly():
     assert lbsd._lib.lb_set_cfl(h, 0.0) == lbsd.LB_EINVAL
     assert lbsd._lib.lb_bind(h, None, 0, None) == lbsd.LB_EINVAL
     lbsd._lib.lb_destroy(h)
+
+
+def _pool(lbsd, dim=1, gamma=1.4, d0=None, prec=0, slots=8, arena=1 << 20):
+    vs = lbsd.lb_velset(1 if dim == 1 else 2, (0.5 if dim == 1 else 0.0) if d0 is None else d0)
+    h = ctypes.c_void_p()
+    rc = lbsd._lib.lb_pool_create(dim, gamma, ctypes.byref(vs), prec, slots, arena, ctypes.byref(h))
+    return rc, h
+
+
+def test_pool_create_validation_and_sizes():
+    from paper_1602_02675_amd import lbsd
+
+    rc, h = _pool(lbsd)
+    assert rc == lbsd.LB_OK
+    assert lbsd._lib.lb_pool_bytes(h) >= 1 << 20
+    # footprint: two FP64 sets of 3 fields, each rounded up to 256 bytes
+    assert lbsd._lib.lb_pool_footprint(h, 1000, 1) == 2 * ((3 * 1000 * 8 + 255) // 256 * 256)
+    assert lbsd._lib.lb_pool_shapes(h) == 5
+    # unbound pool: no admission, no stepping
+    g = lbsd.lb_grid(1, 100, 1, 0.0, 1.0, 0, 1)
+    L = lbsd.lb_prim(1.0, 0.0, 0.0, 1.0)
+    slot = ctypes.c_int32(-1)
+    assert lbsd._lib.lb_pool_admit_riemann(h, ctypes.byref(g), 0.0, 0.5, ctypes.byref(L), ctypes.byref(L), 10,
+                                           ctypes.byref(slot)) == lbsd.LB_EINVAL
+    assert lbsd._lib.lb_pool_advance(h, 1) == lbsd.LB_EINVAL
+    assert lbsd._lib.lb_pool_bind(h, None, 0, None) == lbsd.LB_EINVAL
+    lbsd._lib.lb_pool_destroy(h)
+    for kw in (dict(gamma=1.0), dict(dim=3), dict(dim=2, d0=0.3), dict(prec=9), dict(slots=0),
+               dict(arena=16), dict(d0=1.0)):
+        rc, h = _pool(lbsd, **kw)
+        assert rc == lbsd.LB_EINVAL, kw
+    rc, h = _pool(lbsd, dim=2, prec=1)
+    assert rc == lbsd.LB_OK
+    assert lbsd._lib.lb_pool_footprint(h, 64, 64) == 2 * 4 * 64 * 64 * 4
+    lbsd._lib.lb_pool_destroy(h)
