@@ -1,17 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the tau = 1 semi-discrete LB step on one MI355X.
 
-Workload: a 2-D planar shock tube on the square dual-level lattice,
+Headline: a 2-D planar shock tube on the square dual-level lattice,
 4096 x 4096 nodes, seeded Riemann state (rho_L = 1, p_L = 1, u = 0; pressure
 ratio log-uniform in [2, 100], density ratio in [1, 10], diaphragm in
 [0.3, 0.7]; seed 0), lambda from the CFL bound of the initial states,
-transmissive in x, periodic in y.  A step is one pass of the whole step (the
-fused gather kernel plus its totals reduction).  The FP64 plain form is the
-headline number; the FP32 form runs the same workload for comparison
-(node-updates/s and relative L1 density error against FP64).
+transmissive in x, periodic in y; FP64 plain form, one step = the fused
+gather kernel plus its totals reduction.  Alongside, in the same JSON line:
 
-Prints one JSON line.  `--profile` runs a short version plus a plain device
-copy of known size, for rocprofv3 counter runs.
+* fp32:  the same workload in the FP32 form (node-updates/s and relative L1
+  density error against FP64 after the timed steps);
+* batch: 512 independent 1-D tubes, lengths log-uniform in [256, 65536],
+  seeded states, 1000 steps, one persistent launch per step over all tubes,
+  HIP-graph captured, tile shape autotuned, FP32 and FP64;
+* serve: square-lattice requests (sides log-uniform in [64, 2048], steps in
+  [100, 5000], seeded states) arriving as a Poisson process at 0.8 x the
+  measured capacity, continuously batched on an FP32 pool: p50 / p99
+  latency and aggregate node-updates/s;
+* cpu_baseline: the FP64 oracle on a bounded sample, one host thread.
+
+`--profile` runs a short headline plus a plain device copy of known size,
+for rocprofv3 counter runs.
 """
 from __future__ import annotations
 
@@ -92,6 +101,49 @@ def cpu_baseline(seconds_target: float = 15.0):
                 sample=f"{n}x{n} nodes of the same seeded planar tube, {more} steps, FP64, 1 thread")
 
 
+def run_batch(precision: str, steps: int = 1000, n_tubes: int = 512, seed: int = 0):
+    """512 seeded 1-D tubes in one pool: autotune, graph, time `steps` steps."""
+    from paper_1602_02675_amd import inputs
+    from paper_1602_02675_amd.lbsd import Pool
+
+    lens = inputs.tube_lengths(seed, n_tubes)
+    elem = 8 if precision == "fp64" else 4
+    arena = int(sum(2 * (((3 * int(L) * elem) + 255) // 256 * 256) for L in lens)) + (1 << 20)
+    pool = Pool(1, n_tubes, arena, precision=precision)
+    for i, L in enumerate(lens):
+        left, right, xd = inputs.riemann_instance(seed * 100000 + i)
+        pool.admit_riemann(int(L), xd, left, right, steps + 10 ** 6, lam=inputs.cfl_lambda([left, right]))
+    best, tuned_ms = pool.autotune(trials=5)
+    pool.use_graph(50)
+    pool.advance(50)  # warm-up (and graph capture)
+    ms = pool.advance_timed(steps)
+    nodes = int(lens.sum())
+    pool.close()
+    return dict(value=round(nodes * steps / (ms * 1e-3) / 1e6, 1), unit="MLUPS", tubes=n_tubes, nodes=nodes,
+                steps=steps, ms_per_step=round(ms / steps, 5), tile_shape=best,
+                achieved_GBs=round(2 * 3 * elem * nodes / (ms * 1e-3 / steps) / 1e9, 1))
+
+
+def run_serve(n_requests: int = 100, seed: int = 0):
+    """Poisson arrivals at 0.8 x measured capacity on an FP32 square-lattice pool."""
+    from paper_1602_02675_amd import inputs, serve
+    from paper_1602_02675_amd.lbsd import Pool
+
+    probe = inputs.serve_requests(seed, n_requests, rate_per_s=1.0)
+    pool = Pool(2, 64, 24 << 30, precision="fp32")
+    pool.use_graph(25)
+    cap_nups, shape = serve.calibrate(pool, probe)
+    mean_work = sum(r["side"] ** 2 * r["steps"] for r in probe) / len(probe)
+    rate = 0.8 * cap_nups / mean_work
+    reqs = inputs.serve_requests(seed, n_requests, rate_per_s=rate)
+    res = serve.run(pool, reqs, tick=25)
+    pool.close()
+    return dict(value=round(res["nups"] / 1e6, 1), unit="MLUPS", requests=n_requests,
+                rate_per_s=round(rate, 3), capacity_MLUPS=round(cap_nups / 1e6, 1),
+                p50_latency_s=round(res["p50_s"], 4), p99_latency_s=round(res["p99_s"], 4),
+                makespan_s=round(res["makespan_s"], 3), tile_shape=shape, precision="fp32")
+
+
 def traffic_per_launch():
     """HBM bytes per step-kernel launch from the committed counter summary,
     or None when the kernel source changed since the counters were taken."""
@@ -112,6 +164,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="short run + a plain copy of known size, for rocprofv3 counters")
     args = ap.parse_args()
@@ -175,6 +229,10 @@ def main():
                        "rel_l1_density_vs_fp64": rel_l1,
                        "achieved_GBs": round(BYTES_PER_NODE["fp32"] * nodes /
                                              (r32["kernel_ms"] / 1e3 / args.steps) / 1e9, 1)}
+    if not args.no_batch:
+        out["batch"] = {p: run_batch(p) for p in ("fp32", "fp64")}
+    if not args.no_serve:
+        out["serve"] = run_serve()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

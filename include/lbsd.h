@@ -199,6 +199,10 @@ int lb_pool_advance(lb_pool* p, int64_t n);
 int lb_pool_advance_timed(lb_pool* p, int64_t n, float* ms);
 
 int lb_pool_poll(lb_pool* p, int32_t slot, int64_t* steps_done, int32_t* status);
+/* lb_pool_poll for every slot at once: arrays of max_slots entries; a free
+ * slot reports 0 steps and status LB_POOL_FREE. */
+#define LB_POOL_FREE (-100)
+int lb_pool_status(lb_pool* p, int64_t* steps_done, int32_t* status);
 /* As lb_moments / lb_totals for one slot (lb_pool_totals: LB_EINVAL before its first step). */
 int lb_pool_moments(lb_pool* p, int32_t slot, double* out, int32_t out_on_device);
 int lb_pool_totals(lb_pool* p, int32_t slot, double out[4]);

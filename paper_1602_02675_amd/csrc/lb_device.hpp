@@ -223,4 +223,16 @@ __device__ __forceinline__ int64_t clamp_idx(int64_t i, int64_t n)
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
+// Persistent blocks take tiles from a shared counter in claim order: a slow
+// tile (a transition region, a hot problem) then delays only the block that
+// holds it.  Which block computes a tile changes no result.  *s_slot is a
+// shared-memory int; every thread of the block must call this.
+__device__ __forceinline__ int claim_tile(int* counter, int* s_slot)
+{
+    __syncthreads();  // the previous claim has been read by every thread
+    if (threadIdx.x == 0) *s_slot = atomicAdd(counter, 1);
+    __syncthreads();
+    return *s_slot;
+}
+
 }  // namespace lbsd

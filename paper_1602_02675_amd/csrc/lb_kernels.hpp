@@ -15,7 +15,7 @@ constexpr int kErrState = 2;  // rho <= 0 or a non-finite moment
 
 // Per-solver control block in device memory (written by the step kernels).
 struct StepCtl {
-    unsigned int counter;   // unused (kept for layout)
+    int next[2];            // tile claim counters of the two square-lattice passes (reset by finalize)
     int err_code;           // kErr* bits of the first failed step
     long long err_step;     // first failed step (LLONG_MAX if none)
     long long totals_step;  // step whose totals are in `totals`
@@ -23,7 +23,7 @@ struct StepCtl {
     int max_reach;          // largest reach seen in the latest step
     int redo_count;         // steps the square-lattice kernel had to redo with its full FIFO
     long long redo_step;    // step whose short-FIFO pass found a y-reach beyond its FIFO
-    int pad[4];
+    int pad[3];
 };
 
 // Per-block partial results: 4 field sums, reach, error bits.
@@ -43,15 +43,16 @@ hipError_t launch_step1d(const T* Y, T* Yn, const Grid& g, const Consts& k, Step
                          double* partials, long long step, hipStream_t stream);
 int64_t step_blocks_1d(const Grid& g);
 
-// Square lattice, column-march kernel (lb_march2d.hip).  The launch
-// geometry (strip height, blocks) is chosen per device so that one wave of
-// resident blocks covers the grid.
+// Square lattice, column-march kernel (lb_march2d.hip).  The grid is cut into
+// tiles (column strips x row chunks) that the device's resident blocks claim
+// one after another.
 struct MarchGeom {
-    int sy;                   // destination rows per block
-    int64_t grid_x, grid_y;   // blocks along x (column strips) and y (row chunks)
-    int64_t blocks() const { return grid_x * grid_y; }
+    int sy;                   // destination rows per tile
+    int64_t grid_x, grid_y;   // tiles along x (column strips) and y (row chunks)
+    int nblocks;              // persistent blocks (resident at once)
+    int64_t blocks() const { return grid_x * grid_y; }  // tiles (= rows of partials)
 };
-MarchGeom march2d_geometry(const Grid& g, int target_blocks);
+MarchGeom march2d_geometry(const Grid& g, int resident_blocks);
 int64_t march2d_max_blocks(const Grid& g);
 template <typename T>
 int march2d_blocks_per_cu();
@@ -119,6 +120,7 @@ struct PoolView {
     const int32_t* ntiles;  // live tiles (read by the kernels, so admissions need no new launch shape)
     double* partials;       // kPartialStride doubles per tile
     int32_t* flags;         // square lattice: tile needs the full-FIFO pass
+    int32_t* next;          // tile claim counters: [0] step pass, [1] full-FIFO pass; reset by finalize
     void* arena;            // moment sets of all slots (T elements)
 };
 

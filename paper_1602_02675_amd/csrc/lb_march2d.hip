@@ -593,39 +593,50 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
 #ifndef LB_MARCH_WPE
 #define LB_MARCH_WPE 2
 #endif
-// L = kLSmall: the short-FIFO pass; a block whose sources reach beyond the
+// L = kLSmall: the short-FIFO pass; a tile whose sources reach beyond the
 // FIFO marks the step for a redo.  L = kLFull with redo_only: runs only if the
-// short pass of this step asked for it, and then recomputes every block.
+// short pass of this step asked for it, and then recomputes every tile.
+// Persistent blocks claim the tiles (tiles_x column strips x row chunks of sy
+// rows, row chunk major) from the control block's counter of the pass.
 template <typename T, int L>
 __global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? LB_MARCH_WPE : 1)))
 march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
                StepCtl* __restrict__ ctl, double* __restrict__ partials, long long step, int sy,
-               int redo_only)
+               int tiles_x, int ntiles, int redo_only)
 {
+    __shared__ int s_t;
     if (ctl->err_step < step) return;
     if (redo_only && ctl->redo_step != step) return;
-    const int64_t bid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    const int far = march_tile<T, L>(Y, Yn, g, k, (int64_t)blockIdx.x * (kMTPB - 2 * kMH),
-                                     (int64_t)blockIdx.y * sy, sy, partials + bid * kPartialStride);
+    int far = 0;
+    for (;;) {
+        const int t = claim_tile(&ctl->next[L < kLFull ? 0 : 1], &s_t);
+        if (t >= ntiles) break;
+        const int64_t tx = t % tiles_x, ty = t / tiles_x;
+        far |= march_tile<T, L>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
+                                partials + (int64_t)t * kPartialStride);
+    }
     if (threadIdx.x == 0) {
         if (L < kLFull) {
             if (far) ctl->redo_step = step;
-        } else if (redo_only && bid == 0) {
+        } else if (redo_only && blockIdx.x == 0) {
             ctl->redo_count += 1;
         }
     }
 }
 
-// Pool form: persistent blocks walk the tile table (see pool1d_kernel).  The
-// short-FIFO pass flags the tiles it could not complete; the full-FIFO pass
-// recomputes only those.
+// Pool form: persistent blocks claim tiles of the tile table (see
+// pool1d_kernel).  The short-FIFO pass flags the tiles it could not complete;
+// the full-FIFO pass recomputes only those.
 template <typename T, int L>
 __global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? LB_MARCH_WPE : 1)))
 pool2d_kernel(PoolView v, Consts k)
 {
+    __shared__ int s_t;
     const int nt = *v.ntiles;
     T* arena = (T*)v.arena;
-    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (;;) {
+        const int t = claim_tile(&v.next[L < kLFull ? 0 : 1], &s_t);
+        if (t >= nt) break;
         if (L == kLFull && v.flags[t] == 0) continue;
         const PoolTile tl = v.tiles[t];
         const PoolProb& P = v.probs[tl.prob];
@@ -644,19 +655,26 @@ int64_t x_strips(const Grid& g) { return (g.nx + (kMTPB - 2 * kMH) - 1) / (kMTPB
 
 }  // namespace
 
-MarchGeom march2d_geometry(const Grid& g, int target_blocks)
+#ifndef LB_MARCH_TILES_X10
+#define LB_MARCH_TILES_X10 30  // tiles per resident block, times 10
+#endif
+MarchGeom march2d_geometry(const Grid& g, int resident_blocks)
 {
     MarchGeom m;
     const int64_t xs = x_strips(g);
-    // as many row chunks per column strip as keep every block resident at
-    // once (no second, nearly empty round of blocks)
-    int64_t chunks = target_blocks > 0 ? target_blocks / xs : 1;
+    // strips short enough for about LB_MARCH_TILES_X10 / 10 tiles per resident
+    // block (claim-order balance), but not below kMinRows (the 2L halo rows of
+    // each tile are marched again)
+    const int64_t want = ((int64_t)LB_MARCH_TILES_X10 * (resident_blocks > 0 ? resident_blocks : 1) + 9) / 10;
+    int64_t chunks = (want + xs - 1) / xs;
     if (chunks < 1) chunks = 1;
     int64_t sy = (g.ny + chunks - 1) / chunks;
     if (sy < kMinRows) sy = kMinRows;
     m.sy = (int)sy;
     m.grid_x = xs;
     m.grid_y = (g.ny + sy - 1) / sy;
+    m.nblocks = resident_blocks > 0 ? resident_blocks : 1;
+    if (m.nblocks > m.blocks()) m.nblocks = (int)m.blocks();
     return m;
 }
 
@@ -679,14 +697,15 @@ hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, 
                           StepCtl* ctl, double* partials, long long step, bool full_only,
                           hipStream_t stream)
 {
-    const dim3 grid((unsigned)m.grid_x, (unsigned)m.grid_y);
+    const int nt = (int)m.blocks();
     if (!full_only) {
-        march2d_kernel<T, kLSmall><<<grid, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step, m.sy, 0);
+        march2d_kernel<T, kLSmall><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step, m.sy,
+                                                                    (int)m.grid_x, nt, 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    march2d_kernel<T, kLFull><<<grid, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step, m.sy,
-                                                          full_only ? 0 : 1);
+    march2d_kernel<T, kLFull><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step, m.sy,
+                                                               (int)m.grid_x, nt, full_only ? 0 : 1);
     return hipGetLastError();
 }
 

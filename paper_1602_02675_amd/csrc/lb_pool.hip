@@ -72,6 +72,7 @@ PoolView view_of(const lb_pool* p)
     v.ntiles = (const int32_t*)(p->base + p->off_ntiles);
     v.partials = (double*)(p->base + p->off_partials);
     v.flags = (int32_t*)(p->base + p->off_flags);
+    v.next = (int32_t*)(p->base + p->off_ntiles + 64);
     v.arena = p->base + p->off_arena;
     return v;
 }
@@ -149,7 +150,7 @@ int upload_tables(lb_pool* p)
     }
     if ((int64_t)p->tiles.size() > p->max_tiles) return fail(LB_ENOMEM, "tile table full");
     const int32_t nt = (int32_t)p->tiles.size();
-    std::vector<int32_t> zeros((size_t)std::max<int32_t>(nt, 1), 0);
+    std::vector<int32_t> zeros((size_t)std::max<int32_t>(nt, 2), 0);
     hipError_t e;
     if ((e = hipMemcpyAsync(p->base + p->off_probs, p->probs.data(), p->probs.size() * sizeof(PoolProb),
                             hipMemcpyHostToDevice, p->stream)) != hipSuccess)
@@ -160,6 +161,9 @@ int upload_tables(lb_pool* p)
     if ((e = hipMemcpyAsync(p->base + p->off_ntiles, &nt, sizeof nt, hipMemcpyHostToDevice, p->stream)) !=
         hipSuccess)
         return hip_fail(e, "upload tile count");
+    if ((e = hipMemcpyAsync(p->base + p->off_ntiles + 64, zeros.data(), 2 * sizeof(int32_t),
+                            hipMemcpyHostToDevice, p->stream)) != hipSuccess)
+        return hip_fail(e, "clear claim counters");
     if (nt > 0 && (e = hipMemcpyAsync(p->base + p->off_flags, zeros.data(), (size_t)nt * 4,
                                       hipMemcpyHostToDevice, p->stream)) != hipSuccess)
         return hip_fail(e, "clear flags");
@@ -388,7 +392,7 @@ int lb_pool_create(int32_t dim, double gamma, const lb_velset* vs, int32_t preci
     p->off_state = align256((size_t)max_slots * sizeof(PoolProb));
     p->off_tiles = p->off_state + align256((size_t)max_slots * sizeof(PoolState));
     p->off_ntiles = p->off_tiles + align256((size_t)p->max_tiles * sizeof(PoolTile));
-    p->off_partials = p->off_ntiles + 256;
+    p->off_partials = p->off_ntiles + 256;  // tile count at +0, claim counters at +64
     p->off_flags = p->off_partials + align256((size_t)p->max_tiles * kPartialStride * 8);
     p->off_arena = p->off_flags + align256((size_t)p->max_tiles * 4);
     p->total = p->off_arena + p->arena_bytes;
@@ -536,6 +540,30 @@ int lb_pool_poll(lb_pool* p, int32_t slot, int64_t* steps_done, int32_t* status)
     if (status) {
         if (st.err_step != 0) *status = (st.err_code & kErrState) ? LB_ESTATE : LB_EREACH;
         else *status = st.done >= p->probs[(size_t)slot].target ? 1 : 0;
+    }
+    return LB_OK;
+}
+
+int lb_pool_status(lb_pool* p, int64_t* steps_done, int32_t* status)
+{
+    if (!p || !p->bound) return fail(LB_EINVAL, "pool not bound");
+    if (!steps_done || !status) return fail(LB_EINVAL, "null argument");
+    std::vector<PoolState> st;
+    try { st.resize((size_t)p->max_slots); } catch (...) { return fail(LB_ENOMEM, "host allocation failed"); }
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "sync");
+    e = hipMemcpy(st.data(), p->base + p->off_state, st.size() * sizeof(PoolState), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read slot states");
+    for (int32_t i = 0; i < p->max_slots; ++i) {
+        const PoolState& q = st[(size_t)i];
+        if (!p->probs[(size_t)i].active) {
+            steps_done[i] = 0;
+            status[i] = -100;
+            continue;
+        }
+        steps_done[i] = q.done;
+        if (q.err_step != 0) status[i] = (q.err_code & kErrState) ? LB_ESTATE : LB_EREACH;
+        else status[i] = q.done >= p->probs[(size_t)i].target ? 1 : 0;
     }
     return LB_OK;
 }

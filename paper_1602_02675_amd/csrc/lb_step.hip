@@ -113,6 +113,10 @@ finalize_kernel(const double* __restrict__ partials, int64_t nb, StepCtl* __rest
 {
     __shared__ double s_sum[kFinTPB / 64][4];
     __shared__ int s_ir[kFinTPB / 64][2];
+    if (threadIdx.x == 0) {  // the step kernels of this step are done with their counters
+        ctl->next[0] = 0;
+        ctl->next[1] = 0;
+    }
     if (ctl->err_step < step) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
@@ -332,9 +336,12 @@ step1d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
 template <typename T, int TPB, int J>
 __global__ void __launch_bounds__(TPB) pool1d_kernel(PoolView v, Consts k)
 {
+    __shared__ int s_t;
     const int nt = *v.ntiles;
     T* arena = (T*)v.arena;
-    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (;;) {
+        const int t = claim_tile(&v.next[0], &s_t);
+        if (t >= nt) break;
         const PoolTile tl = v.tiles[t];
         const PoolProb& P = v.probs[tl.prob];
         const PoolState& S = v.state[tl.prob];
@@ -355,6 +362,10 @@ __global__ void __launch_bounds__(kFinTPB) pool_finalize_kernel(PoolView v, int 
     __shared__ double s_sum[kFinTPB / 64][4];
     __shared__ int s_ir[kFinTPB / 64][2];
     const int p = blockIdx.x;
+    if (p == 0 && threadIdx.x == 0) {  // the step kernels of this step are done with their counters
+        v.next[0] = 0;
+        v.next[1] = 0;
+    }
     const PoolProb& P = v.probs[p];
     PoolState& S = v.state[p];
     if (!P.active || S.done >= P.target || S.err_step != 0) return;

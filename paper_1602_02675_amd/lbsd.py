@@ -25,6 +25,7 @@ LB_BC_TRANSMISSIVE, LB_BC_PERIODIC = 0, 1
 LB_LATTICE_D1_TRIPLE, LB_LATTICE_D2_SQUARE_DUAL = 1, 2
 LB_FP64, LB_FP32 = 0, 1
 LB_HALO = 5
+LB_POOL_FREE = -100
 
 _ERR_NAMES = {LB_EINVAL: "LB_EINVAL", LB_ENOMEM: "LB_ENOMEM", LB_EDEVICE: "LB_EDEVICE",
               LB_ESTATE: "LB_ESTATE", LB_EREACH: "LB_EREACH"}
@@ -35,7 +36,7 @@ EXPORTED = ["lb_create", "lb_state_bytes", "lb_bind", "lb_set_lambda", "lb_set_c
             "lb_debug_lanes", "lb_destroy", "lb_last_error",
             "lb_pool_create", "lb_pool_bytes", "lb_pool_footprint", "lb_pool_bind", "lb_pool_admit_riemann",
             "lb_pool_admit_moments", "lb_pool_release", "lb_pool_advance", "lb_pool_advance_timed",
-            "lb_pool_poll", "lb_pool_moments", "lb_pool_totals", "lb_pool_lambda", "lb_pool_live",
+            "lb_pool_poll", "lb_pool_status", "lb_pool_moments", "lb_pool_totals", "lb_pool_lambda", "lb_pool_live",
             "lb_pool_shapes", "lb_pool_shape", "lb_pool_set_shape", "lb_pool_autotune", "lb_pool_use_graph",
             "lb_pool_destroy"]
 
@@ -102,6 +103,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lb_pool_advance": (ctypes.c_int, [vp, i64]),
         "lb_pool_advance_timed": (ctypes.c_int, [vp, i64, ctypes.POINTER(ctypes.c_float)]),
         "lb_pool_poll": (ctypes.c_int, [vp, i32, ctypes.POINTER(ctypes.c_int64), I32P]),
+        "lb_pool_status": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int64), I32P]),
         "lb_pool_moments": (ctypes.c_int, [vp, i32, vp, i32]),
         "lb_pool_totals": (ctypes.c_int, [vp, i32, D]),
         "lb_pool_lambda": (dbl, [vp, i32]),
@@ -269,6 +271,8 @@ class Pool:
         if d0_frac is None:
             d0_frac = 0.5 if dim == 1 else 0.0
         self.dim, self.nf, self.precision = dim, dim + 2, precision
+        self.max_slots = int(max_slots)
+        self.arena_bytes = int(arena_bytes)
         vs = lb_velset(LB_LATTICE_D1_TRIPLE if dim == 1 else LB_LATTICE_D2_SQUARE_DUAL, d0_frac)
         prec = {"fp64": LB_FP64, "fp32": LB_FP32}[precision]
         h = ctypes.c_void_p()
@@ -347,6 +351,14 @@ class Pool:
         done, st = ctypes.c_int64(0), ctypes.c_int32(0)
         _check(_lib.lb_pool_poll(self._h, int(slot), ctypes.byref(done), ctypes.byref(st)))
         return int(done.value), int(st.value)
+
+    def status(self):
+        """(steps done, status) arrays over all slots; free slots have status LB_POOL_FREE."""
+        done = np.zeros(self.max_slots, dtype=np.int64)
+        st = np.zeros(self.max_slots, dtype=np.int32)
+        _check(_lib.lb_pool_status(self._h, done.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return done, st
 
     def moments(self, slot: int) -> np.ndarray:
         out = np.empty(self._shape[int(slot)], dtype=np.float64)

@@ -202,3 +202,22 @@ def test_pool_autotune_keeps_states(lbsd):
     for s, b in zip(slots, before):
         assert np.array_equal(pool.moments(s), b)
     pool.close()
+
+
+def test_serve_loop_results_match_alone(lbsd):
+    from paper_1602_02675_amd import serve
+
+    reqs = inputs.serve_requests(11, 6, rate_per_s=200.0, side_lo=32, side_hi=160, steps_lo=5, steps_hi=50)
+    refs = [alone(lbsd, 2, r["side"], r["side"], r["x_d"], r["left"], r["right"],
+                  inputs.cfl_lambda([r["left"], r["right"]]), r["steps"], "fp32") for r in reqs]
+    pool = lbsd.Pool(2, 2, 3 * 2 * 4 * 160 * 160 * 4, precision="fp32")
+    pool.use_graph(5)
+    got = {}
+    res = serve.run(pool, reqs, tick=5, fetch="moments", on_result=lambda i, m: got.__setitem__(i, m))
+    assert sorted(got) == list(range(len(reqs)))
+    for i, ref in enumerate(refs):
+        assert np.array_equal(got[i], ref), i
+    lat = res["latency_s"]
+    assert np.all(lat > 0) and res["p99_s"] >= res["p50_s"] > 0
+    assert res["nups"] > 0 and pool.live == 0
+    pool.close()
