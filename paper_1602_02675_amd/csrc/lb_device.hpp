@@ -37,9 +37,11 @@ struct Src1 {   // one source node of the 1-D lattice
 };
 
 template <typename T>
-struct Src2 {   // one source node of the square lattice
+struct Src2 {   // one source node of the square lattice, as the gather uses it
     int fx, fy, c1;
-    T rx, ry, d1, d2, K;
+    T vx, ry;     // v_x (lattice units) and the y fraction r_y = v_y - floor(v_y)
+    T m[2][2];    // packet mass of level l + 1 (speed c'_{l+1}) at x corner k: d (1 - r_x), d r_x
+    T kk[2];      // K + c'^2 / 2 for c' = c'_1, c'_2, with K = |v|^2 / 2 + phi
     bool bad;
 };
 
@@ -58,7 +60,9 @@ template <typename T>
 __device__ __forceinline__ int isqrt_floor(T A)
 {
 #pragma clang fp contract(off)
-    int c = (int)dev_floor<T>(dev_sqrt<T>(A));
+    // a single-precision root is within one of floor(sqrt(A)) for the clamped
+    // A <= kMaxC1^2 (relative error < 1e-7); the exact comparisons settle it
+    int c = (int)sqrtf((float)A);
     if (c > 0 && (T)c * (T)c > A) --c;
     if ((T)(c + 1) * (T)(c + 1) <= A) ++c;
     return c;
@@ -95,6 +99,20 @@ __device__ __forceinline__ Levels<T> node_levels(T rho, T v2, T E, T d0, const C
 template <typename T>
 __device__ __forceinline__ bool finite_val(T x) { return isfinite(x); }
 
+// w = (A - c'_1^2) / (2 c'_1 + 1) in [0, 1]: the share of level 2 (eq. 24-25
+// rewritten; b_1 d_2 = (rho - b_0 d_0) w).  The divisor is a small odd
+// integer: its reciprocal is a constant for the usual c'_1 <= 3.
+__device__ __forceinline__ double level_w(double A, int c1)
+{
+    const double num = A - (double)(c1 * c1);
+    double w;
+    if (c1 <= 3)
+        w = num * (c1 == 0 ? 1.0 : (c1 == 1 ? 1.0 / 3.0 : (c1 == 2 ? 1.0 / 5.0 : 1.0 / 7.0)));
+    else
+        w = num / (double)(2 * c1 + 1);
+    return w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
+}
+
 // Per-node primitives, level speeds, weights and interpolation split of one
 // source (eq. 15, 24-26, 28-29).  They are computed in FP64 whatever the
 // storage type T: in FP32 storage the per-node energy bookkeeping (E -> e, A,
@@ -125,11 +143,8 @@ __device__ __forceinline__ Src1<T> make_src1(T m0t, T m1t, T m2t, const Consts& 
     s.f = (int)fv;
     s.r = (T)(v - fv);
     s.c1 = L.c1;
-    const double c1s = (double)(L.c1 * L.c1);
-    const double w0 = (L.A - c1s) / (double)(2 * L.c1 + 1);
-    const double w = w0 < 0.0 ? 0.0 : (w0 > 1.0 ? 1.0 : w0);
     const double per = L.rest * k.inv_b1;
-    const double d2 = per * w;
+    const double d2 = per * level_w(L.A, L.c1);
     s.d2 = (T)d2;
     s.d1 = (T)(per - d2);
     s.d0 = (T)d0;
@@ -145,7 +160,9 @@ __device__ __forceinline__ Src2<T> make_src2(T m0t, T m1t, T m2t, T m3t, const C
     s.bad = !(m0 > 0.0) || !finite_val(m0) || !finite_val(m1) || !finite_val(m2) || !finite_val(m3);
     if (s.bad) {
         s.fx = 0; s.fy = 0; s.c1 = 0;
-        s.rx = (T)0; s.ry = (T)0; s.d1 = (T)0; s.d2 = (T)0; s.K = (T)0;
+        s.vx = (T)0; s.ry = (T)0;
+        s.m[0][0] = s.m[0][1] = s.m[1][0] = s.m[1][1] = (T)0;
+        s.kk[0] = s.kk[1] = (T)0;
         return s;
     }
     double vx, vy, E, v2;
@@ -160,17 +177,20 @@ __device__ __forceinline__ Src2<T> make_src2(T m0t, T m1t, T m2t, T m3t, const C
     const double fvx = floor(vx), fvy = floor(vy);
     s.fx = (int)fvx;
     s.fy = (int)fvy;
-    s.rx = (T)(vx - fvx);
+    const double rx = vx - fvx;
+    s.vx = (T)vx;
     s.ry = (T)(vy - fvy);
     s.c1 = L.c1;
-    const double c1s = (double)(L.c1 * L.c1);
-    const double w0 = (L.A - c1s) / (double)(2 * L.c1 + 1);
-    const double w = w0 < 0.0 ? 0.0 : (w0 > 1.0 ? 1.0 : w0);
-    const double per = L.rest * k.inv_b1;
-    const double d2 = per * w;
-    s.d2 = (T)d2;
-    s.d1 = (T)(per - d2);
-    s.K = (T)(0.5 * v2 + k.phi_coef * L.e);
+    const double d2 = L.rest * k.inv_b1 * level_w(L.A, L.c1);
+    const double d1 = L.rest * k.inv_b1 - d2;
+    s.m[0][0] = (T)(d1 * (1.0 - rx));
+    s.m[0][1] = (T)(d1 * rx);
+    s.m[1][0] = (T)(d2 * (1.0 - rx));
+    s.m[1][1] = (T)(d2 * rx);
+    const double K = 0.5 * v2 + k.phi_coef * L.e;
+    const double c1 = (double)L.c1;
+    s.kk[0] = (T)(K + 0.5 * c1 * c1);
+    s.kk[1] = (T)(K + 0.5 * (c1 + 1.0) * (c1 + 1.0));
     return s;
 }
 

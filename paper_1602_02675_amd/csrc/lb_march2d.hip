@@ -71,8 +71,10 @@ __device__ __forceinline__ int mfy(int p) { return ((p >> 8) & 255) - 128; }
 __device__ __forceinline__ int mc1(int p) { return (p >> 16) & 255; }
 
 template <typename T>
-struct MRow {  // one staged source row
-    T rx[kMTPB], ry[kMTPB], d1[kMTPB], d2[kMTPB], K[kMTPB];
+struct MRow {  // one staged source row (per source, see Src2)
+    T vx[kMTPB], ry[kMTPB];
+    T m[2][2][kMTPB];  // [level][x corner]
+    T kk[2][kMTPB];    // [level]
     int pk[kMTPB];
 };
 
@@ -220,32 +222,39 @@ __device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, 
     constexpr bool NOVY = RY0 && FY == 0;
     constexpr int K0 = NKX == 3 ? -1 : 0;  // first x corner relative to floor(v_x) = fx
     const int base = lane - fx;  // staged column of x displacement fx + a is base - a
-    const T fxT = (T)fx;
-    // weight of speed S0 + j for the source in column s
-    auto wgt = [&](int s, int j) -> T {
-        if (UNI) return j == 0 ? R.d1[s] : R.d2[s];
-        const int lev = S0 + j - mc1(R.pk[s]) + 1;  // 1, 2 or out of range
-        return lev == 1 ? R.d1[s] : (lev == 2 ? R.d2[s] : (T)0);
+    // level (0: c'_1, 1: c'_2) that the source in column s has at speed
+    // S0 + j, or -1 (no lane of that speed)
+    auto level = [&](int s, int j) -> int {
+        if (UNI) return j;
+        const int l = S0 + j - mc1(R.pk[s]);
+        return (l == 0 || l == 1) ? l : -1;
     };
-    // weight of corner k (relative to fx) of the source in column s
-    auto xw = [&](int s, int k, T rx) -> T {
-        if (NKX == 2) return k == 0 ? (T)1 - rx : rx;
-        const int kk = k + fx - mfx(R.pk[s]);  // the source's own corner
-        return kk == 0 ? (T)1 - rx : (kk == 1 ? rx : (T)0);
+    // packet mass of the source in column s at x corner k (relative to fx) and
+    // speed S0 + j; with NKX = 3 a source may have floor(v_x) = fx - 1
+    auto mass = [&](int s, int j, int k) -> T {
+        const int l = level(s, j);
+        const int kc = NKX == 2 ? k : k + fx - mfx(R.pk[s]);  // the source's own corner
+        if (UNI && NKX == 2) return R.m[l][kc][s];
+        const T v = R.m[l < 0 ? 0 : l][kc < 0 ? 0 : (kc > 1 ? 1 : kc)][s];
+        return (l >= 0 && kc >= 0 && kc <= 1) ? v : (T)0;
     };
-    auto vxof = [&](int s, T rx) -> T { return (NKX == 2 ? fxT : (T)mfx(R.pk[s])) + rx; };
+    auto kkof = [&](int s, int j) -> T {
+        const int l = level(s, j);
+        return R.kk[l < 0 ? 0 : l][s];  // any finite value when the mass is zero
+    };
 #pragma unroll
     for (int j = 0; j < NSP; ++j) {
         const int c = S0 + j;
-        const T cc = (T)c, hc2 = (T)(0.5 * c * c);
+        const T cc = (T)c;
         // x-lanes: destination row FY + ky, source columns base - (kx +- c)
 #pragma unroll
         for (int kx = K0; kx < 2; ++kx) {
             const int sp = base - (kx + c), sm = base - (kx - c);
-            const T rxp = R.rx[sp], ryp = R.ry[sp], rxm = R.rx[sm], rym = R.ry[sm];
-            const T bp = xw(sp, kx, rxp) * wgt(sp, j), bm = xw(sm, kx, rxm) * wgt(sm, j);
-            const T vxp = vxof(sp, rxp), vxm = vxof(sm, rxm), vyp = (T)FY + ryp, vym = (T)FY + rym;
-            const T zp = fmaT(cc, vxp, R.K[sp] + hc2), zm = fmaT(-cc, vxm, R.K[sm] + hc2);
+            const T bp = mass(sp, j, kx), bm = mass(sm, j, kx);
+            const T vxp = R.vx[sp], vxm = R.vx[sm];
+            const T ryp = R.ry[sp], rym = R.ry[sm];
+            const T vyp = (T)FY + ryp, vym = (T)FY + rym;
+            const T zp = fmaT(cc, vxp, kkof(sp, j)), zm = fmaT(-cc, vxm, kkof(sm, j));
 #pragma unroll
             for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
                 const T mp = RY0 ? bp : bp * (ky ? ryp : (T)1 - ryp);
@@ -258,12 +267,11 @@ __device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, 
 #pragma unroll
         for (int q = 0; q < NKX; ++q) {
             const int kx = K0 + q, sq = base - kx;
-            const T rx = R.rx[sq];
+            b[q] = mass(sq, j, kx);
             ry[q] = R.ry[sq];
-            b[q] = xw(sq, kx, rx) * wgt(sq, j);
-            vx[q] = vxof(sq, rx);
+            vx[q] = R.vx[sq];
             vy[q] = (T)FY + ry[q];
-            kk[q] = R.K[sq] + hc2;
+            kk[q] = kkof(sq, j);
         }
 #pragma unroll
         for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
@@ -289,8 +297,8 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc
 #pragma clang fp contract(off)
     const int nfx = fxhi - fxlo;
 #pragma unroll
-    for (int lev = 1; lev <= 2; ++lev) {
-        const int cl = clo + lev - 1, ch = chi + lev - 1;
+    for (int lev = 0; lev < 2; ++lev) {
+        const int cl = clo + lev, ch = chi + lev;  // speeds of this level in the window
 #pragma unroll
         for (int kx = 0; kx < 2; ++kx) {
             for (int i = 0; i <= nfx; ++i) {
@@ -298,16 +306,14 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc
                 for (int C = cl; C <= ch; ++C) {
                     const int sp = lane - (kx + F + C), sm = lane - (kx + F - C);
                     const int pkp = R.pk[sp], pkm = R.pk[sm];
-                    const bool okp = mfx(pkp) == F && mc1(pkp) + lev - 1 == C;
-                    const bool okm = mfx(pkm) == F && mc1(pkm) + lev - 1 == C;
-                    const T rxp = R.rx[sp], ryp = R.ry[sp], rxm = R.rx[sm], rym = R.ry[sm];
-                    const T dp = lev == 1 ? R.d1[sp] : R.d2[sp];
-                    const T dm = lev == 1 ? R.d1[sm] : R.d2[sm];
-                    const T bp = (kx ? rxp : (T)1 - rxp) * (okp ? dp : (T)0);
-                    const T bm = (kx ? rxm : (T)1 - rxm) * (okm ? dm : (T)0);
-                    const T cc = (T)C, hc2 = (T)(0.5 * C * C);
-                    const T vxp = (T)F + rxp, vxm = (T)F + rxm, vyp = (T)FY + ryp, vym = (T)FY + rym;
-                    const T zp = fmaT(cc, vxp, R.K[sp] + hc2), zm = fmaT(-cc, vxm, R.K[sm] + hc2);
+                    const bool okp = mfx(pkp) == F && mc1(pkp) + lev == C;
+                    const bool okm = mfx(pkm) == F && mc1(pkm) + lev == C;
+                    const T bp = okp ? R.m[lev][kx][sp] : (T)0, bm = okm ? R.m[lev][kx][sm] : (T)0;
+                    const T vxp = R.vx[sp], vxm = R.vx[sm];
+                    const T ryp = R.ry[sp], rym = R.ry[sm];
+                    const T vyp = (T)FY + ryp, vym = (T)FY + rym;
+                    const T cc = (T)C;
+                    const T zp = fmaT(cc, vxp, R.kk[lev][sp]), zm = fmaT(-cc, vxm, R.kk[lev][sm]);
 #pragma unroll
                     for (int ky = 0; ky < 2; ++ky) {
                         const T mp = bp * (ky ? ryp : (T)1 - ryp), mm = bm * (ky ? rym : (T)1 - rym);
@@ -323,20 +329,18 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc
             const int s0 = lane - F, s1 = lane - F - 1;
             const int pk0 = R.pk[s0], pk1 = R.pk[s1];
             const bool ok0 = mfx(pk0) == F, ok1 = mfx(pk1) == F;
-            const int c0 = mc1(pk0) + lev - 1, c1 = mc1(pk1) + lev - 1;
-            const T rx0 = R.rx[s0], rx1 = R.rx[s1];
+            const int c0 = mc1(pk0) + lev, c1 = mc1(pk1) + lev;
             const T ry[2] = {R.ry[s0], R.ry[s1]};
-            const T b0 = ((T)1 - rx0) * (ok0 ? (lev == 1 ? R.d1[s0] : R.d2[s0]) : (T)0);
-            const T b1 = rx1 * (ok1 ? (lev == 1 ? R.d1[s1] : R.d2[s1]) : (T)0);
-            const T vx[2] = {(T)F + rx0, (T)F + rx1};
+            const T b0 = ok0 ? R.m[lev][0][s0] : (T)0, b1 = ok1 ? R.m[lev][1][s1] : (T)0;
+            const T vx[2] = {R.vx[s0], R.vx[s1]};
             const T vy[2] = {(T)FY + ry[0], (T)FY + ry[1]};
+            const T kk[2] = {R.kk[lev][s0], R.kk[lev][s1]};
 #pragma unroll
             for (int C = 0; C <= 3 + 1; ++C) {  // speed of this level, static
                 if (C < cl || C > ch) continue;
                 if (FY + 1 + C > L || FY - C < -L) continue;  // out of the FIFO: redone / reported
                 const T w0 = c0 == C ? b0 : (T)0, w1 = c1 == C ? b1 : (T)0;
-                const T cc = (T)C, hc2 = (T)(0.5 * C * C);
-                const T kk[2] = {R.K[s0] + hc2, R.K[s1] + hc2};
+                const T cc = (T)C;
 #pragma unroll
                 for (int ky = 0; ky < 2; ++ky) {
                     const T m[2] = {w0 * (ky ? ry[0] : (T)1 - ry[0]), w1 * (ky ? ry[1] : (T)1 - ry[1])};
@@ -355,24 +359,25 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc
 template <typename T, int L>
 __device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, int xlo, int xhi, int ylo, int yhi)
 {
+#pragma clang fp contract(off)
 #pragma unroll 1
     for (int a = -kMH; a <= kMH; ++a) {
         const int s = lane - a;
         const int pk = R.pk[s];
         const int fx = mfx(pk), fy = mfy(pk), c1 = mc1(pk), c2 = c1 + 1;
-        const T rx = R.rx[s], ry = R.ry[s], d1 = R.d1[s], d2 = R.d2[s], K = R.K[s];
-        const T vx = (T)fx + rx, vy = (T)fy + ry;
+        const T vx = R.vx[s], ry = R.ry[s];
+        const T vy = (T)fy + ry;
 #pragma unroll 1
         for (int kx = 0; kx < 2; ++kx) {
             const int cx = a - fx - kx;  // x-lane speed needed to land here
-            const T axw = kx ? rx : (T)1 - rx;
-            // x-lanes with c' = cx: +-c1 (both when c1 = 0) and +-c2
+            // x-lanes with c' = cx: +-c1 (both when c1 = 0) or +-c2
             const int n1 = (cx == c1 || cx == -c1) ? (c1 == 0 ? 2 : 1) : 0;
             const int n2 = (cx == c2 || cx == -c2) ? 1 : 0;
             if (n1 + n2 > 0) {
-                const T w = axw * ((T)n1 * d1 + (T)n2 * d2);
+                const int l = n1 > 0 ? 0 : 1;
+                const T w = (T)(n1 + n2) * R.m[l][kx][s];
                 const T cc = (T)cx;
-                const T zx = K + cc * vx + (T)0.5 * cc * cc;
+                const T zx = fmaT(cc, vx, R.kk[l][s]);
 #pragma unroll 1
                 for (int ky = 0; ky < 2; ++ky) {
                     const T m = w * (ky ? ry : (T)1 - ry);
@@ -381,16 +386,15 @@ __device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, i
             }
             if (cx == 0) {  // y-lanes move in x by fx + kx only
 #pragma unroll 1
-                for (int lev = 1; lev <= 2; ++lev) {
-                    const int c = lev == 1 ? c1 : c2;
-                    const T d = lev == 1 ? d1 : d2;
+                for (int l = 0; l < 2; ++l) {
+                    const int c = l == 0 ? c1 : c2;
 #pragma unroll 1
                     for (int sg = -1; sg <= 1; sg += 2) {
                         const T cc = (T)(sg * c);
-                        const T zy = K + cc * vy + (T)0.5 * cc * cc;
+                        const T zy = fmaT(cc, vy, R.kk[l][s]);
 #pragma unroll 1
                         for (int ky = 0; ky < 2; ++ky) {
-                            const T m = axw * (ky ? ry : (T)1 - ry) * d;
+                            const T m = R.m[l][kx][s] * (ky ? ry : (T)1 - ry);
                             const int slot = fy + ky + sg * c + L;
                             fifo_add_sel<Acc<T>, T, L>(f, slot, ylo, yhi, m, m * vx, m * vy, m * zy);
                             fifo_add_g<Acc<T>, T, L>(f, slot, ylo, yhi, m * cc);
@@ -411,9 +415,6 @@ __device__ __forceinline__ void load_node(const T* __restrict__ Y, int64_t nn, i
     m[3] = Y[3 * nn + q];
 }
 
-#ifndef LB_MARCH_WPE
-#define LB_MARCH_WPE 2
-#endif
 // One tile: destination columns [X0, X0 + 256 - 2H) and rows [Y0, Y0 + sy)
 // (clipped to the grid) of grid g, marched from row Y0 - L to Y0 + sy + L - 1.
 // Writes Yn and one row of per-tile partials (field sums, reach, error bits).
@@ -458,11 +459,14 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
         // stage this source row
         const Src2<T> s = make_src2<T>(cur[0], cur[1], cur[2], cur[3], k);
         const int pk = mpack(s.fx, s.fy, s.c1);
-        s_row[b].rx[tid] = s.rx;
+        s_row[b].vx[tid] = s.vx;
         s_row[b].ry[tid] = s.ry;
-        s_row[b].d1[tid] = s.d1;
-        s_row[b].d2[tid] = s.d2;
-        s_row[b].K[tid] = s.K;
+        s_row[b].m[0][0][tid] = s.m[0][0];
+        s_row[b].m[0][1][tid] = s.m[0][1];
+        s_row[b].m[1][0][tid] = s.m[1][0];
+        s_row[b].m[1][1][tid] = s.m[1][1];
+        s_row[b].kk[0][tid] = s.kk[0];
+        s_row[b].kk[1][tid] = s.kk[1];
         s_row[b].pk[tid] = pk;
         const int yr = axis_reach(s.fy, s.c1);
         reach = max(reach, max(axis_reach(s.fx, s.c1), yr));
@@ -590,8 +594,13 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
     return far;
 }
 
+// Wavefronts per SIMD the short-FIFO kernels are compiled for: FP64 keeps its
+// FIFO in registers at two; FP32 fits four with a few spilled registers.
 #ifndef LB_MARCH_WPE
 #define LB_MARCH_WPE 2
+#endif
+#ifndef LB_MARCH_WPE_F32
+#define LB_MARCH_WPE_F32 4
 #endif
 // L = kLSmall: the short-FIFO pass; a tile whose sources reach beyond the
 // FIFO marks the step for a redo.  L = kLFull with redo_only: runs only if the
@@ -599,7 +608,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
 // Persistent blocks claim the tiles (tiles_x column strips x row chunks of sy
 // rows, row chunk major) from the control block's counter of the pass.
 template <typename T, int L>
-__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? LB_MARCH_WPE : 1)))
+__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
 march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
                StepCtl* __restrict__ ctl, double* __restrict__ partials, long long step, int sy,
                int tiles_x, int ntiles, int redo_only)
@@ -628,7 +637,7 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
 // pool1d_kernel).  The short-FIFO pass flags the tiles it could not complete;
 // the full-FIFO pass recomputes only those.
 template <typename T, int L>
-__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? LB_MARCH_WPE : 1)))
+__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
 pool2d_kernel(PoolView v, Consts k)
 {
     __shared__ int s_t;
