@@ -108,16 +108,24 @@ struct PoolState {      // one slot, written by the device, read by the host aft
     double totals[4];   // interior sums after step totals_step (lattice units)
 };
 
-struct PoolTile {
+struct PoolTile {        // one tile, with a copy of its slot's grid so a block reads one record
     int32_t prob, rows;  // slot; destination rows (square lattice; 1 in 1-D)
     int64_t x0, y0;      // first destination column / row
+    int64_t off[2];      // the slot's two moment sets (element offsets in the arena)
+    int64_t nx, ny;
+    int32_t bc_x, bc_y;
 };
+
+// Per-tile word kept by the per-slot reduction: bit 0 = the set holding the
+// slot's current moments (done & 1), bit 1 = the slot still steps.
+constexpr int kTileSet = 1, kTileLive = 2;
 
 struct PoolView {
     const PoolProb* probs;
     PoolState* state;
     const PoolTile* tiles;
-    const int32_t* ntiles;  // live tiles (read by the kernels, so admissions need no new launch shape)
+    int32_t* tstate;        // kTileSet | kTileLive per tile
+    const int32_t* ntiles;  // tiles in the table (read by the kernels, so admissions need no new launch shape)
     double* partials;       // kPartialStride doubles per tile
     int32_t* flags;         // square lattice: tile needs the full-FIFO pass
     int32_t* next;          // tile claim counters: [0] step pass, [1] full-FIFO pass; reset by finalize
@@ -133,13 +141,12 @@ constexpr int kPool2Shapes = 5;
 constexpr int kPool2Rows[kPool2Shapes] = {16, 32, 64, 128, 256};
 constexpr int kPool2Cols = 256 - 2 * kHalo;  // destination columns per square-lattice tile
 
-// One step of every live tile: the 1-D kernel of tile shape `shape`, or the
-// square-lattice short-FIFO pass followed by the full-FIFO pass over the tiles
-// it flagged.  nblocks persistent blocks walk the tile table.
+// One step of every live tile: the 1-D kernel of tile shape `shape` (nblocks =
+// the number of tiles, one block each), or the square-lattice short-FIFO pass
+// followed by the full-FIFO pass over the tiles it flagged (nblocks persistent
+// blocks claim the tiles).
 template <typename T>
 hipError_t launch_pool1d(const PoolView& v, const Consts& k, int shape, int nblocks, hipStream_t stream);
-template <typename T>
-int pool1d_blocks_per_cu(int shape);
 template <typename T>
 hipError_t launch_pool2d(const PoolView& v, const Consts& k, int nblocks, hipStream_t stream);
 template <typename T>

@@ -647,15 +647,14 @@ pool2d_kernel(PoolView v, Consts k)
         const int t = claim_tile(&v.next[L < kLFull ? 0 : 1], &s_t);
         if (t >= nt) break;
         if (L == kLFull && v.flags[t] == 0) continue;
-        const PoolTile tl = v.tiles[t];
-        const PoolProb& P = v.probs[tl.prob];
-        const PoolState& S = v.state[tl.prob];
-        const int64_t done = S.done;
-        if (done >= P.target || S.err_step != 0) continue;  // the same for the whole block
-        const int cur = (int)(done & 1);
-        const Grid g{P.nx, P.ny, P.bc_x, P.bc_y};
-        const int far = march_tile<T, L>(arena + P.off[cur], arena + P.off[cur ^ 1], g, k, tl.x0, tl.y0,
-                                         tl.rows, v.partials + (int64_t)t * kPartialStride);
+        const int ts = v.tstate[t];
+        if (!(ts & kTileLive)) continue;  // the same for the whole block
+        const PoolTile& tl = v.tiles[t];
+        const int64_t o0 = tl.off[0], o1 = tl.off[1];  // selected below, not indexed (keeps them in registers)
+        const int64_t from = (ts & kTileSet) ? o1 : o0, to = (ts & kTileSet) ? o0 : o1;
+        const Grid g{tl.nx, tl.ny, tl.bc_x, tl.bc_y};
+        const int far = march_tile<T, L>(arena + from, arena + to, g, k, tl.x0, tl.y0, tl.rows,
+                                         v.partials + (int64_t)t * kPartialStride);
         if (threadIdx.x == 0) v.flags[t] = L < kLFull ? far : 0;
     }
 }

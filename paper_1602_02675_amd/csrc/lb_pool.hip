@@ -41,8 +41,8 @@ struct lb_pool {
     size_t arena_bytes = 0;
     int64_t max_tiles = 0;
     // layout inside the bound buffer
-    size_t off_probs = 0, off_state = 0, off_tiles = 0, off_ntiles = 0, off_partials = 0, off_flags = 0,
-           off_arena = 0, total = 0;
+    size_t off_probs = 0, off_state = 0, off_tiles = 0, off_tstate = 0, off_ntiles = 0, off_partials = 0,
+           off_flags = 0, off_arena = 0, total = 0;
     char* base = nullptr;
     hipStream_t stream = nullptr;
     bool bound = false;
@@ -69,6 +69,7 @@ PoolView view_of(const lb_pool* p)
     v.probs = (const PoolProb*)(p->base + p->off_probs);
     v.state = (PoolState*)(p->base + p->off_state);
     v.tiles = (const PoolTile*)(p->base + p->off_tiles);
+    v.tstate = (int32_t*)(p->base + p->off_tstate);
     v.ntiles = (const int32_t*)(p->base + p->off_ntiles);
     v.partials = (double*)(p->base + p->off_partials);
     v.flags = (int32_t*)(p->base + p->off_flags);
@@ -108,14 +109,14 @@ int64_t live_max_tiles(const lb_pool* p)
     return n;
 }
 
-int persistent_blocks(const lb_pool* p)
+// Blocks of the step launch.  Square lattice: persistent blocks (as many as
+// are resident at once) that claim tiles, so that slow tiles spread out.  1-D:
+// one block per tile (tiles cost about the same, and the hardware then
+// overlaps one tile's loads with other tiles' work).
+int launch_blocks(const lb_pool* p, int64_t ntiles)
 {
-    int per_cu;
-    if (p->dim == 1)
-        per_cu = p->precision == LB_FP64 ? pool1d_blocks_per_cu<double>(p->shape)
-                                         : pool1d_blocks_per_cu<float>(p->shape);
-    else
-        per_cu = p->precision == LB_FP64 ? pool2d_blocks_per_cu<double>() : pool2d_blocks_per_cu<float>();
+    if (p->dim == 1) return (int)std::max<int64_t>(1, ntiles);
+    const int per_cu = p->precision == LB_FP64 ? pool2d_blocks_per_cu<double>() : pool2d_blocks_per_cu<float>();
     return std::max(1, p->cus * per_cu);
 }
 
@@ -143,6 +144,12 @@ int upload_tables(lb_pool* p)
                     t.rows = (int32_t)tr;
                     t.x0 = x0;
                     t.y0 = y0;
+                    t.off[0] = q.off[0];
+                    t.off[1] = q.off[1];
+                    t.nx = q.nx;
+                    t.ny = q.ny;
+                    t.bc_x = q.bc_x;
+                    t.bc_y = q.bc_y;
                     p->tiles.push_back(t);
                 }
         }
@@ -150,8 +157,26 @@ int upload_tables(lb_pool* p)
     }
     if ((int64_t)p->tiles.size() > p->max_tiles) return fail(LB_ENOMEM, "tile table full");
     const int32_t nt = (int32_t)p->tiles.size();
+    const int nb = launch_blocks(p, nt);
+    if (nb != p->nblocks) {  // a different launch shape: a captured graph is stale
+        drop_graph(p);
+        p->nblocks = nb;
+    }
     std::vector<int32_t> zeros((size_t)std::max<int32_t>(nt, 2), 0);
-    hipError_t e;
+    // tile words from the slots' device states
+    std::vector<PoolState> st((size_t)p->max_slots);
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "sync");
+    if ((e = hipMemcpy(st.data(), p->base + p->off_state, st.size() * sizeof(PoolState), hipMemcpyDeviceToHost)) !=
+        hipSuccess)
+        return hip_fail(e, "read slot states");
+    std::vector<int32_t> words((size_t)std::max<int32_t>(nt, 1), 0);
+    for (int32_t t = 0; t < nt; ++t) {
+        const int i = p->tiles[(size_t)t].prob;
+        const PoolState& q = st[(size_t)i];
+        words[(size_t)t] = (int32_t)(q.done & 1) |
+                           (q.err_step == 0 && q.done < p->probs[(size_t)i].target ? kTileLive : 0);
+    }
     if ((e = hipMemcpyAsync(p->base + p->off_probs, p->probs.data(), p->probs.size() * sizeof(PoolProb),
                             hipMemcpyHostToDevice, p->stream)) != hipSuccess)
         return hip_fail(e, "upload slots");
@@ -167,6 +192,9 @@ int upload_tables(lb_pool* p)
     if (nt > 0 && (e = hipMemcpyAsync(p->base + p->off_flags, zeros.data(), (size_t)nt * 4,
                                       hipMemcpyHostToDevice, p->stream)) != hipSuccess)
         return hip_fail(e, "clear flags");
+    if (nt > 0 && (e = hipMemcpyAsync(p->base + p->off_tstate, words.data(), (size_t)nt * 4,
+                                      hipMemcpyHostToDevice, p->stream)) != hipSuccess)
+        return hip_fail(e, "upload tile words");
     if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_fail(e, "sync");
     return LB_OK;
 }
@@ -177,7 +205,6 @@ int set_shape(lb_pool* p, int shape)
     if (shape < 0 || shape >= ns) return fail(LB_EINVAL, "shape must lie in [0, %d)", ns);
     if (shape != p->shape) drop_graph(p);
     p->shape = shape;
-    p->nblocks = persistent_blocks(p);
     return upload_tables(p);
 }
 
@@ -391,7 +418,8 @@ int lb_pool_create(int32_t dim, double gamma, const lb_velset* vs, int32_t preci
     p->off_probs = 0;
     p->off_state = align256((size_t)max_slots * sizeof(PoolProb));
     p->off_tiles = p->off_state + align256((size_t)max_slots * sizeof(PoolState));
-    p->off_ntiles = p->off_tiles + align256((size_t)p->max_tiles * sizeof(PoolTile));
+    p->off_tstate = p->off_tiles + align256((size_t)p->max_tiles * sizeof(PoolTile));
+    p->off_ntiles = p->off_tstate + align256((size_t)p->max_tiles * 4);
     p->off_partials = p->off_ntiles + 256;  // tile count at +0, claim counters at +64
     p->off_flags = p->off_partials + align256((size_t)p->max_tiles * kPartialStride * 8);
     p->off_arena = p->off_flags + align256((size_t)p->max_tiles * 4);

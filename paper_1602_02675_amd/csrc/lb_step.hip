@@ -257,38 +257,55 @@ __device__ void gather1_general(const Tile1<T>& tl, const TileInfo& ti, int64_t 
     }
 }
 
-// One tile of TPB * J destinations starting at x0 of a tube of nx nodes:
-// stage its sources (plus a halo of H, clamped or wrapped), gather, write Yn,
-// and add the tile's new moments to acc.  Returns the tile's integer summary.
-// Contains block-wide barriers: every thread of the block must call it.
+// One tile of TPB * J destinations starting at x0 of a tube of nx nodes, in
+// two phases: tile1d_load reads its sources (plus a halo of H, clamped or
+// wrapped) into registers; tile1d_gather stages them in LDS, gathers, writes
+// Yn and adds the tile's new moments to acc, returning the tile's integer
+// summary.  Splitting them lets a persistent block load its next tile while
+// it gathers the current one.  tile1d_gather contains block-wide barriers:
+// every thread of the block must call it.
 template <typename T, int H, int TPB, int J>
-__device__ __forceinline__ TileInfo tile1d(const T* __restrict__ Y, T* __restrict__ Yn, int64_t nx, int bc, int64_t x0,
-                           const Consts& k, double (&acc)[3])
+struct Tile1Src {
+    static constexpr int W = TPB * J + 2 * H;
+    static constexpr int NS = (W + TPB - 1) / TPB;
+    T ld[NS][3];
+};
+
+template <typename T, int H, int TPB, int J>
+__device__ __forceinline__ void tile1d_load(const T* __restrict__ Y, int64_t nx, int bc, int64_t x0,
+                                            Tile1Src<T, H, TPB, J>& src)
 {
-    constexpr int TILE = TPB * J;
-    constexpr int W = TILE + 2 * H;
+    using S = Tile1Src<T, H, TPB, J>;
+#pragma unroll
+    for (int u = 0; u < S::NS; ++u) {
+        const int i = (int)threadIdx.x + u * TPB;
+        if (i < S::W) {
+            const int64_t gx = x0 - H + i;
+            const int64_t si = bc == kBcPeriodic ? wrap_near(gx, nx) : clamp_idx(gx, nx);
+            src.ld[u][0] = Y[si];
+            src.ld[u][1] = Y[nx + si];
+            src.ld[u][2] = Y[2 * nx + si];
+        }
+    }
+}
+
+template <typename T, int H, int TPB, int J>
+__device__ __forceinline__ TileInfo tile1d_gather(const Tile1Src<T, H, TPB, J>& src, T* __restrict__ Yn,
+                                                  int64_t nx, int64_t x0, const Consts& k, double (&acc)[3])
+{
+    using S = Tile1Src<T, H, TPB, J>;
+    constexpr int W = S::W;
     constexpr int NW = TPB / 64;
     __shared__ int s_pk[W];
     __shared__ T s_r[W], s_d0[W], s_d1[W], s_d2[W], s_K[W];
     __shared__ int s_red[NW][8];
 
     TileInfo ti = {INT_MAX, INT_MIN, 0, 0, INT_MAX, INT_MIN, 0, 0};
-    constexpr int NS = (W + TPB - 1) / TPB;
-    T ld[NS][3];
 #pragma unroll
-    for (int u = 0; u < NS; ++u) {
-        const int i = (int)threadIdx.x + u * TPB;
-        if (i < W) {
-            const int64_t gx = x0 - H + i;
-            const int64_t si = bc == kBcPeriodic ? wrap_near(gx, nx) : clamp_idx(gx, nx);
-            ld[u][0] = Y[si]; ld[u][1] = Y[nx + si]; ld[u][2] = Y[2 * nx + si];
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < NS; ++u) {
+    for (int u = 0; u < S::NS; ++u) {
         const int i = (int)threadIdx.x + u * TPB;
         if (i >= W) break;
-        const Src1<T> s = make_src1<T>(ld[u][0], ld[u][1], ld[u][2], k);
+        const Src1<T> s = make_src1<T>(src.ld[u][0], src.ld[u][1], src.ld[u][2], k);
         s_pk[i] = pack_lane(s.f, 0, s.c1);
         s_r[i] = s.r;
         s_d0[i] = s.d0;
@@ -324,35 +341,35 @@ step1d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
               StepCtl* __restrict__ ctl, double* __restrict__ partials, long long step)
 {
     if (ctl->err_step < step) return;  // an earlier step failed: keep its input intact
+    const int64_t x0 = (int64_t)blockIdx.x * (TPB * J);
+    Tile1Src<T, H, TPB, J> src;
+    tile1d_load<T, H, TPB, J>(Y, g.nx, g.bc_x, x0, src);
     double acc[3] = {0.0, 0.0, 0.0};
-    const TileInfo ti = tile1d<T, H, TPB, J>(Y, Yn, g.nx, g.bc_x, (int64_t)blockIdx.x * (TPB * J), k, acc);
+    const TileInfo ti = tile1d_gather<T, H, TPB, J>(src, Yn, g.nx, x0, k, acc);
     finish_step<TPB / 64, 3>(acc, ti, partials + (int64_t)blockIdx.x * kPartialStride, H);
 }
 
-// Pool form: persistent blocks walk the tile table; a tile belongs to one
-// slot, whose own step count picks the moment set it reads (done & 1) and
-// writes.  Finished, failed and free slots own no work.  The tile -> block
-// assignment does not change any result.
+// Pool form: one block per tile of the tile table (1-D tiles cost about the
+// same, so the hardware's block scheduling balances them and overlaps one
+// tile's loads with other tiles' work).  A tile belongs to one slot; its word
+// says whether the slot still steps and which moment set holds its state.
 template <typename T, int TPB, int J>
 __global__ void __launch_bounds__(TPB) pool1d_kernel(PoolView v, Consts k)
 {
-    __shared__ int s_t;
-    const int nt = *v.ntiles;
+    const int t = blockIdx.x;
+    if (t >= *v.ntiles) return;
+    const int ts = v.tstate[t];
+    if (!(ts & kTileLive)) return;  // the same for the whole block
     T* arena = (T*)v.arena;
-    for (;;) {
-        const int t = claim_tile(&v.next[0], &s_t);
-        if (t >= nt) break;
-        const PoolTile tl = v.tiles[t];
-        const PoolProb& P = v.probs[tl.prob];
-        const PoolState& S = v.state[tl.prob];
-        const int64_t done = S.done;
-        if (done >= P.target || S.err_step != 0) continue;  // the same for the whole block
-        const int cur = (int)(done & 1);
-        double acc[3] = {0.0, 0.0, 0.0};
-        const TileInfo ti =
-            tile1d<T, kHalo, TPB, J>(arena + P.off[cur], arena + P.off[cur ^ 1], P.nx, P.bc_x, tl.x0, k, acc);
-        finish_step<TPB / 64, 3>(acc, ti, v.partials + (int64_t)t * kPartialStride, kHalo);
-    }
+    const PoolTile& tl = v.tiles[t];
+    const int64_t o0 = tl.off[0], o1 = tl.off[1];  // selected below, not indexed (keeps them in registers)
+    const int64_t from = (ts & kTileSet) ? o1 : o0, to = (ts & kTileSet) ? o0 : o1;
+    const int64_t nx = tl.nx, x0 = tl.x0;
+    Tile1Src<T, kHalo, TPB, J> src;
+    tile1d_load<T, kHalo, TPB, J>(arena + from, nx, tl.bc_x, x0, src);
+    double acc[3] = {0.0, 0.0, 0.0};
+    const TileInfo ti = tile1d_gather<T, kHalo, TPB, J>(src, arena + to, nx, x0, k, acc);
+    finish_step<TPB / 64, 3>(acc, ti, v.partials + (int64_t)t * kPartialStride, kHalo);
 }
 
 // Per slot (one block each): the same fixed-order reduction as finalize_kernel
@@ -390,6 +407,7 @@ __global__ void __launch_bounds__(kFinTPB) pool_finalize_kernel(PoolView v, int 
         s_ir[wid][0] = reach;
         s_ir[wid][1] = err;
     }
+    __shared__ int s_word;
     __syncthreads();
     if (tid == 0 && commit) {
         const int64_t step = S.done + 1;
@@ -408,7 +426,11 @@ __global__ void __launch_bounds__(kFinTPB) pool_finalize_kernel(PoolView v, int 
         } else {
             S.done = step;
         }
+        s_word = (int)(S.done & 1) | (!e && S.done < P.target ? kTileLive : 0);
     }
+    __syncthreads();
+    if (commit)
+        for (int64_t t = P.t0 + tid; t < P.t1; t += kFinTPB) v.tstate[t] = s_word;
 }
 
 #ifndef LB_T1_TPB
@@ -456,29 +478,6 @@ hipError_t launch_pool1d(const PoolView& v, const Consts& k, int shape, int nblo
     }
 }
 
-template <typename T, int S>
-static int pool1d_occupancy()
-{
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pool1d_kernel<T, kPool1TPB[S], kPool1J[S]>,
-                                                     kPool1TPB[S], 0) != hipSuccess)
-        return 1;
-    return nb > 0 ? nb : 1;
-}
-
-template <typename T>
-int pool1d_blocks_per_cu(int shape)
-{
-    switch (shape) {
-        case 0: return pool1d_occupancy<T, 0>();
-        case 1: return pool1d_occupancy<T, 1>();
-        case 2: return pool1d_occupancy<T, 2>();
-        case 3: return pool1d_occupancy<T, 3>();
-        case 4: return pool1d_occupancy<T, 4>();
-        default: return 1;
-    }
-}
-
 hipError_t launch_pool_finalize(const PoolView& v, int nslots, int commit, hipStream_t stream)
 {
     pool_finalize_kernel<<<nslots, kFinTPB, 0, stream>>>(v, commit);
@@ -499,7 +498,5 @@ template hipError_t launch_step1d<float>(const float*, float*, const Grid&, cons
 
 template hipError_t launch_pool1d<double>(const PoolView&, const Consts&, int, int, hipStream_t);
 template hipError_t launch_pool1d<float>(const PoolView&, const Consts&, int, int, hipStream_t);
-template int pool1d_blocks_per_cu<double>(int);
-template int pool1d_blocks_per_cu<float>(int);
 
 }  // namespace lbsd
