@@ -156,15 +156,17 @@ const char* lb_last_error(void);
  * The batching and serving forms.  A pool holds up to max_slots problems of one
  * lattice, gamma and precision (each with its own grid, lambda, boundary
  * conditions and step target) in an arena of arena_bytes inside the caller's
- * device memory.  One pool step is one persistent kernel launch (plus, on the
- * square lattice, a pass that redoes the tiles whose packets reached past the
- * short FIFO, and a per-slot reduction kernel) over a tile table in device
- * memory; every live, unfinished slot advances by one step (eq. 10 / 30 with
- * tau = 1, as lb_step).  Admissions and releases rewrite the tables between
- * launches, so the launch shape and a captured HIP graph stay valid while
- * problems come and go.  A slot's results do not depend on what else is in
- * the pool, the tile shape or graph use: they are bit-identical to an
- * lb_solver run of the same problem.
+ * device memory.  One pool step is one kernel launch over a tile table in
+ * device memory (square lattice: persistent blocks that claim tiles, plus a
+ * pass that redoes the tiles whose packets reached past the short FIFO; 1-D:
+ * one block per tile) and a per-slot reduction kernel; every live, unfinished
+ * slot advances by one step (eq. 10 / 30 with tau = 1, as lb_step).
+ * Admissions and releases rewrite the tables between launches; on the square
+ * lattice the launch shape, and so a captured HIP graph, stays valid while
+ * problems come and go (1-D re-captures when the number of tiles changes).
+ * A slot's results do not depend on what else is in the pool, the tile shape
+ * or graph use: they are bit-identical to an lb_solver run of the same
+ * problem.
  *
  * Slot status (lb_pool_poll): 0 running, 1 reached its step target, or
  * LB_EREACH / LB_ESTATE if one of its steps failed (it then stops at its last
