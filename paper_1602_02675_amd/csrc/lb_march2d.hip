@@ -426,8 +426,11 @@ template <typename T, int L>
 __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict__ Yn, const Grid& g, const Consts& k,
                           int64_t X0, int64_t Y0, int sy, double* __restrict__ prow)
 {
-    __shared__ MRow<T> s_row[2];
-    __shared__ WaveInfo s_w[2][kMNW];
+    // source rows staged per barrier: two in FP64 (fewer barriers, two
+    // independent per-source computations in flight); FP32 has no registers left
+    constexpr int RB = sizeof(T) == 8 ? 2 : 1;
+    __shared__ MRow<T> s_row[2][RB];
+    __shared__ WaveInfo s_w[2][RB][kMNW];
     const int tid = threadIdx.x, lane64 = tid & 63, wid = tid >> 6;
     const int64_t nx = g.nx, ny = g.ny, nn = nx * ny;
     const int64_t gx = X0 - kMH + tid;                           // this thread's source column
@@ -450,118 +453,133 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
         const int64_t yy = g.bc_y == kBcPeriodic ? wrap_near(gy, ny) : clamp_idx(gy, ny);
         return yy * nx + sx;
     };
-    T cur[4], nxt[4];
-    if (nrows > 0) load_node<T>(Y, nn, row_index(Y0 - L), cur);
+    T cur[RB][4], nxt[RB][4];
+#pragma unroll
+    for (int u = 0; u < RB; ++u)
+        if (u < nrows) load_node<T>(Y, nn, row_index(Y0 - L + u), cur[u]);
 
-    for (int r = 0; r < nrows; ++r) {
-        const int b = r & 1;
-        if (r + 1 < nrows) load_node<T>(Y, nn, row_index(Y0 - L + r + 1), nxt);
-        // stage this source row
-        const Src2<T> s = make_src2<T>(cur[0], cur[1], cur[2], cur[3], k);
-        const int pk = mpack(s.fx, s.fy, s.c1);
-        s_row[b].vx[tid] = s.vx;
-        s_row[b].ry[tid] = s.ry;
-        s_row[b].m[0][0][tid] = s.m[0][0];
-        s_row[b].m[0][1][tid] = s.m[0][1];
-        s_row[b].m[1][0][tid] = s.m[1][0];
-        s_row[b].m[1][1][tid] = s.m[1][1];
-        s_row[b].kk[0][tid] = s.kk[0];
-        s_row[b].kk[1][tid] = s.kk[1];
-        s_row[b].pk[tid] = pk;
-        const int yr = axis_reach(s.fy, s.c1);
-        reach = max(reach, max(axis_reach(s.fx, s.c1), yr));
-        yfar |= yr > L ? 1 : 0;
-        bad |= s.bad ? 1 : 0;
-        {
-            const int ry0 = __all(s.ry == (T)0) ? 1 : 0;
-            const int pk0 = __builtin_amdgcn_readfirstlane(pk);
-            WaveInfo wi;
-            if (__all(pk == pk0)) {  // the common case: one ballot instead of six reductions
-                wi = WaveInfo{mfx(pk0), mfx(pk0), mfy(pk0), mfy(pk0), mc1(pk0), mc1(pk0), ry0, 0};
-            } else {
-                wi = WaveInfo{wave_min(s.fx), wave_max(s.fx), wave_min(s.fy), wave_max(s.fy),
-                              wave_min(s.c1), wave_max(s.c1), ry0, 0};
+    for (int r0 = 0; r0 < nrows; r0 += RB) {
+        const int b = (r0 / RB) & 1;
+#pragma unroll
+        for (int u = 0; u < RB; ++u)
+            if (r0 + RB + u < nrows) load_node<T>(Y, nn, row_index(Y0 - L + r0 + RB + u), nxt[u]);
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            if (r0 + u >= nrows) break;
+            // stage this source row
+            const Src2<T> s = make_src2<T>(cur[u][0], cur[u][1], cur[u][2], cur[u][3], k);
+            const int pk = mpack(s.fx, s.fy, s.c1);
+            s_row[b][u].vx[tid] = s.vx;
+            s_row[b][u].ry[tid] = s.ry;
+            s_row[b][u].m[0][0][tid] = s.m[0][0];
+            s_row[b][u].m[0][1][tid] = s.m[0][1];
+            s_row[b][u].m[1][0][tid] = s.m[1][0];
+            s_row[b][u].m[1][1][tid] = s.m[1][1];
+            s_row[b][u].kk[0][tid] = s.kk[0];
+            s_row[b][u].kk[1][tid] = s.kk[1];
+            s_row[b][u].pk[tid] = pk;
+            const int yr = axis_reach(s.fy, s.c1);
+            reach = max(reach, max(axis_reach(s.fx, s.c1), yr));
+            yfar |= yr > L ? 1 : 0;
+            bad |= s.bad ? 1 : 0;
+            {
+                const int ry0 = __all(s.ry == (T)0) ? 1 : 0;
+                const int pk0 = __builtin_amdgcn_readfirstlane(pk);
+                WaveInfo wi;
+                if (__all(pk == pk0)) {  // the common case: one ballot instead of six reductions
+                    wi = WaveInfo{mfx(pk0), mfx(pk0), mfy(pk0), mfy(pk0), mc1(pk0), mc1(pk0), ry0, 0};
+                } else {
+                    wi = WaveInfo{wave_min(s.fx), wave_max(s.fx), wave_min(s.fy), wave_max(s.fy),
+                                  wave_min(s.c1), wave_max(s.c1), ry0, 0};
+                }
+                if (lane64 == 0) s_w[b][u][wid] = wi;
             }
-            if (lane64 == 0) s_w[b][wid] = wi;
+
         }
         __syncthreads();
-
-        // gather this row's packets into the FIFO
-        WaveInfo w = s_w[b][wid];
-        if (wid > 0) w = merge(w, s_w[b][wid - 1]);
-        if (wid + 1 < kMNW) w = merge(w, s_w[b][wid + 1]);
-        // the fast and row paths need every packet of the window inside the
-        // FIFO (y) and the staged row (x); the general path takes any window
-        // whose sources each reach <= H.  A short FIFO that cannot hold the
-        // window's y displacements marks the step for a redo.
-        const int c2max = w.c1max + 1;
-        const bool fits_y = w.fymin - c2max >= -L && w.fymax + 1 + c2max <= L;
-        const bool fits_x = w.fxmin - c2max >= -kMH && w.fxmax + 1 + c2max <= kMH;
-        if (L < kLFull && !fits_y) yfar = 1;
-        const bool rows_ok = fits_x && fits_y && w.fymin == w.fymax && (w.fymin == 0 || w.fymin == -1) &&
-                             w.c1max <= 3 && w.fxmax - w.fxmin <= 2;
-        if (dest && (fits_y || L == kLFull)) {
-            // two adjacent values of c'_1 or of floor(v_x) keep compile-time
-            // offsets; a window mixing both (rare in planar flows) takes the
-            // row path, whose extra registers would otherwise cost occupancy
-            const bool cmix = w.c1max == w.c1min + 1, xmix = w.fxmax == w.fxmin + 1;
-            const bool fastw = rows_ok && (w.c1max == w.c1min || cmix) && (w.fxmax == w.fxmin || xmix) &&
-                               !(cmix && xmix) && (!cmix || w.c1min <= 2) && (!xmix || w.c1min <= 1);
-            if (fastw) {
-                const MRow<T>& R = s_row[b];
-                const int fx0 = w.fxmax;
-                const int sel = ((w.fymin == 0 ? (w.ry0 ? 0 : 1) : 2) * 2 + (xmix ? 1 : 0)) * 8 +
-                                (cmix ? 4 : 0) + w.c1min;
-                switch (sel) {
-#define LB_FAST(S, FYV, S0, NSP, NKX, RY)                                                   \
-    case S:                                                                                 \
-        if constexpr ((FYV) - (S0) - (NSP) + 1 >= -L && (FYV) + 1 + (S0) + (NSP) - 1 <= L)  \
-            gather_fast<T, L, FYV, S0, NSP, NKX, RY>(R, tid, fx0, f);                       \
-        break;
-#define LB_FAST_SET(B, FYV, RY)                                                              \
-    LB_FAST(B + 0, FYV, 0, 2, 2, RY) LB_FAST(B + 1, FYV, 1, 2, 2, RY) LB_FAST(B + 2, FYV, 2, 2, 2, RY) \
-    LB_FAST(B + 3, FYV, 3, 2, 2, RY) LB_FAST(B + 4, FYV, 0, 3, 2, RY) LB_FAST(B + 5, FYV, 1, 3, 2, RY) \
-    LB_FAST(B + 6, FYV, 2, 3, 2, RY)                                                        \
-    LB_FAST(B + 8, FYV, 0, 2, 3, RY) LB_FAST(B + 9, FYV, 1, 2, 3, RY)
-                    LB_FAST_SET(0, 0, true)
-                    LB_FAST_SET(16, 0, false)
-                    LB_FAST_SET(32, -1, false)
-#undef LB_FAST_SET
-#undef LB_FAST
-                    default: break;  // not reached: fastw admits only the cases above
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            const int r = r0 + u;
+            if (r >= nrows) break;
+            // gather this row's packets into the FIFO
+            WaveInfo w = s_w[b][u][wid];
+            if (wid > 0) w = merge(w, s_w[b][u][wid - 1]);
+            if (wid + 1 < kMNW) w = merge(w, s_w[b][u][wid + 1]);
+            // the fast and row paths need every packet of the window inside the
+            // FIFO (y) and the staged row (x); the general path takes any window
+            // whose sources each reach <= H.  A short FIFO that cannot hold the
+            // window's y displacements marks the step for a redo.
+            const int c2max = w.c1max + 1;
+            const bool fits_y = w.fymin - c2max >= -L && w.fymax + 1 + c2max <= L;
+            const bool fits_x = w.fxmin - c2max >= -kMH && w.fxmax + 1 + c2max <= kMH;
+            if (L < kLFull && !fits_y) yfar = 1;
+            const bool rows_ok = fits_x && fits_y && w.fymin == w.fymax && (w.fymin == 0 || w.fymin == -1) &&
+                                 w.c1max <= 3 && w.fxmax - w.fxmin <= 2;
+            if (dest && (fits_y || L == kLFull)) {
+                // two adjacent values of c'_1 or of floor(v_x) keep compile-time
+                // offsets; a window mixing both (rare in planar flows) takes the
+                // row path, whose extra registers would otherwise cost occupancy
+                const bool cmix = w.c1max == w.c1min + 1, xmix = w.fxmax == w.fxmin + 1;
+                const bool fastw = rows_ok && (w.c1max == w.c1min || cmix) && (w.fxmax == w.fxmin || xmix) &&
+                                   !(cmix && xmix) && (!cmix || w.c1min <= 2) && (!xmix || w.c1min <= 1);
+                if (fastw) {
+                    const MRow<T>& R = s_row[b][u];
+                    const int fx0 = w.fxmax;
+                    const int sel = ((w.fymin == 0 ? (w.ry0 ? 0 : 1) : 2) * 2 + (xmix ? 1 : 0)) * 8 +
+                                    (cmix ? 4 : 0) + w.c1min;
+                    switch (sel) {
+    #define LB_FAST(S, FYV, S0, NSP, NKX, RY)                                                   \
+        case S:                                                                                 \
+            if constexpr ((FYV) - (S0) - (NSP) + 1 >= -L && (FYV) + 1 + (S0) + (NSP) - 1 <= L)  \
+                gather_fast<T, L, FYV, S0, NSP, NKX, RY>(R, tid, fx0, f);                       \
+            break;
+    #define LB_FAST_SET(B, FYV, RY)                                                              \
+        LB_FAST(B + 0, FYV, 0, 2, 2, RY) LB_FAST(B + 1, FYV, 1, 2, 2, RY) LB_FAST(B + 2, FYV, 2, 2, 2, RY) \
+        LB_FAST(B + 3, FYV, 3, 2, 2, RY) LB_FAST(B + 4, FYV, 0, 3, 2, RY) LB_FAST(B + 5, FYV, 1, 3, 2, RY) \
+        LB_FAST(B + 6, FYV, 2, 3, 2, RY)                                                        \
+        LB_FAST(B + 8, FYV, 0, 2, 3, RY) LB_FAST(B + 9, FYV, 1, 2, 3, RY)
+                        LB_FAST_SET(0, 0, true)
+                        LB_FAST_SET(16, 0, false)
+                        LB_FAST_SET(32, -1, false)
+    #undef LB_FAST_SET
+    #undef LB_FAST
+                        default: break;  // not reached: fastw admits only the cases above
+                    }
+                } else if (rows_ok) {
+                    if (w.fymin == 0)
+                        gather_rows<T, L, 0>(s_row[b][u], tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max);
+                    else
+                        gather_rows<T, L, -1>(s_row[b][u], tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max);
+                } else {
+                    gather_general<T, L>(s_row[b][u], tid, f, w.fymin + L, w.fymax + 1 + L,
+                                         w.fymin - c2max + L, w.fymax + 1 + c2max + L);
                 }
-            } else if (rows_ok) {
-                if (w.fymin == 0)
-                    gather_rows<T, L, 0>(s_row[b], tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max);
-                else
-                    gather_rows<T, L, -1>(s_row[b], tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max);
-            } else {
-                gather_general<T, L>(s_row[b], tid, f, w.fymin + L, w.fymax + 1 + L,
-                                     w.fymin - c2max + L, w.fymax + 1 + c2max + L);
             }
+            // destination row (source row) - L is complete
+            if (r >= 2 * L && dest) {
+                const int64_t ty = Y0 + r - 2 * L;
+                const int64_t q = ty * nx + gx;
+                const T py = (T)(f.a[0][kPyv] + (f.a[0][kGh] + f.a[0][kGl]));
+                Yn[q] = (T)f.a[0][kR];
+                Yn[nn + q] = (T)f.a[0][kPx];
+                Yn[2 * nn + q] = py;
+                Yn[3 * nn + q] = (T)f.a[0][kE];
+                tot[0] += (double)f.a[0][kR];
+                tot[1] += (double)f.a[0][kPx];
+                tot[2] += (double)py;
+                tot[3] += (double)f.a[0][kE];
+            }
+    #pragma unroll
+            for (int o = 0; o + 1 < NS; ++o)
+    #pragma unroll
+                for (int c = 0; c < kNV; ++c) f.a[o][c] = f.a[o + 1][c];
+    #pragma unroll
+            for (int c = 0; c < kNV; ++c) f.a[NS - 1][c] = (A)0;
         }
-        // destination row (source row) - L is complete
-        if (r >= 2 * L && dest) {
-            const int64_t ty = Y0 + r - 2 * L;
-            const int64_t q = ty * nx + gx;
-            const T py = (T)(f.a[0][kPyv] + (f.a[0][kGh] + f.a[0][kGl]));
-            Yn[q] = (T)f.a[0][kR];
-            Yn[nn + q] = (T)f.a[0][kPx];
-            Yn[2 * nn + q] = py;
-            Yn[3 * nn + q] = (T)f.a[0][kE];
-            tot[0] += (double)f.a[0][kR];
-            tot[1] += (double)f.a[0][kPx];
-            tot[2] += (double)py;
-            tot[3] += (double)f.a[0][kE];
-        }
 #pragma unroll
-        for (int o = 0; o + 1 < NS; ++o)
+        for (int u = 0; u < RB; ++u)
 #pragma unroll
-            for (int c = 0; c < kNV; ++c) f.a[o][c] = f.a[o + 1][c];
-#pragma unroll
-        for (int c = 0; c < kNV; ++c) f.a[NS - 1][c] = (A)0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) cur[c] = nxt[c];
+            for (int c = 0; c < 4; ++c) cur[u][c] = nxt[u][c];
     }
     // per-tile partials: field sums, reach, error bits
     __shared__ double s_sum[kMNW][4];
