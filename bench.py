@@ -170,8 +170,8 @@ def main():
                     help="short run + a plain copy of known size, for rocprofv3 counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path "
+              "(slabs along x with a halo exchange would be the multi-GPU design)", file=sys.stderr)
         sys.exit(2)
 
     import torch

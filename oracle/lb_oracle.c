@@ -22,7 +22,7 @@
  *     copy the edge node and are refilled every step; packets that leave the
  *     interior are dropped.  Periodic directions wrap.
  *
- * Readings of points the paper leaves open (each also listed in the design doc):
+ * Readings of points the paper leaves open:
  *   - "int" in eq. 26 is the floor of a non-negative real; c'_1 is the largest
  *     integer with c'_1^2 <= A, decided by exact comparison.
  *   - d_0 = delta0 * rho with delta0 a parameter (paper: 0.4 .. 0.55).
