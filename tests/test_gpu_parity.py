@@ -390,3 +390,25 @@ def test_fp32_planar_tube_against_oracle(lbsd, seed):
     assert np.all(got == got[:, :1, :])
     rel_l1 = np.sum(np.abs(got[0, :4] - ref[0])) / np.sum(np.abs(ref[0]))
     assert rel_l1 <= 1e-5, rel_l1
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_fp32_form_2000_steps_against_fp64(lbsd, seed):
+    """The FP32 form over the full 2000 steps of the seeded 4096-wide planar
+    tubes (rows are identical, so 16 rows stand for 4096): relative L1
+    density error against the FP64 form (itself parity-checked against the
+    oracle above) within 1e-5."""
+    nx, ny, n = 4096, 16, 2000
+    left, right, xd = inputs.riemann_instance(seed)
+    lam = inputs.cfl_lambda([left, right])
+    out = {}
+    for prec in ("fp64", "fp32"):
+        s = lbsd.Solver(2, nx, ny, precision=prec)
+        s.init_riemann(xd, left, right, lam=lam)
+        s.step(n)
+        out[prec] = s.moments()
+        s.close()
+    a, b = out["fp32"][0], out["fp64"][0]
+    assert np.all(out["fp32"] == out["fp32"][:, :1, :])
+    rel_l1 = np.sum(np.abs(a - b)) / np.sum(np.abs(b))
+    assert rel_l1 <= 1e-5, rel_l1
