@@ -16,7 +16,8 @@ gather kernel plus its totals reduction.  Alongside, in the same JSON line:
 * serve: square-lattice requests (sides log-uniform in [64, 2048], steps in
   [100, 5000], seeded states) arriving as a Poisson process at 0.8 x the
   measured capacity, continuously batched on an FP32 pool: p50 / p99
-  latency and aggregate node-updates/s;
+  latency and aggregate node-updates/s; and the same requests all queued at
+  once (the served throughput at saturation);
 * cpu_baseline: the FP64 oracle on a bounded sample, one host thread.
 
 `--profile` runs a short headline plus a plain device copy of known size,
@@ -137,11 +138,15 @@ def run_serve(n_requests: int = 100, seed: int = 0):
     rate = 0.8 * cap_nups / mean_work
     reqs = inputs.serve_requests(seed, n_requests, rate_per_s=rate)
     res = serve.run(pool, reqs, tick=25)
+    # the same requests all queued at once: the served throughput at saturation
+    sat = serve.run(pool, inputs.serve_requests(seed, n_requests, rate_per_s=1e9), tick=25)
     pool.close()
     return dict(value=round(res["nups"] / 1e6, 1), unit="MLUPS", requests=n_requests,
                 rate_per_s=round(rate, 3), capacity_MLUPS=round(cap_nups / 1e6, 1),
                 p50_latency_s=round(res["p50_s"], 4), p99_latency_s=round(res["p99_s"], 4),
-                makespan_s=round(res["makespan_s"], 3), tile_shape=shape, precision="fp32")
+                makespan_s=round(res["makespan_s"], 3), tile_shape=shape,
+                saturated_MLUPS=round(sat["nups"] / 1e6, 1), saturated_makespan_s=round(sat["makespan_s"], 3),
+                precision="fp32")
 
 
 def traffic_per_launch():

@@ -212,8 +212,9 @@ double lb_pool_lambda(const lb_pool* p, int32_t slot);
 int32_t lb_pool_live(const lb_pool* p);                  /* admitted slots */
 
 /* Tile shapes: 1-D, threads x nodes per thread in {256x1, 256x2, 256x4,
- * 256x8, 512x4}; square lattice, strip heights {16, 32, 64, 128, 256} rows of
- * 246 columns.  lb_pool_autotune times `trials` steps of every shape on the
+ * 256x8, 512x4}; square lattice, tiles of 246 columns whose strip height makes
+ * about {2, 3, 4, 6, 8} tiles per resident block over the live problems (at
+ * least 16 rows).  lb_pool_autotune times `trials` steps of every shape on the
  * admitted problems without changing their states, keeps the fastest and
  * writes its index and median milliseconds per step. */
 int32_t lb_pool_shapes(const lb_pool* p);

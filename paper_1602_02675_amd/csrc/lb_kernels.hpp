@@ -128,7 +128,8 @@ struct PoolView {
     const int32_t* ntiles;  // tiles in the table (read by the kernels, so admissions need no new launch shape)
     double* partials;       // kPartialStride doubles per tile
     int32_t* flags;         // square lattice: tile needs the full-FIFO pass
-    int32_t* next;          // tile claim counters: [0] step pass, [1] full-FIFO pass; reset by finalize
+    int32_t* next;          // [0], [1]: tile claim counters of the step and full-FIFO passes; [2]: tiles
+                            // flagged for the full-FIFO pass; reset by finalize
     void* arena;            // moment sets of all slots (T elements)
 };
 
@@ -136,9 +137,13 @@ struct PoolView {
 constexpr int kPool1Shapes = 5;
 constexpr int kPool1TPB[kPool1Shapes] = {256, 256, 256, 256, 512};
 constexpr int kPool1J[kPool1Shapes] = {1, 2, 4, 8, 4};
-// Strip heights of the square-lattice pool tiles (rows per tile).
+// Square-lattice pool tiles: the strip height is chosen so that the live
+// problems make about kPool2TilesPerBlock[shape] tiles per resident block
+// (claim-order balance against the 2L halo rows each tile marches again), and
+// is at least kPool2MinRows.
 constexpr int kPool2Shapes = 5;
-constexpr int kPool2Rows[kPool2Shapes] = {16, 32, 64, 128, 256};
+constexpr int kPool2TilesPerBlock[kPool2Shapes] = {2, 3, 4, 6, 8};
+constexpr int kPool2MinRows = 16;
 constexpr int kPool2Cols = 256 - 2 * kHalo;  // destination columns per square-lattice tile
 
 // One step of every live tile: the 1-D kernel of tile shape `shape` (nblocks =

@@ -659,6 +659,7 @@ __global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < 
 pool2d_kernel(PoolView v, Consts k)
 {
     __shared__ int s_t;
+    if (L == kLFull && v.next[2] == 0) return;  // the short pass flagged no tile
     const int nt = *v.ntiles;
     T* arena = (T*)v.arena;
     for (;;) {
@@ -673,7 +674,10 @@ pool2d_kernel(PoolView v, Consts k)
         const Grid g{tl.nx, tl.ny, tl.bc_x, tl.bc_y};
         const int far = march_tile<T, L>(arena + from, arena + to, g, k, tl.x0, tl.y0, tl.rows,
                                          v.partials + (int64_t)t * kPartialStride);
-        if (threadIdx.x == 0) v.flags[t] = L < kLFull ? far : 0;
+        if (threadIdx.x == 0) {
+            v.flags[t] = L < kLFull ? far : 0;
+            if (L < kLFull && far) atomicAdd(&v.next[2], 1);
+        }
     }
 }
 

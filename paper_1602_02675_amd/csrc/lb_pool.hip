@@ -81,15 +81,30 @@ PoolView view_of(const lb_pool* p)
 size_t set_bytes(const lb_pool* p, int64_t nn) { return align256((size_t)p->nf * (size_t)nn * p->elem); }
 
 int64_t tile_cols(const lb_pool* p) { return p->dim == 1 ? (int64_t)kPool1TPB[p->shape] * kPool1J[p->shape] : kPool2Cols; }
-int64_t tile_rows(const lb_pool* p) { return p->dim == 1 ? 1 : kPool2Rows[p->shape]; }
-
 int64_t tiles_of(const lb_pool* p, int64_t nx, int64_t ny, int shape)
 {
     if (p->dim == 1) {
         const int64_t t = (int64_t)kPool1TPB[shape] * kPool1J[shape];
         return (nx + t - 1) / t;
     }
-    return ((nx + kPool2Cols - 1) / kPool2Cols) * ((ny + kPool2Rows[shape] - 1) / kPool2Rows[shape]);
+    return ((nx + kPool2Cols - 1) / kPool2Cols) * ((ny + kPool2MinRows - 1) / kPool2MinRows);  // at most
+}
+
+int launch_blocks(const lb_pool* p, int64_t ntiles);
+
+// Rows per tile: 1 in 1-D; on the square lattice about
+// kPool2TilesPerBlock[shape] tiles per resident block over the live problems.
+int64_t tile_rows(const lb_pool* p)
+{
+    if (p->dim == 1) return 1;
+    int64_t strip_rows = 0;  // rows of all column strips of the live problems
+    for (int i = 0; i < p->max_slots; ++i) {
+        const PoolProb& q = p->probs[(size_t)i];
+        if (q.active) strip_rows += ((q.nx + kPool2Cols - 1) / kPool2Cols) * q.ny;
+    }
+    const int64_t want = (int64_t)kPool2TilesPerBlock[p->shape] * launch_blocks(p, 0);
+    const int64_t rows = (strip_rows + want - 1) / std::max<int64_t>(want, 1);
+    return std::max<int64_t>(rows, kPool2MinRows);
 }
 
 // Worst case over the shapes, so that a later shape change always fits.
@@ -162,7 +177,7 @@ int upload_tables(lb_pool* p)
         drop_graph(p);
         p->nblocks = nb;
     }
-    std::vector<int32_t> zeros((size_t)std::max<int32_t>(nt, 2), 0);
+    std::vector<int32_t> zeros((size_t)std::max<int32_t>(nt, 3), 0);
     // tile words from the slots' device states
     std::vector<PoolState> st((size_t)p->max_slots);
     hipError_t e = hipStreamSynchronize(p->stream);
@@ -186,7 +201,7 @@ int upload_tables(lb_pool* p)
     if ((e = hipMemcpyAsync(p->base + p->off_ntiles, &nt, sizeof nt, hipMemcpyHostToDevice, p->stream)) !=
         hipSuccess)
         return hip_fail(e, "upload tile count");
-    if ((e = hipMemcpyAsync(p->base + p->off_ntiles + 64, zeros.data(), 2 * sizeof(int32_t),
+    if ((e = hipMemcpyAsync(p->base + p->off_ntiles + 64, zeros.data(), 3 * sizeof(int32_t),
                             hipMemcpyHostToDevice, p->stream)) != hipSuccess)
         return hip_fail(e, "clear claim counters");
     if (nt > 0 && (e = hipMemcpyAsync(p->base + p->off_flags, zeros.data(), (size_t)nt * 4,

@@ -382,6 +382,7 @@ __global__ void __launch_bounds__(kFinTPB) pool_finalize_kernel(PoolView v, int 
     if (p == 0 && threadIdx.x == 0) {  // the step kernels of this step are done with their counters
         v.next[0] = 0;
         v.next[1] = 0;
+        v.next[2] = 0;
     }
     const PoolProb& P = v.probs[p];
     PoolState& S = v.state[p];
