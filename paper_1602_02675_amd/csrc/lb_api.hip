@@ -180,10 +180,9 @@ struct lb_solver {
     int64_t nn;
     size_t elem;
     // layout inside the bound buffer
-    size_t off_buf[2], off_export, off_ctl, off_partials, total;
+    size_t off_buf[2], off_export, off_ctl, off_partials, off_flags, total;
     int64_t nblocks;      // step-kernel blocks (rows of partials used per step)
     MarchGeom march;      // square lattice launch geometry (set at bind)
-    bool march_full;      // square lattice: launch only the full-FIFO kernel
     char* base;
     hipStream_t stream;
     bool bound, initialized;
@@ -198,6 +197,7 @@ struct lb_solver {
 static void* buf_ptr(lb_solver* s, int i) { return s->base + s->off_buf[i]; }
 static StepCtl* ctl_ptr(lb_solver* s) { return (StepCtl*)(s->base + s->off_ctl); }
 static double* partials_ptr(lb_solver* s) { return (double*)(s->base + s->off_partials); }
+static int* flags_ptr(lb_solver* s) { return (int*)(s->base + s->off_flags); }
 static double* export_ptr(lb_solver* s) { return (double*)(s->base + s->off_export); }
 
 extern "C" {
@@ -232,7 +232,8 @@ int lb_create(const lb_grid* grid, double gamma, const lb_velset* vs, int32_t pr
     s->off_export = 2 * field_bytes;
     s->off_ctl = s->off_export + align256((size_t)s->nf * (size_t)s->nn * 8);
     s->off_partials = s->off_ctl + align256(sizeof(StepCtl));
-    s->total = s->off_partials + align256((size_t)s->nblocks * kPartialStride * 8);
+    s->off_flags = s->off_partials + align256((size_t)s->nblocks * kPartialStride * 8);
+    s->total = s->off_flags + align256((size_t)(dim == 2 ? s->nblocks : 1) * 4);
     s->cfl = 1.0;
     s->lambda_set = 0.0;
     *out = s;
@@ -292,7 +293,6 @@ int lb_set_cfl(lb_solver* s, double cfl)
 
 static int start_state(lb_solver* s)
 {
-    s->march_full = false;
     s->cur = 0;
     s->steps_done = 0;
     s->pending_err = 0;
@@ -352,12 +352,12 @@ static int queue_steps(lb_solver* s, int64_t n, hipEvent_t* ev = nullptr)
         } else {
             if (s->precision == LB_FP64)
                 e = launch_march2d<double>((const double*)buf_ptr(s, in), (double*)buf_ptr(s, out), s->g,
-                                           s->march, s->k, ctl_ptr(s), partials_ptr(s), step,
-                                           s->march_full, s->stream);
+                                           s->march, s->k, ctl_ptr(s), partials_ptr(s), flags_ptr(s), step,
+                                           s->stream);
             else
                 e = launch_march2d<float>((const float*)buf_ptr(s, in), (float*)buf_ptr(s, out), s->g,
-                                          s->march, s->k, ctl_ptr(s), partials_ptr(s), step,
-                                          s->march_full, s->stream);
+                                          s->march, s->k, ctl_ptr(s), partials_ptr(s), flags_ptr(s), step,
+                                          s->stream);
         }
         if (e != hipSuccess) return hip_fail(e, "step launch");
         if (ev && (e = hipEventRecord(ev[2 * i + 1], s->stream)) != hipSuccess) return hip_fail(e, "event");
@@ -388,7 +388,6 @@ int lb_sync(lb_solver* s)
     StepCtl c;
     if ((e = hipMemcpy(&c, ctl_ptr(s), sizeof c, hipMemcpyDeviceToHost)) != hipSuccess)
         return hip_fail(e, "read control block");
-    if (c.redo_count > 0) s->march_full = true;  // the short FIFO no longer covers the flow
     if (c.err_code) {
         // step err_step (1-based since init) failed; its input, the state
         // after err_step - 1 steps, sits in buffer (err_step - 1) & 1.

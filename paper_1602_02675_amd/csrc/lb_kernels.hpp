@@ -15,15 +15,15 @@ constexpr int kErrState = 2;  // rho <= 0 or a non-finite moment
 
 // Per-solver control block in device memory (written by the step kernels).
 struct StepCtl {
-    int next[2];            // tile claim counters of the two square-lattice passes (reset by finalize)
+    int next[3];            // square lattice: tile claim counters of the short- and full-FIFO passes,
+                            // and the number of tiles the short pass flagged (reset by finalize)
     int err_code;           // kErr* bits of the first failed step
     long long err_step;     // first failed step (LLONG_MAX if none)
     long long totals_step;  // step whose totals are in `totals`
     double totals[4];       // interior sums of the moment fields (lattice units)
     int max_reach;          // largest reach seen in the latest step
-    int redo_count;         // steps the square-lattice kernel had to redo with its full FIFO
-    long long redo_step;    // step whose short-FIFO pass found a y-reach beyond its FIFO
-    int pad[3];
+    int redo_tiles;         // tiles the full-FIFO pass has recomputed since the last reset
+    int pad[5];
 };
 
 // Per-block partial results: 4 field sums, reach, error bits.
@@ -56,12 +56,13 @@ MarchGeom march2d_geometry(const Grid& g, int resident_blocks);
 int64_t march2d_max_blocks(const Grid& g);
 template <typename T>
 int march2d_blocks_per_cu();
-// full_only: launch only the full-FIFO kernel; otherwise the short-FIFO
-// kernel runs and the full one redoes the step only if it had to.
+// The short-FIFO kernel runs every tile and flags (flags[tile] != 0) those
+// whose packets reach past its FIFO; the full-FIFO kernel then recomputes only
+// the flagged tiles (it returns at once when there are none).  flags holds
+// one int per tile.
 template <typename T>
 hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
-                          StepCtl* ctl, double* partials, long long step, bool full_only,
-                          hipStream_t stream);
+                          StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream);
 
 // Reduce nb per-block partial rows of one step into ctl (fixed order).
 hipError_t launch_finalize(const double* partials, int64_t nb, StepCtl* ctl, long long step,

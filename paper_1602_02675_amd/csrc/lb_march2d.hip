@@ -352,16 +352,18 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc
 }
 
 // Any mix of floor(v) and c'_1 around the destination (floor(v_y) varies
-// across the wavefront, i.e. the flow is not planar here): examine all 2H + 1
-// staged sources of the row and every packet that reaches this column.
+// across the wavefront, i.e. the flow is not planar here): examine the staged
+// sources at x displacements [alo, ahi] (all that the window's packets can
+// have, within the halo) and every packet that reaches this column.
 // [xlo, xhi] / [ylo, yhi] bound the FIFO slots x- / y-lane packets of the
 // wavefront's sources can reach.
 template <typename T, int L>
-__device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, int xlo, int xhi, int ylo, int yhi)
+__device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, int alo, int ahi, int xlo, int xhi,
+                               int ylo, int yhi)
 {
 #pragma clang fp contract(off)
 #pragma unroll 1
-    for (int a = -kMH; a <= kMH; ++a) {
+    for (int a = alo; a <= ahi; ++a) {  // x displacements the window's packets can have
         const int s = lane - a;
         const int pk = R.pk[s];
         const int fx = mfx(pk), fy = mfy(pk), c1 = mc1(pk), c2 = c1 + 1;
@@ -551,7 +553,8 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                     else
                         gather_rows<T, L, -1>(s_row[b][u], tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max);
                 } else {
-                    gather_general<T, L>(s_row[b][u], tid, f, w.fymin + L, w.fymax + 1 + L,
+                    gather_general<T, L>(s_row[b][u], tid, f, max(-kMH, w.fxmin - c2max),
+                                         min(kMH, w.fxmax + 1 + c2max), w.fymin + L, w.fymax + 1 + L,
                                          w.fymin - c2max + L, w.fymax + 1 + c2max + L);
                 }
             }
@@ -620,33 +623,31 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
 #ifndef LB_MARCH_WPE_F32
 #define LB_MARCH_WPE_F32 4
 #endif
-// L = kLSmall: the short-FIFO pass; a tile whose sources reach beyond the
-// FIFO marks the step for a redo.  L = kLFull with redo_only: runs only if the
-// short pass of this step asked for it, and then recomputes every tile.
-// Persistent blocks claim the tiles (tiles_x column strips x row chunks of sy
-// rows, row chunk major) from the control block's counter of the pass.
+// L = kLSmall: the short-FIFO pass over every tile; a tile whose sources reach
+// beyond its FIFO is flagged.  L = kLFull: recomputes the flagged tiles only
+// (bit-identically: the summation order does not depend on L).  Persistent
+// blocks claim the tiles (tiles_x column strips x row chunks of sy rows, row
+// chunk major) from the control block's counter of the pass.
 template <typename T, int L>
 __global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
 march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
-               StepCtl* __restrict__ ctl, double* __restrict__ partials, long long step, int sy,
-               int tiles_x, int ntiles, int redo_only)
+               StepCtl* __restrict__ ctl, double* __restrict__ partials, int* __restrict__ flags,
+               long long step, int sy, int tiles_x, int ntiles)
 {
     __shared__ int s_t;
     if (ctl->err_step < step) return;
-    if (redo_only && ctl->redo_step != step) return;
-    int far = 0;
+    if (L == kLFull && ctl->next[2] == 0) return;  // the short pass flagged no tile
     for (;;) {
         const int t = claim_tile(&ctl->next[L < kLFull ? 0 : 1], &s_t);
         if (t >= ntiles) break;
+        if (L == kLFull && flags[t] == 0) continue;
         const int64_t tx = t % tiles_x, ty = t / tiles_x;
-        far |= march_tile<T, L>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
-                                partials + (int64_t)t * kPartialStride);
-    }
-    if (threadIdx.x == 0) {
-        if (L < kLFull) {
-            if (far) ctl->redo_step = step;
-        } else if (redo_only && blockIdx.x == 0) {
-            ctl->redo_count += 1;
+        const int far = march_tile<T, L>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
+                                         partials + (int64_t)t * kPartialStride);
+        if (threadIdx.x == 0) {
+            flags[t] = L < kLFull ? far : 0;
+            if (L < kLFull && far) atomicAdd(&ctl->next[2], 1);
+            if (L == kLFull) atomicAdd(&ctl->redo_tiles, 1);
         }
     }
 }
@@ -724,18 +725,15 @@ int march2d_blocks_per_cu()
 
 template <typename T>
 hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
-                          StepCtl* ctl, double* partials, long long step, bool full_only,
-                          hipStream_t stream)
+                          StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream)
 {
     const int nt = (int)m.blocks();
-    if (!full_only) {
-        march2d_kernel<T, kLSmall><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step, m.sy,
-                                                                    (int)m.grid_x, nt, 0);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    march2d_kernel<T, kLFull><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step, m.sy,
-                                                               (int)m.grid_x, nt, full_only ? 0 : 1);
+    march2d_kernel<T, kLSmall><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, flags, step, m.sy,
+                                                                (int)m.grid_x, nt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    march2d_kernel<T, kLFull><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, flags, step, m.sy,
+                                                               (int)m.grid_x, nt);
     return hipGetLastError();
 }
 
@@ -765,10 +763,8 @@ template int pool2d_blocks_per_cu<float>();
 template hipError_t launch_pool2d<double>(const PoolView&, const Consts&, int, hipStream_t);
 template hipError_t launch_pool2d<float>(const PoolView&, const Consts&, int, hipStream_t);
 template hipError_t launch_march2d<double>(const double*, double*, const Grid&, const MarchGeom&,
-                                           const Consts&, StepCtl*, double*, long long, bool,
-                                           hipStream_t);
+                                           const Consts&, StepCtl*, double*, int*, long long, hipStream_t);
 template hipError_t launch_march2d<float>(const float*, float*, const Grid&, const MarchGeom&,
-                                          const Consts&, StepCtl*, double*, long long, bool,
-                                          hipStream_t);
+                                          const Consts&, StepCtl*, double*, int*, long long, hipStream_t);
 
 }  // namespace lbsd

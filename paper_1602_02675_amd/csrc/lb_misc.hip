@@ -58,13 +58,13 @@ __global__ void reset_ctl_kernel(StepCtl* ctl)
     if (threadIdx.x == 0) {
         ctl->next[0] = 0;
         ctl->next[1] = 0;
+        ctl->next[2] = 0;
         ctl->err_code = 0;
         ctl->err_step = LLONG_MAX;
         ctl->totals_step = -1;
         for (int f = 0; f < 4; ++f) ctl->totals[f] = 0.0;
         ctl->max_reach = 0;
-        ctl->redo_count = 0;
-        ctl->redo_step = -1;
+        ctl->redo_tiles = 0;
     }
 }
 

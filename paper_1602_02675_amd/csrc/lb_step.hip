@@ -116,6 +116,7 @@ finalize_kernel(const double* __restrict__ partials, int64_t nb, StepCtl* __rest
     if (threadIdx.x == 0) {  // the step kernels of this step are done with their counters
         ctl->next[0] = 0;
         ctl->next[1] = 0;
+        ctl->next[2] = 0;
     }
     if (ctl->err_step < step) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;

@@ -15,6 +15,8 @@ Sec. V.C, with u = 0 on both sides):
 * ``serve_requests(seed, n)``: square sides round(exp(U[ln 64, ln 2048])),
   steps ~ U{100..5000}, states as ``riemann_instance``, exponential
   inter-arrival gaps.
+* ``quadrant_riemann(seed)``: a 2-D Riemann problem of four seeded
+  constant states (non-planar data for the square lattice).
 * ``random_state(seed, ...)``: random positive-density moment fields in
   lattice units, for index and field parity.
 """
@@ -86,6 +88,45 @@ def serve_requests(seed: int, n: int, rate_per_s: float, side_lo: int = 64, side
         out.append(dict(arrival=t, side=int(sides[i]), steps=int(steps[i]),
                         left=left, right=right, x_d=x_d))
     return out
+
+
+def quadrant_riemann(seed: int):
+    """A seeded 2-D Riemann problem: four constant states meeting at (x_c, y_c)
+    in the unit square.  Each state has rho log-uniform in [0.1, 1], p
+    log-uniform in [0.05, 1] and a velocity of modulus up to 0.3 in a random
+    direction; x_c, y_c ~ U[0.3, 0.7].  Returns (states, (x_c, y_c)) with
+    states ordered lower-left, lower-right, upper-left, upper-right."""
+    rng = np.random.default_rng(seed)
+    states = []
+    for _ in range(4):
+        rho = float(np.exp(rng.uniform(math.log(0.1), 0.0)))
+        p = float(np.exp(rng.uniform(math.log(0.05), 0.0)))
+        sp, ang = rng.uniform(0.0, 0.3), rng.uniform(0.0, 2.0 * math.pi)
+        states.append((rho, float(sp * math.cos(ang)), float(sp * math.sin(ang)), p))
+    xc, yc = rng.uniform(0.3, 0.7, size=2)
+    return states, (float(xc), float(yc))
+
+
+def quadrant_moments(states, center, nx: int, ny: int, gamma: float = GAMMA) -> np.ndarray:
+    """Conserved moments [4, ny, nx] (physical units) of a quadrant problem on
+    cell-centred nodes of [0, 1] x [0, ny/nx] (dy = dx)."""
+    x = node_x(nx)
+    y = (np.arange(ny, dtype=np.float64) + 0.5) / nx
+    X, Yy = np.meshgrid(x, y)
+    Y = np.zeros((4, ny, nx))
+    for k, (rho, u, v, p) in enumerate(states):
+        right, upper = k & 1, k >> 1
+        m = ((X >= center[0]) == bool(right)) & ((Yy >= center[1]) == bool(upper))
+        Y[0][m] = rho
+        Y[1][m] = rho * u
+        Y[2][m] = rho * v
+        Y[3][m] = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    return Y
+
+
+def quadrant_lambda(states, cfl: float = 1.0, gamma: float = GAMMA) -> float:
+    """lambda = cfl / max(|v| + sqrt(gamma p / rho)) over the four states."""
+    return cfl / max(math.hypot(u, v) + math.sqrt(gamma * p / rho) for (rho, u, v, p) in states)
 
 
 def random_state(seed: int, dim: int, nx: int, ny: int = 1, *, rho=(0.2, 2.0), vel=(-1.8, 1.8),
