@@ -355,11 +355,12 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc
 // across the wavefront, i.e. the flow is not planar here): examine the staged
 // sources at x displacements [alo, ahi] (all that the window's packets can
 // have, within the halo) and every packet that reaches this column.
-// [xlo, xhi] / [ylo, yhi] bound the FIFO slots x- / y-lane packets of the
-// wavefront's sources can reach.
+// [fylo, fyhi] and [clo, chi] are the window's ranges of floor(v_y) and c'_1:
+// each packet class then reaches one or two FIFO slots, and only those are
+// visited.
 template <typename T, int L>
-__device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, int alo, int ahi, int xlo, int xhi,
-                               int ylo, int yhi)
+__device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, int alo, int ahi, int fylo, int fyhi,
+                               int clo, int chi)
 {
 #pragma clang fp contract(off)
 #pragma unroll 1
@@ -383,7 +384,8 @@ __device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, i
 #pragma unroll 1
                 for (int ky = 0; ky < 2; ++ky) {
                     const T m = w * (ky ? ry : (T)1 - ry);
-                    fifo_add_sel<Acc<T>, T, L>(f, fy + ky + L, xlo, xhi, m, m * (vx + cc), m * vy, m * zx);
+                    fifo_add_sel<Acc<T>, T, L>(f, fy + ky + L, fylo + ky + L, fyhi + ky + L, m, m * (vx + cc),
+                                               m * vy, m * zx);
                 }
             }
             if (cx == 0) {  // y-lanes move in x by fx + kx only
@@ -398,8 +400,11 @@ __device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, i
                         for (int ky = 0; ky < 2; ++ky) {
                             const T m = R.m[l][kx][s] * (ky ? ry : (T)1 - ry);
                             const int slot = fy + ky + sg * c + L;
-                            fifo_add_sel<Acc<T>, T, L>(f, slot, ylo, yhi, m, m * vx, m * vy, m * zy);
-                            fifo_add_g<Acc<T>, T, L>(f, slot, ylo, yhi, m * cc);
+                            // the window's range of this packet class's slot (uniform)
+                            const int lo = fylo + ky + (sg > 0 ? clo + l : -(chi + l)) + L;
+                            const int hi = fyhi + ky + (sg > 0 ? chi + l : -(clo + l)) + L;
+                            fifo_add_sel<Acc<T>, T, L>(f, slot, lo, hi, m, m * vx, m * vy, m * zy);
+                            fifo_add_g<Acc<T>, T, L>(f, slot, lo, hi, m * cc);
                         }
                     }
                 }
@@ -554,8 +559,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                         gather_rows<T, L, -1>(s_row[b][u], tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max);
                 } else {
                     gather_general<T, L>(s_row[b][u], tid, f, max(-kMH, w.fxmin - c2max),
-                                         min(kMH, w.fxmax + 1 + c2max), w.fymin + L, w.fymax + 1 + L,
-                                         w.fymin - c2max + L, w.fymax + 1 + c2max + L);
+                                         min(kMH, w.fxmax + 1 + c2max), w.fymin, w.fymax, w.c1min, w.c1max);
                 }
             }
             // destination row (source row) - L is complete
