@@ -48,3 +48,22 @@ def test_random_state_physical():
     assert np.all(rho > 0)
     e = Y[3] / rho - 0.5 * ((Y[1] / rho) ** 2 + (Y[2] / rho) ** 2)
     assert np.all(e >= -1e-12)
+
+
+def test_quadrant_riemann_layout():
+    states, (xc, yc) = inputs.quadrant_riemann(4)
+    assert len(states) == 4 and 0.3 <= xc <= 0.7 and 0.3 <= yc <= 0.7
+    for rho, u, v, p in states:
+        assert 0.1 <= rho <= 1.0 and 0.05 <= p <= 1.0 and math.hypot(u, v) <= 0.3
+    nx, ny = 50, 40
+    Y = inputs.quadrant_moments(states, (xc, yc), nx, ny)
+    x = inputs.node_x(nx)
+    y = (np.arange(ny) + 0.5) / nx
+    for j in (0, ny - 1):
+        for i in (0, nx - 1):
+            k = int(x[i] >= xc) + 2 * int(y[j] >= yc)
+            rho, u, v, p = states[k]
+            assert Y[0, j, i] == rho and Y[1, j, i] == rho * u and Y[2, j, i] == rho * v
+            assert Y[3, j, i] == pytest.approx(p / 0.4 + 0.5 * rho * (u * u + v * v), rel=1e-15)
+    lam = inputs.quadrant_lambda(states)
+    assert lam == pytest.approx(1.0 / max(math.hypot(u, v) + math.sqrt(1.4 * p / r) for r, u, v, p in states))
