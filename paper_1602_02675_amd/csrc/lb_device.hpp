@@ -45,16 +45,6 @@ struct Src2 {   // one source node of the square lattice, as the gather uses it
     bool bad;
 };
 
-template <typename T>
-__device__ __forceinline__ T dev_floor(T x) { return floor(x); }
-template <>
-__device__ __forceinline__ float dev_floor<float>(float x) { return floorf(x); }
-
-template <typename T>
-__device__ __forceinline__ T dev_sqrt(T x) { return sqrt(x); }
-template <>
-__device__ __forceinline__ float dev_sqrt<float>(float x) { return sqrtf(x); }
-
 // Largest integer c with c*c <= A, for 0 <= A <= kMaxC1^2 (eq. 26: "int" of sqrt).
 template <typename T>
 __device__ __forceinline__ int isqrt_floor(T A)

@@ -4,24 +4,25 @@
 //
 // Every packet moves along x by floor(v_x) + k_x (+ c' for x-lanes) and along y
 // by floor(v_y) + k_y (+ c' for y-lanes).  The kernel splits the two:
-//   - a block of 256 threads owns 256 consecutive source columns (the middle
-//     256 - 2H of them are its destination columns) and marches down a strip
-//     of rows;
-//   - per source row, each thread turns its node's moments into
-//     (floor v, r, c'_1, d_1, d_2, K) once and stages them in an LDS row
-//     buffer (double-buffered: one barrier per row);
+//   - a tile is 256 consecutive source columns (the middle 256 - 2H of them
+//     are its destination columns) by a strip of destination rows; a block of
+//     256 threads marches down the strip (persistent blocks claim tiles);
+//   - per source row, each thread turns its node's moments into what its
+//     packets need (floor v, r_y, c'_1, v_x, the packet masses per level and
+//     x corner, K + c'^2 / 2 per level) once and stages them in an LDS row
+//     buffer (double-buffered: one barrier per staged group of rows);
 //   - each destination thread gathers the packets that move into its column
 //     from the staged row (the x part of the migration) and adds each to a
 //     register FIFO of pending destination rows, indexed by the y
-//     displacement o = floor(v_y) + k_y (+ c' for y-lanes), o in [-H, H]
-//     (the y part); after source row sy the FIFO slot of row sy - H can
+//     displacement o = floor(v_y) + k_y (+ c' for y-lanes), o in [-L, L]
+//     (the y part); once source row r is in, the FIFO slot of row r - L can
 //     receive nothing more and is written out.
-// Where the staged sources around a wavefront share floor(v) and c'_1 (the
-// integer parts of the migration vectors are piecewise constant), the 32
-// packet classes have compile-time column offsets and FIFO slots; elsewhere
-// every source within the halo is examined and slots are chosen at run time.
-// The same packets are summed either way; only the summation order differs
-// from the scatter definition.
+// Where the staged sources around a wavefront share floor(v) and c'_1, or
+// take two adjacent values of one of floor(v_x) and c'_1 (the integer parts of
+// the migration vectors are piecewise constant), the packet classes have
+// compile-time column offsets and FIFO slots; elsewhere candidate sources are
+// matched at run time.  The same packets are summed either way; only the
+// summation order differs from the scatter definition.
 #include <climits>
 
 #include "lb_kernels.hpp"
