@@ -28,6 +28,7 @@ _lib = None
 
 TRANSMISSIVE = 0
 PERIODIC = 1
+REFLECTING = 2
 
 
 def build() -> str:

@@ -21,6 +21,13 @@
  *   - boundaries (Sec. V.B): transmissive ends use explicit ghost nodes that
  *     copy the edge node and are refilled every step; packets that leave the
  *     interior are dropped.  Periodic directions wrap.
+ *   - reflecting walls (the shock reflection the conclusions name as an
+ *     extension): a wall stands on the outer face of each edge node, half a
+ *     node beyond it.  A packet whose destination lies past the wall is
+ *     reflected specularly: it lands as far inside the wall as it would have
+ *     landed outside (index -1 - i below the low end, 2n - 1 - i above the
+ *     high end), and the component of its momentum normal to the wall changes
+ *     sign; its mass and energy are unchanged.
  *
  * Readings of points the paper leaves open:
  *   - "int" in eq. 26 is the floor of a non-negative real; c'_1 is the largest
@@ -45,7 +52,8 @@
 typedef struct {
     int dim;        /* 1: 1-D triple-level lattice; 2: square dual-level lattice */
     long nx, ny;    /* ny = 1 when dim = 1 */
-    int bc_x, bc_y; /* 0: transmissive (ghost nodes copy the edge); 1: periodic */
+    int bc_x, bc_y; /* 0: transmissive (ghost nodes copy the edge); 1: periodic;
+                       2: reflecting wall at each end */
     double gamma;   /* ratio of specific heats */
     double delta0;  /* d_0 = delta0 * rho (1-D); 0 on the square lattice */
 } oc_problem;
@@ -190,6 +198,18 @@ int oc_packets(const oc_problem* P, const double* Yn, int* off, double* pay)
 static long oc_clamp(long i, long n) { return i < 0 ? 0 : (i >= n ? n - 1 : i); }
 static long oc_wrap(long i, long n) { long r = i % n; return r < 0 ? r + n : r; }
 
+/* Specular reflection off the walls on the outer faces of nodes 0 and n - 1:
+ * the landing index, reflected (again, should it cross the opposite wall)
+ * until inside; *flips counts the reflections. */
+static long oc_reflect(long i, long n, int* flips)
+{
+    while (i < 0 || i >= n) {
+        i = i < 0 ? -1 - i : 2 * n - 1 - i;
+        ++*flips;
+    }
+    return i;
+}
+
 /*
  * One step Y -> Ynew (SoA [nf][ny][nx], lattice units).  max_reach (may be
  * NULL) receives the largest |displacement| component of any packet of any
@@ -207,9 +227,10 @@ int oc_step(const oc_problem* P, const double* Y, double* Ynew, int* max_reach)
     for (long q = 0; q < nn; ++q)
         if (!(Y[q] > 0.0)) status = -4;
     memset(Ynew, 0, sizeof(double) * (size_t)nf * (size_t)nn);
-    /* source range: ghosts beyond transmissive ends (Sec. V.B) */
-    const long gx = P->bc_x == 1 ? 0 : OC_GHOSTS;
-    const long gy = (D == 2 && P->bc_y != 1) ? OC_GHOSTS : 0;
+    if (P->bc_x < 0 || P->bc_x > 2 || (D == 2 && (P->bc_y < 0 || P->bc_y > 2))) return -1;
+    /* source range: ghosts beyond transmissive ends only (Sec. V.B) */
+    const long gx = P->bc_x == 0 ? OC_GHOSTS : 0;
+    const long gy = (D == 2 && P->bc_y == 0) ? OC_GHOSTS : 0;
     int off[2 * OC_MAX_PACKETS];
     double pay[4 * OC_MAX_PACKETS];
     double Yn[4];
@@ -229,14 +250,21 @@ int oc_step(const oc_problem* P, const double* Y, double* Ynew, int* max_reach)
                 }
                 long ti = si + off[2 * p + 0];
                 long tj = sj + off[2 * p + 1];
+                int flips[2] = {0, 0};
                 if (P->bc_x == 1) ti = oc_wrap(ti, nx);
+                else if (P->bc_x == 2) ti = oc_reflect(ti, nx, &flips[0]);
                 else if (ti < 0 || ti >= nx) continue; /* leaves the tube */
                 if (D == 2) {
                     if (P->bc_y == 1) tj = oc_wrap(tj, ny);
+                    else if (P->bc_y == 2) tj = oc_reflect(tj, ny, &flips[1]);
                     else if (tj < 0 || tj >= ny) continue;
                 }
-                for (int fld = 0; fld < nf; ++fld)
-                    Ynew[(long)fld * nn + tj * nx + ti] += pay[nf * p + fld];
+                for (int fld = 0; fld < nf; ++fld) {
+                    double q = pay[nf * p + fld];
+                    /* a reflected packet's normal momentum changes sign */
+                    if (fld >= 1 && fld <= D && (flips[fld - 1] & 1)) q = -q;
+                    Ynew[(long)fld * nn + tj * nx + ti] += q;
+                }
             }
         }
     }
