@@ -48,6 +48,10 @@ extern "C" {
 /* ---- enumerations ---- */
 #define LB_BC_TRANSMISSIVE 0 /* ghost nodes copy the edge node every step; packets leaving are dropped (Sec. V.B) */
 #define LB_BC_PERIODIC 1     /* the lateral direction of the 2-D lattice (Sec. V.B); also allowed along x */
+#define LB_BC_REFLECTING 2   /* a wall on the outer face of each edge node reflects crossing packets
+                              * specularly: normal momentum negated, mass and energy kept (the shock
+                              * reflection the conclusions name as an extension); needs n >= LB_HALO
+                              * along that axis */
 
 #define LB_LATTICE_D1_TRIPLE 1       /* 1-D triple-level set (Sec. IV.A): c' in {0, +-c'_1, +-c'_2}, b0=1, b1=b2=2 */
 #define LB_LATTICE_D2_SQUARE_DUAL 2  /* square dual-level set (Sec. IV.B): +-c'_1, +-c'_2 along x and y, d0=0, b1=b2=4 */

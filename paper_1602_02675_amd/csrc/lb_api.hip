@@ -66,8 +66,13 @@ int check_grid(const lb_grid* grid, int dim)
     if (!(grid->x_hi > grid->x_lo) || !isfinite(grid->x_lo) || !isfinite(grid->x_hi))
         return fail(LB_EINVAL, "need x_lo < x_hi");
     for (int b : {grid->bc_x, grid->bc_y})
-        if (b != LB_BC_TRANSMISSIVE && b != LB_BC_PERIODIC)
+        if (b != LB_BC_TRANSMISSIVE && b != LB_BC_PERIODIC && b != LB_BC_REFLECTING)
             return fail(LB_EINVAL, "unknown boundary condition %d", b);
+    // mirror images of the halo nodes must lie inside the grid
+    if (grid->bc_x == LB_BC_REFLECTING && grid->nx < LB_HALO)
+        return fail(LB_EINVAL, "reflecting walls along x need nx >= %d", LB_HALO);
+    if (dim == 2 && grid->bc_y == LB_BC_REFLECTING && grid->ny < LB_HALO)
+        return fail(LB_EINVAL, "reflecting walls along y need ny >= %d", LB_HALO);
     return LB_OK;
 }
 

@@ -20,6 +20,11 @@ namespace lbsd {
 
 constexpr int kMaxC1 = 1000;  // caps A (any real reach check fails far earlier)
 
+// Boundary of a grid axis (the values of LB_BC_*).
+constexpr int kBcTransmissive = 0;
+constexpr int kBcPeriodic = 1;
+constexpr int kBcReflecting = 2;
+
 // Problem constants shared by every kernel (lattice units).
 struct Consts {
     double Dg1;       // D (gamma - 1)
@@ -231,6 +236,27 @@ __device__ __forceinline__ int64_t wrap_near(int64_t i, int64_t n)
 __device__ __forceinline__ int64_t clamp_idx(int64_t i, int64_t n)
 {
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+// Reflecting walls stand on the outer faces of nodes 0 and n - 1: a node
+// beyond a wall is the mirror image of node -1 - i (low end) or 2n - 1 - i
+// (high end), with its normal momentum negated.  Sources within the halo of
+// the domain (n >= halo) map exactly; indices further out, which only the
+// spare columns of a last tile read and whose packets reach no destination,
+// are clamped into range.
+__device__ __forceinline__ int64_t mirror_idx(int64_t i, int64_t n)
+{
+    if (i < 0) { const int64_t m = -1 - i; return m < n ? m : n - 1; }
+    if (i >= n) { const int64_t m = 2 * n - 1 - i; return m >= 0 ? m : 0; }
+    return i;
+}
+// Source index of (possibly halo) index i along an axis of n nodes with
+// boundary bc; *mirrored tells whether the normal momentum must be negated.
+__device__ __forceinline__ int64_t source_idx(int64_t i, int64_t n, int bc, bool* mirrored)
+{
+    *mirrored = bc == kBcReflecting && (i < 0 || i >= n);
+    if (bc == kBcPeriodic) return wrap_near(i, n);
+    if (bc == kBcReflecting) return mirror_idx(i, n);
+    return clamp_idx(i, n);
 }
 
 // Persistent blocks take tiles from a shared counter in claim order: a slow

@@ -7,9 +7,6 @@
 
 namespace lbsd {
 
-constexpr int kBcTransmissive = 0;
-constexpr int kBcPeriodic = 1;
-
 constexpr int kErrReach = 1;  // a packet would travel further than the halo
 constexpr int kErrState = 2;  // rho <= 0 or a non-finite moment
 
@@ -152,9 +149,10 @@ constexpr int kPool2Cols = 256 - 2 * kHalo;  // destination columns per square-l
 // followed by the full-FIFO pass over the tiles it flagged (nblocks persistent
 // blocks claim the tiles).
 template <typename T>
-hipError_t launch_pool1d(const PoolView& v, const Consts& k, int shape, int nblocks, hipStream_t stream);
+hipError_t launch_pool1d(const PoolView& v, const Consts& k, int shape, int nblocks, bool walls,
+                         hipStream_t stream);
 template <typename T>
-hipError_t launch_pool2d(const PoolView& v, const Consts& k, int nblocks, hipStream_t stream);
+hipError_t launch_pool2d(const PoolView& v, const Consts& k, int nblocks, bool walls, hipStream_t stream);
 template <typename T>
 int pool2d_blocks_per_cu();
 // Per slot: reduce its tiles' partial rows (fixed order) into its state and,

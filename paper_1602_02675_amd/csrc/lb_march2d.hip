@@ -430,7 +430,7 @@ __device__ __forceinline__ void load_node(const T* __restrict__ Y, int64_t nn, i
 // source's y-displacement: the tile's output is then incomplete and must be
 // recomputed with L = kLFull, which sums in the same order (bit-identical).
 // Contains block-wide barriers: every thread of the block must call it.
-template <typename T, int L>
+template <typename T, int L, bool WALLS>
 __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict__ Yn, const Grid& g, const Consts& k,
                           int64_t X0, int64_t Y0, int sy, double* __restrict__ prow)
 {
@@ -442,7 +442,10 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
     const int tid = threadIdx.x, lane64 = tid & 63, wid = tid >> 6;
     const int64_t nx = g.nx, ny = g.ny, nn = nx * ny;
     const int64_t gx = X0 - kMH + tid;                           // this thread's source column
-    const int64_t sx = g.bc_x == kBcPeriodic ? wrap_near(gx, nx) : clamp_idx(gx, nx);
+    bool mir_x = false;
+    int64_t sx;
+    if constexpr (WALLS) sx = source_idx(gx, nx, g.bc_x, &mir_x);
+    else sx = g.bc_x == kBcPeriodic ? wrap_near(gx, nx) : clamp_idx(gx, nx);
     const bool dest = tid >= kMH && tid < kMTPB - kMH && gx < nx;
     const int64_t ylast = min(Y0 + (int64_t)sy, ny);  // destination rows [Y0, ylast)
     const int nrows = Y0 < ny ? (int)(ylast - Y0) + 2 * L : 0;
@@ -457,25 +460,37 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
     double tot[4] = {0.0, 0.0, 0.0, 0.0};
     int reach = 0, bad = 0, yfar = 0;
 
-    auto row_index = [&](int64_t gy) -> int64_t {
-        const int64_t yy = g.bc_y == kBcPeriodic ? wrap_near(gy, ny) : clamp_idx(gy, ny);
-        return yy * nx + sx;
+    // moments of this thread's source column in row gy (halo rows and
+    // columns mapped by the boundaries); *mir_y tells whether the row is a
+    // mirror image beyond a wall.  Mirror images negate normal momentum when
+    // the row is staged, so that the loads issued a row ahead are not waited for.
+    auto load_src = [&](int64_t gy, T (&m)[4], bool* mir_y) {
+        int64_t yy;
+        if constexpr (WALLS) yy = source_idx(gy, ny, g.bc_y, mir_y);
+        else yy = g.bc_y == kBcPeriodic ? wrap_near(gy, ny) : clamp_idx(gy, ny);
+        load_node<T>(Y, nn, yy * nx + sx, m);
     };
     T cur[RB][4], nxt[RB][4];
+    bool cur_my[RB] = {}, nxt_my[RB] = {};
 #pragma unroll
     for (int u = 0; u < RB; ++u)
-        if (u < nrows) load_node<T>(Y, nn, row_index(Y0 - L + u), cur[u]);
+        if (u < nrows) load_src(Y0 - L + u, cur[u], &cur_my[u]);
 
     for (int r0 = 0; r0 < nrows; r0 += RB) {
         const int b = (r0 / RB) & 1;
 #pragma unroll
         for (int u = 0; u < RB; ++u)
-            if (r0 + RB + u < nrows) load_node<T>(Y, nn, row_index(Y0 - L + r0 + RB + u), nxt[u]);
+            if (r0 + RB + u < nrows) load_src(Y0 - L + r0 + RB + u, nxt[u], &nxt_my[u]);
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
             if (r0 + u >= nrows) break;
             // stage this source row
-            const Src2<T> s = make_src2<T>(cur[u][0], cur[u][1], cur[u][2], cur[u][3], k);
+            T mx = cur[u][1], my = cur[u][2];
+            if constexpr (WALLS) {
+                mx = mir_x ? -mx : mx;
+                my = cur_my[u] ? -my : my;
+            }
+            const Src2<T> s = make_src2<T>(cur[u][0], mx, my, cur[u][3], k);
             const int pk = mpack(s.fx, s.fy, s.c1);
             s_row[b][u].vx[tid] = s.vx;
             s_row[b][u].ry[tid] = s.ry;
@@ -585,9 +600,11 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
             for (int c = 0; c < kNV; ++c) f.a[NS - 1][c] = (A)0;
         }
 #pragma unroll
-        for (int u = 0; u < RB; ++u)
+        for (int u = 0; u < RB; ++u) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) cur[u][c] = nxt[u][c];
+            if constexpr (WALLS) cur_my[u] = nxt_my[u];
+        }
     }
     // per-tile partials: field sums, reach, error bits
     __shared__ double s_sum[kMNW][4];
@@ -633,7 +650,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
 // (bit-identically: the summation order does not depend on L).  Persistent
 // blocks claim the tiles (tiles_x column strips x row chunks of sy rows, row
 // chunk major) from the control block's counter of the pass.
-template <typename T, int L>
+template <typename T, int L, bool WALLS>
 __global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
 march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
                StepCtl* __restrict__ ctl, double* __restrict__ partials, int* __restrict__ flags,
@@ -647,8 +664,8 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
         if (t >= ntiles) break;
         if (L == kLFull && flags[t] == 0) continue;
         const int64_t tx = t % tiles_x, ty = t / tiles_x;
-        const int far = march_tile<T, L>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
-                                         partials + (int64_t)t * kPartialStride);
+        const int far = march_tile<T, L, WALLS>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
+                                                partials + (int64_t)t * kPartialStride);
         if (threadIdx.x == 0) {
             flags[t] = L < kLFull ? far : 0;
             if (L < kLFull && far) atomicAdd(&ctl->next[2], 1);
@@ -660,7 +677,7 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
 // Pool form: persistent blocks claim tiles of the tile table (see
 // pool1d_kernel).  The short-FIFO pass flags the tiles it could not complete;
 // the full-FIFO pass recomputes only those.
-template <typename T, int L>
+template <typename T, int L, bool WALLS>
 __global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
 pool2d_kernel(PoolView v, Consts k)
 {
@@ -678,8 +695,8 @@ pool2d_kernel(PoolView v, Consts k)
         const int64_t o0 = tl.off[0], o1 = tl.off[1];  // selected below, not indexed (keeps them in registers)
         const int64_t from = (ts & kTileSet) ? o1 : o0, to = (ts & kTileSet) ? o0 : o1;
         const Grid g{tl.nx, tl.ny, tl.bc_x, tl.bc_y};
-        const int far = march_tile<T, L>(arena + from, arena + to, g, k, tl.x0, tl.y0, tl.rows,
-                                         v.partials + (int64_t)t * kPartialStride);
+        const int far = march_tile<T, L, WALLS>(arena + from, arena + to, g, k, tl.x0, tl.y0, tl.rows,
+                                                v.partials + (int64_t)t * kPartialStride);
         if (threadIdx.x == 0) {
             v.flags[t] = L < kLFull ? far : 0;
             if (L < kLFull && far) atomicAdd(&v.next[2], 1);
@@ -723,50 +740,66 @@ template <typename T>
 int march2d_blocks_per_cu()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, march2d_kernel<T, kLSmall>, kMTPB, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, march2d_kernel<T, kLSmall, false>, kMTPB, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
+template <typename T, bool WALLS>
+hipError_t launch_march2d_w(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
+                            StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream)
+{
+    const int nt = (int)m.blocks();
+    march2d_kernel<T, kLSmall, WALLS><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, flags, step,
+                                                                       m.sy, (int)m.grid_x, nt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    march2d_kernel<T, kLFull, WALLS><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, flags, step,
+                                                                      m.sy, (int)m.grid_x, nt);
+    return hipGetLastError();
+}
+
+// Grids without reflecting walls run the instances that keep no mirror state.
 template <typename T>
 hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
                           StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream)
 {
-    const int nt = (int)m.blocks();
-    march2d_kernel<T, kLSmall><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, flags, step, m.sy,
-                                                                (int)m.grid_x, nt);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    march2d_kernel<T, kLFull><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, flags, step, m.sy,
-                                                               (int)m.grid_x, nt);
-    return hipGetLastError();
+    if (g.bc_x == kBcReflecting || g.bc_y == kBcReflecting)
+        return launch_march2d_w<T, true>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
+    return launch_march2d_w<T, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
 }
 
 template <typename T>
 int pool2d_blocks_per_cu()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pool2d_kernel<T, kLSmall>, kMTPB, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pool2d_kernel<T, kLSmall, false>, kMTPB, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-template <typename T>
-hipError_t launch_pool2d(const PoolView& v, const Consts& k, int nblocks, hipStream_t stream)
+template <typename T, bool WALLS>
+hipError_t launch_pool2d_w(const PoolView& v, const Consts& k, int nblocks, hipStream_t stream)
 {
-    pool2d_kernel<T, kLSmall><<<nblocks, kMTPB, 0, stream>>>(v, k);
+    pool2d_kernel<T, kLSmall, WALLS><<<nblocks, kMTPB, 0, stream>>>(v, k);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    pool2d_kernel<T, kLFull><<<nblocks, kMTPB, 0, stream>>>(v, k);
+    pool2d_kernel<T, kLFull, WALLS><<<nblocks, kMTPB, 0, stream>>>(v, k);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pool2d(const PoolView& v, const Consts& k, int nblocks, bool walls, hipStream_t stream)
+{
+    return walls ? launch_pool2d_w<T, true>(v, k, nblocks, stream) : launch_pool2d_w<T, false>(v, k, nblocks, stream);
 }
 
 template int march2d_blocks_per_cu<double>();
 template int march2d_blocks_per_cu<float>();
 template int pool2d_blocks_per_cu<double>();
 template int pool2d_blocks_per_cu<float>();
-template hipError_t launch_pool2d<double>(const PoolView&, const Consts&, int, hipStream_t);
-template hipError_t launch_pool2d<float>(const PoolView&, const Consts&, int, hipStream_t);
+template hipError_t launch_pool2d<double>(const PoolView&, const Consts&, int, bool, hipStream_t);
+template hipError_t launch_pool2d<float>(const PoolView&, const Consts&, int, bool, hipStream_t);
 template hipError_t launch_march2d<double>(const double*, double*, const Grid&, const MarchGeom&,
                                            const Consts&, StepCtl*, double*, int*, long long, hipStream_t);
 template hipError_t launch_march2d<float>(const float*, float*, const Grid&, const MarchGeom&,

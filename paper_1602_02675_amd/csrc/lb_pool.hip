@@ -54,6 +54,7 @@ struct lb_pool {
     std::vector<PoolTile> tiles;
     int shape = 0;    // 1-D: kernel tile shape; 2-D: strip height index
     int nblocks = 0;  // persistent blocks of the current shape
+    bool walls = false;  // a live slot has reflecting walls: run the kernels that handle them
     // graph of `graph_steps` steps (0: plain launches)
     int graph_steps = 0;
     bool graph_ready = false;
@@ -173,9 +174,13 @@ int upload_tables(lb_pool* p)
     if ((int64_t)p->tiles.size() > p->max_tiles) return fail(LB_ENOMEM, "tile table full");
     const int32_t nt = (int32_t)p->tiles.size();
     const int nb = launch_blocks(p, nt);
-    if (nb != p->nblocks) {  // a different launch shape: a captured graph is stale
+    bool walls = false;
+    for (const PoolProb& q : p->probs)
+        walls |= q.active && (q.bc_x == kBcReflecting || (p->dim == 2 && q.bc_y == kBcReflecting));
+    if (nb != p->nblocks || walls != p->walls) {  // other kernels or launch shape: a captured graph is stale
         drop_graph(p);
         p->nblocks = nb;
+        p->walls = walls;
     }
     std::vector<int32_t> zeros((size_t)std::max<int32_t>(nt, 3), 0);
     // tile words from the slots' device states
@@ -229,11 +234,11 @@ int queue_step(lb_pool* p, int commit)
     const PoolView v = view_of(p);
     hipError_t e;
     if (p->dim == 1)
-        e = p->precision == LB_FP64 ? launch_pool1d<double>(v, p->k, p->shape, p->nblocks, p->stream)
-                                    : launch_pool1d<float>(v, p->k, p->shape, p->nblocks, p->stream);
+        e = p->precision == LB_FP64 ? launch_pool1d<double>(v, p->k, p->shape, p->nblocks, p->walls, p->stream)
+                                    : launch_pool1d<float>(v, p->k, p->shape, p->nblocks, p->walls, p->stream);
     else
-        e = p->precision == LB_FP64 ? launch_pool2d<double>(v, p->k, p->nblocks, p->stream)
-                                    : launch_pool2d<float>(v, p->k, p->nblocks, p->stream);
+        e = p->precision == LB_FP64 ? launch_pool2d<double>(v, p->k, p->nblocks, p->walls, p->stream)
+                                    : launch_pool2d<float>(v, p->k, p->nblocks, p->walls, p->stream);
     if (e != hipSuccess) return hip_fail(e, "pool step launch");
     if ((e = launch_pool_finalize(v, p->max_slots, commit, p->stream)) != hipSuccess)
         return hip_fail(e, "pool finalize launch");

@@ -264,25 +264,29 @@ __device__ void gather1_general(const Tile1<T>& tl, const TileInfo& ti, int64_t 
 // Yn and adds the tile's new moments to acc, returning the tile's integer
 // summary.  Splitting them lets a persistent block load its next tile while
 // it gathers the current one.  tile1d_gather contains block-wide barriers:
-// every thread of the block must call it.
-template <typename T, int H, int TPB, int J>
+// every thread of the block must call it.  WALLS instances also handle
+// reflecting walls (the others keep no per-source mirror state).
+template <typename T, int H, int TPB, int J, bool WALLS>
 struct Tile1Src {
     static constexpr int W = TPB * J + 2 * H;
     static constexpr int NS = (W + TPB - 1) / TPB;
     T ld[NS][3];
+    bool mir[WALLS ? NS : 1];  // mirror image beyond a reflecting wall: momentum negated when used
 };
 
-template <typename T, int H, int TPB, int J>
+template <typename T, int H, int TPB, int J, bool WALLS>
 __device__ __forceinline__ void tile1d_load(const T* __restrict__ Y, int64_t nx, int bc, int64_t x0,
-                                            Tile1Src<T, H, TPB, J>& src)
+                                            Tile1Src<T, H, TPB, J, WALLS>& src)
 {
-    using S = Tile1Src<T, H, TPB, J>;
+    using S = Tile1Src<T, H, TPB, J, WALLS>;
 #pragma unroll
     for (int u = 0; u < S::NS; ++u) {
         const int i = (int)threadIdx.x + u * TPB;
         if (i < S::W) {
             const int64_t gx = x0 - H + i;
-            const int64_t si = bc == kBcPeriodic ? wrap_near(gx, nx) : clamp_idx(gx, nx);
+            int64_t si;
+            if constexpr (WALLS) si = source_idx(gx, nx, bc, &src.mir[u]);
+            else si = bc == kBcPeriodic ? wrap_near(gx, nx) : clamp_idx(gx, nx);
             src.ld[u][0] = Y[si];
             src.ld[u][1] = Y[nx + si];
             src.ld[u][2] = Y[2 * nx + si];
@@ -290,11 +294,11 @@ __device__ __forceinline__ void tile1d_load(const T* __restrict__ Y, int64_t nx,
     }
 }
 
-template <typename T, int H, int TPB, int J>
-__device__ __forceinline__ TileInfo tile1d_gather(const Tile1Src<T, H, TPB, J>& src, T* __restrict__ Yn,
+template <typename T, int H, int TPB, int J, bool WALLS>
+__device__ __forceinline__ TileInfo tile1d_gather(const Tile1Src<T, H, TPB, J, WALLS>& src, T* __restrict__ Yn,
                                                   int64_t nx, int64_t x0, const Consts& k, double (&acc)[3])
 {
-    using S = Tile1Src<T, H, TPB, J>;
+    using S = Tile1Src<T, H, TPB, J, WALLS>;
     constexpr int W = S::W;
     constexpr int NW = TPB / 64;
     __shared__ int s_pk[W];
@@ -306,7 +310,11 @@ __device__ __forceinline__ TileInfo tile1d_gather(const Tile1Src<T, H, TPB, J>& 
     for (int u = 0; u < S::NS; ++u) {
         const int i = (int)threadIdx.x + u * TPB;
         if (i >= W) break;
-        const Src1<T> s = make_src1<T>(src.ld[u][0], src.ld[u][1], src.ld[u][2], k);
+        // (the sign of a mirror image is applied here, once its load has
+        // arrived, so that loads issued ahead of time are not waited for)
+        T mom = src.ld[u][1];
+        if constexpr (WALLS) mom = src.mir[u] ? -mom : mom;
+        const Src1<T> s = make_src1<T>(src.ld[u][0], mom, src.ld[u][2], k);
         s_pk[i] = pack_lane(s.f, 0, s.c1);
         s_r[i] = s.r;
         s_d0[i] = s.d0;
@@ -336,17 +344,17 @@ __device__ __forceinline__ TileInfo tile1d_gather(const Tile1Src<T, H, TPB, J>& 
     return ti;
 }
 
-template <typename T, int H, int TPB, int J>
+template <typename T, int H, int TPB, int J, bool WALLS>
 __global__ void __launch_bounds__(TPB)
 step1d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
               StepCtl* __restrict__ ctl, double* __restrict__ partials, long long step)
 {
     if (ctl->err_step < step) return;  // an earlier step failed: keep its input intact
     const int64_t x0 = (int64_t)blockIdx.x * (TPB * J);
-    Tile1Src<T, H, TPB, J> src;
-    tile1d_load<T, H, TPB, J>(Y, g.nx, g.bc_x, x0, src);
+    Tile1Src<T, H, TPB, J, WALLS> src;
+    tile1d_load<T, H, TPB, J, WALLS>(Y, g.nx, g.bc_x, x0, src);
     double acc[3] = {0.0, 0.0, 0.0};
-    const TileInfo ti = tile1d_gather<T, H, TPB, J>(src, Yn, g.nx, x0, k, acc);
+    const TileInfo ti = tile1d_gather<T, H, TPB, J, WALLS>(src, Yn, g.nx, x0, k, acc);
     finish_step<TPB / 64, 3>(acc, ti, partials + (int64_t)blockIdx.x * kPartialStride, H);
 }
 
@@ -354,7 +362,7 @@ step1d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
 // same, so the hardware's block scheduling balances them and overlaps one
 // tile's loads with other tiles' work).  A tile belongs to one slot; its word
 // says whether the slot still steps and which moment set holds its state.
-template <typename T, int TPB, int J>
+template <typename T, int TPB, int J, bool WALLS>
 __global__ void __launch_bounds__(TPB) pool1d_kernel(PoolView v, Consts k)
 {
     const int t = blockIdx.x;
@@ -366,10 +374,10 @@ __global__ void __launch_bounds__(TPB) pool1d_kernel(PoolView v, Consts k)
     const int64_t o0 = tl.off[0], o1 = tl.off[1];  // selected below, not indexed (keeps them in registers)
     const int64_t from = (ts & kTileSet) ? o1 : o0, to = (ts & kTileSet) ? o0 : o1;
     const int64_t nx = tl.nx, x0 = tl.x0;
-    Tile1Src<T, kHalo, TPB, J> src;
-    tile1d_load<T, kHalo, TPB, J>(arena + from, nx, tl.bc_x, x0, src);
+    Tile1Src<T, kHalo, TPB, J, WALLS> src;
+    tile1d_load<T, kHalo, TPB, J, WALLS>(arena + from, nx, tl.bc_x, x0, src);
     double acc[3] = {0.0, 0.0, 0.0};
-    const TileInfo ti = tile1d_gather<T, kHalo, TPB, J>(src, arena + to, nx, x0, k, acc);
+    const TileInfo ti = tile1d_gather<T, kHalo, TPB, J, WALLS>(src, arena + to, nx, x0, k, acc);
     finish_step<TPB / 64, 3>(acc, ti, v.partials + (int64_t)t * kPartialStride, kHalo);
 }
 
@@ -456,26 +464,34 @@ hipError_t launch_step1d(const T* Y, T* Yn, const Grid& g, const Consts& k, Step
                          double* partials, long long step, hipStream_t stream)
 {
     const dim3 grid((unsigned)step_blocks_1d(g));
-    step1d_kernel<T, kHalo, k1TPB, k1J><<<grid, k1TPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step);
+    if (g.bc_x == kBcReflecting)
+        step1d_kernel<T, kHalo, k1TPB, k1J, true><<<grid, k1TPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step);
+    else
+        step1d_kernel<T, kHalo, k1TPB, k1J, false><<<grid, k1TPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step);
     return hipGetLastError();
 }
 
 template <typename T, int S>
-static hipError_t pool1d_launch_shape(const PoolView& v, const Consts& k, int nblocks, hipStream_t stream)
+static hipError_t pool1d_launch_shape(const PoolView& v, const Consts& k, int nblocks, bool walls,
+                                      hipStream_t stream)
 {
-    pool1d_kernel<T, kPool1TPB[S], kPool1J[S]><<<nblocks, kPool1TPB[S], 0, stream>>>(v, k);
+    if (walls)
+        pool1d_kernel<T, kPool1TPB[S], kPool1J[S], true><<<nblocks, kPool1TPB[S], 0, stream>>>(v, k);
+    else
+        pool1d_kernel<T, kPool1TPB[S], kPool1J[S], false><<<nblocks, kPool1TPB[S], 0, stream>>>(v, k);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_pool1d(const PoolView& v, const Consts& k, int shape, int nblocks, hipStream_t stream)
+hipError_t launch_pool1d(const PoolView& v, const Consts& k, int shape, int nblocks, bool walls,
+                         hipStream_t stream)
 {
     switch (shape) {
-        case 0: return pool1d_launch_shape<T, 0>(v, k, nblocks, stream);
-        case 1: return pool1d_launch_shape<T, 1>(v, k, nblocks, stream);
-        case 2: return pool1d_launch_shape<T, 2>(v, k, nblocks, stream);
-        case 3: return pool1d_launch_shape<T, 3>(v, k, nblocks, stream);
-        case 4: return pool1d_launch_shape<T, 4>(v, k, nblocks, stream);
+        case 0: return pool1d_launch_shape<T, 0>(v, k, nblocks, walls, stream);
+        case 1: return pool1d_launch_shape<T, 1>(v, k, nblocks, walls, stream);
+        case 2: return pool1d_launch_shape<T, 2>(v, k, nblocks, walls, stream);
+        case 3: return pool1d_launch_shape<T, 3>(v, k, nblocks, walls, stream);
+        case 4: return pool1d_launch_shape<T, 4>(v, k, nblocks, walls, stream);
         default: return hipErrorInvalidValue;
     }
 }
@@ -498,7 +514,7 @@ template hipError_t launch_step1d<double>(const double*, double*, const Grid&, c
 template hipError_t launch_step1d<float>(const float*, float*, const Grid&, const Consts&,
                                          StepCtl*, double*, long long, hipStream_t);
 
-template hipError_t launch_pool1d<double>(const PoolView&, const Consts&, int, int, hipStream_t);
-template hipError_t launch_pool1d<float>(const PoolView&, const Consts&, int, int, hipStream_t);
+template hipError_t launch_pool1d<double>(const PoolView&, const Consts&, int, int, bool, hipStream_t);
+template hipError_t launch_pool1d<float>(const PoolView&, const Consts&, int, int, bool, hipStream_t);
 
 }  // namespace lbsd

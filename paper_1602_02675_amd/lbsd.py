@@ -21,7 +21,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBSD_LIBRARY") or os.path.join(_PKG, "liblbsd.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ESTATE, LB_EREACH = 0, -1, -2, -3, -4, -5
-LB_BC_TRANSMISSIVE, LB_BC_PERIODIC = 0, 1
+LB_BC_TRANSMISSIVE, LB_BC_PERIODIC, LB_BC_REFLECTING = 0, 1, 2
 LB_LATTICE_D1_TRIPLE, LB_LATTICE_D2_SQUARE_DUAL = 1, 2
 LB_FP64, LB_FP32 = 0, 1
 LB_HALO = 5
@@ -132,7 +132,8 @@ def _check(rc: int):
 
 def _bc(v) -> int:
     if isinstance(v, str):
-        return {"transmissive": LB_BC_TRANSMISSIVE, "periodic": LB_BC_PERIODIC}[v]
+        return {"transmissive": LB_BC_TRANSMISSIVE, "periodic": LB_BC_PERIODIC,
+                "reflecting": LB_BC_REFLECTING}[v]
     return int(v)
 
 

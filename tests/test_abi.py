@@ -47,11 +47,19 @@ def test_create_validation():
     bad = [dict(gamma=1.0), dict(gamma=3.5), dict(dim=2, lattice=2, d0=0.0, gamma=2.5),
            dict(d0=1.0), dict(d0=-0.1), dict(dim=3), dict(nx=0), dict(ny=2),
            dict(dim=2, lattice=1, d0=0.0), dict(dim=2, lattice=2, d0=0.5),
-           dict(bc_x=7), dict(x_hi=0.0), dict(prec=5)]
+           dict(bc_x=7), dict(x_hi=0.0), dict(prec=5),
+           # reflecting walls need the mirror images of the halo inside the grid
+           dict(bc_x=2, nx=4), dict(dim=2, lattice=2, d0=0.0, nx=64, ny=4, bc_y=2),
+           dict(dim=2, lattice=2, d0=0.0, nx=4, ny=64, bc_x=2)]
     for kw in bad:
         rc, h = _create(lbsd, **kw)
         assert rc == lbsd.LB_EINVAL, kw
         assert lbsd._lib.lb_last_error()
+    for kw in (dict(bc_x=2, nx=5), dict(bc_x=2, bc_y=2),
+               dict(dim=2, lattice=2, d0=0.0, nx=5, ny=5, bc_x=2, bc_y=2)):
+        rc, h = _create(lbsd, **kw)
+        assert rc == lbsd.LB_OK, kw
+        lbsd._lib.lb_destroy(h)
     rc, h = _create(lbsd, dim=2, lattice=2, d0=0.0, nx=64, ny=32, prec=1)
     assert rc == lbsd.LB_OK
     # 2 FP32 buffers of 4 fields + FP64 staging

@@ -12,9 +12,10 @@ import pytest
 import oracle
 from paper_1602_02675_amd import inputs
 
+from parity_helpers import TOL64, normwise_err, run_pair, self_divergence
+
 pytestmark = pytest.mark.gpu
 
-TOL64 = 1e-12
 
 
 @pytest.fixture(scope="module")
@@ -25,27 +26,6 @@ def lbsd():
     from paper_1602_02675_amd import lbsd as m
 
     return m
-
-
-def normwise_err(got, ref, dim):
-    got = np.asarray(got).reshape(ref.shape)
-    errs = []
-    mom = max(np.max(np.abs(ref[1:1 + dim])), 1e-300)
-    for f in range(ref.shape[0]):
-        scale = mom if 1 <= f <= dim else max(np.max(np.abs(ref[f])), 1e-300)
-        errs.append(np.max(np.abs(got[f] - ref[f])) / scale)
-    return max(errs)
-
-
-def run_pair(lbsd, dim, Y_phys, lam, n, *, nx, ny=1, bcx=0, bcy=1, delta0=None, prec="fp64"):
-    P = oracle.Problem(dim, nx, ny, bc_x=bcx, bc_y=bcy, delta0=delta0)
-    ref, st, reach = oracle.run(P, oracle.to_lattice(P, Y_phys, lam), n)
-    assert st == 0 and reach <= 5
-    s = lbsd.Solver(dim, nx, ny, bc_x=bcx, bc_y=bcy, d0_frac=delta0, precision=prec)
-    s.init_moments(Y_phys, lam)
-    s.step(n)
-    got = s.moments()
-    return P, oracle.from_lattice(P, ref, lam), got, s
 
 
 def test_sod_1d_config0(lbsd):
@@ -416,16 +396,6 @@ def test_fp32_form_2000_steps_against_fp64(lbsd, seed):
     assert rel_l1 <= 1e-5, rel_l1
 
 
-def _self_divergence(P, Yl, n, seed=0):
-    """How far the oracle itself moves after n steps when its input is
-    perturbed at the level of FP64 rounding (relative 1e-16): the square
-    dual-level lattice amplifies rounding differences on non-planar data."""
-    rng = np.random.default_rng(seed)
-    a, _, _ = oracle.run(P, Yl, n)
-    b, _, _ = oracle.run(P, Yl * (1.0 + 1e-16 * rng.standard_normal(Yl.shape)), n)
-    return normwise_err(b, a, 2)
-
-
 @pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("fp32", 2e-4)])
 @pytest.mark.parametrize("seed", [1, 2])
 def test_quadrant_riemann_2d(lbsd, prec, tol, seed):
@@ -451,5 +421,5 @@ def test_quadrant_riemann_2d(lbsd, prec, tol, seed):
         assert np.sum(np.abs(got[0] - ref[0])) / np.sum(np.abs(ref[0])) <= 1e-5
     else:
         P, ref, got, s = run_pair(lbsd, 2, Y, lam, 30, nx=nx, ny=ny, bcx=0, bcy=0, prec=prec)
-        sens = _self_divergence(P, oracle.to_lattice(P, Y, lam), 30)
+        sens = self_divergence(P, oracle.to_lattice(P, Y, lam), 30)
         assert normwise_err(got, ref, 2) <= max(TOL64, 4.0 * sens)

@@ -126,6 +126,51 @@ def test_pool_2d_equals_solver(lbsd, prec):
     pool.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pool_walls_equal_solver(lbsd, prec):
+    """Slots with reflecting walls beside open and periodic ones, on both
+    lattices, long enough for waves to reflect: each equals its lb_solver
+    run bit for bit, for two tile shapes."""
+    SL, SR = inputs.SOD_LEFT, inputs.SOD_RIGHT
+    lam = inputs.cfl_lambda([SL, SR])
+    t1 = [(1000, 0.5, "reflecting"), (5, 0.5, "reflecting"), (333, 0.3, "transmissive"),
+          (2049, 0.6, "periodic"), (700, 0.8, "reflecting")]
+    t2 = [(64, 64, "reflecting", "reflecting"), (300, 20, "reflecting", "periodic"),
+          (90, 45, "transmissive", "reflecting")]
+    steps = 400
+    ref1 = [alone(lbsd, 1, nx, 1, xd, SL, SR, lam, steps, prec, bx) for nx, xd, bx in t1]
+    ref2 = [alone(lbsd, 2, nx, ny, 0.4, SL, SR, lam, 120, prec, bx, by) for nx, ny, bx, by in t2]
+    states, center = inputs.quadrant_riemann(4)
+    lq = inputs.quadrant_lambda(states)
+    Yq = inputs.quadrant_moments(states, center, 61, 53)
+    s = lbsd.Solver(2, 61, 53, precision=prec, bc_x="reflecting", bc_y="reflecting")
+    s.init_moments(Yq, lq)
+    s.step(40)
+    ref_q = s.moments()
+    s.close()
+    p1 = lbsd.Pool(1, 8, 8 << 20, precision=prec)
+    p2 = lbsd.Pool(2, 8, 64 << 20, precision=prec)
+    for shape in (0, 2):
+        s1 = [p1.admit_riemann(nx, xd, SL, SR, steps, lam=lam, bc_x=bx) for nx, xd, bx in t1]
+        s2 = [p2.admit_riemann(nx, 0.4, SL, SR, 120, ny=ny, lam=lam, bc_x=bx, bc_y=by)
+              for nx, ny, bx, by in t2]
+        sq = p2.admit_moments(Yq, lq, 40, bc_x="reflecting", bc_y="reflecting")
+        p1.set_shape(shape)
+        p2.set_shape(shape)
+        p1.advance(steps)
+        p2.advance(120)
+        for i, sl in enumerate(s1):
+            assert np.array_equal(p1.moments(sl), ref1[i]), (shape, i)
+            p1.release(sl)
+        for i, sl in enumerate(s2):
+            assert np.array_equal(p2.moments(sl), ref2[i]), (shape, i)
+            p2.release(sl)
+        assert np.array_equal(p2.moments(sq), ref_q)
+        p2.release(sq)
+    p1.close()
+    p2.close()
+
+
 def test_pool_continuous_admission_same_as_alone(lbsd):
     """Requests admitted while others are mid-run, released when done, their
     memory reused by later ones: each result equals its run alone."""
