@@ -13,6 +13,10 @@ gather kernel plus its totals reduction.  Alongside, in the same JSON line:
 * batch: 512 independent 1-D tubes, lengths log-uniform in [256, 65536],
   seeded states, 1000 steps, one persistent launch per step over all tubes,
   HIP-graph captured, tile shape autotuned, FP32 and FP64;
+* walls: the headline tube between reflecting walls at both x ends (FP64;
+  the kernel instances that handle walls);
+* nonplanar: a seeded four-state 2-D Riemann problem (both velocity
+  components of both signs) on 2048 x 2048 nodes, FP64;
 * serve: square-lattice requests (sides log-uniform in [64, 2048], steps in
   [100, 5000], seeded states) arriving as a Poisson process at 0.8 x the
   measured capacity, continuously batched on an FP32 pool: p50 / p99
@@ -60,12 +64,12 @@ def workload():
     return left, right, x_d, lam
 
 
-def run_gpu(precision: str, steps: int, warmup: int):
+def run_gpu(precision: str, steps: int, warmup: int, bc_x: str = "transmissive"):
     import torch
     from paper_1602_02675_amd.lbsd import Solver
 
     left, right, x_d, lam = workload()
-    s = Solver(2, NX, NY, precision=precision, bc_x="transmissive", bc_y="periodic")
+    s = Solver(2, NX, NY, precision=precision, bc_x=bc_x, bc_y="periodic")
     s.init_riemann(x_d, left, right, lam=lam)
     if warmup:
         s.step(warmup)
@@ -78,6 +82,25 @@ def run_gpu(precision: str, steps: int, warmup: int):
     rho = s.moments_device()[0].clone()
     s.close()
     return dict(kernel_ms=kernel_ms, total_ms=total_ms, wall_s=wall, rho=rho)
+
+
+def run_nonplanar(steps: int = 200, n: int = 2048, seed: int = 1):
+    """Four-state 2-D Riemann problem (non-planar data), FP64, transmissive."""
+    import torch
+    from paper_1602_02675_amd import inputs
+    from paper_1602_02675_amd.lbsd import Solver
+
+    states, center = inputs.quadrant_riemann(seed)
+    lam = inputs.quadrant_lambda(states)
+    s = Solver(2, n, n, precision="fp64", bc_x="transmissive", bc_y="transmissive")
+    s.init_moments(inputs.quadrant_moments(states, center, n, n), lam)
+    s.step(10)
+    s.sync()
+    torch.cuda.synchronize()
+    kernel_ms, total_ms = s.step_profiled(steps)
+    s.close()
+    return dict(value=round(n * n * steps / (total_ms * 1e-3) / 1e6, 1), unit="MLUPS", nx=n, ny=n, seed=seed,
+                steps=steps, ms_per_step=round(total_ms / steps, 5), precision="fp64")
 
 
 def cpu_baseline(seconds_target: float = 15.0):
@@ -171,6 +194,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the walls and nonplanar legs")
     ap.add_argument("--profile", action="store_true",
                     help="short run + a plain copy of known size, for rocprofv3 counters")
     args = ap.parse_args()
@@ -234,6 +258,12 @@ def main():
                        "rel_l1_density_vs_fp64": rel_l1,
                        "achieved_GBs": round(BYTES_PER_NODE["fp32"] * nodes /
                                              (r32["kernel_ms"] / 1e3 / args.steps) / 1e9, 1)}
+    if not args.no_extra:
+        rw = run_gpu("fp64", 500, args.warmup, bc_x="reflecting")
+        out["walls"] = {"value": round(nodes * 500 / (rw["total_ms"] / 1e3) / 1e6, 1), "unit": "MLUPS",
+                        "steps": 500, "ms_per_step": round(rw["total_ms"] / 500, 5),
+                        "bc": "reflecting x / periodic y", "precision": "fp64"}
+        out["nonplanar"] = run_nonplanar()
     if not args.no_batch:
         out["batch"] = {p: run_batch(p) for p in ("fp32", "fp64")}
     if not args.no_serve:
