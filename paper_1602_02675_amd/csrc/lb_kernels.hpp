@@ -20,7 +20,9 @@ struct StepCtl {
     double totals[4];       // interior sums of the moment fields (lattice units)
     int max_reach;          // largest reach seen in the latest step
     int redo_tiles;         // tiles the full-FIFO pass has recomputed since the last reset
-    int pad[5];
+    int keep[2];            // square lattice: tiles the full-FIFO pass left flagged in this step [0]
+                            // and in the previous step [1] (finalize moves [0] to [1])
+    int pad[3];
 };
 
 // Per-block partial results: 4 field sums, reach, error bits.

@@ -290,10 +290,12 @@ __device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, 
 // and c'_1 may vary along the row.  Packets are taken per class (level, k_x,
 // floor(v_x) = F, speed C): the x-lane pair +-C of a class comes from the two
 // sources at x displacement k_x + F -+ C, and counts when that source has this
-// F and speed C on this level (zero mass otherwise).
+// F and speed C on this level (zero mass otherwise).  With chk (uniform), a
+// source counts only if its floor(v_y) is FY as well: two such calls, for FY
+// and FY + 1, take a window whose floor(v_y) has two adjacent values.
 template <typename T, int L, int FY>
 __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, int fxlo, int fxhi,
-                                            int clo, int chi)
+                                            int clo, int chi, bool chk)
 {
 #pragma clang fp contract(off)
     const int nfx = fxhi - fxlo;
@@ -307,8 +309,8 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc
                 for (int C = cl; C <= ch; ++C) {
                     const int sp = lane - (kx + F + C), sm = lane - (kx + F - C);
                     const int pkp = R.pk[sp], pkm = R.pk[sm];
-                    const bool okp = mfx(pkp) == F && mc1(pkp) + lev == C;
-                    const bool okm = mfx(pkm) == F && mc1(pkm) + lev == C;
+                    const bool okp = mfx(pkp) == F && mc1(pkp) + lev == C && (!chk || mfy(pkp) == FY);
+                    const bool okm = mfx(pkm) == F && mc1(pkm) + lev == C && (!chk || mfy(pkm) == FY);
                     const T bp = okp ? R.m[lev][kx][sp] : (T)0, bm = okm ? R.m[lev][kx][sm] : (T)0;
                     const T vxp = R.vx[sp], vxm = R.vx[sm];
                     const T ryp = R.ry[sp], rym = R.ry[sm];
@@ -329,7 +331,8 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc
             const int F = fxlo + i;
             const int s0 = lane - F, s1 = lane - F - 1;
             const int pk0 = R.pk[s0], pk1 = R.pk[s1];
-            const bool ok0 = mfx(pk0) == F, ok1 = mfx(pk1) == F;
+            const bool ok0 = mfx(pk0) == F && (!chk || mfy(pk0) == FY);
+            const bool ok1 = mfx(pk1) == F && (!chk || mfy(pk1) == FY);
             const int c0 = mc1(pk0) + lev, c1 = mc1(pk1) + lev;
             const T ry[2] = {R.ry[s0], R.ry[s1]};
             const T b0 = ok0 ? R.m[lev][0][s0] : (T)0, b1 = ok1 ? R.m[lev][1][s1] : (T)0;
@@ -426,9 +429,13 @@ __device__ __forceinline__ void load_node(const T* __restrict__ Y, int64_t nn, i
 // One tile: destination columns [X0, X0 + 256 - 2H) and rows [Y0, Y0 + sy)
 // (clipped to the grid) of grid g, marched from row Y0 - L to Y0 + sy + L - 1.
 // Writes Yn and one row of per-tile partials (field sums, reach, error bits).
-// Returns 1 (the same in every thread) when the FIFO of this L cannot hold a
-// source's y-displacement: the tile's output is then incomplete and must be
-// recomputed with L = kLFull, which sums in the same order (bit-identical).
+// Returns 1 (the same in every thread) when the short pass cannot take some
+// window of the tile: a y-displacement beyond the short FIFO (kLSmall), or a
+// non-planar window (floor(v_y) not uniform, and the mixes the row path does
+// not take), which only the full pass's paths handle.  With L = kLSmall the
+// tile's output is then incomplete and must be recomputed with L = kLFull,
+// which sums in the same order (bit-identical); with L = kLFull it tells that
+// the tile still needs the full pass.
 // Contains block-wide barriers: every thread of the block must call it.
 template <typename T, int L, bool WALLS>
 __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict__ Yn, const Grid& g, const Consts& k,
@@ -503,7 +510,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
             s_row[b][u].pk[tid] = pk;
             const int yr = axis_reach(s.fy, s.c1);
             reach = max(reach, max(axis_reach(s.fx, s.c1), yr));
-            yfar |= yr > L ? 1 : 0;
+            yfar |= yr > kLSmall ? 1 : 0;
             bad |= s.bad ? 1 : 0;
             {
                 const int ry0 = __all(s.ry == (T)0) ? 1 : 0;
@@ -529,15 +536,23 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
             if (wid > 0) w = merge(w, s_w[b][u][wid - 1]);
             if (wid + 1 < kMNW) w = merge(w, s_w[b][u][wid + 1]);
             // the fast and row paths need every packet of the window inside the
-            // FIFO (y) and the staged row (x); the general path takes any window
-            // whose sources each reach <= H.  A short FIFO that cannot hold the
-            // window's y displacements marks the step for a redo.
+            // FIFO (y) and the staged row (x); the full pass's general path
+            // takes any window whose sources each reach <= H.
             const int c2max = w.c1max + 1;
             const bool fits_y = w.fymin - c2max >= -L && w.fymax + 1 + c2max <= L;
+            const bool fits_small = w.fymin - c2max >= -kLSmall && w.fymax + 1 + c2max <= kLSmall;
             const bool fits_x = w.fxmin - c2max >= -kMH && w.fxmax + 1 + c2max <= kMH;
-            if (L < kLFull && !fits_y) yfar = 1;
-            const bool rows_ok = fits_x && fits_y && w.fymin == w.fymax && (w.fymin == 0 || w.fymin == -1) &&
-                                 w.c1max <= 3 && w.fxmax - w.fxmin <= 2;
+            const bool planar = fits_x && w.fymin == w.fymax && (w.fymin == 0 || w.fymin == -1) &&
+                                w.c1max <= 3 && w.fxmax - w.fxmin <= 2;
+            const bool rows_ok = planar && fits_y;
+            // the short pass takes planar windows within its FIFO; a tile with
+            // any other window is flagged for the full pass
+            if (!(planar && fits_small)) yfar = 1;
+            // full pass, floor(v_y) in {-1, 0} (where v_y changes sign): the row
+            // path once per value (other pairs of values take the general path:
+            // their instances made the compiler spill the FIFO on every path)
+            const bool ymix_ok = fits_x && fits_y && w.fymin == -1 && w.fymax == 0 && w.c1max <= 3 &&
+                                 w.fxmax - w.fxmin <= 2;
             if (dest && (fits_y || L == kLFull)) {
                 // two adjacent values of c'_1 or of floor(v_x) keep compile-time
                 // offsets; a window mixing both (rare in planar flows) takes the
@@ -568,11 +583,18 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
     #undef LB_FAST
                         default: break;  // not reached: fastw admits only the cases above
                     }
-                } else if (rows_ok) {
-                    if (w.fymin == 0)
-                        gather_rows<T, L, 0>(s_row[b][u], tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max);
-                    else
-                        gather_rows<T, L, -1>(s_row[b][u], tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max);
+                } else if (L < kLFull) {
+                    if (rows_ok) {
+                        const MRow<T>& R = s_row[b][u];
+                        if (w.fymin == -1) gather_rows<T, L, -1>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, false);
+                        else gather_rows<T, L, 0>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, false);
+                    }  // other windows: the tile is flagged (above)
+                } else if (rows_ok || ymix_ok) {
+                    // one call per value of floor(v_y) in the window (one
+                    // call site per instance keeps the kernel's code compact)
+                    const MRow<T>& R = s_row[b][u];
+                    if (w.fymin == -1) gather_rows<T, L, -1>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, ymix_ok);
+                    if (w.fymax == 0) gather_rows<T, L, 0>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, ymix_ok);
                 } else {
                     gather_general<T, L>(s_row[b][u], tid, f, max(-kMH, w.fxmin - c2max),
                                          min(kMH, w.fxmax + 1 + c2max), w.fymin, w.fymax, w.c1min, w.c1max);
@@ -619,7 +641,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
         s_ir[wid][0] = reach;
         s_ir[wid][1] = bad;
     }
-    const int far = __syncthreads_or(L < kLFull ? yfar : 0);
+    const int far = __syncthreads_or(yfar);
     if (tid == 0) {
         int rr = 0, bb = 0;
         for (int c = 0; c < 4; ++c) {
@@ -645,11 +667,13 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
 #ifndef LB_MARCH_WPE_F32
 #define LB_MARCH_WPE_F32 4
 #endif
-// L = kLSmall: the short-FIFO pass over every tile; a tile whose sources reach
-// beyond its FIFO is flagged.  L = kLFull: recomputes the flagged tiles only
-// (bit-identically: the summation order does not depend on L).  Persistent
-// blocks claim the tiles (tiles_x column strips x row chunks of sy rows, row
-// chunk major) from the control block's counter of the pass.
+// L = kLSmall: the short-FIFO pass; a tile whose sources reach beyond its FIFO
+// is flagged.  L = kLFull: computes the flagged tiles (bit-identically: the
+// summation order does not depend on L) and keeps the flag of each that still
+// needs the full FIFO; the next step's short pass leaves such tiles to the
+// full pass instead of computing them twice (flows change little per step).
+// Persistent blocks claim the tiles (tiles_x column strips x row chunks of sy
+// rows, row chunk major) from the control block's counter of the pass.
 template <typename T, int L, bool WALLS>
 __global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
 march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
@@ -659,24 +683,38 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
     __shared__ int s_t;
     if (ctl->err_step < step) return;
     if (L == kLFull && ctl->next[2] == 0) return;  // the short pass flagged no tile
+    // some tile kept its flag in the previous step's full pass (else every
+    // flag is clear and the short pass need not read them)
+    const bool kept = L < kLFull && ctl->keep[1] != 0;
     for (;;) {
         const int t = claim_tile(&ctl->next[L < kLFull ? 0 : 1], &s_t);
         if (t >= ntiles) break;
-        if (L == kLFull && flags[t] == 0) continue;
+        if (L < kLFull) {
+            if (kept && flags[t]) {  // needed the full pass last step: left to it
+                if (threadIdx.x == 0) atomicAdd(&ctl->next[2], 1);
+                continue;
+            }
+        } else if (!flags[t]) {
+            continue;
+        }
         const int64_t tx = t % tiles_x, ty = t / tiles_x;
         const int far = march_tile<T, L, WALLS>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
                                                 partials + (int64_t)t * kPartialStride);
         if (threadIdx.x == 0) {
-            flags[t] = L < kLFull ? far : 0;
+            flags[t] = far;
             if (L < kLFull && far) atomicAdd(&ctl->next[2], 1);
-            if (L == kLFull) atomicAdd(&ctl->redo_tiles, 1);
+            if (L == kLFull) {
+                atomicAdd(&ctl->redo_tiles, 1);
+                if (far) atomicAdd(&ctl->keep[0], 1);
+            }
         }
     }
 }
 
 // Pool form: persistent blocks claim tiles of the tile table (see
 // pool1d_kernel).  The short-FIFO pass flags the tiles it could not complete;
-// the full-FIFO pass recomputes only those.
+// the full-FIFO pass computes only those, and keeps the flags of the tiles
+// that still need it (as in march2d_kernel).
 template <typename T, int L, bool WALLS>
 __global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
 pool2d_kernel(PoolView v, Consts k)
@@ -688,9 +726,14 @@ pool2d_kernel(PoolView v, Consts k)
     for (;;) {
         const int t = claim_tile(&v.next[L < kLFull ? 0 : 1], &s_t);
         if (t >= nt) break;
-        if (L == kLFull && v.flags[t] == 0) continue;
         const int ts = v.tstate[t];
         if (!(ts & kTileLive)) continue;  // the same for the whole block
+        const int flagged = v.flags[t];
+        if (L < kLFull && flagged) {  // needed the full FIFO last step: left to the full pass
+            if (threadIdx.x == 0) atomicAdd(&v.next[2], 1);
+            continue;
+        }
+        if (L == kLFull && !flagged) continue;
         const PoolTile& tl = v.tiles[t];
         const int64_t o0 = tl.off[0], o1 = tl.off[1];  // selected below, not indexed (keeps them in registers)
         const int64_t from = (ts & kTileSet) ? o1 : o0, to = (ts & kTileSet) ? o0 : o1;
@@ -698,7 +741,7 @@ pool2d_kernel(PoolView v, Consts k)
         const int far = march_tile<T, L, WALLS>(arena + from, arena + to, g, k, tl.x0, tl.y0, tl.rows,
                                                 v.partials + (int64_t)t * kPartialStride);
         if (threadIdx.x == 0) {
-            v.flags[t] = L < kLFull ? far : 0;
+            v.flags[t] = far;
             if (L < kLFull && far) atomicAdd(&v.next[2], 1);
         }
     }

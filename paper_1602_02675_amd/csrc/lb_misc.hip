@@ -65,6 +65,8 @@ __global__ void reset_ctl_kernel(StepCtl* ctl)
         for (int f = 0; f < 4; ++f) ctl->totals[f] = 0.0;
         ctl->max_reach = 0;
         ctl->redo_tiles = 0;
+        ctl->keep[0] = 0;
+        ctl->keep[1] = 0;
     }
 }
 

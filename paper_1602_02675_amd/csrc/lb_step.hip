@@ -117,6 +117,8 @@ finalize_kernel(const double* __restrict__ partials, int64_t nb, StepCtl* __rest
         ctl->next[0] = 0;
         ctl->next[1] = 0;
         ctl->next[2] = 0;
+        ctl->keep[1] = ctl->keep[0];
+        ctl->keep[0] = 0;
     }
     if (ctl->err_step < step) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
