@@ -125,8 +125,8 @@ def packets(P: Problem, node):
     """All packets of one node: (offsets [n, 2] int, payload [n, nf] = m, m*xi, m*zeta)."""
     lib = _load()
     y = np.ascontiguousarray(node, dtype=np.float64)
-    off = np.zeros((32, 2), dtype=np.int32)
-    pay = np.zeros(32 * 4, dtype=np.float64)
+    off = np.zeros((36, 2), dtype=np.int32)  # at most 36 packets (2-D with a rest level)
+    pay = np.zeros(36 * 4, dtype=np.float64)
     n = lib.oc_packets(ctypes.byref(P._c), _dptr(y), _iptr(off), _dptr(pay))
     return off[:n].copy(), pay[: n * P.nf].reshape(n, P.nf).copy()
 

@@ -39,6 +39,11 @@
  *     (2-D) opposite to it.
  *   - a node with rho <= 0 emits nothing.
  *   - 2-D lanes are the four axis directions at speeds c'_1, c'_2.
+ *   - the square lattice with a rest level (delta0 > 0 in 2-D: the 2-D
+ *     triple-level set, which the paper's eq. 24-26 cover through b_0 but
+ *     whose figures show only the dual-level set): one rest particle group,
+ *     b_0 = 1, d_0 = delta0 * rho, next to the four directions at c'_1, c'_2
+ *     (b_1 = b_2 = 4).  delta0 = 0 is the paper's dual-level set.
  *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC.
  */
@@ -47,7 +52,7 @@
 #include <string.h>
 
 #define OC_GHOSTS 8       /* ghost nodes per transmissive end (>= any reach) */
-#define OC_MAX_PACKETS 32 /* 10 in 1-D, 32 in 2-D */
+#define OC_MAX_PACKETS 36 /* 10 in 1-D, 32 in 2-D (36 with the rest level) */
 
 typedef struct {
     int dim;        /* 1: 1-D triple-level lattice; 2: square dual-level lattice */
@@ -55,7 +60,7 @@ typedef struct {
     int bc_x, bc_y; /* 0: transmissive (ghost nodes copy the edge); 1: periodic;
                        2: reflecting wall at each end */
     double gamma;   /* ratio of specific heats */
-    double delta0;  /* d_0 = delta0 * rho (1-D); 0 on the square lattice */
+    double delta0;  /* d_0 = delta0 * rho; in 2-D, delta0 > 0 adds the rest level */
 } oc_problem;
 
 typedef struct {
@@ -105,9 +110,13 @@ int oc_levels_of(const oc_problem* P, const double* Yn, oc_levels* L)
     if (L->e < 0.0) L->e = 0.0;
     /* non-translational energy (eq. 15) */
     L->phi = (1.0 - ((double)D / 2.0) * (P->gamma - 1.0)) * L->e;
-    /* velocity set (Sec. IV): 1-D b0=1, b1=b2=2; square lattice b0=0, b1=b2=4 */
+    /* velocity set (Sec. IV): 1-D b0=1, b1=b2=2; square lattice b0=0, b1=b2=4
+     * (dual level), or b0=1 with d0 = delta0 rho (triple level) */
     if (D == 1) {
         L->b0 = 1; L->b1 = 2; L->b2 = 2;
+        L->d0 = P->delta0 * L->rho;
+    } else if (P->delta0 > 0.0) {
+        L->b0 = 1; L->b1 = 4; L->b2 = 4;
         L->d0 = P->delta0 * L->rho;
     } else {
         L->b0 = 0; L->b1 = 4; L->b2 = 4;
@@ -139,7 +148,8 @@ int oc_levels_of(const oc_problem* P, const double* Yn, oc_levels* L)
 /*
  * All packets one node emits (eq. 19-23, 30-33): for each lane, for each
  * corner, the displacement (integer, per axis) and eta = {m, m xi, m zeta}.
- * Returns the number of packets (10 in 1-D, 32 in 2-D; 0 if rho <= 0).
+ * Returns the number of packets (10 in 1-D, 32 in 2-D, 36 with the 2-D rest
+ * level; 0 if rho <= 0).
  * off: [n][2] integer displacement; pay: [n][nf].
  */
 int oc_packets(const oc_problem* P, const double* Yn, int* off, double* pay)
@@ -148,8 +158,8 @@ int oc_packets(const oc_problem* P, const double* Yn, int* off, double* pay)
     const int D = P->dim, nf = oc_nf(P);
     if (!oc_levels_of(P, Yn, &L)) return 0;
     /* lanes: c' per axis and weight d_v */
-    int lane_c[8][2];
-    double lane_d[8];
+    int lane_c[9][2];
+    double lane_d[9];
     int nl = 0;
     if (D == 1) {
         lane_c[nl][0] = 0;       lane_c[nl][1] = 0; lane_d[nl++] = L.d0;
@@ -158,6 +168,9 @@ int oc_packets(const oc_problem* P, const double* Yn, int* off, double* pay)
         lane_c[nl][0] = +L.c2;   lane_c[nl][1] = 0; lane_d[nl++] = L.d2;
         lane_c[nl][0] = -L.c2;   lane_c[nl][1] = 0; lane_d[nl++] = L.d2;
     } else {
+        if (L.b0 == 1) { /* rest level of the triple-level square set */
+            lane_c[nl][0] = 0; lane_c[nl][1] = 0; lane_d[nl++] = L.d0;
+        }
         for (int lev = 1; lev <= 2; ++lev) {
             const int c = lev == 1 ? L.c1 : L.c2;
             const double d = lev == 1 ? L.d1 : L.d2;
