@@ -55,6 +55,9 @@ extern "C" {
 
 #define LB_LATTICE_D1_TRIPLE 1       /* 1-D triple-level set (Sec. IV.A): c' in {0, +-c'_1, +-c'_2}, b0=1, b1=b2=2 */
 #define LB_LATTICE_D2_SQUARE_DUAL 2  /* square dual-level set (Sec. IV.B): +-c'_1, +-c'_2 along x and y, d0=0, b1=b2=4 */
+#define LB_LATTICE_D2_SQUARE_TRIPLE 3 /* square set with a rest level: the dual-level set plus one rest group,
+                                       * b0=1, d0 = d0_frac rho, d0_frac in (0, 1) (eq. 24-26 with b_0 d_0;
+                                       * the paper's square lattice takes d0 = 0) */
 
 #define LB_FP64 0 /* FP64 storage and arithmetic */
 #define LB_FP32 1 /* FP32 storage and arithmetic, FP64 conservation totals */
@@ -73,8 +76,8 @@ typedef struct {
 } lb_grid;
 
 /* Velocity set: lattice (must match dim) and d0_frac = d_0 / rho, the rest
- * weight of the 1-D triple-level set (the paper picks 0.4 .. 0.55; 0.5 is the
- * usual choice); must be 0 for the square dual-level set. */
+ * weight of the triple-level sets (the paper picks 0.4 .. 0.55 in 1-D; 0.5 is
+ * the usual choice); must be 0 for the square dual-level set. */
 typedef struct {
     int32_t lattice;
     double d0_frac;

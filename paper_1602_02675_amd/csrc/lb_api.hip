@@ -43,12 +43,14 @@ int check_model(int dim, double gamma, const lb_velset* vs, int precision)
     if (!(gamma > 1.0) || !(gamma <= 1.0 + 2.0 / dim))
         return fail(LB_EINVAL, "gamma must lie in (1, 1 + 2/D] (phi >= 0, eq. 15); got %g", gamma);
     if ((dim == 1 && vs->lattice != LB_LATTICE_D1_TRIPLE) ||
-        (dim == 2 && vs->lattice != LB_LATTICE_D2_SQUARE_DUAL))
+        (dim == 2 && vs->lattice != LB_LATTICE_D2_SQUARE_DUAL && vs->lattice != LB_LATTICE_D2_SQUARE_TRIPLE))
         return fail(LB_EINVAL, "lattice %d does not match dim %d", vs->lattice, dim);
     if (dim == 1 && !(vs->d0_frac >= 0.0 && vs->d0_frac < 1.0))
         return fail(LB_EINVAL, "d0_frac must lie in [0, 1); got %g", vs->d0_frac);
-    if (dim == 2 && vs->d0_frac != 0.0)
+    if (vs->lattice == LB_LATTICE_D2_SQUARE_DUAL && vs->d0_frac != 0.0)
         return fail(LB_EINVAL, "the square dual-level set has d0 = 0");
+    if (vs->lattice == LB_LATTICE_D2_SQUARE_TRIPLE && !(vs->d0_frac > 0.0 && vs->d0_frac < 1.0))
+        return fail(LB_EINVAL, "the square set with a rest level needs d0_frac in (0, 1); got %g", vs->d0_frac);
     if (precision != LB_FP64 && precision != LB_FP32)
         return fail(LB_EINVAL, "precision must be LB_FP64 or LB_FP32");
     return LB_OK;
@@ -81,9 +83,13 @@ Consts make_consts(int dim, double gamma, const lb_velset* vs)
     Consts k;
     k.Dg1 = (double)dim * (gamma - 1.0);
     k.phi_coef = 1.0 - ((double)dim / 2.0) * (gamma - 1.0);
-    k.delta0 = dim == 1 ? vs->d0_frac : 0.0;
-    k.b0 = dim == 1 ? 1.0 : 0.0;
+    const bool rest = dim == 1 || vs->lattice == LB_LATTICE_D2_SQUARE_TRIPLE;
+    k.delta0 = rest ? vs->d0_frac : 0.0;
+    k.b0 = rest ? 1.0 : 0.0;
     k.inv_b1 = dim == 1 ? 0.5 : 0.25;
+    // square lattice with a rest level: d_0 = q (d_1 + d_2), q = b_1 delta0 / (1 - delta0),
+    // so that a rest packet's mass follows from the staged level masses
+    k.rest_q = (dim == 2 && rest) ? 4.0 * vs->d0_frac / (1.0 - vs->d0_frac) : 0.0;
     return k;
 }
 

@@ -29,9 +29,10 @@ constexpr int kBcReflecting = 2;
 struct Consts {
     double Dg1;       // D (gamma - 1)
     double phi_coef;  // 1 - (D/2)(gamma - 1), eq. 15
-    double delta0;    // d_0 / rho on the 1-D triple-level set
-    double b0;        // rest-lane multiplicity b_0 (1 in 1-D, 0 on the square lattice)
+    double delta0;    // d_0 / rho on the triple-level sets (0 on the square dual-level set)
+    double b0;        // rest-lane multiplicity b_0 (1 with a rest level, else 0)
     double inv_b1;    // 1 / b_1
+    double rest_q;    // square lattice with a rest level: d_0 / (d_1 + d_2) = b_1 delta0 / (1 - delta0)
 };
 
 template <typename T>
@@ -147,7 +148,9 @@ __device__ __forceinline__ Src1<T> make_src1(T m0t, T m1t, T m2t, const Consts& 
     return s;
 }
 
-template <typename T>
+// REST: the square set with a rest level (d_0 = delta0 rho); the staged level
+// masses then carry (rho - d_0) / b_1 between them.
+template <typename T, bool REST = false>
 __device__ __forceinline__ Src2<T> make_src2(T m0t, T m1t, T m2t, T m3t, const Consts& k)
 {
     const double m0 = m0t, m1 = m1t, m2 = m2t, m3 = m3t;
@@ -168,7 +171,7 @@ __device__ __forceinline__ Src2<T> make_src2(T m0t, T m1t, T m2t, T m3t, const C
         E = m3 / m0;
         v2 = vx * vx + vy * vy;
     }
-    Levels<double> L = node_levels<double>(m0, v2, E, 0.0, k);
+    Levels<double> L = node_levels<double>(m0, v2, E, REST ? k.delta0 * m0 : 0.0, k);
     const double fvx = floor(vx), fvy = floor(vy);
     s.fx = (int)fvx;
     s.fy = (int)fvy;

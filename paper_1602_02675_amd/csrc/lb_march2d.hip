@@ -361,10 +361,11 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc
 // have, within the halo) and every packet that reaches this column.
 // [fylo, fyhi] and [clo, chi] are the window's ranges of floor(v_y) and c'_1:
 // each packet class then reaches one or two FIFO slots, and only those are
-// visited.
-template <typename T, int L>
+// visited.  REST: the set has a rest group, whose packets (mass
+// rq (d_1 + d_2) per corner, energy K) move like the y-lanes with c' = 0.
+template <typename T, int L, bool REST>
 __device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, int alo, int ahi, int fylo, int fyhi,
-                               int clo, int chi)
+                               int clo, int chi, T rq)
 {
 #pragma clang fp contract(off)
 #pragma unroll 1
@@ -392,7 +393,17 @@ __device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, i
                                                m * vy, m * zx);
                 }
             }
-            if (cx == 0) {  // y-lanes move in x by fx + kx only
+            if (cx == 0) {  // y-lanes (and the rest group) move in x by fx + kx only
+                if constexpr (REST) {
+                    const T mr = rq * (R.m[0][kx][s] + R.m[1][kx][s]);
+                    const T zr = R.kk[0][s] - (T)0.5 * (T)(c1 * c1);  // K
+#pragma unroll 1
+                    for (int ky = 0; ky < 2; ++ky) {
+                        const T m = mr * (ky ? ry : (T)1 - ry);
+                        fifo_add_sel<Acc<T>, T, L>(f, fy + ky + L, fylo + ky + L, fyhi + ky + L, m, m * vx,
+                                                   m * vy, m * zr);
+                    }
+                }
 #pragma unroll 1
                 for (int l = 0; l < 2; ++l) {
                     const int c = l == 0 ? c1 : c2;
@@ -437,7 +448,7 @@ __device__ __forceinline__ void load_node(const T* __restrict__ Y, int64_t nn, i
 // which sums in the same order (bit-identical); with L = kLFull it tells that
 // the tile still needs the full pass.
 // Contains block-wide barriers: every thread of the block must call it.
-template <typename T, int L, bool WALLS>
+template <typename T, int L, bool WALLS, bool REST>
 __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict__ Yn, const Grid& g, const Consts& k,
                           int64_t X0, int64_t Y0, int sy, double* __restrict__ prow)
 {
@@ -497,7 +508,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                 mx = mir_x ? -mx : mx;
                 my = cur_my[u] ? -my : my;
             }
-            const Src2<T> s = make_src2<T>(cur[u][0], mx, my, cur[u][3], k);
+            const Src2<T> s = make_src2<T, REST>(cur[u][0], mx, my, cur[u][3], k);
             const int pk = mpack(s.fx, s.fy, s.c1);
             s_row[b][u].vx[tid] = s.vx;
             s_row[b][u].ry[tid] = s.ry;
@@ -547,13 +558,18 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
             const bool rows_ok = planar && fits_y;
             // the short pass takes planar windows within its FIFO; a tile with
             // any other window is flagged for the full pass
-            if (!(planar && fits_small)) yfar = 1;
+            if (!((planar || REST) && fits_small)) yfar = 1;
             // full pass, floor(v_y) in {-1, 0} (where v_y changes sign): the row
             // path once per value (other pairs of values take the general path:
             // their instances made the compiler spill the FIFO on every path)
             const bool ymix_ok = fits_x && fits_y && w.fymin == -1 && w.fymax == 0 && w.c1max <= 3 &&
                                  w.fxmax - w.fxmin <= 2;
-            if (dest && (fits_y || L == kLFull)) {
+            if constexpr (REST) {  // only the general path adds the rest group's packets
+                if (dest && (fits_y || L == kLFull))
+                    gather_general<T, L, true>(s_row[b][u], tid, f, max(-kMH, w.fxmin - c2max),
+                                               min(kMH, w.fxmax + 1 + c2max), w.fymin, w.fymax, w.c1min, w.c1max,
+                                               (T)k.rest_q);
+            } else if (dest && (fits_y || L == kLFull)) {
                 // two adjacent values of c'_1 or of floor(v_x) keep compile-time
                 // offsets; a window mixing both (rare in planar flows) takes the
                 // row path, whose extra registers would otherwise cost occupancy
@@ -596,8 +612,9 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                     if (w.fymin == -1) gather_rows<T, L, -1>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, ymix_ok);
                     if (w.fymax == 0) gather_rows<T, L, 0>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, ymix_ok);
                 } else {
-                    gather_general<T, L>(s_row[b][u], tid, f, max(-kMH, w.fxmin - c2max),
-                                         min(kMH, w.fxmax + 1 + c2max), w.fymin, w.fymax, w.c1min, w.c1max);
+                    gather_general<T, L, false>(s_row[b][u], tid, f, max(-kMH, w.fxmin - c2max),
+                                                min(kMH, w.fxmax + 1 + c2max), w.fymin, w.fymax, w.c1min, w.c1max,
+                                                (T)0);
                 }
             }
             // destination row (source row) - L is complete
@@ -674,7 +691,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
 // full pass instead of computing them twice (flows change little per step).
 // Persistent blocks claim the tiles (tiles_x column strips x row chunks of sy
 // rows, row chunk major) from the control block's counter of the pass.
-template <typename T, int L, bool WALLS>
+template <typename T, int L, bool WALLS, bool REST>
 __global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
 march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
                StepCtl* __restrict__ ctl, double* __restrict__ partials, int* __restrict__ flags,
@@ -698,8 +715,8 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
             continue;
         }
         const int64_t tx = t % tiles_x, ty = t / tiles_x;
-        const int far = march_tile<T, L, WALLS>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
-                                                partials + (int64_t)t * kPartialStride);
+        const int far = march_tile<T, L, WALLS, REST>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
+                                                      partials + (int64_t)t * kPartialStride);
         if (threadIdx.x == 0) {
             flags[t] = far;
             if (L < kLFull && far) atomicAdd(&ctl->next[2], 1);
@@ -715,7 +732,7 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
 // pool1d_kernel).  The short-FIFO pass flags the tiles it could not complete;
 // the full-FIFO pass computes only those, and keeps the flags of the tiles
 // that still need it (as in march2d_kernel).
-template <typename T, int L, bool WALLS>
+template <typename T, int L, bool WALLS, bool REST>
 __global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
 pool2d_kernel(PoolView v, Consts k)
 {
@@ -738,8 +755,8 @@ pool2d_kernel(PoolView v, Consts k)
         const int64_t o0 = tl.off[0], o1 = tl.off[1];  // selected below, not indexed (keeps them in registers)
         const int64_t from = (ts & kTileSet) ? o1 : o0, to = (ts & kTileSet) ? o0 : o1;
         const Grid g{tl.nx, tl.ny, tl.bc_x, tl.bc_y};
-        const int far = march_tile<T, L, WALLS>(arena + from, arena + to, g, k, tl.x0, tl.y0, tl.rows,
-                                                v.partials + (int64_t)t * kPartialStride);
+        const int far = march_tile<T, L, WALLS, REST>(arena + from, arena + to, g, k, tl.x0, tl.y0, tl.rows,
+                                                      v.partials + (int64_t)t * kPartialStride);
         if (threadIdx.x == 0) {
             v.flags[t] = far;
             if (L < kLFull && far) atomicAdd(&v.next[2], 1);
@@ -783,58 +800,66 @@ template <typename T>
 int march2d_blocks_per_cu()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, march2d_kernel<T, kLSmall, false>, kMTPB, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, march2d_kernel<T, kLSmall, false, false>, kMTPB, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-template <typename T, bool WALLS>
+template <typename T, bool WALLS, bool REST>
 hipError_t launch_march2d_w(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
                             StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream)
 {
     const int nt = (int)m.blocks();
-    march2d_kernel<T, kLSmall, WALLS><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, flags, step,
-                                                                       m.sy, (int)m.grid_x, nt);
+    march2d_kernel<T, kLSmall, WALLS, REST><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, flags,
+                                                                             step, m.sy, (int)m.grid_x, nt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    march2d_kernel<T, kLFull, WALLS><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, flags, step,
-                                                                      m.sy, (int)m.grid_x, nt);
+    march2d_kernel<T, kLFull, WALLS, REST><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, flags,
+                                                                            step, m.sy, (int)m.grid_x, nt);
     return hipGetLastError();
 }
 
-// Grids without reflecting walls run the instances that keep no mirror state.
+// Grids without reflecting walls run the instances that keep no mirror state,
+// the dual-level set those without the rest group.
 template <typename T>
 hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
                           StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream)
 {
-    if (g.bc_x == kBcReflecting || g.bc_y == kBcReflecting)
-        return launch_march2d_w<T, true>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
-    return launch_march2d_w<T, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
+    const bool walls = g.bc_x == kBcReflecting || g.bc_y == kBcReflecting, rest = k.rest_q > 0.0;
+    if (rest)
+        return walls ? launch_march2d_w<T, true, true>(Y, Yn, g, m, k, ctl, partials, flags, step, stream)
+                     : launch_march2d_w<T, false, true>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
+    return walls ? launch_march2d_w<T, true, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream)
+                 : launch_march2d_w<T, false, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
 }
 
 template <typename T>
 int pool2d_blocks_per_cu()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pool2d_kernel<T, kLSmall, false>, kMTPB, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pool2d_kernel<T, kLSmall, false, false>, kMTPB, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-template <typename T, bool WALLS>
+template <typename T, bool WALLS, bool REST>
 hipError_t launch_pool2d_w(const PoolView& v, const Consts& k, int nblocks, hipStream_t stream)
 {
-    pool2d_kernel<T, kLSmall, WALLS><<<nblocks, kMTPB, 0, stream>>>(v, k);
+    pool2d_kernel<T, kLSmall, WALLS, REST><<<nblocks, kMTPB, 0, stream>>>(v, k);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    pool2d_kernel<T, kLFull, WALLS><<<nblocks, kMTPB, 0, stream>>>(v, k);
+    pool2d_kernel<T, kLFull, WALLS, REST><<<nblocks, kMTPB, 0, stream>>>(v, k);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_pool2d(const PoolView& v, const Consts& k, int nblocks, bool walls, hipStream_t stream)
 {
-    return walls ? launch_pool2d_w<T, true>(v, k, nblocks, stream) : launch_pool2d_w<T, false>(v, k, nblocks, stream);
+    if (k.rest_q > 0.0)
+        return walls ? launch_pool2d_w<T, true, true>(v, k, nblocks, stream)
+                     : launch_pool2d_w<T, false, true>(v, k, nblocks, stream);
+    return walls ? launch_pool2d_w<T, true, false>(v, k, nblocks, stream)
+                 : launch_pool2d_w<T, false, false>(v, k, nblocks, stream);
 }
 
 template int march2d_blocks_per_cu<double>();

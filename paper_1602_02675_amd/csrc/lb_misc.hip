@@ -46,7 +46,9 @@ __global__ void lanes_kernel(const T* __restrict__ Y, int64_t nn, int dim, Const
         fy[q] = 0;
         c1[q] = s.c1;
     } else {
-        const Src2<T> s = make_src2<T>(Y[q], Y[nn + q], Y[2 * nn + q], Y[3 * nn + q], k);
+        // the same device function the step uses (with or without the rest group)
+        const Src2<T> s = k.rest_q > 0.0 ? make_src2<T, true>(Y[q], Y[nn + q], Y[2 * nn + q], Y[3 * nn + q], k)
+                                         : make_src2<T, false>(Y[q], Y[nn + q], Y[2 * nn + q], Y[3 * nn + q], k);
         fx[q] = s.fx;
         fy[q] = s.fy;
         c1[q] = s.c1;

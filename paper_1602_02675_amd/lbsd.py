@@ -22,7 +22,7 @@ LIB_PATH = os.environ.get("LBSD_LIBRARY") or os.path.join(_PKG, "liblbsd.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ESTATE, LB_EREACH = 0, -1, -2, -3, -4, -5
 LB_BC_TRANSMISSIVE, LB_BC_PERIODIC, LB_BC_REFLECTING = 0, 1, 2
-LB_LATTICE_D1_TRIPLE, LB_LATTICE_D2_SQUARE_DUAL = 1, 2
+LB_LATTICE_D1_TRIPLE, LB_LATTICE_D2_SQUARE_DUAL, LB_LATTICE_D2_SQUARE_TRIPLE = 1, 2, 3
 LB_FP64, LB_FP32 = 0, 1
 LB_HALO = 5
 LB_POOL_FREE = -100
@@ -130,6 +130,14 @@ def _check(rc: int):
         raise LBError(rc, _lib.lb_last_error().decode())
 
 
+def _lattice(dim: int, d0_frac: float) -> int:
+    """The 1-D triple-level set, or on the square lattice the dual-level set
+    (d0_frac = 0) or the set with a rest level (d0_frac > 0)."""
+    if dim == 1:
+        return LB_LATTICE_D1_TRIPLE
+    return LB_LATTICE_D2_SQUARE_TRIPLE if d0_frac > 0.0 else LB_LATTICE_D2_SQUARE_DUAL
+
+
 def _bc(v) -> int:
     if isinstance(v, str):
         return {"transmissive": LB_BC_TRANSMISSIVE, "periodic": LB_BC_PERIODIC,
@@ -151,7 +159,7 @@ class Solver:
         self.nf = dim + 2
         self.precision = precision
         g = lb_grid(dim, self.nx, self.ny, x_lo, x_hi, _bc(bc_x), _bc(bc_y))
-        vs = lb_velset(LB_LATTICE_D1_TRIPLE if dim == 1 else LB_LATTICE_D2_SQUARE_DUAL, d0_frac)
+        vs = lb_velset(_lattice(dim, d0_frac), d0_frac)
         prec = {"fp64": LB_FP64, "fp32": LB_FP32}[precision]
         h = ctypes.c_void_p()
         _check(_lib.lb_create(ctypes.byref(g), gamma, ctypes.byref(vs), prec, ctypes.byref(h)))
@@ -274,7 +282,7 @@ class Pool:
         self.dim, self.nf, self.precision = dim, dim + 2, precision
         self.max_slots = int(max_slots)
         self.arena_bytes = int(arena_bytes)
-        vs = lb_velset(LB_LATTICE_D1_TRIPLE if dim == 1 else LB_LATTICE_D2_SQUARE_DUAL, d0_frac)
+        vs = lb_velset(_lattice(dim, d0_frac), d0_frac)
         prec = {"fp64": LB_FP64, "fp32": LB_FP32}[precision]
         h = ctypes.c_void_p()
         _check(_lib.lb_pool_create(dim, gamma, ctypes.byref(vs), prec, int(max_slots), int(arena_bytes),

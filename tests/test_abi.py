@@ -50,12 +50,14 @@ def test_create_validation():
            dict(bc_x=7), dict(x_hi=0.0), dict(prec=5),
            # reflecting walls need the mirror images of the halo inside the grid
            dict(bc_x=2, nx=4), dict(dim=2, lattice=2, d0=0.0, nx=64, ny=4, bc_y=2),
-           dict(dim=2, lattice=2, d0=0.0, nx=4, ny=64, bc_x=2)]
+           dict(dim=2, lattice=2, d0=0.0, nx=4, ny=64, bc_x=2),
+           # the square set with a rest level needs 0 < d0_frac < 1, and 2-D
+           dict(dim=2, lattice=3, d0=0.0), dict(dim=2, lattice=3, d0=1.0), dict(dim=1, lattice=3, d0=0.5)]
     for kw in bad:
         rc, h = _create(lbsd, **kw)
         assert rc == lbsd.LB_EINVAL, kw
         assert lbsd._lib.lb_last_error()
-    for kw in (dict(bc_x=2, nx=5), dict(bc_x=2, bc_y=2),
+    for kw in (dict(bc_x=2, nx=5), dict(bc_x=2, bc_y=2), dict(dim=2, lattice=3, d0=0.5, nx=8, ny=8),
                dict(dim=2, lattice=2, d0=0.0, nx=5, ny=5, bc_x=2, bc_y=2)):
         rc, h = _create(lbsd, **kw)
         assert rc == lbsd.LB_OK, kw
