@@ -17,6 +17,8 @@ gather kernel plus its totals reduction.  Alongside, in the same JSON line:
   the kernel instances that handle walls);
 * nonplanar: a seeded four-state 2-D Riemann problem (both velocity
   components of both signs) on 2048 x 2048 nodes, FP64;
+* rest_level: the headline tube on the square lattice with a rest level
+  (d_0 = rho / 2), FP64, 100 steps;
 * serve: square-lattice requests (sides log-uniform in [64, 2048], steps in
   [100, 5000], seeded states) arriving as a Poisson process at 0.8 x the
   measured capacity, continuously batched on an FP32 pool: p50 / p99
@@ -64,12 +66,12 @@ def workload():
     return left, right, x_d, lam
 
 
-def run_gpu(precision: str, steps: int, warmup: int, bc_x: str = "transmissive"):
+def run_gpu(precision: str, steps: int, warmup: int, bc_x: str = "transmissive", d0_frac: float = 0.0):
     import torch
     from paper_1602_02675_amd.lbsd import Solver
 
     left, right, x_d, lam = workload()
-    s = Solver(2, NX, NY, precision=precision, bc_x=bc_x, bc_y="periodic")
+    s = Solver(2, NX, NY, precision=precision, bc_x=bc_x, bc_y="periodic", d0_frac=d0_frac)
     s.init_riemann(x_d, left, right, lam=lam)
     if warmup:
         s.step(warmup)
@@ -194,7 +196,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the walls and nonplanar legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the walls, nonplanar and rest_level legs")
     ap.add_argument("--profile", action="store_true",
                     help="short run + a plain copy of known size, for rocprofv3 counters")
     args = ap.parse_args()
@@ -264,6 +266,10 @@ def main():
                         "steps": 500, "ms_per_step": round(rw["total_ms"] / 500, 5),
                         "bc": "reflecting x / periodic y", "precision": "fp64"}
         out["nonplanar"] = run_nonplanar()
+        rr = run_gpu("fp64", 100, 5, d0_frac=0.5)
+        out["rest_level"] = {"value": round(nodes * 100 / (rr["total_ms"] / 1e3) / 1e6, 1), "unit": "MLUPS",
+                             "steps": 100, "ms_per_step": round(rr["total_ms"] / 100, 5), "d0_frac": 0.5,
+                             "precision": "fp64"}
     if not args.no_batch:
         out["batch"] = {p: run_batch(p) for p in ("fp32", "fp64")}
     if not args.no_serve:
