@@ -44,7 +44,8 @@ def build() -> str:
 class _Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_long), ("ny", ctypes.c_long),
                 ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
-                ("gamma", ctypes.c_double), ("delta0", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("delta0", ctypes.c_double),
+                ("species", ctypes.c_int), ("gamma2", ctypes.c_double)]
 
 
 class _Levels(ctypes.Structure):
@@ -55,7 +56,7 @@ class _Levels(ctypes.Structure):
                 ("d0", ctypes.c_double), ("d1", ctypes.c_double), ("d2", ctypes.c_double),
                 ("b0", ctypes.c_int), ("b1", ctypes.c_int), ("b2", ctypes.c_int),
                 ("f", ctypes.c_int * 2), ("vp0", ctypes.c_double * 2),
-                ("vp1", ctypes.c_double * 2)]
+                ("vp1", ctypes.c_double * 2), ("chi", ctypes.c_double), ("gm1", ctypes.c_double)]
 
 
 def _load():
@@ -86,16 +87,27 @@ class Problem:
     """Lattice, grid, boundaries and gas of one oracle problem."""
 
     def __init__(self, dim: int, nx: int, ny: int = 1, *, gamma: float = 1.4,
-                 delta0: float | None = None, bc_x: int = TRANSMISSIVE, bc_y: int = PERIODIC):
+                 delta0: float | None = None, bc_x: int = TRANSMISSIVE, bc_y: int = PERIODIC,
+                 gamma2: float | None = None):
+        """gamma2: a second gas (gamma of gas 2, gamma of gas 1); the state
+        then has a species field rho chi (mass of gas 1) after rho E."""
         if delta0 is None:
             delta0 = 0.5 if dim == 1 else 0.0
         self.dim, self.nx, self.ny = dim, int(nx), int(ny if dim == 2 else 1)
         self.gamma, self.delta0, self.bc_x, self.bc_y = float(gamma), float(delta0), bc_x, bc_y
-        self._c = _Problem(dim, self.nx, self.ny, bc_x, bc_y, self.gamma, self.delta0)
+        self.species = gamma2 is not None
+        self.gamma2 = float(gamma2) if self.species else self.gamma
+        self._c = _Problem(dim, self.nx, self.ny, bc_x, bc_y, self.gamma, self.delta0,
+                           1 if self.species else 0, self.gamma2)
+
+    @property
+    def ie(self) -> int:
+        """Index of the energy field rho E."""
+        return self.dim + 1
 
     @property
     def nf(self) -> int:
-        return self.dim + 2
+        return self.dim + 2 + (1 if self.species else 0)
 
     @property
     def shape(self):
@@ -118,7 +130,8 @@ def levels(P: Problem, node) -> dict:
     lib.oc_levels_of(ctypes.byref(P._c), _dptr(y), ctypes.byref(L))
     return dict(valid=L.valid, rho=L.rho, v=tuple(L.v[: P.dim]), E=L.E, e=L.e, phi=L.phi,
                 A=L.A, c1=L.c1, c2=L.c2, d0=L.d0, d1=L.d1, d2=L.d2, b=(L.b0, L.b1, L.b2),
-                f=tuple(L.f[: P.dim]), vp0=tuple(L.vp0[: P.dim]), vp1=tuple(L.vp1[: P.dim]))
+                f=tuple(L.f[: P.dim]), vp0=tuple(L.vp0[: P.dim]), vp1=tuple(L.vp1[: P.dim]),
+                chi=L.chi, gm1=L.gm1)
 
 
 def packets(P: Problem, node):
@@ -126,7 +139,7 @@ def packets(P: Problem, node):
     lib = _load()
     y = np.ascontiguousarray(node, dtype=np.float64)
     off = np.zeros((36, 2), dtype=np.int32)  # at most 36 packets (2-D with a rest level)
-    pay = np.zeros(36 * 4, dtype=np.float64)
+    pay = np.zeros(36 * 5, dtype=np.float64)
     n = lib.oc_packets(ctypes.byref(P._c), _dptr(y), _iptr(off), _dptr(pay))
     return off[:n].copy(), pay[: n * P.nf].reshape(n, P.nf).copy()
 
@@ -180,17 +193,19 @@ def riemann_moments(P: Problem, x, prim_left, prim_right, x_d: float) -> np.ndar
     prim_* = (rho, u, v, p); node i is on the left iff x_i < x_d.  The total
     energy follows from the equation of state p = (gamma - 1) rho e (eq. 27).
     """
-    g = P.gamma
     left = np.asarray(x) < x_d
     Y = np.zeros(P.shape)
-    for side, (rho, u, v, p) in ((left, prim_left), (~left, prim_right)):
+    # with two gases, gas 1 (gamma) fills the left side and gas 2 (gamma2) the right
+    for side, (rho, u, v, p), g, chi in ((left, prim_left, P.gamma, 1.0), (~left, prim_right, P.gamma2, 0.0)):
         rE = p / (g - 1.0) + 0.5 * rho * (u * u + v * v)
         cols = np.nonzero(side)[0]
         Y[0][:, cols] = rho
         Y[1][:, cols] = rho * u
         if P.dim == 2:
             Y[2][:, cols] = rho * v
-        Y[-1][:, cols] = rE
+        Y[P.ie][:, cols] = rE
+        if P.species:
+            Y[P.ie + 1][:, cols] = rho * chi
     return Y
 
 
@@ -199,7 +214,7 @@ def to_lattice(P: Problem, Y, lam: float) -> np.ndarray:
     Y = np.array(Y, dtype=np.float64).reshape(P.shape)
     lam2 = lam * lam
     Y[1:1 + P.dim] *= lam
-    Y[-1] *= lam2
+    Y[P.ie] *= lam2
     return Y
 
 
@@ -207,16 +222,23 @@ def from_lattice(P: Problem, Y, lam: float) -> np.ndarray:
     Y = np.array(Y, dtype=np.float64).reshape(P.shape)
     lam2 = lam * lam
     Y[1:1 + P.dim] /= lam
-    Y[-1] /= lam2
+    Y[P.ie] /= lam2
     return Y
 
 
 def primitives(P: Problem, Y_phys) -> dict:
-    """rho, u, (v), e, p from physical-unit moments (Sec. V.D outputs)."""
+    """rho, u, (v), e, p (and chi with two gases) from physical-unit moments
+    (Sec. V.D outputs); p uses the node's gas."""
     Y = np.asarray(Y_phys).reshape(P.shape)
     rho = Y[0]
     u = Y[1] / rho
     v = Y[2] / rho if P.dim == 2 else np.zeros_like(u)
-    e = Y[-1] / rho - 0.5 * (u * u + v * v)
-    p = (P.gamma - 1.0) * rho * e
-    return dict(rho=rho, u=u, v=v, e=e, p=p)
+    e = Y[P.ie] / rho - 0.5 * (u * u + v * v)
+    out = dict(rho=rho, u=u, v=v, e=e)
+    gm1 = P.gamma - 1.0
+    if P.species:
+        chi = np.clip(Y[P.ie + 1] / rho, 0.0, 1.0)
+        gm1 = 1.0 / (chi / (P.gamma - 1.0) + (1.0 - chi) / (P.gamma2 - 1.0))
+        out["chi"] = chi
+    out["p"] = gm1 * rho * e
+    return out

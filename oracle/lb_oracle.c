@@ -39,6 +39,15 @@
  *     (2-D) opposite to it.
  *   - a node with rho <= 0 emits nothing.
  *   - 2-D lanes are the four axis directions at speeds c'_1, c'_2.
+ *   - two gases (the different gases on the two sides of the tube that the
+ *     conclusions name as an extension): both ideal with one gas constant R,
+ *     ratios gamma (gas 1) and gamma2 (gas 2).  A species moment rho chi
+ *     (chi = mass fraction of gas 1) is carried as a further field: every
+ *     packet carries m chi of its source, as it carries its mass.  A node's
+ *     gas is the mixture: c_v = chi c_v1 + (1 - chi) c_v2 with
+ *     c_vi = R / (gamma_i - 1), so gamma - 1 = R / c_v =
+ *     1 / (chi / (gamma - 1) + (1 - chi) / (gamma2 - 1)), which then enters
+ *     phi (eq. 15) and A (eq. 26).
  *   - the square lattice with a rest level (delta0 > 0 in 2-D: the 2-D
  *     triple-level set, which the paper's eq. 24-26 cover through b_0 but
  *     whose figures show only the dual-level set): one rest particle group,
@@ -61,6 +70,8 @@ typedef struct {
                        2: reflecting wall at each end */
     double gamma;   /* ratio of specific heats */
     double delta0;  /* d_0 = delta0 * rho; in 2-D, delta0 > 0 adds the rest level */
+    int species;    /* 1: two gases, a species field rho chi after rho E */
+    double gamma2;  /* ratio of specific heats of gas 2 (species only) */
 } oc_problem;
 
 typedef struct {
@@ -72,10 +83,12 @@ typedef struct {
     int f[2];     /* floor of v per axis: corner 0 is x + f */
     double vp0[2]; /* v'_1 = (x + f) - (x + v): towards corner 0 */
     double vp1[2]; /* v'_2 = (x + f + 1) - (x + v): towards corner 1 */
+    double chi;    /* mass fraction of gas 1 (two gases) */
+    double gm1;    /* gamma - 1 of the node's gas */
 } oc_levels;
 
 /* Number of moment fields: rho, rho*v (dim components), rho*E. */
-static int oc_nf(const oc_problem* P) { return P->dim + 2; }
+static int oc_nf(const oc_problem* P) { return P->dim + 2 + (P->species ? 1 : 0); }
 
 /* Largest integer c with c*c <= A (A >= 0): the floor of sqrt(A), eq. 26. */
 static int oc_isqrt_floor(double A)
@@ -87,8 +100,8 @@ static int oc_isqrt_floor(double A)
 }
 
 /*
- * Equilibrium of one node (Sec. III.B).  Yn = [rho, rho*v_1..v_D, rho*E] in
- * lattice units (dx = dt = 1).
+ * Equilibrium of one node (Sec. III.B).  Yn = [rho, rho*v_1..v_D, rho*E
+ * (, rho*chi)] in lattice units (dx = dt = 1).
  */
 int oc_levels_of(const oc_problem* P, const double* Yn, oc_levels* L)
 {
@@ -109,7 +122,15 @@ int oc_levels_of(const oc_problem* P, const double* Yn, oc_levels* L)
     L->e = L->E - 0.5 * v2;
     if (L->e < 0.0) L->e = 0.0;
     /* non-translational energy (eq. 15) */
-    L->phi = (1.0 - ((double)D / 2.0) * (P->gamma - 1.0)) * L->e;
+    /* the node's gas: one gamma, or the mixture of two by mass fraction */
+    L->gm1 = P->gamma - 1.0;
+    if (P->species) {
+        double chi = Yn[D + 2] / L->rho;
+        chi = chi < 0.0 ? 0.0 : (chi > 1.0 ? 1.0 : chi);
+        L->chi = chi;
+        L->gm1 = 1.0 / (chi / (P->gamma - 1.0) + (1.0 - chi) / (P->gamma2 - 1.0));
+    }
+    L->phi = (1.0 - ((double)D / 2.0) * L->gm1) * L->e;
     /* velocity set (Sec. IV): 1-D b0=1, b1=b2=2; square lattice b0=0, b1=b2=4
      * (dual level), or b0=1 with d0 = delta0 rho (triple level) */
     if (D == 1) {
@@ -123,7 +144,7 @@ int oc_levels_of(const oc_problem* P, const double* Yn, oc_levels* L)
         L->d0 = 0.0;
     }
     /* level speeds (eq. 26) */
-    const double Dg1 = (double)D * (P->gamma - 1.0);
+    const double Dg1 = (double)D * L->gm1;
     L->A = Dg1 * L->e * L->rho / (L->rho - (double)L->b0 * L->d0);
     if (!(L->A >= 0.0)) L->A = 0.0;
     if (L->A > 1.0e6) L->A = 1.0e6; /* far beyond any admissible reach */
@@ -202,6 +223,7 @@ int oc_packets(const oc_problem* P, const double* Yn, int* off, double* pay)
             pay[nf * n + 0] = m;
             for (int a = 0; a < D; ++a) pay[nf * n + 1 + a] = m * xi[a];
             pay[nf * n + 1 + D] = m * zeta;
+            if (P->species) pay[nf * n + 2 + D] = m * L.chi; /* gas 1 moves with the mass */
             ++n;
         }
     }
@@ -245,8 +267,8 @@ int oc_step(const oc_problem* P, const double* Y, double* Ynew, int* max_reach)
     const long gx = P->bc_x == 0 ? OC_GHOSTS : 0;
     const long gy = (D == 2 && P->bc_y == 0) ? OC_GHOSTS : 0;
     int off[2 * OC_MAX_PACKETS];
-    double pay[4 * OC_MAX_PACKETS];
-    double Yn[4];
+    double pay[5 * OC_MAX_PACKETS];
+    double Yn[5];
     for (long sj = -gy; sj < ny + gy; ++sj) {
         for (long si = -gx; si < nx + gx; ++si) {
             /* ghost nodes hold a copy of the nearest edge node */
@@ -322,7 +344,7 @@ void oc_lanes(const oc_problem* P, const double* Y, int* fx, int* fy, int* c1)
 {
     const int D = P->dim, nf = oc_nf(P);
     const long nn = P->nx * (D == 2 ? P->ny : 1);
-    double Yn[4];
+    double Yn[5];
     for (long q = 0; q < nn; ++q) {
         oc_levels L;
         for (int fld = 0; fld < nf; ++fld) Yn[fld] = Y[(long)fld * nn + q];

@@ -13,6 +13,9 @@ an ideal gas p = (gamma - 1) rho e:
 * the star pressure solves f_L(p) + f_R(p) + (u_R - u_L) = 0 (monotone in p,
   found by bisection refined with Newton steps), u* = (u_L + u_R + f_R - f_L)/2.
 
+Each side may hold its own gas (gamma_L, gamma_R): every wave lies inside
+one gas and the contact separates them, so f_K uses the gamma of side K.
+
 The solution is self-similar in s = (x - x_d) / t.
 """
 from __future__ import annotations
@@ -34,22 +37,23 @@ def _f_and_df(p, rho_k, p_k, c_k, g):
 
 
 class RiemannSolution:
-    """Exact solution for left/right states (rho, u, p) and gamma."""
+    """Exact solution for left/right states (rho, u, p) and gamma, or a pair
+    (gamma_L, gamma_R) for two gases."""
 
-    def __init__(self, left, right, gamma: float = 1.4):
-        g = float(gamma)
-        self.g = g
+    def __init__(self, left, right, gamma=1.4):
+        gl, gr = (float(gamma[0]), float(gamma[1])) if isinstance(gamma, (tuple, list)) else (float(gamma),) * 2
+        self.gl, self.gr = gl, gr
         self.rl, self.ul, self.pl = map(float, left)
         self.rr, self.ur, self.pr = map(float, right)
-        self.cl = math.sqrt(g * self.pl / self.rl)
-        self.cr = math.sqrt(g * self.pr / self.rr)
+        self.cl = math.sqrt(gl * self.pl / self.rl)
+        self.cr = math.sqrt(gr * self.pr / self.rr)
         du = self.ur - self.ul
-        if 2.0 * (self.cl + self.cr) / (g - 1.0) <= du:
+        if 2.0 * self.cl / (gl - 1.0) + 2.0 * self.cr / (gr - 1.0) <= du:
             raise ValueError("vacuum is generated; not handled")
 
         def F(p):
-            fl, dfl = _f_and_df(p, self.rl, self.pl, self.cl, g)
-            fr, dfr = _f_and_df(p, self.rr, self.pr, self.cr, g)
+            fl, dfl = _f_and_df(p, self.rl, self.pl, self.cl, gl)
+            fr, dfr = _f_and_df(p, self.rr, self.pr, self.cr, gr)
             return fl + fr + du, dfl + dfr
 
         lo, hi = 1e-14, max(self.pl, self.pr)
@@ -78,11 +82,12 @@ class RiemannSolution:
                 break
             p = pn
         self.p_star = p
-        fl, _ = _f_and_df(p, self.rl, self.pl, self.cl, g)
-        fr, _ = _f_and_df(p, self.rr, self.pr, self.cr, g)
+        fl, _ = _f_and_df(p, self.rl, self.pl, self.cl, gl)
+        fr, _ = _f_and_df(p, self.rr, self.pr, self.cr, gr)
         self.u_star = 0.5 * (self.ul + self.ur) + 0.5 * (fr - fl)
+        # left wave (gas of the left side)
+        g = gl
         gm = (g - 1.0) / (g + 1.0)
-        # left wave
         if p > self.pl:
             self.rho_star_l = self.rl * (p / self.pl + gm) / (gm * p / self.pl + 1.0)
             self.s_l = self.ul - self.cl * math.sqrt((g + 1.0) / (2.0 * g) * p / self.pl + (g - 1.0) / (2.0 * g))
@@ -93,7 +98,9 @@ class RiemannSolution:
             self.head_l = self.ul - self.cl
             self.tail_l = self.u_star - self.c_star_l
             self.left_shock = False
-        # right wave
+        # right wave (gas of the right side)
+        g = gr
+        gm = (g - 1.0) / (g + 1.0)
         if p > self.pr:
             self.rho_star_r = self.rr * (p / self.pr + gm) / (gm * p / self.pr + 1.0)
             self.s_r = self.ur + self.cr * math.sqrt((g + 1.0) / (2.0 * g) * p / self.pr + (g - 1.0) / (2.0 * g))
@@ -107,7 +114,7 @@ class RiemannSolution:
 
     def sample(self, s):
         """(rho, u, p) at similarity coordinates s = (x - x_d) / t (array)."""
-        g = self.g
+        g = self.gl
         s = np.asarray(s, dtype=np.float64)
         rho = np.empty_like(s)
         u = np.empty_like(s)
@@ -131,6 +138,7 @@ class RiemannSolution:
             u[f] = uf
             p[f] = self.pl * (cf / self.cl) ** (2.0 * g / (g - 1.0))
         right = ~left
+        g = self.gr
         if self.right_shock:
             a = right & (s > self.s_r)
             b = right & (s <= self.s_r)
