@@ -94,6 +94,20 @@ typedef struct {
 int lb_create(const lb_grid* grid, double gamma, const lb_velset* velset, int32_t precision,
               lb_solver** out);
 
+/* Two gases on the 1-D lattice (the different gases on the two sides of the
+ * tube that the conclusions name as an extension): gas 1 with gamma_1 and gas
+ * 2 with gamma_2, both ideal with one gas constant, each in (1, 3].  The state
+ * gains a species moment rho chi (chi = mass fraction of gas 1) after rho E
+ * (nf = 4); every packet carries its source's chi as it carries its mass, and
+ * a node's gas is the mixture by mass fraction:
+ * gamma - 1 = 1 / (chi / (gamma_1 - 1) + (1 - chi) / (gamma_2 - 1)), which
+ * sets phi (eq. 15) and the level speeds (eq. 26).  lb_init_riemann puts gas 1
+ * on the left and gas 2 on the right (rho E and the CFL speed of each side
+ * from its own gamma); lb_init_moments and lb_moments take and give the four
+ * fields.  A square-lattice grid is LB_EINVAL. */
+int lb_create_two_gas(const lb_grid* grid, double gamma_1, double gamma_2, const lb_velset* velset,
+                      int32_t precision, lb_solver** out);
+
 /* Bytes of device memory the solver needs (two ping-pong SoA moment sets,
  * export staging, control block, per-block partials). */
 size_t lb_state_bytes(const lb_solver* s);
@@ -114,8 +128,9 @@ int lb_set_cfl(lb_solver* s, double cfl);
 int lb_init_riemann(lb_solver* s, double x_diaphragm, const lb_prim* left, const lb_prim* right);
 
 /* General initial state: host_Y is FP64 SoA [nf][ny][nx] of the conserved
- * moments rho, rho u, (rho v), rho E in physical units (nf = dim + 2), and
- * lambda > 0 the time-step ratio to use.  Copied synchronously. */
+ * moments rho, rho u, (rho v), rho E (, rho chi with two gases) in physical
+ * units (nf = dim + 2, or 4 with two gases), and lambda > 0 the time-step
+ * ratio to use.  Copied synchronously. */
 int lb_init_moments(lb_solver* s, const double* host_Y, double lambda);
 
 /* Queue n >= 0 steps (eq. 10 / eq. 30 with tau = 1, Sec. V.A).  Each step is
@@ -144,6 +159,10 @@ int lb_moments(lb_solver* s, double* out, int32_t out_on_device);
  * in physical units per node (multiply by dx for integrals).  The step
  * kernels form them in FP64 with a fixed reduction order.  Synchronises. */
 int lb_totals(lb_solver* s, double out[4]);
+
+/* Two gases: interior sum of rho chi (the mass of gas 1 per dx) of the
+ * current state, as lb_totals forms it.  LB_EINVAL for a one-gas solver. */
+int lb_species_total(lb_solver* s, double* out);
 
 double lb_lambda(const lb_solver* s);         /* lambda of the current state (0 before init) */
 double lb_dt(const lb_solver* s);             /* physical time step lambda * dx */

@@ -99,16 +99,18 @@ static bool prim_ok(const lb_prim* p)
            isfinite(p->v) && isfinite(p->p);
 }
 
-int riemann_sides(int dim, double gamma, double lam_set, double cfl, const lb_prim* L, const lb_prim* R,
-                  double* lam_out, double side[2][4])
+int riemann_sides(int dim, double gamma_l, double gamma_r, bool species, double lam_set, double cfl,
+                  const lb_prim* L, const lb_prim* R, double* lam_out, double side[2][4])
 {
     if (!prim_ok(L) || !prim_ok(R)) return fail(LB_ESTATE, "need rho > 0, p >= 0, finite values");
+    const double gs[2] = {gamma_l, gamma_r};
     double lam = lam_set;
     if (!(lam > 0.0)) {
         double smax = 0.0;
-        for (const lb_prim* q : {L, R}) {
+        for (int i = 0; i < 2; ++i) {
+            const lb_prim* q = i == 0 ? L : R;
             const double uu = dim == 2 ? sqrt(q->u * q->u + q->v * q->v) : fabs(q->u);
-            const double c = uu + sqrt(gamma * q->p / q->rho);
+            const double c = uu + sqrt(gs[i] * q->p / q->rho);
             smax = c > smax ? c : smax;
         }
         if (!(smax > 0.0)) return fail(LB_ESTATE, "both states have zero signal speed; set lambda");
@@ -118,7 +120,7 @@ int riemann_sides(int dim, double gamma, double lam_set, double cfl, const lb_pr
     const double lam2 = lam * lam;
     for (int i = 0; i < 2; ++i) {
         const double rho = P[i]->rho, u = P[i]->u, v = dim == 2 ? P[i]->v : 0.0, p = P[i]->p;
-        const double rE = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v);
+        const double rE = p / (gs[i] - 1.0) + 0.5 * rho * (u * u + v * v);
         side[i][0] = rho;
         side[i][1] = (rho * u) * lam;
         if (dim == 2) {
@@ -126,7 +128,7 @@ int riemann_sides(int dim, double gamma, double lam_set, double cfl, const lb_pr
             side[i][3] = rE * lam2;
         } else {
             side[i][2] = rE * lam2;
-            side[i][3] = 0.0;
+            side[i][3] = species && i == 0 ? rho : 0.0;  // gas 1 fills the left side
         }
     }
     *lam_out = lam;
@@ -143,7 +145,7 @@ int check_moments(const double* Y, int nf, int64_t nn)
     return LB_OK;
 }
 
-int upload_moments(void* dst, const double* Y, int nf, int64_t nn, double lambda, bool fp64,
+int upload_moments(void* dst, const double* Y, int nf, int ie, int64_t nn, double lambda, bool fp64,
                    hipStream_t stream)
 {
     const double lam2 = lambda * lambda;
@@ -156,10 +158,10 @@ int upload_moments(void* dst, const double* Y, int nf, int64_t nn, double lambda
         return fail(LB_ENOMEM, "host staging allocation failed");
     }
     for (int f = 0; f < nf; ++f) {
-        const double sc = f == nf - 1 ? lam2 : lambda;
+        const double sc = f == ie ? lam2 : lambda;
         for (int64_t q = 0; q < nn; ++q) {
             const double y = Y[(int64_t)f * nn + q];
-            const double v = f == 0 ? y : y * sc;
+            const double v = (f == 0 || f > ie) ? y : y * sc;
             if (fp64) tmp[(size_t)f * nn + q] = v;
             else tmpf[(size_t)f * nn + q] = (float)v;
         }
@@ -171,12 +173,12 @@ int upload_moments(void* dst, const double* Y, int nf, int64_t nn, double lambda
     return LB_OK;
 }
 
-void field_scales(int nf, double lambda, double sc[4])
+void field_scales(int nf, int ie, double lambda, double sc[4])
 {
     const double lam2 = lambda * lambda;
     for (int f = 0; f < 4; ++f) sc[f] = 1.0;
-    for (int f = 1; f < nf - 1; ++f) sc[f] = lambda;
-    sc[nf - 1] = lam2;
+    for (int f = 1; f < ie && f < nf; ++f) sc[f] = lambda;
+    if (ie < nf) sc[ie] = lam2;
 }
 
 }  // namespace lbsd
@@ -185,7 +187,8 @@ struct lb_solver {
     lb_grid grid;
     Grid g;
     int dim, nf, precision;
-    double gamma;
+    double gamma, gamma2;  // gamma2: gas 2 (two gases), else gamma
+    bool species;          // two gases: a species field rho chi after rho E
     lb_velset vs;
     Consts k;
     int64_t nn;
@@ -215,13 +218,17 @@ extern "C" {
 
 const char* lb_last_error(void) { return g_last_error.c_str(); }
 
-int lb_create(const lb_grid* grid, double gamma, const lb_velset* vs, int32_t precision,
-              lb_solver** out)
+static int create_solver(const lb_grid* grid, double gamma, double gamma2, bool species, const lb_velset* vs,
+                         int32_t precision, lb_solver** out)
 {
     if (!grid || !vs || !out) return fail(LB_EINVAL, "null argument");
     const int dim = grid->dim;
     int rc = check_model(dim, gamma, vs, precision);
     if (rc != LB_OK) return rc;
+    if (species) {
+        if (dim != 1) return fail(LB_EINVAL, "two gases: the 1-D lattice only");
+        if ((rc = check_model(dim, gamma2, vs, precision)) != LB_OK) return rc;
+    }
     if ((rc = check_grid(grid, dim)) != LB_OK) return rc;
 
     lb_solver* s = new (std::nothrow) lb_solver();
@@ -229,11 +236,16 @@ int lb_create(const lb_grid* grid, double gamma, const lb_velset* vs, int32_t pr
     s->grid = *grid;
     s->g = Grid{grid->nx, grid->ny, grid->bc_x, grid->bc_y};
     s->dim = dim;
-    s->nf = dim + 2;
+    s->species = species;
+    s->nf = dim + 2 + (species ? 1 : 0);
     s->precision = precision;
     s->gamma = gamma;
+    s->gamma2 = species ? gamma2 : gamma;
     s->vs = *vs;
     s->k = make_consts(dim, gamma, vs);
+    s->k.g1m1 = gamma - 1.0;
+    s->k.g2m1 = s->gamma2 - 1.0;
+    s->k.species = species ? 1 : 0;
     s->nn = grid->nx * grid->ny;
     s->elem = precision == LB_FP64 ? 8 : 4;
     const size_t field_bytes = align256((size_t)s->nf * (size_t)s->nn * s->elem);
@@ -249,6 +261,18 @@ int lb_create(const lb_grid* grid, double gamma, const lb_velset* vs, int32_t pr
     s->lambda_set = 0.0;
     *out = s;
     return LB_OK;
+}
+
+int lb_create(const lb_grid* grid, double gamma, const lb_velset* vs, int32_t precision,
+              lb_solver** out)
+{
+    return create_solver(grid, gamma, gamma, false, vs, precision, out);
+}
+
+int lb_create_two_gas(const lb_grid* grid, double gamma_1, double gamma_2, const lb_velset* vs,
+                      int32_t precision, lb_solver** out)
+{
+    return create_solver(grid, gamma_1, gamma_2, true, vs, precision, out);
 }
 
 size_t lb_state_bytes(const lb_solver* s) { return s ? s->total : 0; }
@@ -317,7 +341,8 @@ int lb_init_riemann(lb_solver* s, double x_d, const lb_prim* L, const lb_prim* R
     if (!s || !s->bound) return fail(LB_EINVAL, "solver not bound");
     if (!isfinite(x_d)) return fail(LB_EINVAL, "diaphragm position must be finite");
     double lam = 0.0, side[2][4];
-    const int rc = riemann_sides(s->dim, s->gamma, s->lambda_set, s->cfl, L, R, &lam, side);
+    const int rc = riemann_sides(s->dim, s->gamma, s->gamma2, s->species, s->lambda_set, s->cfl, L, R, &lam,
+                                 side);
     if (rc != LB_OK) return rc;
     s->lambda = lam;
     const double dx = (s->grid.x_hi - s->grid.x_lo) / (double)s->grid.nx;
@@ -338,7 +363,7 @@ int lb_init_moments(lb_solver* s, const double* Y, double lambda)
     if (!(lambda > 0.0) || !isfinite(lambda)) return fail(LB_EINVAL, "lambda must be > 0");
     int rc = check_moments(Y, s->nf, s->nn);
     if (rc != LB_OK) return rc;
-    rc = upload_moments(buf_ptr(s, 0), Y, s->nf, s->nn, lambda, s->precision == LB_FP64, s->stream);
+    rc = upload_moments(buf_ptr(s, 0), Y, s->nf, s->dim + 1, s->nn, lambda, s->precision == LB_FP64, s->stream);
     if (rc != LB_OK) return rc;
     s->lambda = lambda;
     return start_state(s);
@@ -474,7 +499,7 @@ int lb_moments(lb_solver* s, double* out, int32_t on_device)
     if (rc != LB_OK && rc != LB_EREACH && rc != LB_ESTATE) return rc;
     // After a failed step the state is the last good one; exporting it is allowed.
     double sc[4];
-    field_scales(s->nf, s->lambda, sc);
+    field_scales(s->nf, s->dim + 1, s->lambda, sc);
     double* dst = on_device ? out : export_ptr(s);
     hipError_t e = s->precision == LB_FP64
         ? launch_export<double>((const double*)buf_ptr(s, s->cur), dst, s->nn, s->nf, sc, s->stream)
@@ -489,18 +514,17 @@ int lb_moments(lb_solver* s, double* out, int32_t on_device)
     return LB_OK;
 }
 
-int lb_totals(lb_solver* s, double out[4])
+// Interior sums of the device fields (lattice units) of the latest state:
+// the step's own totals, or (no step since init) a host sum of the state.
+static int field_totals(lb_solver* s, double t[4])
 {
-    if (!s || !out) return fail(LB_EINVAL, "null argument");
     if (!s->initialized) return fail(LB_EINVAL, "solver not initialised");
     int rc = lb_sync(s);
     if (rc != LB_OK) return rc;
     StepCtl c;
     hipError_t e = hipMemcpy(&c, ctl_ptr(s), sizeof c, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "read control block");
-    double sc[4];
-    field_scales(s->nf, s->lambda, sc);
-    double t[4] = {0, 0, 0, 0};
+    for (int f = 0; f < 4; ++f) t[f] = 0.0;
     if (c.totals_step == (long long)s->steps_done && s->steps_done > 0) {
         for (int f = 0; f < 4; ++f) t[f] = c.totals[f];
     } else {
@@ -521,7 +545,18 @@ int lb_totals(lb_solver* s, double out[4])
             t[f] = a;
         }
     }
-    // field order on the device: rho, rho u, (rho v), rho E -> out[0..3]
+    return LB_OK;
+}
+
+int lb_totals(lb_solver* s, double out[4])
+{
+    if (!s || !out) return fail(LB_EINVAL, "null argument");
+    double t[4];
+    const int rc = field_totals(s, t);
+    if (rc != LB_OK) return rc;
+    double sc[4];
+    field_scales(s->nf, s->dim + 1, s->lambda, sc);
+    // field order on the device: rho, rho u, (rho v), rho E (, rho chi) -> out[0..3]
     double o[4] = {0, 0, 0, 0};
     o[0] = t[0] / sc[0];
     o[1] = t[1] / sc[1];
@@ -532,6 +567,17 @@ int lb_totals(lb_solver* s, double out[4])
         o[3] = t[2] / sc[2];
     }
     for (int f = 0; f < 4; ++f) out[f] = o[f];
+    return LB_OK;
+}
+
+int lb_species_total(lb_solver* s, double* out)
+{
+    if (!s || !out) return fail(LB_EINVAL, "null argument");
+    if (!s->species) return fail(LB_EINVAL, "the solver has one gas");
+    double t[4];
+    const int rc = field_totals(s, t);
+    if (rc != LB_OK) return rc;
+    *out = t[s->nf - 1];  // rho chi needs no unit conversion
     return LB_OK;
 }
 

@@ -33,12 +33,16 @@ struct Consts {
     double b0;        // rest-lane multiplicity b_0 (1 with a rest level, else 0)
     double inv_b1;    // 1 / b_1
     double rest_q;    // square lattice with a rest level: d_0 / (d_1 + d_2) = b_1 delta0 / (1 - delta0)
+    double g1m1;      // two gases: gamma_1 - 1 (gas 1, the species field's gas)
+    double g2m1;      // two gases: gamma_2 - 1
+    int species;      // 1: two gases, a species moment rho chi after rho E (1-D)
 };
 
 template <typename T>
 struct Src1 {   // one source node of the 1-D lattice
     int f, c1;
     T r, d0, d1, d2, K;
+    T chi;      // two gases: mass fraction of gas 1 (what each packet carries per unit mass)
     bool bad;   // rho <= 0 or a non-finite moment
 };
 
@@ -114,17 +118,32 @@ __device__ __forceinline__ double level_w(double A, int c1)
 // storage type T: in FP32 storage the per-node energy bookkeeping (E -> e, A,
 // the d_1 / d_2 split near a switch of c'_1) is where FP32 arithmetic would
 // lose the most, and FP64 costs the same VALU issue rate on this chip.  The
-// staged results are rounded to T.
-template <typename T>
-__device__ __forceinline__ Src1<T> make_src1(T m0t, T m1t, T m2t, const Consts& k)
+// staged results are rounded to T.  SP: two gases; m3t is the species moment
+// rho chi, and the node's gas is the mixture of the two by mass fraction
+// (c_v weighted, one gas constant): gamma - 1 = 1 / (chi / (gamma_1 - 1) +
+// (1 - chi) / (gamma_2 - 1)), which sets phi (eq. 15) and A (eq. 26).
+template <typename T, bool SP = false>
+__device__ __forceinline__ Src1<T> make_src1(T m0t, T m1t, T m2t, const Consts& kc, T m3t = (T)0)
 {
     const double m0 = m0t, m1 = m1t, m2 = m2t;
     Src1<T> s;
-    s.bad = !(m0 > 0.0) || !finite_val(m0) || !finite_val(m1) || !finite_val(m2);
+    s.bad = !(m0 > 0.0) || !finite_val(m0) || !finite_val(m1) || !finite_val(m2) ||
+            (SP && !finite_val((double)m3t));
+    s.chi = (T)0;
     if (s.bad) {
         s.f = 0; s.c1 = 0;
         s.r = (T)0; s.d0 = (T)0; s.d1 = (T)0; s.d2 = (T)0; s.K = (T)0;
         return s;
+    }
+    Consts k = kc;
+    if constexpr (SP) {
+#pragma clang fp contract(off)
+        double chi = (double)m3t / m0;
+        chi = chi < 0.0 ? 0.0 : (chi > 1.0 ? 1.0 : chi);
+        const double gm1 = 1.0 / (chi / k.g1m1 + (1.0 - chi) / k.g2m1);
+        k.Dg1 = 1.0 * gm1;
+        k.phi_coef = 1.0 - 0.5 * gm1;
+        s.chi = (T)chi;
     }
     double v, E, v2, d0;
     {

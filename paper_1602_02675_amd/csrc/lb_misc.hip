@@ -41,7 +41,9 @@ __global__ void lanes_kernel(const T* __restrict__ Y, int64_t nn, int dim, Const
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nn) return;
     if (dim == 1) {
-        const Src1<T> s = make_src1<T>(Y[q], Y[nn + q], Y[2 * nn + q], k);
+        // the same device function the step uses (one gas, or the mixture of two)
+        const Src1<T> s = k.species ? make_src1<T, true>(Y[q], Y[nn + q], Y[2 * nn + q], k, Y[3 * nn + q])
+                                    : make_src1<T, false>(Y[q], Y[nn + q], Y[2 * nn + q], k);
         fx[q] = s.f;
         fy[q] = 0;
         c1[q] = s.c1;

@@ -493,7 +493,7 @@ int lb_pool_admit_riemann(lb_pool* p, const lb_grid* grid, double lambda, double
     if (!isfinite(x_d)) return fail(LB_EINVAL, "diaphragm position must be finite");
     if (!p) return fail(LB_EINVAL, "null pool");
     double lam = 0.0, side[2][4];
-    int rc = riemann_sides(p->dim, p->gamma, lambda, 1.0, L, R, &lam, side);
+    int rc = riemann_sides(p->dim, p->gamma, p->gamma, false, lambda, 1.0, L, R, &lam, side);
     if (rc != LB_OK) return rc;
     int32_t s = -1;
     if ((rc = reserve(p, grid, steps, &s)) != LB_OK) return rc;
@@ -527,7 +527,8 @@ int lb_pool_admit_moments(lb_pool* p, const lb_grid* grid, const double* host_Y,
     if ((rc = check_moments(host_Y, p->nf, grid->nx * grid->ny)) != LB_OK) return rc;
     int32_t s = -1;
     if ((rc = reserve(p, grid, steps, &s)) != LB_OK) return rc;
-    rc = upload_moments(set_ptr(p, s, 0), host_Y, p->nf, grid->nx * grid->ny, lambda, p->precision == LB_FP64,
+    rc = upload_moments(set_ptr(p, s, 0), host_Y, p->nf, p->dim + 1, grid->nx * grid->ny, lambda,
+                        p->precision == LB_FP64,
                         p->stream);
     if (rc == LB_OK) {
         p->info[(size_t)s].lambda = lambda;
@@ -626,7 +627,7 @@ int lb_pool_moments(lb_pool* p, int32_t slot, double* out, int32_t on_device)
     const SlotInfo& si = p->info[(size_t)slot];
     const int64_t nn = si.grid.nx * si.grid.ny;
     double sc[4];
-    field_scales(p->nf, si.lambda, sc);
+    field_scales(p->nf, p->dim + 1, si.lambda, sc);
     const void* src = set_ptr(p, slot, (int)(st.done & 1));
     hipError_t e;
     if (on_device) {
@@ -666,7 +667,7 @@ int lb_pool_totals(lb_pool* p, int32_t slot, double out[4])
     if ((rc = read_state(p, slot, &st)) != LB_OK) return rc;
     if (st.done == 0 || st.totals_step != st.done) return fail(LB_EINVAL, "no completed step to report");
     double sc[4];
-    field_scales(p->nf, p->info[(size_t)slot].lambda, sc);
+    field_scales(p->nf, p->dim + 1, p->info[(size_t)slot].lambda, sc);
     double o[4] = {0, 0, 0, 0};
     o[0] = st.totals[0] / sc[0];
     o[1] = st.totals[1] / sc[1];

@@ -166,13 +166,15 @@ template <typename T>
 struct Tile1 {
     int* pk;
     T *r, *d0, *d1, *d2, *K;
+    T* chi;  // two gases: mass fraction of gas 1 per source
 };
 
 // One packet of a 1-D source s at displacement k + c' from its floor node:
-// mass alpha_k d, momentum m (v + c'), energy m (K + c' v + c'^2/2).
-template <typename T>
+// mass alpha_k d, momentum m (v + c'), energy m (K + c' v + c'^2/2); with two
+// gases (SP) also the species moment m chi.
+template <typename T, bool SP>
 __device__ __forceinline__ void add_packet1(const Tile1<T>& tl, int s, int f, int k, int lane_c,
-                                            int lev, T& R, T& P, T& En)
+                                            int lev, T& R, T& P, T& En, T& X)
 {
     const T r = tl.r[s];
     const T a = k ? r : (T)1 - r;
@@ -185,28 +187,29 @@ __device__ __forceinline__ void add_packet1(const Tile1<T>& tl, int s, int f, in
     R += m;
     P += m * xi;
     En += m * zeta;
+    if constexpr (SP) X += m * tl.chi[s];
 }
 
 // Lane l of the 1-D set: 0 rest (d0), 1/2 +-c1 (d1), 3/4 +-c2 (d2).
 __device__ __forceinline__ constexpr int lane_level1(int l) { return l == 0 ? 0 : (l <= 2 ? 1 : 2); }
 __device__ __forceinline__ constexpr int lane_sign1(int l) { return l == 0 ? 0 : ((l & 1) ? 1 : -1); }
 
-template <typename T, int H, int TPB, int J, int C1>
+template <typename T, int H, int TPB, int J, int C1, bool SP, int NF>
 __device__ __forceinline__ void gather1_uniform(const Tile1<T>& tl, int f, int64_t x0, int64_t nx,
-                                                T* __restrict__ Yn, double (&acc)[3])
+                                                T* __restrict__ Yn, double (&acc)[NF])
 {
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int t = j * TPB + (int)threadIdx.x;
         const int base = t + H - f;  // source of displacement f + o is base - o
-        T R = 0, P = 0, En = 0;
+        T R = 0, P = 0, En = 0, X = 0;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
 #pragma unroll
             for (int l = 0; l < 5; ++l) {
                 const int lev = lane_level1(l);
                 const int c = lane_sign1(l) * (lev == 0 ? 0 : C1 + lev - 1);
-                add_packet1<T>(tl, base - (k + c), f, k, c, lev, R, P, En);
+                add_packet1<T, SP>(tl, base - (k + c), f, k, c, lev, R, P, En, X);
             }
         }
         const int64_t x = x0 + t;
@@ -217,17 +220,21 @@ __device__ __forceinline__ void gather1_uniform(const Tile1<T>& tl, int f, int64
             acc[0] += (double)R;
             acc[1] += (double)P;
             acc[2] += (double)En;
+            if constexpr (SP) {
+                Yn[3 * nx + x] = X;
+                acc[3] += (double)X;
+            }
         }
     }
 }
 
-template <typename T, int H, int TPB, int J>
+template <typename T, int H, int TPB, int J, bool SP, int NF>
 __device__ void gather1_general(const Tile1<T>& tl, const TileInfo& ti, int64_t x0, int64_t nx,
-                                T* __restrict__ Yn, double (&acc)[3])
+                                T* __restrict__ Yn, double (&acc)[NF])
 {
     for (int j = 0; j < J; ++j) {
         const int t = j * TPB + (int)threadIdx.x;
-        T R = 0, P = 0, En = 0;
+        T R = 0, P = 0, En = 0, X = 0;
         for (int k = 0; k < 2; ++k) {
             for (int l = 0; l < 5; ++l) {
                 const int lev = lane_level1(l), sg = lane_sign1(l);
@@ -244,7 +251,7 @@ __device__ void gather1_general(const Tile1<T>& tl, const TileInfo& ti, int64_t 
                     const int fs = lane_fx(p);
                     const int cs = lev == 0 ? 0 : sg * (lane_c1(p) + lev - 1);
                     if (fs + k + cs != dl) continue;
-                    add_packet1<T>(tl, s, fs, k, cs, lev, R, P, En);
+                    add_packet1<T, SP>(tl, s, fs, k, cs, lev, R, P, En, X);
                 }
             }
         }
@@ -256,6 +263,10 @@ __device__ void gather1_general(const Tile1<T>& tl, const TileInfo& ti, int64_t 
             acc[0] += (double)R;
             acc[1] += (double)P;
             acc[2] += (double)En;
+            if constexpr (SP) {
+                Yn[3 * nx + x] = X;
+                acc[3] += (double)X;
+            }
         }
     }
 }
@@ -267,20 +278,22 @@ __device__ void gather1_general(const Tile1<T>& tl, const TileInfo& ti, int64_t 
 // summary.  Splitting them lets a persistent block load its next tile while
 // it gathers the current one.  tile1d_gather contains block-wide barriers:
 // every thread of the block must call it.  WALLS instances also handle
-// reflecting walls (the others keep no per-source mirror state).
-template <typename T, int H, int TPB, int J, bool WALLS>
+// reflecting walls (the others keep no per-source mirror state); SP instances
+// carry the species moment of two gases as a fourth field.
+template <typename T, int H, int TPB, int J, bool WALLS, bool SP>
 struct Tile1Src {
     static constexpr int W = TPB * J + 2 * H;
     static constexpr int NS = (W + TPB - 1) / TPB;
-    T ld[NS][3];
+    static constexpr int NF = SP ? 4 : 3;
+    T ld[NS][NF];
     bool mir[WALLS ? NS : 1];  // mirror image beyond a reflecting wall: momentum negated when used
 };
 
-template <typename T, int H, int TPB, int J, bool WALLS>
+template <typename T, int H, int TPB, int J, bool WALLS, bool SP>
 __device__ __forceinline__ void tile1d_load(const T* __restrict__ Y, int64_t nx, int bc, int64_t x0,
-                                            Tile1Src<T, H, TPB, J, WALLS>& src)
+                                            Tile1Src<T, H, TPB, J, WALLS, SP>& src)
 {
-    using S = Tile1Src<T, H, TPB, J, WALLS>;
+    using S = Tile1Src<T, H, TPB, J, WALLS, SP>;
 #pragma unroll
     for (int u = 0; u < S::NS; ++u) {
         const int i = (int)threadIdx.x + u * TPB;
@@ -292,19 +305,23 @@ __device__ __forceinline__ void tile1d_load(const T* __restrict__ Y, int64_t nx,
             src.ld[u][0] = Y[si];
             src.ld[u][1] = Y[nx + si];
             src.ld[u][2] = Y[2 * nx + si];
+            if constexpr (SP) src.ld[u][3] = Y[3 * nx + si];
         }
     }
 }
 
-template <typename T, int H, int TPB, int J, bool WALLS>
-__device__ __forceinline__ TileInfo tile1d_gather(const Tile1Src<T, H, TPB, J, WALLS>& src, T* __restrict__ Yn,
-                                                  int64_t nx, int64_t x0, const Consts& k, double (&acc)[3])
+template <typename T, int H, int TPB, int J, bool WALLS, bool SP>
+__device__ __forceinline__ TileInfo tile1d_gather(const Tile1Src<T, H, TPB, J, WALLS, SP>& src, T* __restrict__ Yn,
+                                                  int64_t nx, int64_t x0, const Consts& k,
+                                                  double (&acc)[Tile1Src<T, H, TPB, J, WALLS, SP>::NF])
 {
-    using S = Tile1Src<T, H, TPB, J, WALLS>;
+    using S = Tile1Src<T, H, TPB, J, WALLS, SP>;
+    constexpr int NF = S::NF;
     constexpr int W = S::W;
     constexpr int NW = TPB / 64;
     __shared__ int s_pk[W];
     __shared__ T s_r[W], s_d0[W], s_d1[W], s_d2[W], s_K[W];
+    __shared__ T s_chi[SP ? W : 1];
     __shared__ int s_red[NW][8];
 
     TileInfo ti = {INT_MAX, INT_MIN, 0, 0, INT_MAX, INT_MIN, 0, 0};
@@ -316,7 +333,10 @@ __device__ __forceinline__ TileInfo tile1d_gather(const Tile1Src<T, H, TPB, J, W
         // arrived, so that loads issued ahead of time are not waited for)
         T mom = src.ld[u][1];
         if constexpr (WALLS) mom = src.mir[u] ? -mom : mom;
-        const Src1<T> s = make_src1<T>(src.ld[u][0], mom, src.ld[u][2], k);
+        Src1<T> s;
+        if constexpr (SP) s = make_src1<T, true>(src.ld[u][0], mom, src.ld[u][2], k, src.ld[u][3]);
+        else s = make_src1<T, false>(src.ld[u][0], mom, src.ld[u][2], k);
+        if constexpr (SP) s_chi[i] = s.chi;
         s_pk[i] = pack_lane(s.f, 0, s.c1);
         s_r[i] = s.r;
         s_d0[i] = s.d0;
@@ -331,33 +351,34 @@ __device__ __forceinline__ TileInfo tile1d_gather(const Tile1Src<T, H, TPB, J, W
         ti.bad |= s.bad ? 1 : 0;
     }
     ti = block_tile_info<NW>(ti, s_red);  // contains the barrier after staging
-    const Tile1<T> tl = {s_pk, s_r, s_d0, s_d1, s_d2, s_K};
+    const Tile1<T> tl = {s_pk, s_r, s_d0, s_d1, s_d2, s_K, s_chi};
     const bool uniform = ti.fxmin == ti.fxmax && ti.cmin == ti.cmax && ti.reach <= H;
     if (uniform && ti.cmin == 0)
-        gather1_uniform<T, H, TPB, J, 0>(tl, ti.fxmin, x0, nx, Yn, acc);
+        gather1_uniform<T, H, TPB, J, 0, SP, NF>(tl, ti.fxmin, x0, nx, Yn, acc);
     else if (uniform && ti.cmin == 1)
-        gather1_uniform<T, H, TPB, J, 1>(tl, ti.fxmin, x0, nx, Yn, acc);
+        gather1_uniform<T, H, TPB, J, 1, SP, NF>(tl, ti.fxmin, x0, nx, Yn, acc);
     else if (uniform && ti.cmin == 2)
-        gather1_uniform<T, H, TPB, J, 2>(tl, ti.fxmin, x0, nx, Yn, acc);
+        gather1_uniform<T, H, TPB, J, 2, SP, NF>(tl, ti.fxmin, x0, nx, Yn, acc);
     else if (uniform && ti.cmin == 3)
-        gather1_uniform<T, H, TPB, J, 3>(tl, ti.fxmin, x0, nx, Yn, acc);
+        gather1_uniform<T, H, TPB, J, 3, SP, NF>(tl, ti.fxmin, x0, nx, Yn, acc);
     else
-        gather1_general<T, H, TPB, J>(tl, ti, x0, nx, Yn, acc);
+        gather1_general<T, H, TPB, J, SP, NF>(tl, ti, x0, nx, Yn, acc);
     return ti;
 }
 
-template <typename T, int H, int TPB, int J, bool WALLS>
+template <typename T, int H, int TPB, int J, bool WALLS, bool SP>
 __global__ void __launch_bounds__(TPB)
 step1d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
               StepCtl* __restrict__ ctl, double* __restrict__ partials, long long step)
 {
     if (ctl->err_step < step) return;  // an earlier step failed: keep its input intact
     const int64_t x0 = (int64_t)blockIdx.x * (TPB * J);
-    Tile1Src<T, H, TPB, J, WALLS> src;
-    tile1d_load<T, H, TPB, J, WALLS>(Y, g.nx, g.bc_x, x0, src);
-    double acc[3] = {0.0, 0.0, 0.0};
-    const TileInfo ti = tile1d_gather<T, H, TPB, J, WALLS>(src, Yn, g.nx, x0, k, acc);
-    finish_step<TPB / 64, 3>(acc, ti, partials + (int64_t)blockIdx.x * kPartialStride, H);
+    using S = Tile1Src<T, H, TPB, J, WALLS, SP>;
+    S src;
+    tile1d_load<T, H, TPB, J, WALLS, SP>(Y, g.nx, g.bc_x, x0, src);
+    double acc[S::NF] = {};
+    const TileInfo ti = tile1d_gather<T, H, TPB, J, WALLS, SP>(src, Yn, g.nx, x0, k, acc);
+    finish_step<TPB / 64, S::NF>(acc, ti, partials + (int64_t)blockIdx.x * kPartialStride, H);
 }
 
 // Pool form: one block per tile of the tile table (1-D tiles cost about the
@@ -376,10 +397,10 @@ __global__ void __launch_bounds__(TPB) pool1d_kernel(PoolView v, Consts k)
     const int64_t o0 = tl.off[0], o1 = tl.off[1];  // selected below, not indexed (keeps them in registers)
     const int64_t from = (ts & kTileSet) ? o1 : o0, to = (ts & kTileSet) ? o0 : o1;
     const int64_t nx = tl.nx, x0 = tl.x0;
-    Tile1Src<T, kHalo, TPB, J, WALLS> src;
-    tile1d_load<T, kHalo, TPB, J, WALLS>(arena + from, nx, tl.bc_x, x0, src);
+    Tile1Src<T, kHalo, TPB, J, WALLS, false> src;
+    tile1d_load<T, kHalo, TPB, J, WALLS, false>(arena + from, nx, tl.bc_x, x0, src);
     double acc[3] = {0.0, 0.0, 0.0};
-    const TileInfo ti = tile1d_gather<T, kHalo, TPB, J, WALLS>(src, arena + to, nx, x0, k, acc);
+    const TileInfo ti = tile1d_gather<T, kHalo, TPB, J, WALLS, false>(src, arena + to, nx, x0, k, acc);
     finish_step<TPB / 64, 3>(acc, ti, v.partials + (int64_t)t * kPartialStride, kHalo);
 }
 
@@ -466,10 +487,17 @@ hipError_t launch_step1d(const T* Y, T* Yn, const Grid& g, const Consts& k, Step
                          double* partials, long long step, hipStream_t stream)
 {
     const dim3 grid((unsigned)step_blocks_1d(g));
-    if (g.bc_x == kBcReflecting)
-        step1d_kernel<T, kHalo, k1TPB, k1J, true><<<grid, k1TPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step);
-    else
-        step1d_kernel<T, kHalo, k1TPB, k1J, false><<<grid, k1TPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step);
+    const bool walls = g.bc_x == kBcReflecting;
+    if (k.species) {
+        if (walls)
+            step1d_kernel<T, kHalo, k1TPB, k1J, true, true><<<grid, k1TPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step);
+        else
+            step1d_kernel<T, kHalo, k1TPB, k1J, false, true><<<grid, k1TPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step);
+    } else if (walls) {
+        step1d_kernel<T, kHalo, k1TPB, k1J, true, false><<<grid, k1TPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step);
+    } else {
+        step1d_kernel<T, kHalo, k1TPB, k1J, false, false><<<grid, k1TPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, step);
+    }
     return hipGetLastError();
 }
 

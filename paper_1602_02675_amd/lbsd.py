@@ -30,7 +30,8 @@ LB_POOL_FREE = -100
 _ERR_NAMES = {LB_EINVAL: "LB_EINVAL", LB_ENOMEM: "LB_ENOMEM", LB_EDEVICE: "LB_EDEVICE",
               LB_ESTATE: "LB_ESTATE", LB_EREACH: "LB_EREACH"}
 
-EXPORTED = ["lb_create", "lb_state_bytes", "lb_bind", "lb_set_lambda", "lb_set_cfl",
+EXPORTED = ["lb_create", "lb_create_two_gas", "lb_species_total", "lb_state_bytes", "lb_bind", "lb_set_lambda",
+            "lb_set_cfl",
             "lb_init_riemann", "lb_init_moments", "lb_step", "lb_step_timed", "lb_step_profiled", "lb_sync",
             "lb_moments", "lb_totals", "lb_lambda", "lb_dt", "lb_steps_done", "lb_max_reach",
             "lb_debug_lanes", "lb_destroy", "lb_last_error",
@@ -71,6 +72,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     sig = {
         "lb_create": (ctypes.c_int, [ctypes.POINTER(lb_grid), dbl, ctypes.POINTER(lb_velset), i32,
                                      ctypes.POINTER(vp)]),
+        "lb_create_two_gas": (ctypes.c_int, [ctypes.POINTER(lb_grid), dbl, dbl, ctypes.POINTER(lb_velset),
+                                             i32, ctypes.POINTER(vp)]),
         "lb_state_bytes": (ctypes.c_size_t, [vp]),
         "lb_bind": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
         "lb_set_lambda": (ctypes.c_int, [vp, dbl]),
@@ -84,6 +87,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lb_sync": (ctypes.c_int, [vp]),
         "lb_moments": (ctypes.c_int, [vp, vp, i32]),
         "lb_totals": (ctypes.c_int, [vp, D]),
+        "lb_species_total": (ctypes.c_int, [vp, D]),
         "lb_lambda": (dbl, [vp]),
         "lb_dt": (dbl, [vp]),
         "lb_steps_done": (i64, [vp]),
@@ -150,19 +154,26 @@ class Solver:
 
     def __init__(self, dim: int, nx: int, ny: int = 1, *, gamma: float = 1.4, d0_frac=None,
                  precision: str = "fp64", bc_x="transmissive", bc_y="periodic", x_lo: float = 0.0,
-                 x_hi: float = 1.0, device=None, stream=None):
+                 x_hi: float = 1.0, device=None, stream=None, gamma2=None):
+        """gamma2: a second gas (1-D; lb_create_two_gas): gamma is gas 1's,
+        and the state gains the species field rho chi."""
         import torch
 
         if d0_frac is None:
             d0_frac = 0.5 if dim == 1 else 0.0
         self.dim, self.nx, self.ny = dim, int(nx), int(ny if dim == 2 else 1)
-        self.nf = dim + 2
+        self.species = gamma2 is not None
+        self.nf = dim + 2 + (1 if self.species else 0)
         self.precision = precision
         g = lb_grid(dim, self.nx, self.ny, x_lo, x_hi, _bc(bc_x), _bc(bc_y))
         vs = lb_velset(_lattice(dim, d0_frac), d0_frac)
         prec = {"fp64": LB_FP64, "fp32": LB_FP32}[precision]
         h = ctypes.c_void_p()
-        _check(_lib.lb_create(ctypes.byref(g), gamma, ctypes.byref(vs), prec, ctypes.byref(h)))
+        if self.species:
+            _check(_lib.lb_create_two_gas(ctypes.byref(g), gamma, float(gamma2), ctypes.byref(vs), prec,
+                                          ctypes.byref(h)))
+        else:
+            _check(_lib.lb_create(ctypes.byref(g), gamma, ctypes.byref(vs), prec, ctypes.byref(h)))
         self._h = h
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         nbytes = int(_lib.lb_state_bytes(h))
@@ -242,6 +253,12 @@ class Solver:
         out = np.zeros(4, dtype=np.float64)
         _check(_lib.lb_totals(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
+
+    def species_total(self) -> float:
+        """Two gases: interior sum of rho chi (lb_species_total)."""
+        out = ctypes.c_double(0.0)
+        _check(_lib.lb_species_total(self._h, ctypes.byref(out)))
+        return float(out.value)
 
     def lanes(self):
         n = self.nx * self.ny

@@ -69,6 +69,31 @@ def test_create_validation():
     lbsd._lib.lb_destroy(h)
 
 
+def test_two_gas_create_validation():
+    from paper_1602_02675_amd import lbsd
+
+    def make(dim, g1, g2, nx=100, ny=1, lattice=1, d0=0.5):
+        g = lbsd.lb_grid(dim, nx, ny, 0.0, 1.0, 0, 1)
+        vs = lbsd.lb_velset(lattice, d0)
+        h = ctypes.c_void_p()
+        return lbsd._lib.lb_create_two_gas(ctypes.byref(g), g1, g2, ctypes.byref(vs), 0, ctypes.byref(h)), h
+
+    rc, h = make(1, 1.4, 5.0 / 3.0)
+    assert rc == lbsd.LB_OK
+    # four fields (rho, rho u, rho E, rho chi) in two sets
+    assert lbsd._lib.lb_state_bytes(h) >= 2 * 4 * 100 * 8
+    out = ctypes.c_double()
+    lbsd._lib.lb_destroy(h)
+    for args in ((2, 1.4, 1.4, 8, 8, 2, 0.0), (1, 1.4, 1.0), (1, 1.4, 3.5), (1, 0.9, 1.4)):
+        rc, h = make(*args)
+        assert rc == lbsd.LB_EINVAL, args
+    # one gas: no species total
+    rc, h = _create(lbsd)
+    assert rc == lbsd.LB_OK
+    assert lbsd._lib.lb_species_total(h, ctypes.byref(out)) == lbsd.LB_EINVAL
+    lbsd._lib.lb_destroy(h)
+
+
 def test_calls_on_unbound_solver_fail_cleanly():
     from paper_1602_02675_amd import lbsd
 

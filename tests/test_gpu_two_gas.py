@@ -1,0 +1,129 @@
+"""GPU parity of the two-gas 1-D step (lb_create_two_gas) against the oracle,
+through the C ABI: the species moment rho chi travels with the packets and
+each node's gas is the mixture by mass fraction.  Same bar as the other
+parity tests (FP64 1e-12 normwise, FP32 relative L1 density 1e-5, integer
+decisions bit-exact)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1602_02675_amd import inputs
+
+from parity_helpers import TOL64, normwise_err
+
+pytestmark = pytest.mark.gpu
+
+G1, G2 = 1.4, 5.0 / 3.0
+W = oracle.REFLECTING
+
+
+@pytest.fixture(scope="module")
+def lbsd():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_1602_02675_amd import lbsd as m
+
+    return m
+
+
+def _lam(nx, t_end=0.2):
+    speeds = [abs(u) + np.sqrt(g * p / r) for (r, u, _, p), g in ((inputs.SOD_LEFT, G1), (inputs.SOD_RIGHT, G2))]
+    lam = 1.0 / max(speeds)
+    n = int(np.ceil(t_end * nx / lam))
+    return n, t_end * nx / n
+
+
+def _with_species(Y, chi):
+    return np.concatenate([Y, (Y[0] * chi)[None]], axis=0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("bc", [0, W])
+def test_two_gas_sod(lbsd, prec, bc):
+    """Sod with gamma 7/5 on the left and 5/3 on the right, 1000 nodes; with
+    walls, 600 steps (the shock reflects and crosses the contact)."""
+    nx = 1000
+    n, lam = _lam(nx)
+    if bc == W:
+        n = 600
+    P = oracle.Problem(1, nx, gamma=G1, gamma2=G2, bc_x=bc)
+    Y0 = oracle.riemann_moments(P, inputs.node_x(nx), inputs.SOD_LEFT, inputs.SOD_RIGHT, 0.5)
+    ref, st, _ = oracle.run(P, oracle.to_lattice(P, Y0, lam), n)
+    assert st == 0
+    ref = oracle.from_lattice(P, ref, lam)
+    s = lbsd.Solver(1, nx, gamma=G1, gamma2=G2, precision=prec, bc_x="reflecting" if bc == W else "transmissive")
+    s.init_riemann(0.5, inputs.SOD_LEFT, inputs.SOD_RIGHT, lam=lam)
+    assert s.lam == pytest.approx(lam, rel=1e-15)
+    s.step(n)
+    got = s.moments()
+    assert got.shape == (4, 1, nx)
+    if prec == "fp64":
+        assert normwise_err(got, ref, 1) <= TOL64
+        assert s.species_total() == pytest.approx(oracle.totals(P, ref)[3], rel=1e-13)
+    else:
+        assert np.sum(np.abs(got[0] - ref[0])) / np.sum(np.abs(ref[0])) <= 1e-5
+        assert np.sum(np.abs(got[3] - ref[3])) / np.sum(np.abs(ref[3])) <= 1e-5
+    # chi = (rho chi) / rho stays in [0, 1] up to the storage's rounding
+    chi, eps = got[3] / got[0], (1e-12 if prec == "fp64" else 1e-6)
+    assert np.all(chi >= -eps) and np.all(chi <= 1 + eps)
+    s.close()
+
+
+@pytest.mark.parametrize("nx", [1, 7, 1025, 3001])
+@pytest.mark.parametrize("bc", [0, 1, W])
+def test_random_fields(lbsd, nx, bc):
+    if bc == W and nx < 5:
+        pytest.skip("walls need 5 nodes")
+    for smooth, seed in ((9, 51), (0, 52)):
+        Y = inputs.random_state(seed, 1, nx, vel=(-1.3, 1.3), e=(0.0, 1.5), smooth=smooth if nx > 9 else 0)
+        chi = np.random.default_rng(seed).uniform(0.0, 1.0, size=(1, nx))
+        Y = _with_species(Y, chi)
+        P = oracle.Problem(1, nx, gamma=G1, gamma2=G2, bc_x=bc)
+        ref, st, reach = oracle.run(P, oracle.to_lattice(P, Y, 1.0), 12)
+        assert st == 0 and reach <= 5
+        ref = oracle.from_lattice(P, ref, 1.0)
+        s = lbsd.Solver(1, nx, gamma=G1, gamma2=G2, bc_x=bc)
+        s.init_moments(Y, 1.0)
+        s.step(12)
+        assert normwise_err(s.moments(), ref, 1) <= TOL64, (nx, bc, smooth)
+        s.close()
+
+
+def test_lanes_bit_exact(lbsd):
+    """c'_1 depends on the node's mixture; states built with A = c^2 exactly
+    for the mixture at chi = 1/2 (gamma - 1 = 1/2)."""
+    nx = 3000
+    rng = np.random.default_rng(53)
+    Y = _with_species(inputs.random_state(54, 1, nx, vel=(-2.0, 2.0), e=(0.0, 3.0)),
+                      rng.uniform(0.0, 1.0, size=(1, nx)))
+    pick = rng.random(nx) < 0.3
+    c = rng.integers(0, 3, size=nx).astype(float)
+    v = np.round(rng.uniform(-2, 2, size=nx))
+    rho = Y[0, 0]
+    e = c * c * 0.5 / 0.5  # A = (gamma - 1) e / (1 - delta0) with gamma - 1 = 1/2, delta0 = 1/2
+    Y[1, 0] = np.where(pick, rho * v, Y[1, 0])
+    Y[2, 0] = np.where(pick, rho * (e + 0.5 * v * v), Y[2, 0])
+    Y[3, 0] = np.where(pick, 0.5 * rho, Y[3, 0])
+    P = oracle.Problem(1, nx, gamma=G1, gamma2=G2)
+    s = lbsd.Solver(1, nx, gamma=G1, gamma2=G2)
+    s.init_moments(Y, 1.0)
+    fx, fy, c1 = s.lanes()
+    ofx, ofy, oc1 = oracle.lanes(P, Y)
+    assert np.array_equal(fx.ravel(), ofx.ravel()) and np.array_equal(c1.ravel(), oc1.ravel())
+    s.close()
+
+
+def test_equal_gases_match_one_gas(lbsd):
+    nx = 2049
+    Y = inputs.random_state(55, 1, nx, vel=(-1.2, 1.2), e=(0.1, 2.0), smooth=5)
+    one = lbsd.Solver(1, nx, bc_x="periodic")
+    one.init_moments(Y, 1.0)
+    one.step(30)
+    two = lbsd.Solver(1, nx, gamma2=1.4, bc_x="periodic")
+    two.init_moments(_with_species(Y, np.where(np.arange(nx) < nx // 2, 1.0, 0.0)[None]), 1.0)
+    two.step(30)
+    a, b = one.moments(), two.moments()
+    assert normwise_err(b[:3], a, 1) <= 1e-13
+    one.close()
+    two.close()
