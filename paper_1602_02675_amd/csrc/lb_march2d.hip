@@ -205,6 +205,42 @@ __device__ __forceinline__ void add_ylanes(Fifo<A, L>& f, int op, int om, const 
     }
 }
 
+// The rest-group packets (square set with a rest level) of NQ x-corner
+// sources (masses m[q], energy K[q]) into slot o; summed over the corners
+// first, in order, like add_ylanes.
+template <typename A, typename T, int L, int NQ, bool NOVY>
+__device__ __forceinline__ void add_rest(Fifo<A, L>& f, int o, const T (&m)[NQ], const T (&vx)[NQ],
+                                         const T (&vy)[NQ], const T (&K)[NQ])
+{
+#pragma clang fp contract(off)
+    T msum = m[0], pr = m[0] * vx[0], py = m[0] * vy[0], pe = m[0] * K[0];
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+        msum += m[q];
+        pr = fmaT(m[q], vx[q], pr);
+        py = fmaT(m[q], vy[q], py);
+        pe = fmaT(m[q], K[q], pe);
+    }
+    f.a[o][kR] += (A)msum;
+    f.a[o][kPx] += (A)pr;
+    if (!NOVY) f.a[o][kPyv] += (A)py;
+    f.a[o][kE] += (A)pe;
+}
+
+// Rest-group mass at x corner kc of the source in column s: d_0 = rq (d_1 +
+// d_2) of the staged level masses; and its energy per unit mass, K.
+template <typename T>
+__device__ __forceinline__ T rest_mass(const MRow<T>& R, int kc, int s, T rq)
+{
+    return rq * (R.m[0][kc][s] + R.m[1][kc][s]);
+}
+template <typename T>
+__device__ __forceinline__ T rest_k(const MRow<T>& R, int s)
+{
+    const int c1 = mc1(R.pk[s]);
+    return R.kk[0][s] - (T)0.5 * (T)(c1 * c1);
+}
+
 // Window where every source has floor(v_y) = FY, floor(v_x) in {fx - NKX + 2,
 // fx} and c'_1 in {S0, S0 + NSP - 2}: the lanes of the window have speeds
 // S0 .. S0 + NSP - 1, four per speed (+-x, +-y), and a source puts its level-1
@@ -214,9 +250,11 @@ __device__ __forceinline__ void add_ylanes(Fifo<A, L>& f, int op, int om, const 
 // offset and FIFO slot.  NSP = 2, NKX = 2 is the uniform window.
 // RY0: every source has r_y = 0, so the corners k_y = 1 carry no mass (eq. 29)
 // and are skipped; with FY = 0 also v_y = 0 and the m v_y terms vanish.  The
-// sums are the same, term for term.
-template <typename T, int L, int FY, int S0, int NSP, int NKX, bool RY0>
-__device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, Fifo<Acc<T>, L>& f)
+// sums are the same, term for term.  REST: the rest group's packets (from the
+// sources at x displacement floor(v_x) + k_x, into row FY + k_y) follow the
+// lanes.
+template <typename T, int L, int FY, int S0, int NSP, int NKX, bool RY0, bool REST>
+__device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, Fifo<Acc<T>, L>& f, T rq)
 {
 #pragma clang fp contract(off)
     constexpr bool UNI = NSP == 2;
@@ -282,6 +320,27 @@ __device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, 
             add_ylanes<Acc<T>, T, L, NKX, NOVY>(f, FY + ky + c + L, FY + ky - c + L, m, vx, vy, kk, cc);
         }
     }
+    if constexpr (REST) {  // rest group: source columns base - kx, row FY + ky
+        T b[NKX], ry[NKX], vx[NKX], vy[NKX], kr[NKX];
+#pragma unroll
+        for (int q = 0; q < NKX; ++q) {
+            const int kx = K0 + q, sq = base - kx;
+            const int kc = NKX == 2 ? kx : kx + fx - mfx(R.pk[sq]);  // the source's own corner
+            const T v = rest_mass(R, kc < 0 ? 0 : (kc > 1 ? 1 : kc), sq, rq);
+            b[q] = (kc >= 0 && kc <= 1) ? v : (T)0;
+            ry[q] = R.ry[sq];
+            vx[q] = R.vx[sq];
+            vy[q] = (T)FY + ry[q];
+            kr[q] = rest_k(R, sq);
+        }
+#pragma unroll
+        for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
+            T m[NKX];
+#pragma unroll
+            for (int q = 0; q < NKX; ++q) m[q] = RY0 ? b[q] : b[q] * (ky ? ry[q] : (T)1 - ry[q]);
+            add_rest<Acc<T>, T, L, NKX, NOVY>(f, FY + ky + L, m, vx, vy, kr);
+        }
+    }
 }
 
 // Rows where every source seen by this wavefront has floor(v_y) = FY: the
@@ -292,10 +351,11 @@ __device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, 
 // sources at x displacement k_x + F -+ C, and counts when that source has this
 // F and speed C on this level (zero mass otherwise).  With chk (uniform), a
 // source counts only if its floor(v_y) is FY as well: two such calls, for FY
-// and FY + 1, take a window whose floor(v_y) has two adjacent values.
-template <typename T, int L, int FY>
+// and FY + 1, take a window whose floor(v_y) has two adjacent values.  REST:
+// the rest group's packets follow the lanes, in the fast path's order.
+template <typename T, int L, int FY, bool REST>
 __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, int fxlo, int fxhi,
-                                            int clo, int chi, bool chk)
+                                            int clo, int chi, bool chk, T rq)
 {
 #pragma clang fp contract(off)
     const int nfx = fxhi - fxlo;
@@ -350,6 +410,25 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc
                     const T m[2] = {w0 * (ky ? ry[0] : (T)1 - ry[0]), w1 * (ky ? ry[1] : (T)1 - ry[1])};
                     add_ylanes<Acc<T>, T, L, 2, false>(f, FY + ky + C + L, FY + ky - C + L, m, vx, vy, kk, cc);
                 }
+            }
+        }
+    }
+    if constexpr (REST) {  // rest group: corners k_x = 0, 1 of floor(v_x) = F at F and F + 1
+        for (int i = 0; i <= nfx; ++i) {
+            const int F = fxlo + i;
+            const int s0 = lane - F, s1 = lane - F - 1;
+            const int pk0 = R.pk[s0], pk1 = R.pk[s1];
+            const bool ok0 = mfx(pk0) == F && (!chk || mfy(pk0) == FY);
+            const bool ok1 = mfx(pk1) == F && (!chk || mfy(pk1) == FY);
+            const T ry[2] = {R.ry[s0], R.ry[s1]};
+            const T b0 = ok0 ? rest_mass(R, 0, s0, rq) : (T)0, b1 = ok1 ? rest_mass(R, 1, s1, rq) : (T)0;
+            const T vx[2] = {R.vx[s0], R.vx[s1]};
+            const T vy[2] = {(T)FY + ry[0], (T)FY + ry[1]};
+            const T kr[2] = {rest_k(R, s0), rest_k(R, s1)};
+#pragma unroll
+            for (int ky = 0; ky < 2; ++ky) {
+                const T m[2] = {b0 * (ky ? ry[0] : (T)1 - ry[0]), b1 * (ky ? ry[1] : (T)1 - ry[1])};
+                add_rest<Acc<T>, T, L, 2, false>(f, FY + ky + L, m, vx, vy, kr);
             }
         }
     }
@@ -458,6 +537,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
     __shared__ MRow<T> s_row[2][RB];
     __shared__ WaveInfo s_w[2][RB][kMNW];
     const int tid = threadIdx.x, lane64 = tid & 63, wid = tid >> 6;
+    const T rq = REST ? (T)k.rest_q : (T)0;  // rest-group mass per unit of staged level mass
     const int64_t nx = g.nx, ny = g.ny, nn = nx * ny;
     const int64_t gx = X0 - kMH + tid;                           // this thread's source column
     bool mir_x = false;
@@ -558,18 +638,13 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
             const bool rows_ok = planar && fits_y;
             // the short pass takes planar windows within its FIFO; a tile with
             // any other window is flagged for the full pass
-            if (!((planar || REST) && fits_small)) yfar = 1;
+            if (!(planar && fits_small)) yfar = 1;
             // full pass, floor(v_y) in {-1, 0} (where v_y changes sign): the row
             // path once per value (other pairs of values take the general path:
             // their instances made the compiler spill the FIFO on every path)
             const bool ymix_ok = fits_x && fits_y && w.fymin == -1 && w.fymax == 0 && w.c1max <= 3 &&
                                  w.fxmax - w.fxmin <= 2;
-            if constexpr (REST) {  // only the general path adds the rest group's packets
-                if (dest && (fits_y || L == kLFull))
-                    gather_general<T, L, true>(s_row[b][u], tid, f, max(-kMH, w.fxmin - c2max),
-                                               min(kMH, w.fxmax + 1 + c2max), w.fymin, w.fymax, w.c1min, w.c1max,
-                                               (T)k.rest_q);
-            } else if (dest && (fits_y || L == kLFull)) {
+            if (dest && (fits_y || L == kLFull)) {
                 // two adjacent values of c'_1 or of floor(v_x) keep compile-time
                 // offsets; a window mixing both (rare in planar flows) takes the
                 // row path, whose extra registers would otherwise cost occupancy
@@ -585,7 +660,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
     #define LB_FAST(S, FYV, S0, NSP, NKX, RY)                                                   \
         case S:                                                                                 \
             if constexpr ((FYV) - (S0) - (NSP) + 1 >= -L && (FYV) + 1 + (S0) + (NSP) - 1 <= L)  \
-                gather_fast<T, L, FYV, S0, NSP, NKX, RY>(R, tid, fx0, f);                       \
+                gather_fast<T, L, FYV, S0, NSP, NKX, RY, REST>(R, tid, fx0, f, rq);             \
             break;
     #define LB_FAST_SET(B, FYV, RY)                                                              \
         LB_FAST(B + 0, FYV, 0, 2, 2, RY) LB_FAST(B + 1, FYV, 1, 2, 2, RY) LB_FAST(B + 2, FYV, 2, 2, 2, RY) \
@@ -602,19 +677,23 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                 } else if (L < kLFull) {
                     if (rows_ok) {
                         const MRow<T>& R = s_row[b][u];
-                        if (w.fymin == -1) gather_rows<T, L, -1>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, false);
-                        else gather_rows<T, L, 0>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, false);
+                        if (w.fymin == -1)
+                            gather_rows<T, L, -1, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, false, rq);
+                        else
+                            gather_rows<T, L, 0, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, false, rq);
                     }  // other windows: the tile is flagged (above)
                 } else if (rows_ok || ymix_ok) {
                     // one call per value of floor(v_y) in the window (one
                     // call site per instance keeps the kernel's code compact)
                     const MRow<T>& R = s_row[b][u];
-                    if (w.fymin == -1) gather_rows<T, L, -1>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, ymix_ok);
-                    if (w.fymax == 0) gather_rows<T, L, 0>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, ymix_ok);
+                    if (w.fymin == -1)
+                        gather_rows<T, L, -1, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, ymix_ok, rq);
+                    if (w.fymax == 0)
+                        gather_rows<T, L, 0, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, ymix_ok, rq);
                 } else {
-                    gather_general<T, L, false>(s_row[b][u], tid, f, max(-kMH, w.fxmin - c2max),
-                                                min(kMH, w.fxmax + 1 + c2max), w.fymin, w.fymax, w.c1min, w.c1max,
-                                                (T)0);
+                    gather_general<T, L, REST>(s_row[b][u], tid, f, max(-kMH, w.fxmin - c2max),
+                                               min(kMH, w.fxmax + 1 + c2max), w.fymin, w.fymax, w.c1min, w.c1max,
+                                               rq);
                 }
             }
             // destination row (source row) - L is complete
