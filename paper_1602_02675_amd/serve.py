@@ -97,14 +97,15 @@ def fill(pool: Pool, requests, steps: int):
     return slots, nodes
 
 
-def calibrate(pool: Pool, requests, steps: int = 20, trials: int = 3):
+def calibrate(pool: Pool, requests, steps: int = 30, trials: int = 3, windows: int = 3):
     """Fill the pool with the first requests that fit, pick the tile shape
-    with the pool's autotuner, and measure node-updates/s over `steps` steps.
-    Returns (node-updates/s, chosen shape); the pool is left empty."""
-    slots, nodes = fill(pool, requests, 10 * steps)
+    with the pool's autotuner, and measure node-updates/s over `windows`
+    windows of `steps` steps (the median window).  Returns (node-updates/s,
+    chosen shape); the pool is left empty."""
+    slots, nodes = fill(pool, requests, 2 + (windows + 1) * steps)
     pool.advance(2)
     shape, _ = pool.autotune(trials=trials)
-    ms = pool.advance_timed(steps)
+    ms = sorted(pool.advance_timed(steps) for _ in range(windows))[windows // 2]
     for s in slots:
         pool.release(s)
     return nodes * steps / (ms * 1e-3), shape
