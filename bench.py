@@ -19,6 +19,8 @@ gather kernel plus its totals reduction.  Alongside, in the same JSON line:
   components of both signs) on 2048 x 2048 nodes, FP64;
 * rest_level: the headline tube on the square lattice with a rest level
   (d_0 = rho / 2), FP64, 100 steps;
+* tube1d / two_gas: one 1-D Sod tube of 2^24 nodes, FP64, 200 steps, with
+  one gas and with gamma 7/5 | 5/3 on the two sides (species field);
 * serve: square-lattice requests (sides log-uniform in [64, 2048], steps in
   [100, 5000], seeded states) arriving as a Poisson process at 0.8 x the
   measured capacity, continuously batched on an FP32 pool: p50 / p99
@@ -50,9 +52,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_march2d_fp64_4096.json")
 KERNEL_SOURCES = ["paper_1602_02675_amd/csrc/lb_march2d.hip", "paper_1602_02675_amd/csrc/lb_device.hpp"]
 
 
-def kernel_source_sha() -> str:
+def kernel_source_sha(sources=None) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -105,6 +107,26 @@ def run_nonplanar(steps: int = 200, n: int = 2048, seed: int = 1):
                 steps=steps, ms_per_step=round(total_ms / steps, 5), precision="fp64")
 
 
+def run_tube1d(gamma2=None, n: int = 1 << 24, steps: int = 200):
+    """One long 1-D Sod tube (FP64); with gamma2, gas 2 on the right."""
+    import torch
+    from paper_1602_02675_amd import inputs
+    from paper_1602_02675_amd.lbsd import Solver
+
+    s = Solver(1, n, gamma=1.4, gamma2=gamma2)
+    s.init_riemann(0.5, inputs.SOD_LEFT, inputs.SOD_RIGHT)
+    s.step(5)
+    s.sync()
+    torch.cuda.synchronize()
+    kernel_ms, total_ms = s.step_profiled(steps)
+    s.close()
+    nf = 3 if gamma2 is None else 4
+    return dict(value=round(n * steps / (total_ms * 1e-3) / 1e6, 1), unit="MLUPS", nodes=n, steps=steps,
+                ms_per_step=round(total_ms / steps, 5),
+                achieved_GBs=round(2 * nf * 8 * n / (kernel_ms * 1e-3 / steps) / 1e9, 1), precision="fp64",
+                gammas=[1.4] if gamma2 is None else [1.4, gamma2])
+
+
 def cpu_baseline(seconds_target: float = 15.0):
     """The oracle, single-threaded, on a bounded sample of the same workload."""
     import oracle
@@ -127,8 +149,10 @@ def cpu_baseline(seconds_target: float = 15.0):
                 sample=f"{n}x{n} nodes of the same seeded planar tube, {more} steps, FP64, 1 thread")
 
 
-def run_batch(precision: str, steps: int = 1000, n_tubes: int = 512, seed: int = 0):
-    """512 seeded 1-D tubes in one pool: autotune, graph, time `steps` steps."""
+def run_batch(precision: str, steps: int = 1000, n_tubes: int = 512, seed: int = 0, shape=None,
+              graph: bool = True):
+    """512 seeded 1-D tubes in one pool: autotune (or the given tile shape),
+    graph, time `steps` steps."""
     from paper_1602_02675_amd import inputs
     from paper_1602_02675_amd.lbsd import Pool
 
@@ -139,8 +163,13 @@ def run_batch(precision: str, steps: int = 1000, n_tubes: int = 512, seed: int =
     for i, L in enumerate(lens):
         left, right, xd = inputs.riemann_instance(seed * 100000 + i)
         pool.admit_riemann(int(L), xd, left, right, steps + 10 ** 6, lam=inputs.cfl_lambda([left, right]))
-    best, tuned_ms = pool.autotune(trials=5)
-    pool.use_graph(50)
+    if shape is None:
+        best, tuned_ms = pool.autotune(trials=5)
+    else:
+        pool.set_shape(shape)
+        best = shape
+    if graph:
+        pool.use_graph(50)
     pool.advance(50)  # warm-up (and graph capture)
     ms = pool.advance_timed(steps)
     nodes = int(lens.sum())
@@ -196,9 +225,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the walls, nonplanar and rest_level legs")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the walls, nonplanar, rest_level, tube1d and two_gas legs")
     ap.add_argument("--profile", action="store_true",
                     help="short run + a plain copy of known size, for rocprofv3 counters")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="as --profile, for the FP64 tube batch (tile shape 2, --steps steps)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path "
@@ -208,7 +240,7 @@ def main():
     import torch
 
     torch.cuda.set_device(0)
-    if args.profile:
+    if args.profile or args.profile_batch:
         # plain device copy of 1 GiB, three times (counter calibration)
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
         b = torch.empty_like(a)
@@ -216,6 +248,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+        if args.profile_batch:
+            print(json.dumps({"profile": True, "batch": run_batch("fp64", steps=args.steps, shape=2, graph=False)}), flush=True)
+            return
         r = run_gpu("fp64", args.steps, args.warmup)
         print(json.dumps({"profile": True, "steps": args.steps, "kernel_ms": r["kernel_ms"],
                           "kernel_source_sha": kernel_source_sha()}), flush=True)
@@ -270,6 +305,8 @@ def main():
         out["rest_level"] = {"value": round(nodes * 100 / (rr["total_ms"] / 1e3) / 1e6, 1), "unit": "MLUPS",
                              "steps": 100, "ms_per_step": round(rr["total_ms"] / 100, 5), "d0_frac": 0.5,
                              "precision": "fp64"}
+        out["tube1d"] = run_tube1d()
+        out["two_gas"] = run_tube1d(gamma2=5.0 / 3.0)
     if not args.no_batch:
         out["batch"] = {p: run_batch(p) for p in ("fp32", "fp64")}
     if not args.no_serve:

@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--cmd", default="")
     ap.add_argument("--bytes-per-launch", type=float, required=True,
                     help="algorithmic bytes per step-kernel launch")
+    ap.add_argument("--sources", nargs="*", default=None,
+                    help="kernel source files whose hash is recorded (default: the benchmark's step kernel)")
     args = ap.parse_args()
 
     sys.path.insert(0, ROOT)
@@ -97,7 +99,7 @@ def main():
     traffic = fetch_b + write_b
     res = {
         "kernel": kr["Name"],
-        "kernel_source_sha": bench.kernel_source_sha(),
+        "kernel_source_sha": bench.kernel_source_sha(args.sources),
         "calls": int(kr["Calls"]),
         "avg_duration_us": avg_ns / 1e3,
         "fetch_kib_per_launch": sum(kf) / len(kf),

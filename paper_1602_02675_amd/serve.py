@@ -97,14 +97,17 @@ def fill(pool: Pool, requests, steps: int):
     return slots, nodes
 
 
-def calibrate(pool: Pool, requests, steps: int = 30, trials: int = 3, windows: int = 3):
+def calibrate(pool: Pool, requests, steps: int = 30, trials: int = 3, windows: int = 3, warm: int = 150):
     """Fill the pool with the first requests that fit, pick the tile shape
-    with the pool's autotuner, and measure node-updates/s over `windows`
-    windows of `steps` steps (the median window).  Returns (node-updates/s,
-    chosen shape); the pool is left empty."""
-    slots, nodes = fill(pool, requests, 2 + (windows + 1) * steps)
+    with the pool's autotuner, run `warm` steps (the first steps after a
+    Riemann start run up to 1.6x slower than the developed flow a request
+    spends most of its 100-5000 steps in), and measure node-updates/s over
+    `windows` windows of `steps` steps (the median window).  Returns
+    (node-updates/s, chosen shape); the pool is left empty."""
+    slots, nodes = fill(pool, requests, 2 + warm + (windows + 1) * steps)
     pool.advance(2)
     shape, _ = pool.autotune(trials=trials)
+    pool.advance(warm)
     ms = sorted(pool.advance_timed(steps) for _ in range(windows))[windows // 2]
     for s in slots:
         pool.release(s)
