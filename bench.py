@@ -40,6 +40,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -150,9 +152,10 @@ def cpu_baseline(seconds_target: float = 15.0):
 
 
 def run_batch(precision: str, steps: int = 1000, n_tubes: int = 512, seed: int = 0, shape=None,
-              graph: bool = True):
+              graph: bool = True, keep_rho: bool = False):
     """512 seeded 1-D tubes in one pool: autotune (or the given tile shape),
-    graph, time `steps` steps."""
+    graph, time `steps` steps; with keep_rho also return every tube's
+    density (slot order = tube order) after the run."""
     from paper_1602_02675_amd import inputs
     from paper_1602_02675_amd.lbsd import Pool
 
@@ -173,10 +176,13 @@ def run_batch(precision: str, steps: int = 1000, n_tubes: int = 512, seed: int =
     pool.advance(50)  # warm-up (and graph capture)
     ms = pool.advance_timed(steps)
     nodes = int(lens.sum())
+    # densities of every tube after the run (untimed), for the FP32-vs-FP64 error
+    rho = [pool.moments(slot)[0, 0] for slot in range(n_tubes)] if keep_rho else None
     pool.close()
-    return dict(value=round(nodes * steps / (ms * 1e-3) / 1e6, 1), unit="MLUPS", tubes=n_tubes, nodes=nodes,
-                steps=steps, ms_per_step=round(ms / steps, 5), tile_shape=best,
-                achieved_GBs=round(2 * 3 * elem * nodes / (ms * 1e-3 / steps) / 1e9, 1))
+    out = dict(value=round(nodes * steps / (ms * 1e-3) / 1e6, 1), unit="MLUPS", tubes=n_tubes, nodes=nodes,
+               steps=steps, ms_per_step=round(ms / steps, 5), tile_shape=best,
+               achieved_GBs=round(2 * 3 * elem * nodes / (ms * 1e-3 / steps) / 1e9, 1))
+    return (out, rho) if keep_rho else out
 
 
 def run_serve(n_requests: int = 100, seed: int = 0):
@@ -308,7 +314,13 @@ def main():
         out["tube1d"] = run_tube1d()
         out["two_gas"] = run_tube1d(gamma2=5.0 / 3.0)
     if not args.no_batch:
-        out["batch"] = {p: run_batch(p) for p in ("fp32", "fp64")}
+        (b32, rho32), (b64, rho64) = (run_batch(p, keep_rho=True) for p in ("fp32", "fp64"))
+        # the FP32 batch against the FP64 batch after the same steps: relative
+        # L1 density error over all tubes (every tube has done 50 + 1000 steps)
+        num = sum(float(np.sum(np.abs(a - b))) for a, b in zip(rho32, rho64))
+        den = sum(float(np.sum(np.abs(b))) for b in rho64)
+        b32["rel_l1_density_vs_fp64"] = num / den
+        out["batch"] = {"fp32": b32, "fp64": b64}
     if not args.no_serve:
         out["serve"] = run_serve()
     if not args.no_cpu_baseline:
