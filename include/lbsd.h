@@ -130,7 +130,8 @@ int lb_init_riemann(lb_solver* s, double x_diaphragm, const lb_prim* left, const
 /* General initial state: host_Y is FP64 SoA [nf][ny][nx] of the conserved
  * moments rho, rho u, (rho v), rho E (, rho chi with two gases) in physical
  * units (nf = dim + 2, or 4 with two gases), and lambda > 0 the time-step
- * ratio to use.  Copied synchronously. */
+ * ratio to use.  Copied synchronously.  LB_ESTATE for rho <= 0, a
+ * non-finite value, or (two gases) rho chi outside [0, rho]. */
 int lb_init_moments(lb_solver* s, const double* host_Y, double lambda);
 
 /* Queue n >= 0 steps (eq. 10 / eq. 30 with tau = 1, Sec. V.A).  Each step is

@@ -143,3 +143,15 @@ def test_equal_gases_match_one_gas(lbsd):
     assert normwise_err(b[:3], a, 1) <= 1e-13
     one.close()
     two.close()
+
+
+def test_species_out_of_range_is_rejected(lbsd):
+    nx = 64
+    Y = inputs.random_state(56, 1, nx, vel=(-1.0, 1.0), e=(0.1, 1.0))
+    s = lbsd.Solver(1, nx, gamma2=G2)
+    for chi in (-0.1, 1.5):
+        with pytest.raises(lbsd.LBError) as ei:
+            s.init_moments(_with_species(Y, np.full((1, nx), chi)), 1.0)
+        assert ei.value.code == lbsd.LB_ESTATE
+    s.init_moments(_with_species(Y, np.full((1, nx), 1.0)), 1.0)  # the bounds themselves are fine
+    s.close()
