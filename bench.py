@@ -21,6 +21,10 @@ gather kernel plus its totals reduction.  Alongside, in the same JSON line:
   (d_0 = rho / 2), FP64, 100 steps;
 * tube1d / two_gas: one 1-D Sod tube of 2^24 nodes, FP64, 200 steps, with
   one gas and with gamma 7/5 | 5/3 on the two sides (species field);
+* batch2d: 48 planar square-lattice tubes of uneven sizes (nx log-uniform in
+  [256, 4096], ny in [64, 1024]), seeded states, one pool, autotuned tiles,
+  HIP-graph steps, 250 steps, FP32 and FP64 (and the FP32 density error
+  against FP64);
 * serve: square-lattice requests (sides log-uniform in [64, 2048], steps in
   [100, 5000], seeded states) arriving as a Poisson process at 0.8 x the
   measured capacity, continuously batched on an FP32 pool: p50 / p99
@@ -185,6 +189,39 @@ def run_batch(precision: str, steps: int = 1000, n_tubes: int = 512, seed: int =
     return (out, rho) if keep_rho else out
 
 
+def run_batch2d(precision: str, n: int = 48, steps: int = 250, seed: int = 5, keep_rho: bool = False):
+    """Planar 2-D tubes of uneven sizes in one square-lattice pool."""
+    from paper_1602_02675_amd import inputs
+    from paper_1602_02675_amd.lbsd import Pool
+
+    rng = np.random.default_rng(seed)
+    nxs = np.rint(np.exp(rng.uniform(np.log(256), np.log(4096), size=n))).astype(int)
+    nys = np.rint(np.exp(rng.uniform(np.log(64), np.log(1024), size=n))).astype(int)
+    pool = Pool(2, n, 1 << 30, precision=precision)  # sized below
+    need = sum(pool.footprint(int(a), int(b)) for a, b in zip(nxs, nys))
+    pool.close()
+    pool = Pool(2, n, need + (1 << 24), precision=precision)
+    slots = []
+    for i, (a, b) in enumerate(zip(nxs, nys)):
+        left, right, xd = inputs.riemann_instance(seed * 100000 + i)
+        sl = pool.admit_riemann(int(a), xd, left, right, steps + 10 ** 6, ny=int(b),
+                                lam=inputs.cfl_lambda([left, right]))
+        assert sl is not None, "the arena holds every tube"
+        slots.append(sl)
+    best, _ = pool.autotune(trials=3)
+    pool.use_graph(25)
+    pool.advance(50)  # warm-up (and graph capture)
+    ms = pool.advance_timed(steps)
+    nodes = int(np.sum(nxs * nys))
+    rho = [pool.moments(sl)[0] for sl in slots] if keep_rho else None
+    pool.close()
+    elem = 8 if precision == "fp64" else 4
+    out = dict(value=round(nodes * steps / (ms * 1e-3) / 1e6, 1), unit="MLUPS", tubes=n, nodes=nodes,
+               steps=steps, ms_per_step=round(ms / steps, 5), tile_shape=best,
+               achieved_GBs=round(2 * 4 * elem * nodes / (ms * 1e-3 / steps) / 1e9, 1))
+    return (out, rho) if keep_rho else out
+
+
 def run_serve(n_requests: int = 100, seed: int = 0):
     """Poisson arrivals at 0.8 x measured capacity on an FP32 square-lattice pool."""
     from paper_1602_02675_amd import inputs, serve
@@ -321,6 +358,10 @@ def main():
         den = sum(float(np.sum(np.abs(b))) for b in rho64)
         b32["rel_l1_density_vs_fp64"] = num / den
         out["batch"] = {"fp32": b32, "fp64": b64}
+        (c32, r32), (c64, r64) = (run_batch2d(p, keep_rho=True) for p in ("fp32", "fp64"))
+        c32["rel_l1_density_vs_fp64"] = (sum(float(np.sum(np.abs(a - b))) for a, b in zip(r32, r64)) /
+                                         sum(float(np.sum(np.abs(b))) for b in r64))
+        out["batch2d"] = {"fp32": c32, "fp64": c64}
     if not args.no_serve:
         out["serve"] = run_serve()
     if not args.no_cpu_baseline:
