@@ -21,6 +21,8 @@ gather kernel plus its totals reduction.  Alongside, in the same JSON line:
   (d_0 = rho / 2), FP64, 100 steps;
 * tube1d / two_gas: one 1-D Sod tube of 2^24 nodes, FP64, 200 steps, with
   one gas and with gamma 7/5 | 5/3 on the two sides (species field);
+* two_gas2d: the headline tube with gamma 5/3 on the right (species field
+  on the square lattice), FP64, 100 steps;
 * batch2d: 48 planar square-lattice tubes of uneven sizes (nx log-uniform in
   [256, 4096], ny in [64, 1024]), seeded states, one pool, autotuned tiles,
   HIP-graph steps, 250 steps, FP32 and FP64 (and the FP32 density error
@@ -74,13 +76,16 @@ def workload():
     return left, right, x_d, lam
 
 
-def run_gpu(precision: str, steps: int, warmup: int, bc_x: str = "transmissive", d0_frac: float = 0.0):
+def run_gpu(precision: str, steps: int, warmup: int, bc_x: str = "transmissive", d0_frac: float = 0.0,
+            gamma2=None):
+    """The headline tube; with gamma2, gas 2 on the right (lambda then from
+    CFL 1 over both sides, each with its own gamma)."""
     import torch
     from paper_1602_02675_amd.lbsd import Solver
 
     left, right, x_d, lam = workload()
-    s = Solver(2, NX, NY, precision=precision, bc_x=bc_x, bc_y="periodic", d0_frac=d0_frac)
-    s.init_riemann(x_d, left, right, lam=lam)
+    s = Solver(2, NX, NY, precision=precision, bc_x=bc_x, bc_y="periodic", d0_frac=d0_frac, gamma2=gamma2)
+    s.init_riemann(x_d, left, right, lam=None if gamma2 else lam)
     if warmup:
         s.step(warmup)
     s.sync()
@@ -269,7 +274,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the walls, nonplanar, rest_level, tube1d and two_gas legs")
+                    help="skip the walls, nonplanar, rest_level, tube1d, two_gas and two_gas2d legs")
     ap.add_argument("--profile", action="store_true",
                     help="short run + a plain copy of known size, for rocprofv3 counters")
     ap.add_argument("--profile-batch", action="store_true",
@@ -350,6 +355,10 @@ def main():
                              "precision": "fp64"}
         out["tube1d"] = run_tube1d()
         out["two_gas"] = run_tube1d(gamma2=5.0 / 3.0)
+        rg = run_gpu("fp64", 100, 5, gamma2=5.0 / 3.0)
+        out["two_gas2d"] = {"value": round(nodes * 100 / (rg["total_ms"] / 1e3) / 1e6, 1), "unit": "MLUPS",
+                            "steps": 100, "ms_per_step": round(rg["total_ms"] / 100, 5),
+                            "gammas": [1.4, 5.0 / 3.0], "precision": "fp64"}
     if not args.no_batch:
         (b32, rho32), (b64, rho64) = (run_batch(p, keep_rho=True) for p in ("fp32", "fp64"))
         # the FP32 batch against the FP64 batch after the same steps: relative

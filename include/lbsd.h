@@ -94,17 +94,19 @@ typedef struct {
 int lb_create(const lb_grid* grid, double gamma, const lb_velset* velset, int32_t precision,
               lb_solver** out);
 
-/* Two gases on the 1-D lattice (the different gases on the two sides of the
- * tube that the conclusions name as an extension): gas 1 with gamma_1 and gas
- * 2 with gamma_2, both ideal with one gas constant, each in (1, 3].  The state
- * gains a species moment rho chi (chi = mass fraction of gas 1) after rho E
- * (nf = 4); every packet carries its source's chi as it carries its mass, and
- * a node's gas is the mixture by mass fraction:
+/* Two gases (the different gases on the two sides of the tube that the
+ * conclusions name as an extension), on the 1-D lattice or the square
+ * dual-level set: gas 1 with gamma_1 and gas 2 with gamma_2, both ideal with
+ * one gas constant, each in (1, 1 + 2/D].  The state gains a species moment
+ * rho chi (chi = mass fraction of gas 1) after rho E (nf = dim + 3); every
+ * packet carries its source's chi as it carries its mass, and a node's gas is
+ * the mixture by mass fraction:
  * gamma - 1 = 1 / (chi / (gamma_1 - 1) + (1 - chi) / (gamma_2 - 1)), which
  * sets phi (eq. 15) and the level speeds (eq. 26).  lb_init_riemann puts gas 1
  * on the left and gas 2 on the right (rho E and the CFL speed of each side
- * from its own gamma); lb_init_moments and lb_moments take and give the four
- * fields.  A square-lattice grid is LB_EINVAL. */
+ * from its own gamma); lb_init_moments and lb_moments take and give all
+ * fields.  The square set with a rest level (LB_LATTICE_D2_SQUARE_TRIPLE) is
+ * LB_EINVAL. */
 int lb_create_two_gas(const lb_grid* grid, double gamma_1, double gamma_2, const lb_velset* velset,
                       int32_t precision, lb_solver** out);
 
@@ -129,7 +131,7 @@ int lb_init_riemann(lb_solver* s, double x_diaphragm, const lb_prim* left, const
 
 /* General initial state: host_Y is FP64 SoA [nf][ny][nx] of the conserved
  * moments rho, rho u, (rho v), rho E (, rho chi with two gases) in physical
- * units (nf = dim + 2, or 4 with two gases), and lambda > 0 the time-step
+ * units (nf = dim + 2, or dim + 3 with two gases), and lambda > 0 the time-step
  * ratio to use.  Copied synchronously.  LB_ESTATE for rho <= 0, a
  * non-finite value, or (two gases) rho chi outside [0, rho]. */
 int lb_init_moments(lb_solver* s, const double* host_Y, double lambda);

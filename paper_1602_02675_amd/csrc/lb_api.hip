@@ -100,7 +100,7 @@ static bool prim_ok(const lb_prim* p)
 }
 
 int riemann_sides(int dim, double gamma_l, double gamma_r, bool species, double lam_set, double cfl,
-                  const lb_prim* L, const lb_prim* R, double* lam_out, double side[2][4])
+                  const lb_prim* L, const lb_prim* R, double* lam_out, double side[2][5])
 {
     if (!prim_ok(L) || !prim_ok(R)) return fail(LB_ESTATE, "need rho > 0, p >= 0, finite values");
     const double gs[2] = {gamma_l, gamma_r};
@@ -123,12 +123,14 @@ int riemann_sides(int dim, double gamma_l, double gamma_r, bool species, double 
         const double rE = p / (gs[i] - 1.0) + 0.5 * rho * (u * u + v * v);
         side[i][0] = rho;
         side[i][1] = (rho * u) * lam;
+        side[i][4] = 0.0;
         if (dim == 2) {
             side[i][2] = (rho * v) * lam;
             side[i][3] = rE * lam2;
+            side[i][4] = species && i == 0 ? rho : 0.0;  // gas 1 fills the left side
         } else {
             side[i][2] = rE * lam2;
-            side[i][3] = species && i == 0 ? rho : 0.0;  // gas 1 fills the left side
+            side[i][3] = species && i == 0 ? rho : 0.0;
         }
     }
     *lam_out = lam;
@@ -173,10 +175,10 @@ int upload_moments(void* dst, const double* Y, int nf, int ie, int64_t nn, doubl
     return LB_OK;
 }
 
-void field_scales(int nf, int ie, double lambda, double sc[4])
+void field_scales(int nf, int ie, double lambda, double sc[5])
 {
     const double lam2 = lambda * lambda;
-    for (int f = 0; f < 4; ++f) sc[f] = 1.0;
+    for (int f = 0; f < 5; ++f) sc[f] = 1.0;
     for (int f = 1; f < ie && f < nf; ++f) sc[f] = lambda;
     if (ie < nf) sc[ie] = lam2;
 }
@@ -226,7 +228,8 @@ static int create_solver(const lb_grid* grid, double gamma, double gamma2, bool 
     int rc = check_model(dim, gamma, vs, precision);
     if (rc != LB_OK) return rc;
     if (species) {
-        if (dim != 1) return fail(LB_EINVAL, "two gases: the 1-D lattice only");
+        if (vs->lattice == LB_LATTICE_D2_SQUARE_TRIPLE)
+            return fail(LB_EINVAL, "two gases: the 1-D lattice or the square dual-level set");
         if ((rc = check_model(dim, gamma2, vs, precision)) != LB_OK) return rc;
     }
     if ((rc = check_grid(grid, dim)) != LB_OK) return rc;
@@ -340,7 +343,7 @@ int lb_init_riemann(lb_solver* s, double x_d, const lb_prim* L, const lb_prim* R
 {
     if (!s || !s->bound) return fail(LB_EINVAL, "solver not bound");
     if (!isfinite(x_d)) return fail(LB_EINVAL, "diaphragm position must be finite");
-    double lam = 0.0, side[2][4];
+    double lam = 0.0, side[2][5];
     const int rc = riemann_sides(s->dim, s->gamma, s->gamma2, s->species, s->lambda_set, s->cfl, L, R, &lam,
                                  side);
     if (rc != LB_OK) return rc;
@@ -403,7 +406,8 @@ static int queue_steps(lb_solver* s, int64_t n, hipEvent_t* ev = nullptr)
         }
         if (e != hipSuccess) return hip_fail(e, "step launch");
         if (ev && (e = hipEventRecord(ev[2 * i + 1], s->stream)) != hipSuccess) return hip_fail(e, "event");
-        e = launch_finalize(partials_ptr(s), s->nblocks, ctl_ptr(s), step, s->stream);
+        e = launch_finalize(partials_ptr(s), s->nblocks, ctl_ptr(s), step, s->stream,
+                            s->dim == 2 && s->species);
         if (e != hipSuccess) return hip_fail(e, "finalize launch");
         s->cur = out;
         s->steps_done += 1;
@@ -504,7 +508,7 @@ int lb_moments(lb_solver* s, double* out, int32_t on_device)
     int rc = lb_sync(s);
     if (rc != LB_OK && rc != LB_EREACH && rc != LB_ESTATE) return rc;
     // After a failed step the state is the last good one; exporting it is allowed.
-    double sc[4];
+    double sc[5];
     field_scales(s->nf, s->dim + 1, s->lambda, sc);
     double* dst = on_device ? out : export_ptr(s);
     hipError_t e = s->precision == LB_FP64
@@ -522,7 +526,7 @@ int lb_moments(lb_solver* s, double* out, int32_t on_device)
 
 // Interior sums of the device fields (lattice units) of the latest state:
 // the step's own totals, or (no step since init) a host sum of the state.
-static int field_totals(lb_solver* s, double t[4])
+static int field_totals(lb_solver* s, double t[5])
 {
     if (!s->initialized) return fail(LB_EINVAL, "solver not initialised");
     int rc = lb_sync(s);
@@ -530,14 +534,15 @@ static int field_totals(lb_solver* s, double t[4])
     StepCtl c;
     hipError_t e = hipMemcpy(&c, ctl_ptr(s), sizeof c, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "read control block");
-    for (int f = 0; f < 4; ++f) t[f] = 0.0;
+    for (int f = 0; f < 5; ++f) t[f] = 0.0;
     if (c.totals_step == (long long)s->steps_done && s->steps_done > 0) {
         for (int f = 0; f < 4; ++f) t[f] = c.totals[f];
+        if (s->nf == 5) t[4] = c.totals_sp;
     } else {
         // no step since init: sum the exported state on the host (index order)
         std::vector<double> y;
         try { y.resize((size_t)s->nf * s->nn); } catch (...) { return fail(LB_ENOMEM, "host alloc"); }
-        double sc1[4] = {1, 1, 1, 1};
+        double sc1[5] = {1, 1, 1, 1, 1};
         e = s->precision == LB_FP64
             ? launch_export<double>((const double*)buf_ptr(s, s->cur), export_ptr(s), s->nn, s->nf, sc1, s->stream)
             : launch_export<float>((const float*)buf_ptr(s, s->cur), export_ptr(s), s->nn, s->nf, sc1, s->stream);
@@ -557,10 +562,10 @@ static int field_totals(lb_solver* s, double t[4])
 int lb_totals(lb_solver* s, double out[4])
 {
     if (!s || !out) return fail(LB_EINVAL, "null argument");
-    double t[4];
+    double t[5];
     const int rc = field_totals(s, t);
     if (rc != LB_OK) return rc;
-    double sc[4];
+    double sc[5];
     field_scales(s->nf, s->dim + 1, s->lambda, sc);
     // field order on the device: rho, rho u, (rho v), rho E (, rho chi) -> out[0..3]
     double o[4] = {0, 0, 0, 0};
@@ -580,7 +585,7 @@ int lb_species_total(lb_solver* s, double* out)
 {
     if (!s || !out) return fail(LB_EINVAL, "null argument");
     if (!s->species) return fail(LB_EINVAL, "the solver has one gas");
-    double t[4];
+    double t[5];
     const int rc = field_totals(s, t);
     if (rc != LB_OK) return rc;
     *out = t[s->nf - 1];  // rho chi needs no unit conversion

@@ -52,6 +52,7 @@ struct Src2 {   // one source node of the square lattice, as the gather uses it
     T vx, ry;     // v_x (lattice units) and the y fraction r_y = v_y - floor(v_y)
     T m[2][2];    // packet mass of level l + 1 (speed c'_{l+1}) at x corner k: d (1 - r_x), d r_x
     T kk[2];      // K + c'^2 / 2 for c' = c'_1, c'_2, with K = |v|^2 / 2 + phi
+    T chi;        // two gases: mass fraction of gas 1
     bool bad;
 };
 
@@ -168,13 +169,27 @@ __device__ __forceinline__ Src1<T> make_src1(T m0t, T m1t, T m2t, const Consts& 
 }
 
 // REST: the square set with a rest level (d_0 = delta0 rho); the staged level
-// masses then carry (rho - d_0) / b_1 between them.
-template <typename T, bool REST = false>
-__device__ __forceinline__ Src2<T> make_src2(T m0t, T m1t, T m2t, T m3t, const Consts& k)
+// masses then carry (rho - d_0) / b_1 between them.  SP: two gases; m4t is
+// the species moment rho chi and the node's gas the mixture (as in make_src1,
+// with D = 2).
+template <typename T, bool REST = false, bool SP = false>
+__device__ __forceinline__ Src2<T> make_src2(T m0t, T m1t, T m2t, T m3t, const Consts& kc, T m4t = (T)0)
 {
     const double m0 = m0t, m1 = m1t, m2 = m2t, m3 = m3t;
     Src2<T> s;
-    s.bad = !(m0 > 0.0) || !finite_val(m0) || !finite_val(m1) || !finite_val(m2) || !finite_val(m3);
+    s.bad = !(m0 > 0.0) || !finite_val(m0) || !finite_val(m1) || !finite_val(m2) || !finite_val(m3) ||
+            (SP && !finite_val((double)m4t));
+    s.chi = (T)0;
+    Consts k = kc;
+    if constexpr (SP) {
+#pragma clang fp contract(off)
+        double chi = (double)m4t / (m0 > 0.0 ? m0 : 1.0);
+        chi = chi < 0.0 ? 0.0 : (chi > 1.0 ? 1.0 : chi);
+        const double gm1 = 1.0 / (chi / k.g1m1 + (1.0 - chi) / k.g2m1);
+        k.Dg1 = 2.0 * gm1;
+        k.phi_coef = 1.0 - 1.0 * gm1;
+        s.chi = (T)chi;
+    }
     if (s.bad) {
         s.fx = 0; s.fy = 0; s.c1 = 0;
         s.vx = (T)0; s.ry = (T)0;

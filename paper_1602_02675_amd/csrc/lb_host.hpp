@@ -19,10 +19,10 @@ Consts make_consts(int dim, double gamma, const lb_velset* vs);
 // Riemann states in lattice units: lambda = lam_set if > 0, else cfl over
 // the largest |u| + sqrt(gamma p / rho) of the two states; side[i] holds
 // rho, rho u lambda, (rho v lambda), rho E lambda^2 (eq. 27 for rho E) and,
-// with two gases (species, 1-D), rho chi: gas 1 (gamma_l) on the left,
-// gas 2 (gamma_r) on the right.
+// with two gases (species), rho chi: gas 1 (gamma_l) on the left, gas 2
+// (gamma_r) on the right.  side[i][4] is 0 where nf < 5.
 int riemann_sides(int dim, double gamma_l, double gamma_r, bool species, double lam_set, double cfl,
-                  const lb_prim* L, const lb_prim* R, double* lam_out, double side[2][4]);
+                  const lb_prim* L, const lb_prim* R, double* lam_out, double side[2][5]);
 // rho > 0 and finite everywhere (LB_ESTATE otherwise).
 int check_moments(const double* Y, int nf, int64_t nn);
 // Physical FP64 SoA moments -> lattice units of the storage type, copied to
@@ -31,6 +31,6 @@ int upload_moments(void* dst, const double* Y, int nf, int ie, int64_t nn, doubl
                    hipStream_t stream);
 // Lattice -> physical divisor per field: 1 (rho, rho chi), lambda (momenta),
 // lambda^2 (rho E, field ie).
-void field_scales(int nf, int ie, double lambda, double sc[4]);
+void field_scales(int nf, int ie, double lambda, double sc[5]);
 
 }  // namespace lbsd

@@ -22,10 +22,11 @@ struct StepCtl {
     int redo_tiles;         // tiles the full-FIFO pass has recomputed since the last reset
     int keep[2];            // square lattice: tiles the full-FIFO pass left flagged in this step [0]
                             // and in the previous step [1] (finalize moves [0] to [1])
-    int pad[3];
+    double totals_sp;       // square lattice with two gases: interior sum of rho chi
 };
 
-// Per-block partial results: 4 field sums, reach, error bits.
+// Per-block partial results: 4 field sums, reach, error bits; the square
+// lattice with two gases puts the sum of rho chi at index 6.
 constexpr int kPartialStride = 8;
 
 struct Grid {
@@ -63,18 +64,20 @@ template <typename T>
 hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
                           StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream);
 
-// Reduce nb per-block partial rows of one step into ctl (fixed order).
+// Reduce nb per-block partial rows of one step into ctl (fixed order);
+// species2d: also the rho chi sums of the square lattice with two gases.
 hipError_t launch_finalize(const double* partials, int64_t nb, StepCtl* ctl, long long step,
-                           hipStream_t stream);
+                           hipStream_t stream, bool species2d = false);
 constexpr int kHalo = 5;
 
 // Riemann initial state: node i (cell centre x_lo + (i + 1/2) dx) takes the
-// left moments when x < x_d, else the right ones (lattice units).
+// left moments when x < x_d, else the right ones (lattice units; left and
+// right hold 5 values, of which the first nf are used).
 template <typename T>
 hipError_t launch_init_riemann(T* Y, const Grid& g, int nf, double x_lo, double dx, double x_d,
                                const double* left, const double* right, hipStream_t stream);
 
-// Lattice-unit state -> FP64 physical moments (divide by scale[f]).
+// Lattice-unit state -> FP64 physical moments (divide by scale[f]; 5 values).
 template <typename T>
 hipError_t launch_export(const T* Y, double* out, int64_t nn, int nf, const double* scale,
                          hipStream_t stream);

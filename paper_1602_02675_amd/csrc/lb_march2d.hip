@@ -71,13 +71,28 @@ __device__ __forceinline__ int mfx(int p) { return (p & 255) - 128; }
 __device__ __forceinline__ int mfy(int p) { return ((p >> 8) & 255) - 128; }
 __device__ __forceinline__ int mc1(int p) { return (p >> 16) & 255; }
 
+template <typename T, bool SP>
+struct MRowSpecies {  // two gases: mass fraction of gas 1 per source
+    T chi[kMTPB];
+};
 template <typename T>
-struct MRow {  // one staged source row (per source, see Src2)
+struct MRowSpecies<T, false> {};  // one gas: empty (the row keeps its layout)
+
+template <typename T, bool SP = false>
+struct MRow : MRowSpecies<T, SP> {  // one staged source row (per source, see Src2)
     T vx[kMTPB], ry[kMTPB];
     T m[2][2][kMTPB];  // [level][x corner]
     T kk[2][kMTPB];    // [level]
     int pk[kMTPB];
 };
+
+// chi of the source in column s (0 with one gas)
+template <typename T, bool SP>
+__device__ __forceinline__ T chi_of(const MRow<T, SP>& R, int s)
+{
+    if constexpr (SP) return R.chi[s];
+    else return (T)0;
+}
 
 struct WaveInfo {  // per wavefront and staged row: ranges over its 64 sources
     int fxmin, fxmax, fymin, fymax, c1min, c1max;
@@ -98,18 +113,20 @@ __device__ __forceinline__ WaveInfo merge(const WaveInfo& a, const WaveInfo& b)
 template <typename T>
 using Acc = T;
 
-template <typename T, int L>
+template <typename T, int L, bool SP = false>
 struct Fifo {
     static constexpr int NS = 2 * L + 1;
-    T a[NS][kNV];  // slot o + L: destination row (current source row) + o
+    T a[NS][kNV];        // slot o + L: destination row (current source row) + o
+    T x[SP ? NS : 1];    // two gases: the species moment m chi per slot
 };
 
 // Add to the FIFO slot `slot` (differs between lanes) for slots in the
 // wavefront-uniform range [lo, hi]: each slot in range takes a select, so the
 // FIFO keeps compile-time indices (registers).  Slots out of range occur only
 // with reach > H (reported).
-template <typename A, typename T, int L>
-__device__ __forceinline__ void fifo_add_sel(Fifo<A, L>& f, int slot, int lo, int hi, T r, T px, T pyv, T e)
+template <typename A, typename T, int L, bool SP>
+__device__ __forceinline__ void fifo_add_sel(Fifo<A, L, SP>& f, int slot, int lo, int hi, T r, T px, T pyv, T e,
+                                             T xs = (T)0)
 {
 #pragma unroll
     for (int o = 0; o < 2 * L + 1; ++o) {
@@ -119,11 +136,12 @@ __device__ __forceinline__ void fifo_add_sel(Fifo<A, L>& f, int slot, int lo, in
         f.a[o][kPx] += (A)(h ? px : (T)0);
         f.a[o][kPyv] += (A)(h ? pyv : (T)0);
         f.a[o][kE] += (A)(h ? e : (T)0);
+        if constexpr (SP) f.x[o] += (A)(h ? xs : (T)0);
     }
 }
 
-template <typename A, typename T, int L>
-__device__ __forceinline__ void fifo_add_g(Fifo<A, L>& f, int slot, int lo, int hi, T v)
+template <typename A, typename T, int L, bool SP>
+__device__ __forceinline__ void fifo_add_g(Fifo<A, L, SP>& f, int slot, int lo, int hi, T v)
 {
 #pragma unroll
     for (int o = 0; o < 2 * L + 1; ++o) {
@@ -157,22 +175,23 @@ __device__ __forceinline__ double fmaT<double>(double a, double b, double c)
 // One +-c pair of x-lane packets: masses mp (+c) and mm (-c) into slot o.
 // The pair's momentum m c' enters as (mp - mm) c, exactly zero for mirrored
 // packets of equal mass.
-template <typename A, typename T, int L, bool NOVY>
-__device__ __forceinline__ void add_xpair(Fifo<A, L>& f, int o, T mp, T mm, T vxp, T vxm, T vyp, T vym, T cc,
-                                          T zp, T zm)
+template <typename A, typename T, int L, bool NOVY, bool SP>
+__device__ __forceinline__ void add_xpair(Fifo<A, L, SP>& f, int o, T mp, T mm, T vxp, T vxm, T vyp, T vym, T cc,
+                                          T zp, T zm, T xp = (T)0, T xm = (T)0)
 {
 #pragma clang fp contract(off)
     f.a[o][kR] += (A)(mp + mm);
     f.a[o][kPx] += (A)fmaT(mp - mm, cc, fmaT(mp, vxp, mm * vxm));
     if (!NOVY) f.a[o][kPyv] += (A)fmaT(mp, vyp, mm * vym);
     f.a[o][kE] += (A)fmaT(mp, zp, mm * zm);
+    if constexpr (SP) f.x[o] += (A)fmaT(mp, xp, mm * xm);
 }
 
 // The +-c y-lane packets of NQ x-corner sources (masses m[q], kk = K + c^2/2)
 // into slots op (+c) and om (-c); summed over the corners first, in order.
-template <typename A, typename T, int L, int NQ, bool NOVY>
-__device__ __forceinline__ void add_ylanes(Fifo<A, L>& f, int op, int om, const T (&m)[NQ], const T (&vx)[NQ],
-                                           const T (&vy)[NQ], const T (&kk)[NQ], T cc)
+template <typename A, typename T, int L, int NQ, bool NOVY, bool SP>
+__device__ __forceinline__ void add_ylanes(Fifo<A, L, SP>& f, int op, int om, const T (&m)[NQ], const T (&vx)[NQ],
+                                           const T (&vy)[NQ], const T (&kk)[NQ], T cc, const T* xq = nullptr)
 {
 #pragma clang fp contract(off)
     T msum = m[0], pr = m[0] * vx[0], py = m[0] * vy[0];
@@ -181,6 +200,12 @@ __device__ __forceinline__ void add_ylanes(Fifo<A, L>& f, int op, int om, const 
         msum += m[q];
         pr = fmaT(m[q], vx[q], pr);
         py = fmaT(m[q], vy[q], py);
+    }
+    T xsum = (T)0;
+    if constexpr (SP) {
+        xsum = m[0] * xq[0];
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) xsum = fmaT(m[q], xq[q], xsum);
     }
     const T gm = msum * cc;
 #pragma unroll
@@ -202,15 +227,16 @@ __device__ __forceinline__ void add_ylanes(Fifo<A, L>& f, int op, int om, const 
         if (!NOVY) f.a[o][kPyv] += (A)py;
         dd_add<A>(f.a[o][kGh], f.a[o][kGl], (A)(sg > 0 ? gm : -gm));
         f.a[o][kE] += (A)pe;
+        if constexpr (SP) f.x[o] += (A)xsum;
     }
 }
 
 // The rest-group packets (square set with a rest level) of NQ x-corner
 // sources (masses m[q], energy K[q]) into slot o; summed over the corners
 // first, in order, like add_ylanes.
-template <typename A, typename T, int L, int NQ, bool NOVY>
-__device__ __forceinline__ void add_rest(Fifo<A, L>& f, int o, const T (&m)[NQ], const T (&vx)[NQ],
-                                         const T (&vy)[NQ], const T (&K)[NQ])
+template <typename A, typename T, int L, int NQ, bool NOVY, bool SP>
+__device__ __forceinline__ void add_rest(Fifo<A, L, SP>& f, int o, const T (&m)[NQ], const T (&vx)[NQ],
+                                         const T (&vy)[NQ], const T (&K)[NQ], const T* xq = nullptr)
 {
 #pragma clang fp contract(off)
     T msum = m[0], pr = m[0] * vx[0], py = m[0] * vy[0], pe = m[0] * K[0];
@@ -225,17 +251,23 @@ __device__ __forceinline__ void add_rest(Fifo<A, L>& f, int o, const T (&m)[NQ],
     f.a[o][kPx] += (A)pr;
     if (!NOVY) f.a[o][kPyv] += (A)py;
     f.a[o][kE] += (A)pe;
+    if constexpr (SP) {
+        T xsum = m[0] * xq[0];
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) xsum = fmaT(m[q], xq[q], xsum);
+        f.x[o] += (A)xsum;
+    }
 }
 
 // Rest-group mass at x corner kc of the source in column s: d_0 = rq (d_1 +
 // d_2) of the staged level masses; and its energy per unit mass, K.
-template <typename T>
-__device__ __forceinline__ T rest_mass(const MRow<T>& R, int kc, int s, T rq)
+template <typename T, bool SP>
+__device__ __forceinline__ T rest_mass(const MRow<T, SP>& R, int kc, int s, T rq)
 {
     return rq * (R.m[0][kc][s] + R.m[1][kc][s]);
 }
-template <typename T>
-__device__ __forceinline__ T rest_k(const MRow<T>& R, int s)
+template <typename T, bool SP>
+__device__ __forceinline__ T rest_k(const MRow<T, SP>& R, int s)
 {
     const int c1 = mc1(R.pk[s]);
     return R.kk[0][s] - (T)0.5 * (T)(c1 * c1);
@@ -253,8 +285,8 @@ __device__ __forceinline__ T rest_k(const MRow<T>& R, int s)
 // sums are the same, term for term.  REST: the rest group's packets (from the
 // sources at x displacement floor(v_x) + k_x, into row FY + k_y) follow the
 // lanes.
-template <typename T, int L, int FY, int S0, int NSP, int NKX, bool RY0, bool REST>
-__device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, Fifo<Acc<T>, L>& f, T rq)
+template <typename T, int L, int FY, int S0, int NSP, int NKX, bool RY0, bool REST, bool SP>
+__device__ __forceinline__ void gather_fast(const MRow<T, SP>& R, int lane, int fx, Fifo<Acc<T>, L, SP>& f, T rq)
 {
 #pragma clang fp contract(off)
     constexpr bool UNI = NSP == 2;
@@ -298,11 +330,15 @@ __device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, 
             for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
                 const T mp = RY0 ? bp : bp * (ky ? ryp : (T)1 - ryp);
                 const T mm = RY0 ? bm : bm * (ky ? rym : (T)1 - rym);
-                add_xpair<Acc<T>, T, L, NOVY>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm);
+                if constexpr (SP)
+                    add_xpair<Acc<T>, T, L, NOVY>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm,
+                                                  chi_of(R, sp), chi_of(R, sm));
+                else
+                    add_xpair<Acc<T>, T, L, NOVY>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm);
             }
         }
         // y-lanes: source columns base - kx
-        T b[NKX], ry[NKX], vx[NKX], vy[NKX], kk[NKX];
+        T b[NKX], ry[NKX], vx[NKX], vy[NKX], kk[NKX], xq[NKX];
 #pragma unroll
         for (int q = 0; q < NKX; ++q) {
             const int kx = K0 + q, sq = base - kx;
@@ -311,17 +347,18 @@ __device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, 
             vx[q] = R.vx[sq];
             vy[q] = (T)FY + ry[q];
             kk[q] = kkof(sq, j);
+            xq[q] = chi_of(R, sq);
         }
 #pragma unroll
         for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
             T m[NKX];
 #pragma unroll
             for (int q = 0; q < NKX; ++q) m[q] = RY0 ? b[q] : b[q] * (ky ? ry[q] : (T)1 - ry[q]);
-            add_ylanes<Acc<T>, T, L, NKX, NOVY>(f, FY + ky + c + L, FY + ky - c + L, m, vx, vy, kk, cc);
+            add_ylanes<Acc<T>, T, L, NKX, NOVY>(f, FY + ky + c + L, FY + ky - c + L, m, vx, vy, kk, cc, xq);
         }
     }
     if constexpr (REST) {  // rest group: source columns base - kx, row FY + ky
-        T b[NKX], ry[NKX], vx[NKX], vy[NKX], kr[NKX];
+        T b[NKX], ry[NKX], vx[NKX], vy[NKX], kr[NKX], xq[NKX];
 #pragma unroll
         for (int q = 0; q < NKX; ++q) {
             const int kx = K0 + q, sq = base - kx;
@@ -332,13 +369,14 @@ __device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, 
             vx[q] = R.vx[sq];
             vy[q] = (T)FY + ry[q];
             kr[q] = rest_k(R, sq);
+            xq[q] = chi_of(R, sq);
         }
 #pragma unroll
         for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
             T m[NKX];
 #pragma unroll
             for (int q = 0; q < NKX; ++q) m[q] = RY0 ? b[q] : b[q] * (ky ? ry[q] : (T)1 - ry[q]);
-            add_rest<Acc<T>, T, L, NKX, NOVY>(f, FY + ky + L, m, vx, vy, kr);
+            add_rest<Acc<T>, T, L, NKX, NOVY>(f, FY + ky + L, m, vx, vy, kr, xq);
         }
     }
 }
@@ -353,9 +391,9 @@ __device__ __forceinline__ void gather_fast(const MRow<T>& R, int lane, int fx, 
 // source counts only if its floor(v_y) is FY as well: two such calls, for FY
 // and FY + 1, take a window whose floor(v_y) has two adjacent values.  REST:
 // the rest group's packets follow the lanes, in the fast path's order.
-template <typename T, int L, int FY, bool REST>
-__device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, int fxlo, int fxhi,
-                                            int clo, int chi, bool chk, T rq)
+template <typename T, int L, int FY, bool REST, bool SP>
+__device__ __forceinline__ void gather_rows(const MRow<T, SP>& R, int lane, Fifo<Acc<T>, L, SP>& f, int fxlo,
+                                            int fxhi, int clo, int chi, bool chk, T rq)
 {
 #pragma clang fp contract(off)
     const int nfx = fxhi - fxlo;
@@ -380,7 +418,11 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc
 #pragma unroll
                     for (int ky = 0; ky < 2; ++ky) {
                         const T mp = bp * (ky ? ryp : (T)1 - ryp), mm = bm * (ky ? rym : (T)1 - rym);
-                        add_xpair<Acc<T>, T, L, false>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm);
+                        if constexpr (SP)
+                            add_xpair<Acc<T>, T, L, false>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm,
+                                                           chi_of(R, sp), chi_of(R, sm));
+                        else
+                            add_xpair<Acc<T>, T, L, false>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm);
                     }
                 }
             }
@@ -399,6 +441,7 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc
             const T vx[2] = {R.vx[s0], R.vx[s1]};
             const T vy[2] = {(T)FY + ry[0], (T)FY + ry[1]};
             const T kk[2] = {R.kk[lev][s0], R.kk[lev][s1]};
+            const T xq[2] = {chi_of(R, s0), chi_of(R, s1)};
 #pragma unroll
             for (int C = 0; C <= 3 + 1; ++C) {  // speed of this level, static
                 if (C < cl || C > ch) continue;
@@ -408,7 +451,7 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc
 #pragma unroll
                 for (int ky = 0; ky < 2; ++ky) {
                     const T m[2] = {w0 * (ky ? ry[0] : (T)1 - ry[0]), w1 * (ky ? ry[1] : (T)1 - ry[1])};
-                    add_ylanes<Acc<T>, T, L, 2, false>(f, FY + ky + C + L, FY + ky - C + L, m, vx, vy, kk, cc);
+                    add_ylanes<Acc<T>, T, L, 2, false>(f, FY + ky + C + L, FY + ky - C + L, m, vx, vy, kk, cc, xq);
                 }
             }
         }
@@ -425,10 +468,11 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc
             const T vx[2] = {R.vx[s0], R.vx[s1]};
             const T vy[2] = {(T)FY + ry[0], (T)FY + ry[1]};
             const T kr[2] = {rest_k(R, s0), rest_k(R, s1)};
+            const T xq[2] = {chi_of(R, s0), chi_of(R, s1)};
 #pragma unroll
             for (int ky = 0; ky < 2; ++ky) {
                 const T m[2] = {b0 * (ky ? ry[0] : (T)1 - ry[0]), b1 * (ky ? ry[1] : (T)1 - ry[1])};
-                add_rest<Acc<T>, T, L, 2, false>(f, FY + ky + L, m, vx, vy, kr);
+                add_rest<Acc<T>, T, L, 2, false>(f, FY + ky + L, m, vx, vy, kr, xq);
             }
         }
     }
@@ -442,9 +486,9 @@ __device__ __forceinline__ void gather_rows(const MRow<T>& R, int lane, Fifo<Acc
 // each packet class then reaches one or two FIFO slots, and only those are
 // visited.  REST: the set has a rest group, whose packets (mass
 // rq (d_1 + d_2) per corner, energy K) move like the y-lanes with c' = 0.
-template <typename T, int L, bool REST>
-__device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, int alo, int ahi, int fylo, int fyhi,
-                               int clo, int chi, T rq)
+template <typename T, int L, bool REST, bool SP>
+__device__ void gather_general(const MRow<T, SP>& R, int lane, Fifo<Acc<T>, L, SP>& f, int alo, int ahi, int fylo,
+                               int fyhi, int clo, int chi, T rq)
 {
 #pragma clang fp contract(off)
 #pragma unroll 1
@@ -454,6 +498,7 @@ __device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, i
         const int fx = mfx(pk), fy = mfy(pk), c1 = mc1(pk), c2 = c1 + 1;
         const T vx = R.vx[s], ry = R.ry[s];
         const T vy = (T)fy + ry;
+        const T xs = chi_of(R, s);  // two gases: mass fraction of gas 1
 #pragma unroll 1
         for (int kx = 0; kx < 2; ++kx) {
             const int cx = a - fx - kx;  // x-lane speed needed to land here
@@ -469,7 +514,7 @@ __device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, i
                 for (int ky = 0; ky < 2; ++ky) {
                     const T m = w * (ky ? ry : (T)1 - ry);
                     fifo_add_sel<Acc<T>, T, L>(f, fy + ky + L, fylo + ky + L, fyhi + ky + L, m, m * (vx + cc),
-                                               m * vy, m * zx);
+                                               m * vy, m * zx, m * xs);
                 }
             }
             if (cx == 0) {  // y-lanes (and the rest group) move in x by fx + kx only
@@ -480,7 +525,7 @@ __device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, i
                     for (int ky = 0; ky < 2; ++ky) {
                         const T m = mr * (ky ? ry : (T)1 - ry);
                         fifo_add_sel<Acc<T>, T, L>(f, fy + ky + L, fylo + ky + L, fyhi + ky + L, m, m * vx,
-                                                   m * vy, m * zr);
+                                                   m * vy, m * zr, m * xs);
                     }
                 }
 #pragma unroll 1
@@ -497,7 +542,7 @@ __device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, i
                             // the window's range of this packet class's slot (uniform)
                             const int lo = fylo + ky + (sg > 0 ? clo + l : -(chi + l)) + L;
                             const int hi = fyhi + ky + (sg > 0 ? chi + l : -(clo + l)) + L;
-                            fifo_add_sel<Acc<T>, T, L>(f, slot, lo, hi, m, m * vx, m * vy, m * zy);
+                            fifo_add_sel<Acc<T>, T, L>(f, slot, lo, hi, m, m * vx, m * vy, m * zy, m * xs);
                             fifo_add_g<Acc<T>, T, L>(f, slot, lo, hi, m * cc);
                         }
                     }
@@ -507,13 +552,14 @@ __device__ void gather_general(const MRow<T>& R, int lane, Fifo<Acc<T>, L>& f, i
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void load_node(const T* __restrict__ Y, int64_t nn, int64_t q, T (&m)[4])
+template <typename T, int NF>
+__device__ __forceinline__ void load_node(const T* __restrict__ Y, int64_t nn, int64_t q, T (&m)[NF])
 {
     m[0] = Y[q];
     m[1] = Y[nn + q];
     m[2] = Y[2 * nn + q];
     m[3] = Y[3 * nn + q];
+    if constexpr (NF > 4) m[4] = Y[4 * nn + q];
 }
 
 // One tile: destination columns [X0, X0 + 256 - 2H) and rows [Y0, Y0 + sy)
@@ -527,14 +573,15 @@ __device__ __forceinline__ void load_node(const T* __restrict__ Y, int64_t nn, i
 // which sums in the same order (bit-identical); with L = kLFull it tells that
 // the tile still needs the full pass.
 // Contains block-wide barriers: every thread of the block must call it.
-template <typename T, int L, bool WALLS, bool REST>
+template <typename T, int L, bool WALLS, bool REST, bool SP>
 __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict__ Yn, const Grid& g, const Consts& k,
                           int64_t X0, int64_t Y0, int sy, double* __restrict__ prow)
 {
     // source rows staged per barrier: two in FP64 (fewer barriers, two
     // independent per-source computations in flight); FP32 has no registers left
     constexpr int RB = sizeof(T) == 8 ? 2 : 1;
-    __shared__ MRow<T> s_row[2][RB];
+    constexpr int NF = SP ? 5 : 4;  // moment fields (two gases: rho chi after rho E)
+    __shared__ MRow<T, SP> s_row[2][RB];
     __shared__ WaveInfo s_w[2][RB][kMNW];
     const int tid = threadIdx.x, lane64 = tid & 63, wid = tid >> 6;
     const T rq = REST ? (T)k.rest_q : (T)0;  // rest-group mass per unit of staged level mass
@@ -550,25 +597,27 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
     constexpr int NS = 2 * L + 1;
 
     using A = Acc<T>;
-    Fifo<A, L> f;
+    Fifo<A, L, SP> f;
 #pragma unroll
-    for (int o = 0; o < NS; ++o)
+    for (int o = 0; o < NS; ++o) {
 #pragma unroll
         for (int c = 0; c < kNV; ++c) f.a[o][c] = (A)0;
-    double tot[4] = {0.0, 0.0, 0.0, 0.0};
+        if constexpr (SP) f.x[o] = (A)0;
+    }
+    double tot[NF] = {};
     int reach = 0, bad = 0, yfar = 0;
 
     // moments of this thread's source column in row gy (halo rows and
     // columns mapped by the boundaries); *mir_y tells whether the row is a
     // mirror image beyond a wall.  Mirror images negate normal momentum when
     // the row is staged, so that the loads issued a row ahead are not waited for.
-    auto load_src = [&](int64_t gy, T (&m)[4], bool* mir_y) {
+    auto load_src = [&](int64_t gy, T (&m)[NF], bool* mir_y) {
         int64_t yy;
         if constexpr (WALLS) yy = source_idx(gy, ny, g.bc_y, mir_y);
         else yy = g.bc_y == kBcPeriodic ? wrap_near(gy, ny) : clamp_idx(gy, ny);
-        load_node<T>(Y, nn, yy * nx + sx, m);
+        load_node<T, NF>(Y, nn, yy * nx + sx, m);
     };
-    T cur[RB][4], nxt[RB][4];
+    T cur[RB][NF], nxt[RB][NF];
     bool cur_my[RB] = {}, nxt_my[RB] = {};
 #pragma unroll
     for (int u = 0; u < RB; ++u)
@@ -588,7 +637,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                 mx = mir_x ? -mx : mx;
                 my = cur_my[u] ? -my : my;
             }
-            const Src2<T> s = make_src2<T, REST>(cur[u][0], mx, my, cur[u][3], k);
+            const Src2<T> s = make_src2<T, REST, SP>(cur[u][0], mx, my, cur[u][3], k, cur[u][NF - 1]);
             const int pk = mpack(s.fx, s.fy, s.c1);
             s_row[b][u].vx[tid] = s.vx;
             s_row[b][u].ry[tid] = s.ry;
@@ -599,6 +648,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
             s_row[b][u].kk[0][tid] = s.kk[0];
             s_row[b][u].kk[1][tid] = s.kk[1];
             s_row[b][u].pk[tid] = pk;
+            if constexpr (SP) s_row[b][u].chi[tid] = s.chi;
             const int yr = axis_reach(s.fy, s.c1);
             reach = max(reach, max(axis_reach(s.fx, s.c1), yr));
             yfar |= yr > kLSmall ? 1 : 0;
@@ -652,7 +702,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                 const bool fastw = rows_ok && (w.c1max == w.c1min || cmix) && (w.fxmax == w.fxmin || xmix) &&
                                    !(cmix && xmix) && (!cmix || w.c1min <= 2) && (!xmix || w.c1min <= 1);
                 if (fastw) {
-                    const MRow<T>& R = s_row[b][u];
+                    const auto& R = s_row[b][u];
                     const int fx0 = w.fxmax;
                     const int sel = ((w.fymin == 0 ? (w.ry0 ? 0 : 1) : 2) * 2 + (xmix ? 1 : 0)) * 8 +
                                     (cmix ? 4 : 0) + w.c1min;
@@ -676,7 +726,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                     }
                 } else if (L < kLFull) {
                     if (rows_ok) {
-                        const MRow<T>& R = s_row[b][u];
+                        const auto& R = s_row[b][u];
                         if (w.fymin == -1)
                             gather_rows<T, L, -1, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, false, rq);
                         else
@@ -685,7 +735,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                 } else if (rows_ok || ymix_ok) {
                     // one call per value of floor(v_y) in the window (one
                     // call site per instance keeps the kernel's code compact)
-                    const MRow<T>& R = s_row[b][u];
+                    const auto& R = s_row[b][u];
                     if (w.fymin == -1)
                         gather_rows<T, L, -1, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, ymix_ok, rq);
                     if (w.fymax == 0)
@@ -709,41 +759,48 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                 tot[1] += (double)f.a[0][kPx];
                 tot[2] += (double)py;
                 tot[3] += (double)f.a[0][kE];
+                if constexpr (SP) {
+                    Yn[4 * nn + q] = (T)f.x[0];
+                    tot[NF - 1] += (double)f.x[0];
+                }
             }
     #pragma unroll
-            for (int o = 0; o + 1 < NS; ++o)
+            for (int o = 0; o + 1 < NS; ++o) {
     #pragma unroll
                 for (int c = 0; c < kNV; ++c) f.a[o][c] = f.a[o + 1][c];
+                if constexpr (SP) f.x[o] = f.x[o + 1];
+            }
     #pragma unroll
             for (int c = 0; c < kNV; ++c) f.a[NS - 1][c] = (A)0;
+            if constexpr (SP) f.x[NS - 1] = (A)0;
         }
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) cur[u][c] = nxt[u][c];
+            for (int c = 0; c < NF; ++c) cur[u][c] = nxt[u][c];
             if constexpr (WALLS) cur_my[u] = nxt_my[u];
         }
     }
-    // per-tile partials: field sums, reach, error bits
-    __shared__ double s_sum[kMNW][4];
+    // per-tile partials: field sums (a fifth, rho chi, at index 6), reach, error bits
+    __shared__ double s_sum[kMNW][NF];
     __shared__ int s_ir[kMNW][2];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) tot[c] = wave_sum(tot[c]);
+    for (int c = 0; c < NF; ++c) tot[c] = wave_sum(tot[c]);
     reach = wave_max(reach);
     bad = wave_max(bad);
     if (lane64 == 0) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) s_sum[wid][c] = tot[c];
+        for (int c = 0; c < NF; ++c) s_sum[wid][c] = tot[c];
         s_ir[wid][0] = reach;
         s_ir[wid][1] = bad;
     }
     const int far = __syncthreads_or(yfar);
     if (tid == 0) {
         int rr = 0, bb = 0;
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < NF; ++c) {
             double t = s_sum[0][c];
             for (int w = 1; w < kMNW; ++w) t += s_sum[w][c];
-            prow[c] = t;
+            prow[c < 4 ? c : 6] = t;
         }
         for (int w = 0; w < kMNW; ++w) {
             rr = max(rr, s_ir[w][0]);
@@ -770,7 +827,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
 // full pass instead of computing them twice (flows change little per step).
 // Persistent blocks claim the tiles (tiles_x column strips x row chunks of sy
 // rows, row chunk major) from the control block's counter of the pass.
-template <typename T, int L, bool WALLS, bool REST>
+template <typename T, int L, bool WALLS, bool REST, bool SP>
 __global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
 march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
                StepCtl* __restrict__ ctl, double* __restrict__ partials, int* __restrict__ flags,
@@ -794,7 +851,7 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
             continue;
         }
         const int64_t tx = t % tiles_x, ty = t / tiles_x;
-        const int far = march_tile<T, L, WALLS, REST>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
+        const int far = march_tile<T, L, WALLS, REST, SP>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
                                                       partials + (int64_t)t * kPartialStride);
         if (threadIdx.x == 0) {
             flags[t] = far;
@@ -834,7 +891,7 @@ pool2d_kernel(PoolView v, Consts k)
         const int64_t o0 = tl.off[0], o1 = tl.off[1];  // selected below, not indexed (keeps them in registers)
         const int64_t from = (ts & kTileSet) ? o1 : o0, to = (ts & kTileSet) ? o0 : o1;
         const Grid g{tl.nx, tl.ny, tl.bc_x, tl.bc_y};
-        const int far = march_tile<T, L, WALLS, REST>(arena + from, arena + to, g, k, tl.x0, tl.y0, tl.rows,
+        const int far = march_tile<T, L, WALLS, REST, false>(arena + from, arena + to, g, k, tl.x0, tl.y0, tl.rows,
                                                       v.partials + (int64_t)t * kPartialStride);
         if (threadIdx.x == 0) {
             v.flags[t] = far;
@@ -879,22 +936,24 @@ template <typename T>
 int march2d_blocks_per_cu()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, march2d_kernel<T, kLSmall, false, false>, kMTPB, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, march2d_kernel<T, kLSmall, false, false, false>, kMTPB, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-template <typename T, bool WALLS, bool REST>
+template <typename T, bool WALLS, bool REST, bool SP>
 hipError_t launch_march2d_w(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
                             StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream)
 {
     const int nt = (int)m.blocks();
-    march2d_kernel<T, kLSmall, WALLS, REST><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, flags,
-                                                                             step, m.sy, (int)m.grid_x, nt);
+    march2d_kernel<T, kLSmall, WALLS, REST, SP><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials,
+                                                                                 flags, step, m.sy,
+                                                                                 (int)m.grid_x, nt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    march2d_kernel<T, kLFull, WALLS, REST><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials, flags,
-                                                                            step, m.sy, (int)m.grid_x, nt);
+    march2d_kernel<T, kLFull, WALLS, REST, SP><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials,
+                                                                                flags, step, m.sy,
+                                                                                (int)m.grid_x, nt);
     return hipGetLastError();
 }
 
@@ -905,11 +964,14 @@ hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, 
                           StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream)
 {
     const bool walls = g.bc_x == kBcReflecting || g.bc_y == kBcReflecting, rest = k.rest_q > 0.0;
+    if (k.species)  // two gases (dual-level set only)
+        return walls ? launch_march2d_w<T, true, false, true>(Y, Yn, g, m, k, ctl, partials, flags, step, stream)
+                     : launch_march2d_w<T, false, false, true>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
     if (rest)
-        return walls ? launch_march2d_w<T, true, true>(Y, Yn, g, m, k, ctl, partials, flags, step, stream)
-                     : launch_march2d_w<T, false, true>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
-    return walls ? launch_march2d_w<T, true, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream)
-                 : launch_march2d_w<T, false, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
+        return walls ? launch_march2d_w<T, true, true, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream)
+                     : launch_march2d_w<T, false, true, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
+    return walls ? launch_march2d_w<T, true, false, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream)
+                 : launch_march2d_w<T, false, false, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
 }
 
 template <typename T>

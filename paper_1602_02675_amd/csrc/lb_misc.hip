@@ -11,7 +11,7 @@ namespace {
 template <typename T>
 __global__ void init_riemann_kernel(T* __restrict__ Y, int64_t nx, int64_t nn, int nf, double x_lo,
                                     double dx, double x_d, double l0, double l1, double l2, double l3,
-                                    double r0, double r1, double r2, double r3)
+                                    double l4, double r0, double r1, double r2, double r3, double r4)
 {
 #pragma clang fp contract(off)
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -19,17 +19,17 @@ __global__ void init_riemann_kernel(T* __restrict__ Y, int64_t nx, int64_t nn, i
     const int64_t i = q % nx;
     const double x = x_lo + ((double)i + 0.5) * dx;  // cell centre
     const bool left = x < x_d;
-    const double v[4] = {left ? l0 : r0, left ? l1 : r1, left ? l2 : r2, left ? l3 : r3};
+    const double v[5] = {left ? l0 : r0, left ? l1 : r1, left ? l2 : r2, left ? l3 : r3, left ? l4 : r4};
     for (int f = 0; f < nf; ++f) Y[(int64_t)f * nn + q] = (T)v[f];
 }
 
 template <typename T>
 __global__ void export_kernel(const T* __restrict__ Y, double* __restrict__ out, int64_t nn, int nf,
-                              double s0, double s1, double s2, double s3)
+                              double s0, double s1, double s2, double s3, double s4)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nn) return;
-    const double s[4] = {s0, s1, s2, s3};
+    const double s[5] = {s0, s1, s2, s3, s4};
     for (int f = 0; f < nf; ++f) out[(int64_t)f * nn + q] = (double)Y[(int64_t)f * nn + q] / s[f];
 }
 
@@ -49,8 +49,10 @@ __global__ void lanes_kernel(const T* __restrict__ Y, int64_t nn, int dim, Const
         c1[q] = s.c1;
     } else {
         // the same device function the step uses (with or without the rest group)
-        const Src2<T> s = k.rest_q > 0.0 ? make_src2<T, true>(Y[q], Y[nn + q], Y[2 * nn + q], Y[3 * nn + q], k)
-                                         : make_src2<T, false>(Y[q], Y[nn + q], Y[2 * nn + q], Y[3 * nn + q], k);
+        const Src2<T> s =
+            k.species ? make_src2<T, false, true>(Y[q], Y[nn + q], Y[2 * nn + q], Y[3 * nn + q], k, Y[4 * nn + q])
+            : k.rest_q > 0.0 ? make_src2<T, true>(Y[q], Y[nn + q], Y[2 * nn + q], Y[3 * nn + q], k)
+                             : make_src2<T, false>(Y[q], Y[nn + q], Y[2 * nn + q], Y[3 * nn + q], k);
         fx[q] = s.fx;
         fy[q] = s.fy;
         c1[q] = s.c1;
@@ -67,6 +69,7 @@ __global__ void reset_ctl_kernel(StepCtl* ctl)
         ctl->err_step = LLONG_MAX;
         ctl->totals_step = -1;
         for (int f = 0; f < 4; ++f) ctl->totals[f] = 0.0;
+        ctl->totals_sp = 0.0;
         ctl->max_reach = 0;
         ctl->redo_tiles = 0;
         ctl->keep[0] = 0;
@@ -84,7 +87,7 @@ hipError_t launch_init_riemann(T* Y, const Grid& g, int nf, double x_lo, double 
 {
     const int64_t nn = g.nx * g.ny;
     init_riemann_kernel<T><<<blocks_for(nn, 256), 256, 0, stream>>>(
-        Y, g.nx, nn, nf, x_lo, dx, x_d, l[0], l[1], l[2], l[3], r[0], r[1], r[2], r[3]);
+        Y, g.nx, nn, nf, x_lo, dx, x_d, l[0], l[1], l[2], l[3], l[4], r[0], r[1], r[2], r[3], r[4]);
     return hipGetLastError();
 }
 
@@ -92,7 +95,7 @@ template <typename T>
 hipError_t launch_export(const T* Y, double* out, int64_t nn, int nf, const double* s,
                          hipStream_t stream)
 {
-    export_kernel<T><<<blocks_for(nn, 256), 256, 0, stream>>>(Y, out, nn, nf, s[0], s[1], s[2], s[3]);
+    export_kernel<T><<<blocks_for(nn, 256), 256, 0, stream>>>(Y, out, nn, nf, s[0], s[1], s[2], s[3], s[4]);
     return hipGetLastError();
 }
 

@@ -492,7 +492,7 @@ int lb_pool_admit_riemann(lb_pool* p, const lb_grid* grid, double lambda, double
     if (!slot) return fail(LB_EINVAL, "null slot");
     if (!isfinite(x_d)) return fail(LB_EINVAL, "diaphragm position must be finite");
     if (!p) return fail(LB_EINVAL, "null pool");
-    double lam = 0.0, side[2][4];
+    double lam = 0.0, side[2][5];
     int rc = riemann_sides(p->dim, p->gamma, p->gamma, false, lambda, 1.0, L, R, &lam, side);
     if (rc != LB_OK) return rc;
     int32_t s = -1;
@@ -626,7 +626,7 @@ int lb_pool_moments(lb_pool* p, int32_t slot, double* out, int32_t on_device)
     if ((rc = read_state(p, slot, &st)) != LB_OK) return rc;
     const SlotInfo& si = p->info[(size_t)slot];
     const int64_t nn = si.grid.nx * si.grid.ny;
-    double sc[4];
+    double sc[5];
     field_scales(p->nf, p->dim + 1, si.lambda, sc);
     const void* src = set_ptr(p, slot, (int)(st.done & 1));
     hipError_t e;
@@ -666,7 +666,7 @@ int lb_pool_totals(lb_pool* p, int32_t slot, double out[4])
     PoolState st;
     if ((rc = read_state(p, slot, &st)) != LB_OK) return rc;
     if (st.done == 0 || st.totals_step != st.done) return fail(LB_EINVAL, "no completed step to report");
-    double sc[4];
+    double sc[5];
     field_scales(p->nf, p->dim + 1, p->info[(size_t)slot].lambda, sc);
     double o[4] = {0, 0, 0, 0};
     o[0] = st.totals[0] / sc[0];

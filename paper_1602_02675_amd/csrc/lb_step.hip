@@ -109,9 +109,9 @@ __device__ void finish_step(double (&acc)[NF], const TileInfo& ti, double* __res
 constexpr int kFinTPB = 256;
 __global__ void __launch_bounds__(kFinTPB)
 finalize_kernel(const double* __restrict__ partials, int64_t nb, StepCtl* __restrict__ ctl,
-                long long step, int H)
+                long long step, int H, int sp2)
 {
-    __shared__ double s_sum[kFinTPB / 64][4];
+    __shared__ double s_sum[kFinTPB / 64][5];
     __shared__ int s_ir[kFinTPB / 64][2];
     if (threadIdx.x == 0) {  // the step kernels of this step are done with their counters
         ctl->next[0] = 0;
@@ -122,32 +122,34 @@ finalize_kernel(const double* __restrict__ partials, int64_t nb, StepCtl* __rest
     }
     if (ctl->err_step < step) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     int reach = 0, err = 0;
     for (int64_t b = tid; b < nb; b += kFinTPB) {
         const double* p = partials + b * kPartialStride;
 #pragma unroll
         for (int f = 0; f < 4; ++f) s[f] += p[f];
+        if (sp2) s[4] += p[6];  // rho chi (square lattice, two gases)
         reach = max(reach, (int)p[4]);
         err |= (int)p[5];
     }
 #pragma unroll
-    for (int f = 0; f < 4; ++f) s[f] = wave_sum(s[f]);
+    for (int f = 0; f < 5; ++f) s[f] = wave_sum(s[f]);
     reach = wave_max(reach);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) err |= __shfl_xor(err, o, 64);
     if (lane == 0) {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) s_sum[wid][f] = s[f];
+        for (int f = 0; f < 5; ++f) s_sum[wid][f] = s[f];
         s_ir[wid][0] = reach;
         s_ir[wid][1] = err;
     }
     __syncthreads();
     if (tid == 0) {
-        for (int f = 0; f < 4; ++f) {
+        for (int f = 0; f < 5; ++f) {
             double t = s_sum[0][f];
             for (int w = 1; w < kFinTPB / 64; ++w) t += s_sum[w][f];
-            ctl->totals[f] = t;
+            if (f < 4) ctl->totals[f] = t;
+            else ctl->totals_sp = t;
         }
         int r = s_ir[0][0], e = s_ir[0][1];
         for (int w = 1; w < kFinTPB / 64; ++w) { r = max(r, s_ir[w][0]); e |= s_ir[w][1]; }
@@ -533,9 +535,9 @@ hipError_t launch_pool_finalize(const PoolView& v, int nslots, int commit, hipSt
 }
 
 hipError_t launch_finalize(const double* partials, int64_t nb, StepCtl* ctl, long long step,
-                           hipStream_t stream)
+                           hipStream_t stream, bool species2d)
 {
-    finalize_kernel<<<1, kFinTPB, 0, stream>>>(partials, nb, ctl, step, kHalo);
+    finalize_kernel<<<1, kFinTPB, 0, stream>>>(partials, nb, ctl, step, kHalo, species2d ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -17,11 +17,12 @@ def normwise_err(got, ref, dim):
     return max(errs)
 
 
-def run_pair(lbsd, dim, Y_phys, lam, n, *, nx, ny=1, bcx=0, bcy=1, delta0=None, prec="fp64"):
-    P = oracle.Problem(dim, nx, ny, bc_x=bcx, bc_y=bcy, delta0=delta0)
+def run_pair(lbsd, dim, Y_phys, lam, n, *, nx, ny=1, bcx=0, bcy=1, delta0=None, prec="fp64", gamma2=None):
+    """gamma2: two gases (gamma 1.4 for gas 1); Y_phys then holds rho chi last."""
+    P = oracle.Problem(dim, nx, ny, bc_x=bcx, bc_y=bcy, delta0=delta0, gamma2=gamma2)
     ref, st, reach = oracle.run(P, oracle.to_lattice(P, Y_phys, lam), n)
     assert st == 0 and reach <= 5
-    s = lbsd.Solver(dim, nx, ny, bc_x=bcx, bc_y=bcy, d0_frac=delta0, precision=prec)
+    s = lbsd.Solver(dim, nx, ny, bc_x=bcx, bc_y=bcy, d0_frac=delta0, precision=prec, gamma2=gamma2)
     s.init_moments(Y_phys, lam)
     s.step(n)
     got = s.moments()

@@ -84,7 +84,13 @@ def test_two_gas_create_validation():
     assert lbsd._lib.lb_state_bytes(h) >= 2 * 4 * 100 * 8
     out = ctypes.c_double()
     lbsd._lib.lb_destroy(h)
-    for args in ((2, 1.4, 1.4, 8, 8, 2, 0.0), (1, 1.4, 1.0), (1, 1.4, 3.5), (1, 0.9, 1.4)):
+    # the square dual-level set: five fields; the gases' gamma in (1, 2]
+    rc, h = make(2, 1.4, 5.0 / 3.0, 8, 8, 2, 0.0)
+    assert rc == lbsd.LB_OK
+    assert lbsd._lib.lb_state_bytes(h) >= 2 * 5 * 64 * 8
+    lbsd._lib.lb_destroy(h)
+    for args in ((2, 1.4, 1.4, 8, 8, 3, 0.5), (2, 1.4, 2.5, 8, 8, 2, 0.0), (1, 1.4, 1.0), (1, 1.4, 3.5),
+                 (1, 0.9, 1.4)):
         rc, h = make(*args)
         assert rc == lbsd.LB_EINVAL, args
     # one gas: no species total

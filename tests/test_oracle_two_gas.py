@@ -170,3 +170,113 @@ def test_two_gas_shock_tube_converges_to_exact():
     # differs from the one-gas tube (the right gas matters)
     one = RiemannSolution((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), G1)
     assert abs(one.p_star - rs.p_star) > 0.01
+
+
+# ---------------------------------------------------------------- square lattice
+# The same mixture rule on the square dual-level set (D = 2: phi = (1 - gm1) e,
+# A = 2 gm1 e, b_1 = 4).
+
+
+def test_mixture_node_by_hand_square():
+    """chi = 1/2 of gamma 7/5 and 5/3 (gamma - 1 = 1/2) on the square set:
+    rho = 1, v = 0, p = 1: e = 2, phi = (1 - 1/2) e = 1, A = 2 (1/2) 2 = 2,
+    c' = (1, 2); d_1 = (4 - 2) / (4 * 3) = 1/6, d_2 = (2 - 1) / 12 = 1/12
+    (4 (d_1 + d_2) = rho, 2 (d_1 c_1^2 + d_2 c_2^2) = p)."""
+    P = oracle.Problem(2, 4, 4, gamma=G1, gamma2=G2)
+    node = [1.0, 0.0, 0.0, 2.0, 0.5]
+    L = oracle.levels(P, node)
+    assert L["gm1"] == pytest.approx(0.5, rel=1e-15)
+    assert L["e"] == 2.0 and L["phi"] == pytest.approx(1.0, rel=1e-15)
+    assert L["A"] == pytest.approx(2.0, rel=1e-15)
+    assert (L["c1"], L["c2"]) == (1, 2)
+    assert (L["d1"], L["d2"]) == pytest.approx((1.0 / 6.0, 1.0 / 12.0), rel=1e-14)
+    # pure gases
+    assert oracle.levels(P, [1.0, 0.0, 0.0, 2.0, 1.0])["gm1"] == pytest.approx(G1 - 1.0, rel=1e-15)
+    assert oracle.levels(P, [1.0, 0.0, 0.0, 2.0, 0.0])["gm1"] == pytest.approx(G2 - 1.0, rel=1e-15)
+
+
+def test_moment_identities_with_species_square():
+    P = oracle.Problem(2, 4, 4, gamma=G1, gamma2=G2)
+    rng = np.random.default_rng(44)
+    for _ in range(200):
+        rho, e, chi = rng.uniform(0.01, 5.0), rng.uniform(0.0, 6.0), rng.uniform()
+        v = rng.uniform(-2.5, 2.5, size=2)
+        node = [rho, rho * v[0], rho * v[1], rho * (e + 0.5 * v @ v), rho * chi]
+        L = oracle.levels(P, node)
+        off, pay = oracle.packets(P, node)
+        assert pay.shape == (32, 5)
+        tot = pay.sum(axis=0)
+        vm = np.abs(v).max() + math.sqrt(e) + 1
+        scale = np.array([rho, rho * vm, rho * vm, node[3] + rho, rho])
+        assert np.all(np.abs(tot - np.array(node)) <= 3e-14 * scale)
+        # pressure of the mixture: the x-lane second moment about v (eq. 24-25)
+        p = L["gm1"] * rho * L["e"]
+        assert 2 * L["d1"] * L["c1"] ** 2 + 2 * L["d2"] * L["c2"] ** 2 == pytest.approx(p, rel=1e-12, abs=1e-14 * rho)
+        m = pay[:, 0]
+        assert np.allclose(pay[:, 4], m * chi, rtol=1e-15, atol=1e-300)
+
+
+def test_equal_gases_are_one_gas_with_a_passive_label_square():
+    nx, ny = 41, 23
+    Y0 = inputs.random_state(45, 2, nx, ny, vel=(-1.1, 1.1), e=(0.1, 1.5), smooth=3)
+    P1 = oracle.Problem(2, nx, ny, bc_x=oracle.PERIODIC, bc_y=oracle.PERIODIC)
+    P2 = oracle.Problem(2, nx, ny, bc_x=oracle.PERIODIC, bc_y=oracle.PERIODIC, gamma2=P1.gamma)
+    chi = np.where(np.arange(nx)[None, :] + np.arange(ny)[:, None] < (nx + ny) // 2, 1.0, 0.0)
+    Y2 = np.concatenate([Y0, (Y0[0] * chi)[None]], axis=0)
+    A, st, _ = oracle.run(P1, Y0, 12)
+    B, st2, _ = oracle.run(P2, Y2, 12)
+    assert st == 0 and st2 == 0
+    assert np.max(np.abs(A - B[:4]) / np.max(np.abs(A), axis=(1, 2), keepdims=True)) < 1e-13
+    chi_new = B[4] / B[0]
+    assert np.all(chi_new >= -1e-15) and np.all(chi_new <= 1 + 1e-15)
+
+
+def test_two_gas_conservation_and_transpose_square():
+    n = 29
+    P = oracle.Problem(2, n, n, bc_x=oracle.PERIODIC, bc_y=oracle.PERIODIC, gamma2=G2)
+    Y0 = inputs.random_state(46, 2, n, n, vel=(-1.1, 1.1), e=(0.1, 1.5), smooth=3)
+    chi = np.random.default_rng(47).uniform(0.0, 1.0, size=(n, n))
+    Y = np.concatenate([Y0, (Y0[0] * chi)[None]], axis=0)
+    B, st, reach = oracle.run(P, Y, 10)
+    assert st == 0 and reach <= 5
+    t0, t1 = oracle.totals(P, Y), oracle.totals(P, B)
+    mom = np.sum(np.abs(Y[1])) + np.sum(np.abs(Y[2]))
+    assert np.all(np.abs(t1 - t0) <= 2e-13 * np.array([t0[0], mom, mom, t0[3], t0[0]]))
+    chi_new = B[4] / B[0]
+    assert np.all(chi_new >= -1e-15) and np.all(chi_new <= 1 + 1e-15)
+    # x <-> y: the transposed state evolves into the transposed result
+    T = np.stack([Y[0].T, Y[2].T, Y[1].T, Y[3].T, Y[4].T])
+    C, _, _ = oracle.run(P, T, 10)
+    C = np.stack([C[0].T, C[2].T, C[1].T, C[3].T, C[4].T])
+    assert np.max(np.abs(B - C) / np.max(np.abs(B), axis=(1, 2), keepdims=True)) <= 1e-13
+
+
+def _two_gas_sod_planar(nx, t_end=0.2):
+    P = oracle.Problem(2, nx, 4, gamma=G1, gamma2=G2, bc_y=oracle.TRANSMISSIVE)
+    speeds = [abs(u) + math.sqrt(g * p / r) for (r, u, _, p), g in
+              ((inputs.SOD_LEFT, G1), (inputs.SOD_RIGHT, G2))]
+    lam = 1.0 / max(speeds)
+    n = int(math.ceil(t_end * nx / lam))
+    lam = t_end * nx / n
+    x = inputs.node_x(nx)
+    Y0 = oracle.to_lattice(P, oracle.riemann_moments(P, x, inputs.SOD_LEFT, inputs.SOD_RIGHT, 0.5), lam)
+    Y, st, _ = oracle.run(P, Y0, n)
+    assert st == 0
+    return P, x, oracle.from_lattice(P, Y, lam)
+
+
+def test_two_gas_planar_tube_converges_to_exact():
+    rs = RiemannSolution((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), (G1, G2))
+    errs = []
+    for nx in (200, 400, 800):
+        P, x, Y = _two_gas_sod_planar(nx)
+        assert np.all(Y == Y[:, :1, :])  # rows stay identical
+        rho_ex, _, _ = rs.profile(x, 0.5, 0.2)
+        errs.append(l1_error(Y[0, 0], rho_ex, 1.0 / nx))
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+    pr = oracle.primitives(P, Y)
+    rho_ex, u_ex, p_ex = rs.profile(x, 0.5, 0.2)
+    assert l1_error(pr["p"][0], p_ex, 1.0 / 800) < 0.015
+    xc = 0.5 + rs.u_star * 0.2
+    i = int(np.argmax(pr["chi"][0] < 0.5))
+    assert abs(x[i] - xc) < 0.015
