@@ -95,8 +95,7 @@ int lb_create(const lb_grid* grid, double gamma, const lb_velset* velset, int32_
               lb_solver** out);
 
 /* Two gases (the different gases on the two sides of the tube that the
- * conclusions name as an extension), on the 1-D lattice or the square
- * dual-level set: gas 1 with gamma_1 and gas 2 with gamma_2, both ideal with
+ * conclusions name as an extension), on every lattice: gas 1 with gamma_1 and gas 2 with gamma_2, both ideal with
  * one gas constant, each in (1, 1 + 2/D].  The state gains a species moment
  * rho chi (chi = mass fraction of gas 1) after rho E (nf = dim + 3); every
  * packet carries its source's chi as it carries its mass, and a node's gas is
@@ -105,8 +104,8 @@ int lb_create(const lb_grid* grid, double gamma, const lb_velset* velset, int32_
  * sets phi (eq. 15) and the level speeds (eq. 26).  lb_init_riemann puts gas 1
  * on the left and gas 2 on the right (rho E and the CFL speed of each side
  * from its own gamma); lb_init_moments and lb_moments take and give all
- * fields.  The square set with a rest level (LB_LATTICE_D2_SQUARE_TRIPLE) is
- * LB_EINVAL. */
+ * fields.  With the rest level of LB_LATTICE_D2_SQUARE_TRIPLE, d_0 = d0_frac
+ * rho carries chi too. */
 int lb_create_two_gas(const lb_grid* grid, double gamma_1, double gamma_2, const lb_velset* velset,
                       int32_t precision, lb_solver** out);
 

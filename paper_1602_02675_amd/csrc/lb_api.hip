@@ -228,8 +228,6 @@ static int create_solver(const lb_grid* grid, double gamma, double gamma2, bool 
     int rc = check_model(dim, gamma, vs, precision);
     if (rc != LB_OK) return rc;
     if (species) {
-        if (vs->lattice == LB_LATTICE_D2_SQUARE_TRIPLE)
-            return fail(LB_EINVAL, "two gases: the 1-D lattice or the square dual-level set");
         if ((rc = check_model(dim, gamma2, vs, precision)) != LB_OK) return rc;
     }
     if ((rc = check_grid(grid, dim)) != LB_OK) return rc;

@@ -1,868 +1,11 @@
-// Square-lattice step as a column march (Sec. IV.B and V.A of Komeili,
-// Mirzaei, Shabouei, arXiv 1602.02675; tau = 1 so a step is the migration of
-// the equilibrium, eq. 10 / eq. 30).
-//
-// Every packet moves along x by floor(v_x) + k_x (+ c' for x-lanes) and along y
-// by floor(v_y) + k_y (+ c' for y-lanes).  The kernel splits the two:
-//   - a tile is 256 consecutive source columns (the middle 256 - 2H of them
-//     are its destination columns) by a strip of destination rows; a block of
-//     256 threads marches down the strip (persistent blocks claim tiles);
-//   - per source row, each thread turns its node's moments into what its
-//     packets need (floor v, r_y, c'_1, v_x, the packet masses per level and
-//     x corner, K + c'^2 / 2 per level) once and stages them in an LDS row
-//     buffer (double-buffered: one barrier per staged group of rows);
-//   - each destination thread gathers the packets that move into its column
-//     from the staged row (the x part of the migration) and adds each to a
-//     register FIFO of pending destination rows, indexed by the y
-//     displacement o = floor(v_y) + k_y (+ c' for y-lanes), o in [-L, L]
-//     (the y part); once source row r is in, the FIFO slot of row r - L can
-//     receive nothing more and is written out.
-// Where the staged sources around a wavefront share floor(v) and c'_1, or
-// take two adjacent values of one of floor(v_x) and c'_1 (the integer parts of
-// the migration vectors are piecewise constant), the packet classes have
-// compile-time column offsets and FIFO slots; elsewhere candidate sources are
-// matched at run time.  The same packets are summed either way; only the
-// summation order differs from the scatter definition.
-#include <climits>
-
-#include "lb_kernels.hpp"
+// Square-lattice step as a column march: the one-gas kernel instances, the
+// pool form, the launch geometry (the kernel templates and how the march
+// works are in lb_march2d.hpp).
+#include "lb_march2d.hpp"
 
 namespace lbsd {
 
 namespace {
-
-constexpr int kMTPB = 256;        // threads (= staged source columns) per block
-constexpr int kMNW = kMTPB / 64;  // wavefronts per block
-constexpr int kMH = kHalo;        // x halo (largest displacement per axis)
-// The FIFO covers y displacements o in [-L, L] (2L + 1 slots).  L = H covers
-// every packet; L = 3 covers every source with c'_1 <= 1 and |floor(v_y)|
-// small (y-reach <= 3), and leaves registers for two wavefronts per SIMD.
-constexpr int kLFull = kMH, kLSmall = 3;
-constexpr int kMinRows = 16;      // smallest strip height (bounds the y-halo overhead)
-
-// FIFO values per slot.  The y-momentum is kept as two parts: what packets
-// carry as m v_y, and the m c' of the y-lanes, summed in double-length
-// (TwoSum) arithmetic.  A y-lane packet and its mirror (opposite sign) reach a
-// destination from two different source rows, after other terms; the
-// double-length sum makes them cancel exactly when those rows are equal, so a
-// planar flow keeps v_y = 0 exactly and floor(v_y) stays uniform.
-enum { kR = 0, kPx = 1, kPyv = 2, kGh = 3, kGl = 4, kE = 5, kNV = 6 };
-
-// (h, l) += x with the rounding error of h + x carried into l (TwoSum).
-template <typename T>
-__device__ __forceinline__ void dd_add(T& h, T& l, T x)
-{
-#pragma clang fp contract(off)
-    const T s = h + x;
-    const T bp = s - h;
-    const T e = (h - (s - bp)) + (x - bp);
-    h = s;
-    l = l + e;
-}
-
-__device__ __forceinline__ int mpack(int fx, int fy, int c1)
-{
-    fx = fx < -127 ? -127 : (fx > 127 ? 127 : fx);
-    fy = fy < -127 ? -127 : (fy > 127 ? 127 : fy);
-    c1 = c1 > 255 ? 255 : c1;
-    return (fx + 128) | ((fy + 128) << 8) | (c1 << 16);
-}
-__device__ __forceinline__ int mfx(int p) { return (p & 255) - 128; }
-__device__ __forceinline__ int mfy(int p) { return ((p >> 8) & 255) - 128; }
-__device__ __forceinline__ int mc1(int p) { return (p >> 16) & 255; }
-
-template <typename T, bool SP>
-struct MRowSpecies {  // two gases: mass fraction of gas 1 per source
-    T chi[kMTPB];
-};
-template <typename T>
-struct MRowSpecies<T, false> {};  // one gas: empty (the row keeps its layout)
-
-template <typename T, bool SP = false>
-struct MRow : MRowSpecies<T, SP> {  // one staged source row (per source, see Src2)
-    T vx[kMTPB], ry[kMTPB];
-    T m[2][2][kMTPB];  // [level][x corner]
-    T kk[2][kMTPB];    // [level]
-    int pk[kMTPB];
-};
-
-// chi of the source in column s (0 with one gas)
-template <typename T, bool SP>
-__device__ __forceinline__ T chi_of(const MRow<T, SP>& R, int s)
-{
-    if constexpr (SP) return R.chi[s];
-    else return (T)0;
-}
-
-struct WaveInfo {  // per wavefront and staged row: ranges over its 64 sources
-    int fxmin, fxmax, fymin, fymax, c1min, c1max;
-    int ry0;       // 1 if every source has v_y integral (r_y = 0)
-    int pad;
-};
-
-__device__ __forceinline__ WaveInfo merge(const WaveInfo& a, const WaveInfo& b)
-{
-    return WaveInfo{min(a.fxmin, b.fxmin), max(a.fxmax, b.fxmax), min(a.fymin, b.fymin),
-                    max(a.fymax, b.fymax), min(a.c1min, b.c1min), max(a.c1max, b.c1max),
-                    a.ry0 & b.ry0, 0};
-}
-
-// Accumulator type of the FIFO for storage type T.  FP32 storage keeps FP32
-// accumulators: with the per-node primitives in FP64, FP64 accumulators did
-// not lower the FP32 form's error against FP64 on the seeded planar tubes.
-template <typename T>
-using Acc = T;
-
-template <typename T, int L, bool SP = false>
-struct Fifo {
-    static constexpr int NS = 2 * L + 1;
-    T a[NS][kNV];        // slot o + L: destination row (current source row) + o
-    T x[SP ? NS : 1];    // two gases: the species moment m chi per slot
-};
-
-// Add to the FIFO slot `slot` (differs between lanes) for slots in the
-// wavefront-uniform range [lo, hi]: each slot in range takes a select, so the
-// FIFO keeps compile-time indices (registers).  Slots out of range occur only
-// with reach > H (reported).
-template <typename A, typename T, int L, bool SP>
-__device__ __forceinline__ void fifo_add_sel(Fifo<A, L, SP>& f, int slot, int lo, int hi, T r, T px, T pyv, T e,
-                                             T xs = (T)0)
-{
-#pragma unroll
-    for (int o = 0; o < 2 * L + 1; ++o) {
-        if (o < lo || o > hi) continue;
-        const bool h = slot == o;
-        f.a[o][kR] += (A)(h ? r : (T)0);
-        f.a[o][kPx] += (A)(h ? px : (T)0);
-        f.a[o][kPyv] += (A)(h ? pyv : (T)0);
-        f.a[o][kE] += (A)(h ? e : (T)0);
-        if constexpr (SP) f.x[o] += (A)(h ? xs : (T)0);
-    }
-}
-
-template <typename A, typename T, int L, bool SP>
-__device__ __forceinline__ void fifo_add_g(Fifo<A, L, SP>& f, int slot, int lo, int hi, T v)
-{
-#pragma unroll
-    for (int o = 0; o < 2 * L + 1; ++o) {
-        if (o < lo || o > hi) continue;
-        dd_add<A>(f.a[o][kGh], f.a[o][kGl], (A)(slot == o ? v : (T)0));
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ T fmaT(T a, T b, T c);
-template <>
-__device__ __forceinline__ float fmaT<float>(float a, float b, float c)
-{
-    return __builtin_fmaf(a, b, c);
-}
-template <>
-__device__ __forceinline__ double fmaT<double>(double a, double b, double c)
-{
-    return __builtin_fma(a, b, c);
-}
-
-// The fast and the row paths add every packet class through the two helpers
-// below, with fixed expressions (explicit fused multiply-adds, no automatic
-// contraction).  A destination whose packets all come from sources of one
-// floor(v_x) and c'_1 then gets the same bits whichever path its wavefront
-// takes: the other classes add exact zeros.  Without this, wavefronts next to
-// a transition would round an at-rest region differently from their
-// neighbours, and the 1-ulp differences grow into momentum noise that flips
-// floor(v_x) between -1 and 0.
-//
-// One +-c pair of x-lane packets: masses mp (+c) and mm (-c) into slot o.
-// The pair's momentum m c' enters as (mp - mm) c, exactly zero for mirrored
-// packets of equal mass.
-template <typename A, typename T, int L, bool NOVY, bool SP>
-__device__ __forceinline__ void add_xpair(Fifo<A, L, SP>& f, int o, T mp, T mm, T vxp, T vxm, T vyp, T vym, T cc,
-                                          T zp, T zm, T xp = (T)0, T xm = (T)0)
-{
-#pragma clang fp contract(off)
-    f.a[o][kR] += (A)(mp + mm);
-    f.a[o][kPx] += (A)fmaT(mp - mm, cc, fmaT(mp, vxp, mm * vxm));
-    if (!NOVY) f.a[o][kPyv] += (A)fmaT(mp, vyp, mm * vym);
-    f.a[o][kE] += (A)fmaT(mp, zp, mm * zm);
-    if constexpr (SP) f.x[o] += (A)fmaT(mp, xp, mm * xm);
-}
-
-// The +-c y-lane packets of NQ x-corner sources (masses m[q], kk = K + c^2/2)
-// into slots op (+c) and om (-c); summed over the corners first, in order.
-template <typename A, typename T, int L, int NQ, bool NOVY, bool SP>
-__device__ __forceinline__ void add_ylanes(Fifo<A, L, SP>& f, int op, int om, const T (&m)[NQ], const T (&vx)[NQ],
-                                           const T (&vy)[NQ], const T (&kk)[NQ], T cc, const T* xq = nullptr)
-{
-#pragma clang fp contract(off)
-    T msum = m[0], pr = m[0] * vx[0], py = m[0] * vy[0];
-#pragma unroll
-    for (int q = 1; q < NQ; ++q) {
-        msum += m[q];
-        pr = fmaT(m[q], vx[q], pr);
-        py = fmaT(m[q], vy[q], py);
-    }
-    T xsum = (T)0;
-    if constexpr (SP) {
-        xsum = m[0] * xq[0];
-#pragma unroll
-        for (int q = 1; q < NQ; ++q) xsum = fmaT(m[q], xq[q], xsum);
-    }
-    const T gm = msum * cc;
-#pragma unroll
-    for (int sg = -1; sg <= 1; sg += 2) {
-        const int o = sg > 0 ? op : om;
-        const T scc = sg > 0 ? cc : -cc;
-        T pe;
-        if (NOVY) {  // v_y = 0: K + c^2/2 + s c v_y is kk exactly
-            pe = m[0] * kk[0];
-#pragma unroll
-            for (int q = 1; q < NQ; ++q) pe = fmaT(m[q], kk[q], pe);
-        } else {
-            pe = m[0] * fmaT(scc, vy[0], kk[0]);
-#pragma unroll
-            for (int q = 1; q < NQ; ++q) pe = fmaT(m[q], fmaT(scc, vy[q], kk[q]), pe);
-        }
-        f.a[o][kR] += (A)msum;
-        f.a[o][kPx] += (A)pr;
-        if (!NOVY) f.a[o][kPyv] += (A)py;
-        dd_add<A>(f.a[o][kGh], f.a[o][kGl], (A)(sg > 0 ? gm : -gm));
-        f.a[o][kE] += (A)pe;
-        if constexpr (SP) f.x[o] += (A)xsum;
-    }
-}
-
-// The rest-group packets (square set with a rest level) of NQ x-corner
-// sources (masses m[q], energy K[q]) into slot o; summed over the corners
-// first, in order, like add_ylanes.
-template <typename A, typename T, int L, int NQ, bool NOVY, bool SP>
-__device__ __forceinline__ void add_rest(Fifo<A, L, SP>& f, int o, const T (&m)[NQ], const T (&vx)[NQ],
-                                         const T (&vy)[NQ], const T (&K)[NQ], const T* xq = nullptr)
-{
-#pragma clang fp contract(off)
-    T msum = m[0], pr = m[0] * vx[0], py = m[0] * vy[0], pe = m[0] * K[0];
-#pragma unroll
-    for (int q = 1; q < NQ; ++q) {
-        msum += m[q];
-        pr = fmaT(m[q], vx[q], pr);
-        py = fmaT(m[q], vy[q], py);
-        pe = fmaT(m[q], K[q], pe);
-    }
-    f.a[o][kR] += (A)msum;
-    f.a[o][kPx] += (A)pr;
-    if (!NOVY) f.a[o][kPyv] += (A)py;
-    f.a[o][kE] += (A)pe;
-    if constexpr (SP) {
-        T xsum = m[0] * xq[0];
-#pragma unroll
-        for (int q = 1; q < NQ; ++q) xsum = fmaT(m[q], xq[q], xsum);
-        f.x[o] += (A)xsum;
-    }
-}
-
-// Rest-group mass at x corner kc of the source in column s: d_0 = rq (d_1 +
-// d_2) of the staged level masses; and its energy per unit mass, K.
-template <typename T, bool SP>
-__device__ __forceinline__ T rest_mass(const MRow<T, SP>& R, int kc, int s, T rq)
-{
-    return rq * (R.m[0][kc][s] + R.m[1][kc][s]);
-}
-template <typename T, bool SP>
-__device__ __forceinline__ T rest_k(const MRow<T, SP>& R, int s)
-{
-    const int c1 = mc1(R.pk[s]);
-    return R.kk[0][s] - (T)0.5 * (T)(c1 * c1);
-}
-
-// Window where every source has floor(v_y) = FY, floor(v_x) in {fx - NKX + 2,
-// fx} and c'_1 in {S0, S0 + NSP - 2}: the lanes of the window have speeds
-// S0 .. S0 + NSP - 1, four per speed (+-x, +-y), and a source puts its level-1
-// weight d_1 on speed c'_1 and d_2 on c'_1 + 1 (zero on the others); its x
-// corners k_x = 0, 1 sit at x displacement floor(v_x) + k_x, i.e. at corners
-// -1 .. 1 relative to fx.  Every packet class then has a compile-time column
-// offset and FIFO slot.  NSP = 2, NKX = 2 is the uniform window.
-// RY0: every source has r_y = 0, so the corners k_y = 1 carry no mass (eq. 29)
-// and are skipped; with FY = 0 also v_y = 0 and the m v_y terms vanish.  The
-// sums are the same, term for term.  REST: the rest group's packets (from the
-// sources at x displacement floor(v_x) + k_x, into row FY + k_y) follow the
-// lanes.
-template <typename T, int L, int FY, int S0, int NSP, int NKX, bool RY0, bool REST, bool SP>
-__device__ __forceinline__ void gather_fast(const MRow<T, SP>& R, int lane, int fx, Fifo<Acc<T>, L, SP>& f, T rq)
-{
-#pragma clang fp contract(off)
-    constexpr bool UNI = NSP == 2;
-    constexpr bool NOVY = RY0 && FY == 0;
-    constexpr int K0 = NKX == 3 ? -1 : 0;  // first x corner relative to floor(v_x) = fx
-    const int base = lane - fx;  // staged column of x displacement fx + a is base - a
-    // level (0: c'_1, 1: c'_2) that the source in column s has at speed
-    // S0 + j, or -1 (no lane of that speed)
-    auto level = [&](int s, int j) -> int {
-        if (UNI) return j;
-        const int l = S0 + j - mc1(R.pk[s]);
-        return (l == 0 || l == 1) ? l : -1;
-    };
-    // packet mass of the source in column s at x corner k (relative to fx) and
-    // speed S0 + j; with NKX = 3 a source may have floor(v_x) = fx - 1
-    auto mass = [&](int s, int j, int k) -> T {
-        const int l = level(s, j);
-        const int kc = NKX == 2 ? k : k + fx - mfx(R.pk[s]);  // the source's own corner
-        if (UNI && NKX == 2) return R.m[l][kc][s];
-        const T v = R.m[l < 0 ? 0 : l][kc < 0 ? 0 : (kc > 1 ? 1 : kc)][s];
-        return (l >= 0 && kc >= 0 && kc <= 1) ? v : (T)0;
-    };
-    auto kkof = [&](int s, int j) -> T {
-        const int l = level(s, j);
-        return R.kk[l < 0 ? 0 : l][s];  // any finite value when the mass is zero
-    };
-#pragma unroll
-    for (int j = 0; j < NSP; ++j) {
-        const int c = S0 + j;
-        const T cc = (T)c;
-        // x-lanes: destination row FY + ky, source columns base - (kx +- c)
-#pragma unroll
-        for (int kx = K0; kx < 2; ++kx) {
-            const int sp = base - (kx + c), sm = base - (kx - c);
-            const T bp = mass(sp, j, kx), bm = mass(sm, j, kx);
-            const T vxp = R.vx[sp], vxm = R.vx[sm];
-            const T ryp = R.ry[sp], rym = R.ry[sm];
-            const T vyp = (T)FY + ryp, vym = (T)FY + rym;
-            const T zp = fmaT(cc, vxp, kkof(sp, j)), zm = fmaT(-cc, vxm, kkof(sm, j));
-#pragma unroll
-            for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
-                const T mp = RY0 ? bp : bp * (ky ? ryp : (T)1 - ryp);
-                const T mm = RY0 ? bm : bm * (ky ? rym : (T)1 - rym);
-                if constexpr (SP)
-                    add_xpair<Acc<T>, T, L, NOVY>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm,
-                                                  chi_of(R, sp), chi_of(R, sm));
-                else
-                    add_xpair<Acc<T>, T, L, NOVY>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm);
-            }
-        }
-        // y-lanes: source columns base - kx
-        T b[NKX], ry[NKX], vx[NKX], vy[NKX], kk[NKX], xq[NKX];
-#pragma unroll
-        for (int q = 0; q < NKX; ++q) {
-            const int kx = K0 + q, sq = base - kx;
-            b[q] = mass(sq, j, kx);
-            ry[q] = R.ry[sq];
-            vx[q] = R.vx[sq];
-            vy[q] = (T)FY + ry[q];
-            kk[q] = kkof(sq, j);
-            xq[q] = chi_of(R, sq);
-        }
-#pragma unroll
-        for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
-            T m[NKX];
-#pragma unroll
-            for (int q = 0; q < NKX; ++q) m[q] = RY0 ? b[q] : b[q] * (ky ? ry[q] : (T)1 - ry[q]);
-            add_ylanes<Acc<T>, T, L, NKX, NOVY>(f, FY + ky + c + L, FY + ky - c + L, m, vx, vy, kk, cc, xq);
-        }
-    }
-    if constexpr (REST) {  // rest group: source columns base - kx, row FY + ky
-        T b[NKX], ry[NKX], vx[NKX], vy[NKX], kr[NKX], xq[NKX];
-#pragma unroll
-        for (int q = 0; q < NKX; ++q) {
-            const int kx = K0 + q, sq = base - kx;
-            const int kc = NKX == 2 ? kx : kx + fx - mfx(R.pk[sq]);  // the source's own corner
-            const T v = rest_mass(R, kc < 0 ? 0 : (kc > 1 ? 1 : kc), sq, rq);
-            b[q] = (kc >= 0 && kc <= 1) ? v : (T)0;
-            ry[q] = R.ry[sq];
-            vx[q] = R.vx[sq];
-            vy[q] = (T)FY + ry[q];
-            kr[q] = rest_k(R, sq);
-            xq[q] = chi_of(R, sq);
-        }
-#pragma unroll
-        for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
-            T m[NKX];
-#pragma unroll
-            for (int q = 0; q < NKX; ++q) m[q] = RY0 ? b[q] : b[q] * (ky ? ry[q] : (T)1 - ry[q]);
-            add_rest<Acc<T>, T, L, NKX, NOVY>(f, FY + ky + L, m, vx, vy, kr, xq);
-        }
-    }
-}
-
-// Rows where every source seen by this wavefront has floor(v_y) = FY: the
-// FIFO slot of every packet is known at compile time up to c'_1, which is
-// taken from its (short) range [clo, chi] in unrolled branches; floor(v_x)
-// and c'_1 may vary along the row.  Packets are taken per class (level, k_x,
-// floor(v_x) = F, speed C): the x-lane pair +-C of a class comes from the two
-// sources at x displacement k_x + F -+ C, and counts when that source has this
-// F and speed C on this level (zero mass otherwise).  With chk (uniform), a
-// source counts only if its floor(v_y) is FY as well: two such calls, for FY
-// and FY + 1, take a window whose floor(v_y) has two adjacent values.  REST:
-// the rest group's packets follow the lanes, in the fast path's order.
-template <typename T, int L, int FY, bool REST, bool SP>
-__device__ __forceinline__ void gather_rows(const MRow<T, SP>& R, int lane, Fifo<Acc<T>, L, SP>& f, int fxlo,
-                                            int fxhi, int clo, int chi, bool chk, T rq)
-{
-#pragma clang fp contract(off)
-    const int nfx = fxhi - fxlo;
-#pragma unroll
-    for (int lev = 0; lev < 2; ++lev) {
-        const int cl = clo + lev, ch = chi + lev;  // speeds of this level in the window
-#pragma unroll
-        for (int kx = 0; kx < 2; ++kx) {
-            for (int i = 0; i <= nfx; ++i) {
-                const int F = fxlo + i;
-                for (int C = cl; C <= ch; ++C) {
-                    const int sp = lane - (kx + F + C), sm = lane - (kx + F - C);
-                    const int pkp = R.pk[sp], pkm = R.pk[sm];
-                    const bool okp = mfx(pkp) == F && mc1(pkp) + lev == C && (!chk || mfy(pkp) == FY);
-                    const bool okm = mfx(pkm) == F && mc1(pkm) + lev == C && (!chk || mfy(pkm) == FY);
-                    const T bp = okp ? R.m[lev][kx][sp] : (T)0, bm = okm ? R.m[lev][kx][sm] : (T)0;
-                    const T vxp = R.vx[sp], vxm = R.vx[sm];
-                    const T ryp = R.ry[sp], rym = R.ry[sm];
-                    const T vyp = (T)FY + ryp, vym = (T)FY + rym;
-                    const T cc = (T)C;
-                    const T zp = fmaT(cc, vxp, R.kk[lev][sp]), zm = fmaT(-cc, vxm, R.kk[lev][sm]);
-#pragma unroll
-                    for (int ky = 0; ky < 2; ++ky) {
-                        const T mp = bp * (ky ? ryp : (T)1 - ryp), mm = bm * (ky ? rym : (T)1 - rym);
-                        if constexpr (SP)
-                            add_xpair<Acc<T>, T, L, false>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm,
-                                                           chi_of(R, sp), chi_of(R, sm));
-                        else
-                            add_xpair<Acc<T>, T, L, false>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm);
-                    }
-                }
-            }
-        }
-        // y-lanes: the corners k_x = 0, 1 of floor(v_x) = F sit at x
-        // displacement F and F + 1
-        for (int i = 0; i <= nfx; ++i) {
-            const int F = fxlo + i;
-            const int s0 = lane - F, s1 = lane - F - 1;
-            const int pk0 = R.pk[s0], pk1 = R.pk[s1];
-            const bool ok0 = mfx(pk0) == F && (!chk || mfy(pk0) == FY);
-            const bool ok1 = mfx(pk1) == F && (!chk || mfy(pk1) == FY);
-            const int c0 = mc1(pk0) + lev, c1 = mc1(pk1) + lev;
-            const T ry[2] = {R.ry[s0], R.ry[s1]};
-            const T b0 = ok0 ? R.m[lev][0][s0] : (T)0, b1 = ok1 ? R.m[lev][1][s1] : (T)0;
-            const T vx[2] = {R.vx[s0], R.vx[s1]};
-            const T vy[2] = {(T)FY + ry[0], (T)FY + ry[1]};
-            const T kk[2] = {R.kk[lev][s0], R.kk[lev][s1]};
-            const T xq[2] = {chi_of(R, s0), chi_of(R, s1)};
-#pragma unroll
-            for (int C = 0; C <= 3 + 1; ++C) {  // speed of this level, static
-                if (C < cl || C > ch) continue;
-                if (FY + 1 + C > L || FY - C < -L) continue;  // out of the FIFO: redone / reported
-                const T w0 = c0 == C ? b0 : (T)0, w1 = c1 == C ? b1 : (T)0;
-                const T cc = (T)C;
-#pragma unroll
-                for (int ky = 0; ky < 2; ++ky) {
-                    const T m[2] = {w0 * (ky ? ry[0] : (T)1 - ry[0]), w1 * (ky ? ry[1] : (T)1 - ry[1])};
-                    add_ylanes<Acc<T>, T, L, 2, false>(f, FY + ky + C + L, FY + ky - C + L, m, vx, vy, kk, cc, xq);
-                }
-            }
-        }
-    }
-    if constexpr (REST) {  // rest group: corners k_x = 0, 1 of floor(v_x) = F at F and F + 1
-        for (int i = 0; i <= nfx; ++i) {
-            const int F = fxlo + i;
-            const int s0 = lane - F, s1 = lane - F - 1;
-            const int pk0 = R.pk[s0], pk1 = R.pk[s1];
-            const bool ok0 = mfx(pk0) == F && (!chk || mfy(pk0) == FY);
-            const bool ok1 = mfx(pk1) == F && (!chk || mfy(pk1) == FY);
-            const T ry[2] = {R.ry[s0], R.ry[s1]};
-            const T b0 = ok0 ? rest_mass(R, 0, s0, rq) : (T)0, b1 = ok1 ? rest_mass(R, 1, s1, rq) : (T)0;
-            const T vx[2] = {R.vx[s0], R.vx[s1]};
-            const T vy[2] = {(T)FY + ry[0], (T)FY + ry[1]};
-            const T kr[2] = {rest_k(R, s0), rest_k(R, s1)};
-            const T xq[2] = {chi_of(R, s0), chi_of(R, s1)};
-#pragma unroll
-            for (int ky = 0; ky < 2; ++ky) {
-                const T m[2] = {b0 * (ky ? ry[0] : (T)1 - ry[0]), b1 * (ky ? ry[1] : (T)1 - ry[1])};
-                add_rest<Acc<T>, T, L, 2, false>(f, FY + ky + L, m, vx, vy, kr, xq);
-            }
-        }
-    }
-}
-
-// Any mix of floor(v) and c'_1 around the destination (floor(v_y) varies
-// across the wavefront, i.e. the flow is not planar here): examine the staged
-// sources at x displacements [alo, ahi] (all that the window's packets can
-// have, within the halo) and every packet that reaches this column.
-// [fylo, fyhi] and [clo, chi] are the window's ranges of floor(v_y) and c'_1:
-// each packet class then reaches one or two FIFO slots, and only those are
-// visited.  REST: the set has a rest group, whose packets (mass
-// rq (d_1 + d_2) per corner, energy K) move like the y-lanes with c' = 0.
-template <typename T, int L, bool REST, bool SP>
-__device__ void gather_general(const MRow<T, SP>& R, int lane, Fifo<Acc<T>, L, SP>& f, int alo, int ahi, int fylo,
-                               int fyhi, int clo, int chi, T rq)
-{
-#pragma clang fp contract(off)
-#pragma unroll 1
-    for (int a = alo; a <= ahi; ++a) {  // x displacements the window's packets can have
-        const int s = lane - a;
-        const int pk = R.pk[s];
-        const int fx = mfx(pk), fy = mfy(pk), c1 = mc1(pk), c2 = c1 + 1;
-        const T vx = R.vx[s], ry = R.ry[s];
-        const T vy = (T)fy + ry;
-        const T xs = chi_of(R, s);  // two gases: mass fraction of gas 1
-#pragma unroll 1
-        for (int kx = 0; kx < 2; ++kx) {
-            const int cx = a - fx - kx;  // x-lane speed needed to land here
-            // x-lanes with c' = cx: +-c1 (both when c1 = 0) or +-c2
-            const int n1 = (cx == c1 || cx == -c1) ? (c1 == 0 ? 2 : 1) : 0;
-            const int n2 = (cx == c2 || cx == -c2) ? 1 : 0;
-            if (n1 + n2 > 0) {
-                const int l = n1 > 0 ? 0 : 1;
-                const T w = (T)(n1 + n2) * R.m[l][kx][s];
-                const T cc = (T)cx;
-                const T zx = fmaT(cc, vx, R.kk[l][s]);
-#pragma unroll 1
-                for (int ky = 0; ky < 2; ++ky) {
-                    const T m = w * (ky ? ry : (T)1 - ry);
-                    fifo_add_sel<Acc<T>, T, L>(f, fy + ky + L, fylo + ky + L, fyhi + ky + L, m, m * (vx + cc),
-                                               m * vy, m * zx, m * xs);
-                }
-            }
-            if (cx == 0) {  // y-lanes (and the rest group) move in x by fx + kx only
-                if constexpr (REST) {
-                    const T mr = rq * (R.m[0][kx][s] + R.m[1][kx][s]);
-                    const T zr = R.kk[0][s] - (T)0.5 * (T)(c1 * c1);  // K
-#pragma unroll 1
-                    for (int ky = 0; ky < 2; ++ky) {
-                        const T m = mr * (ky ? ry : (T)1 - ry);
-                        fifo_add_sel<Acc<T>, T, L>(f, fy + ky + L, fylo + ky + L, fyhi + ky + L, m, m * vx,
-                                                   m * vy, m * zr, m * xs);
-                    }
-                }
-#pragma unroll 1
-                for (int l = 0; l < 2; ++l) {
-                    const int c = l == 0 ? c1 : c2;
-#pragma unroll 1
-                    for (int sg = -1; sg <= 1; sg += 2) {
-                        const T cc = (T)(sg * c);
-                        const T zy = fmaT(cc, vy, R.kk[l][s]);
-#pragma unroll 1
-                        for (int ky = 0; ky < 2; ++ky) {
-                            const T m = R.m[l][kx][s] * (ky ? ry : (T)1 - ry);
-                            const int slot = fy + ky + sg * c + L;
-                            // the window's range of this packet class's slot (uniform)
-                            const int lo = fylo + ky + (sg > 0 ? clo + l : -(chi + l)) + L;
-                            const int hi = fyhi + ky + (sg > 0 ? chi + l : -(clo + l)) + L;
-                            fifo_add_sel<Acc<T>, T, L>(f, slot, lo, hi, m, m * vx, m * vy, m * zy, m * xs);
-                            fifo_add_g<Acc<T>, T, L>(f, slot, lo, hi, m * cc);
-                        }
-                    }
-                }
-            }
-        }
-    }
-}
-
-template <typename T, int NF>
-__device__ __forceinline__ void load_node(const T* __restrict__ Y, int64_t nn, int64_t q, T (&m)[NF])
-{
-    m[0] = Y[q];
-    m[1] = Y[nn + q];
-    m[2] = Y[2 * nn + q];
-    m[3] = Y[3 * nn + q];
-    if constexpr (NF > 4) m[4] = Y[4 * nn + q];
-}
-
-// One tile: destination columns [X0, X0 + 256 - 2H) and rows [Y0, Y0 + sy)
-// (clipped to the grid) of grid g, marched from row Y0 - L to Y0 + sy + L - 1.
-// Writes Yn and one row of per-tile partials (field sums, reach, error bits).
-// Returns 1 (the same in every thread) when the short pass cannot take some
-// window of the tile: a y-displacement beyond the short FIFO (kLSmall), or a
-// non-planar window (floor(v_y) not uniform, and the mixes the row path does
-// not take), which only the full pass's paths handle.  With L = kLSmall the
-// tile's output is then incomplete and must be recomputed with L = kLFull,
-// which sums in the same order (bit-identical); with L = kLFull it tells that
-// the tile still needs the full pass.
-// Contains block-wide barriers: every thread of the block must call it.
-template <typename T, int L, bool WALLS, bool REST, bool SP>
-__device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict__ Yn, const Grid& g, const Consts& k,
-                          int64_t X0, int64_t Y0, int sy, double* __restrict__ prow)
-{
-    // source rows staged per barrier: two in FP64 (fewer barriers, two
-    // independent per-source computations in flight); FP32 has no registers left
-    constexpr int RB = sizeof(T) == 8 ? 2 : 1;
-    constexpr int NF = SP ? 5 : 4;  // moment fields (two gases: rho chi after rho E)
-    __shared__ MRow<T, SP> s_row[2][RB];
-    __shared__ WaveInfo s_w[2][RB][kMNW];
-    const int tid = threadIdx.x, lane64 = tid & 63, wid = tid >> 6;
-    const T rq = REST ? (T)k.rest_q : (T)0;  // rest-group mass per unit of staged level mass
-    const int64_t nx = g.nx, ny = g.ny, nn = nx * ny;
-    const int64_t gx = X0 - kMH + tid;                           // this thread's source column
-    bool mir_x = false;
-    int64_t sx;
-    if constexpr (WALLS) sx = source_idx(gx, nx, g.bc_x, &mir_x);
-    else sx = g.bc_x == kBcPeriodic ? wrap_near(gx, nx) : clamp_idx(gx, nx);
-    const bool dest = tid >= kMH && tid < kMTPB - kMH && gx < nx;
-    const int64_t ylast = min(Y0 + (int64_t)sy, ny);  // destination rows [Y0, ylast)
-    const int nrows = Y0 < ny ? (int)(ylast - Y0) + 2 * L : 0;
-    constexpr int NS = 2 * L + 1;
-
-    using A = Acc<T>;
-    Fifo<A, L, SP> f;
-#pragma unroll
-    for (int o = 0; o < NS; ++o) {
-#pragma unroll
-        for (int c = 0; c < kNV; ++c) f.a[o][c] = (A)0;
-        if constexpr (SP) f.x[o] = (A)0;
-    }
-    double tot[NF] = {};
-    int reach = 0, bad = 0, yfar = 0;
-
-    // moments of this thread's source column in row gy (halo rows and
-    // columns mapped by the boundaries); *mir_y tells whether the row is a
-    // mirror image beyond a wall.  Mirror images negate normal momentum when
-    // the row is staged, so that the loads issued a row ahead are not waited for.
-    auto load_src = [&](int64_t gy, T (&m)[NF], bool* mir_y) {
-        int64_t yy;
-        if constexpr (WALLS) yy = source_idx(gy, ny, g.bc_y, mir_y);
-        else yy = g.bc_y == kBcPeriodic ? wrap_near(gy, ny) : clamp_idx(gy, ny);
-        load_node<T, NF>(Y, nn, yy * nx + sx, m);
-    };
-    T cur[RB][NF], nxt[RB][NF];
-    bool cur_my[RB] = {}, nxt_my[RB] = {};
-#pragma unroll
-    for (int u = 0; u < RB; ++u)
-        if (u < nrows) load_src(Y0 - L + u, cur[u], &cur_my[u]);
-
-    for (int r0 = 0; r0 < nrows; r0 += RB) {
-        const int b = (r0 / RB) & 1;
-#pragma unroll
-        for (int u = 0; u < RB; ++u)
-            if (r0 + RB + u < nrows) load_src(Y0 - L + r0 + RB + u, nxt[u], &nxt_my[u]);
-#pragma unroll
-        for (int u = 0; u < RB; ++u) {
-            if (r0 + u >= nrows) break;
-            // stage this source row
-            T mx = cur[u][1], my = cur[u][2];
-            if constexpr (WALLS) {
-                mx = mir_x ? -mx : mx;
-                my = cur_my[u] ? -my : my;
-            }
-            const Src2<T> s = make_src2<T, REST, SP>(cur[u][0], mx, my, cur[u][3], k, cur[u][NF - 1]);
-            const int pk = mpack(s.fx, s.fy, s.c1);
-            s_row[b][u].vx[tid] = s.vx;
-            s_row[b][u].ry[tid] = s.ry;
-            s_row[b][u].m[0][0][tid] = s.m[0][0];
-            s_row[b][u].m[0][1][tid] = s.m[0][1];
-            s_row[b][u].m[1][0][tid] = s.m[1][0];
-            s_row[b][u].m[1][1][tid] = s.m[1][1];
-            s_row[b][u].kk[0][tid] = s.kk[0];
-            s_row[b][u].kk[1][tid] = s.kk[1];
-            s_row[b][u].pk[tid] = pk;
-            if constexpr (SP) s_row[b][u].chi[tid] = s.chi;
-            const int yr = axis_reach(s.fy, s.c1);
-            reach = max(reach, max(axis_reach(s.fx, s.c1), yr));
-            yfar |= yr > kLSmall ? 1 : 0;
-            bad |= s.bad ? 1 : 0;
-            {
-                const int ry0 = __all(s.ry == (T)0) ? 1 : 0;
-                const int pk0 = __builtin_amdgcn_readfirstlane(pk);
-                WaveInfo wi;
-                if (__all(pk == pk0)) {  // the common case: one ballot instead of six reductions
-                    wi = WaveInfo{mfx(pk0), mfx(pk0), mfy(pk0), mfy(pk0), mc1(pk0), mc1(pk0), ry0, 0};
-                } else {
-                    wi = WaveInfo{wave_min(s.fx), wave_max(s.fx), wave_min(s.fy), wave_max(s.fy),
-                                  wave_min(s.c1), wave_max(s.c1), ry0, 0};
-                }
-                if (lane64 == 0) s_w[b][u][wid] = wi;
-            }
-
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < RB; ++u) {
-            const int r = r0 + u;
-            if (r >= nrows) break;
-            // gather this row's packets into the FIFO
-            WaveInfo w = s_w[b][u][wid];
-            if (wid > 0) w = merge(w, s_w[b][u][wid - 1]);
-            if (wid + 1 < kMNW) w = merge(w, s_w[b][u][wid + 1]);
-            // the fast and row paths need every packet of the window inside the
-            // FIFO (y) and the staged row (x); the full pass's general path
-            // takes any window whose sources each reach <= H.
-            const int c2max = w.c1max + 1;
-            const bool fits_y = w.fymin - c2max >= -L && w.fymax + 1 + c2max <= L;
-            const bool fits_small = w.fymin - c2max >= -kLSmall && w.fymax + 1 + c2max <= kLSmall;
-            const bool fits_x = w.fxmin - c2max >= -kMH && w.fxmax + 1 + c2max <= kMH;
-            const bool planar = fits_x && w.fymin == w.fymax && (w.fymin == 0 || w.fymin == -1) &&
-                                w.c1max <= 3 && w.fxmax - w.fxmin <= 2;
-            const bool rows_ok = planar && fits_y;
-            // the short pass takes planar windows within its FIFO; a tile with
-            // any other window is flagged for the full pass
-            if (!(planar && fits_small)) yfar = 1;
-            // full pass, floor(v_y) in {-1, 0} (where v_y changes sign): the row
-            // path once per value (other pairs of values take the general path:
-            // their instances made the compiler spill the FIFO on every path)
-            const bool ymix_ok = fits_x && fits_y && w.fymin == -1 && w.fymax == 0 && w.c1max <= 3 &&
-                                 w.fxmax - w.fxmin <= 2;
-            if (dest && (fits_y || L == kLFull)) {
-                // two adjacent values of c'_1 or of floor(v_x) keep compile-time
-                // offsets; a window mixing both (rare in planar flows) takes the
-                // row path, whose extra registers would otherwise cost occupancy
-                const bool cmix = w.c1max == w.c1min + 1, xmix = w.fxmax == w.fxmin + 1;
-                const bool fastw = rows_ok && (w.c1max == w.c1min || cmix) && (w.fxmax == w.fxmin || xmix) &&
-                                   !(cmix && xmix) && (!cmix || w.c1min <= 2) && (!xmix || w.c1min <= 1);
-                if (fastw) {
-                    const auto& R = s_row[b][u];
-                    const int fx0 = w.fxmax;
-                    const int sel = ((w.fymin == 0 ? (w.ry0 ? 0 : 1) : 2) * 2 + (xmix ? 1 : 0)) * 8 +
-                                    (cmix ? 4 : 0) + w.c1min;
-                    switch (sel) {
-    #define LB_FAST(S, FYV, S0, NSP, NKX, RY)                                                   \
-        case S:                                                                                 \
-            if constexpr ((FYV) - (S0) - (NSP) + 1 >= -L && (FYV) + 1 + (S0) + (NSP) - 1 <= L)  \
-                gather_fast<T, L, FYV, S0, NSP, NKX, RY, REST>(R, tid, fx0, f, rq);             \
-            break;
-    #define LB_FAST_SET(B, FYV, RY)                                                              \
-        LB_FAST(B + 0, FYV, 0, 2, 2, RY) LB_FAST(B + 1, FYV, 1, 2, 2, RY) LB_FAST(B + 2, FYV, 2, 2, 2, RY) \
-        LB_FAST(B + 3, FYV, 3, 2, 2, RY) LB_FAST(B + 4, FYV, 0, 3, 2, RY) LB_FAST(B + 5, FYV, 1, 3, 2, RY) \
-        LB_FAST(B + 6, FYV, 2, 3, 2, RY)                                                        \
-        LB_FAST(B + 8, FYV, 0, 2, 3, RY) LB_FAST(B + 9, FYV, 1, 2, 3, RY)
-                        LB_FAST_SET(0, 0, true)
-                        LB_FAST_SET(16, 0, false)
-                        LB_FAST_SET(32, -1, false)
-    #undef LB_FAST_SET
-    #undef LB_FAST
-                        default: break;  // not reached: fastw admits only the cases above
-                    }
-                } else if (L < kLFull) {
-                    if (rows_ok) {
-                        const auto& R = s_row[b][u];
-                        if (w.fymin == -1)
-                            gather_rows<T, L, -1, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, false, rq);
-                        else
-                            gather_rows<T, L, 0, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, false, rq);
-                    }  // other windows: the tile is flagged (above)
-                } else if (rows_ok || ymix_ok) {
-                    // one call per value of floor(v_y) in the window (one
-                    // call site per instance keeps the kernel's code compact)
-                    const auto& R = s_row[b][u];
-                    if (w.fymin == -1)
-                        gather_rows<T, L, -1, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, ymix_ok, rq);
-                    if (w.fymax == 0)
-                        gather_rows<T, L, 0, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, ymix_ok, rq);
-                } else {
-                    gather_general<T, L, REST>(s_row[b][u], tid, f, max(-kMH, w.fxmin - c2max),
-                                               min(kMH, w.fxmax + 1 + c2max), w.fymin, w.fymax, w.c1min, w.c1max,
-                                               rq);
-                }
-            }
-            // destination row (source row) - L is complete
-            if (r >= 2 * L && dest) {
-                const int64_t ty = Y0 + r - 2 * L;
-                const int64_t q = ty * nx + gx;
-                const T py = (T)(f.a[0][kPyv] + (f.a[0][kGh] + f.a[0][kGl]));
-                Yn[q] = (T)f.a[0][kR];
-                Yn[nn + q] = (T)f.a[0][kPx];
-                Yn[2 * nn + q] = py;
-                Yn[3 * nn + q] = (T)f.a[0][kE];
-                tot[0] += (double)f.a[0][kR];
-                tot[1] += (double)f.a[0][kPx];
-                tot[2] += (double)py;
-                tot[3] += (double)f.a[0][kE];
-                if constexpr (SP) {
-                    Yn[4 * nn + q] = (T)f.x[0];
-                    tot[NF - 1] += (double)f.x[0];
-                }
-            }
-    #pragma unroll
-            for (int o = 0; o + 1 < NS; ++o) {
-    #pragma unroll
-                for (int c = 0; c < kNV; ++c) f.a[o][c] = f.a[o + 1][c];
-                if constexpr (SP) f.x[o] = f.x[o + 1];
-            }
-    #pragma unroll
-            for (int c = 0; c < kNV; ++c) f.a[NS - 1][c] = (A)0;
-            if constexpr (SP) f.x[NS - 1] = (A)0;
-        }
-#pragma unroll
-        for (int u = 0; u < RB; ++u) {
-#pragma unroll
-            for (int c = 0; c < NF; ++c) cur[u][c] = nxt[u][c];
-            if constexpr (WALLS) cur_my[u] = nxt_my[u];
-        }
-    }
-    // per-tile partials: field sums (a fifth, rho chi, at index 6), reach, error bits
-    __shared__ double s_sum[kMNW][NF];
-    __shared__ int s_ir[kMNW][2];
-#pragma unroll
-    for (int c = 0; c < NF; ++c) tot[c] = wave_sum(tot[c]);
-    reach = wave_max(reach);
-    bad = wave_max(bad);
-    if (lane64 == 0) {
-#pragma unroll
-        for (int c = 0; c < NF; ++c) s_sum[wid][c] = tot[c];
-        s_ir[wid][0] = reach;
-        s_ir[wid][1] = bad;
-    }
-    const int far = __syncthreads_or(yfar);
-    if (tid == 0) {
-        int rr = 0, bb = 0;
-        for (int c = 0; c < NF; ++c) {
-            double t = s_sum[0][c];
-            for (int w = 1; w < kMNW; ++w) t += s_sum[w][c];
-            prow[c < 4 ? c : 6] = t;
-        }
-        for (int w = 0; w < kMNW; ++w) {
-            rr = max(rr, s_ir[w][0]);
-            bb |= s_ir[w][1];
-        }
-        prow[4] = (double)rr;
-        prow[5] = (double)((rr > kMH ? kErrReach : 0) | (bb ? kErrState : 0));
-    }
-    return far;
-}
-
-// Wavefronts per SIMD the short-FIFO kernels are compiled for: FP64 keeps its
-// FIFO in registers at two; FP32 fits four with a few spilled registers.
-#ifndef LB_MARCH_WPE
-#define LB_MARCH_WPE 2
-#endif
-#ifndef LB_MARCH_WPE_F32
-#define LB_MARCH_WPE_F32 4
-#endif
-// L = kLSmall: the short-FIFO pass; a tile whose sources reach beyond its FIFO
-// is flagged.  L = kLFull: computes the flagged tiles (bit-identically: the
-// summation order does not depend on L) and keeps the flag of each that still
-// needs the full FIFO; the next step's short pass leaves such tiles to the
-// full pass instead of computing them twice (flows change little per step).
-// Persistent blocks claim the tiles (tiles_x column strips x row chunks of sy
-// rows, row chunk major) from the control block's counter of the pass.
-template <typename T, int L, bool WALLS, bool REST, bool SP>
-__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
-march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
-               StepCtl* __restrict__ ctl, double* __restrict__ partials, int* __restrict__ flags,
-               long long step, int sy, int tiles_x, int ntiles)
-{
-    __shared__ int s_t;
-    if (ctl->err_step < step) return;
-    if (L == kLFull && ctl->next[2] == 0) return;  // the short pass flagged no tile
-    // some tile kept its flag in the previous step's full pass (else every
-    // flag is clear and the short pass need not read them)
-    const bool kept = L < kLFull && ctl->keep[1] != 0;
-    for (;;) {
-        const int t = claim_tile(&ctl->next[L < kLFull ? 0 : 1], &s_t);
-        if (t >= ntiles) break;
-        if (L < kLFull) {
-            if (kept && flags[t]) {  // needed the full pass last step: left to it
-                if (threadIdx.x == 0) atomicAdd(&ctl->next[2], 1);
-                continue;
-            }
-        } else if (!flags[t]) {
-            continue;
-        }
-        const int64_t tx = t % tiles_x, ty = t / tiles_x;
-        const int far = march_tile<T, L, WALLS, REST, SP>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
-                                                      partials + (int64_t)t * kPartialStride);
-        if (threadIdx.x == 0) {
-            flags[t] = far;
-            if (L < kLFull && far) atomicAdd(&ctl->next[2], 1);
-            if (L == kLFull) {
-                atomicAdd(&ctl->redo_tiles, 1);
-                if (far) atomicAdd(&ctl->keep[0], 1);
-            }
-        }
-    }
-}
 
 // Pool form: persistent blocks claim tiles of the tile table (see
 // pool1d_kernel).  The short-FIFO pass flags the tiles it could not complete;
@@ -941,22 +84,6 @@ int march2d_blocks_per_cu()
     return nb > 0 ? nb : 1;
 }
 
-template <typename T, bool WALLS, bool REST, bool SP>
-hipError_t launch_march2d_w(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
-                            StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream)
-{
-    const int nt = (int)m.blocks();
-    march2d_kernel<T, kLSmall, WALLS, REST, SP><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials,
-                                                                                 flags, step, m.sy,
-                                                                                 (int)m.grid_x, nt);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    march2d_kernel<T, kLFull, WALLS, REST, SP><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials,
-                                                                                flags, step, m.sy,
-                                                                                (int)m.grid_x, nt);
-    return hipGetLastError();
-}
-
 // Grids without reflecting walls run the instances that keep no mirror state,
 // the dual-level set those without the rest group.
 template <typename T>
@@ -964,9 +91,7 @@ hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, 
                           StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream)
 {
     const bool walls = g.bc_x == kBcReflecting || g.bc_y == kBcReflecting, rest = k.rest_q > 0.0;
-    if (k.species)  // two gases (dual-level set only)
-        return walls ? launch_march2d_w<T, true, false, true>(Y, Yn, g, m, k, ctl, partials, flags, step, stream)
-                     : launch_march2d_w<T, false, false, true>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
+    if (k.species) return launch_march2d_species<T>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
     if (rest)
         return walls ? launch_march2d_w<T, true, true, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream)
                      : launch_march2d_w<T, false, true, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);

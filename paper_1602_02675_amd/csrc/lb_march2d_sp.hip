@@ -1,0 +1,28 @@
+// Square-lattice step as a column march with two gases: the instances that
+// carry the species moment rho chi (kernel templates in lb_march2d.hpp; a
+// translation unit of its own so that both halves compile in parallel).
+#include "lb_march2d.hpp"
+
+namespace lbsd {
+
+template <typename T>
+hipError_t launch_march2d_species(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
+                                  StepCtl* ctl, double* partials, int* flags, long long step,
+                                  hipStream_t stream)
+{
+    const bool walls = g.bc_x == kBcReflecting || g.bc_y == kBcReflecting, rest = k.rest_q > 0.0;
+    if (rest)
+        return walls ? launch_march2d_w<T, true, true, true>(Y, Yn, g, m, k, ctl, partials, flags, step, stream)
+                     : launch_march2d_w<T, false, true, true>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
+    return walls ? launch_march2d_w<T, true, false, true>(Y, Yn, g, m, k, ctl, partials, flags, step, stream)
+                 : launch_march2d_w<T, false, false, true>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
+}
+
+template hipError_t launch_march2d_species<double>(const double*, double*, const Grid&, const MarchGeom&,
+                                                   const Consts&, StepCtl*, double*, int*, long long,
+                                                   hipStream_t);
+template hipError_t launch_march2d_species<float>(const float*, float*, const Grid&, const MarchGeom&,
+                                                  const Consts&, StepCtl*, double*, int*, long long,
+                                                  hipStream_t);
+
+}  // namespace lbsd

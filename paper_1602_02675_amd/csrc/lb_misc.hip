@@ -49,10 +49,12 @@ __global__ void lanes_kernel(const T* __restrict__ Y, int64_t nn, int dim, Const
         c1[q] = s.c1;
     } else {
         // the same device function the step uses (with or without the rest group)
-        const Src2<T> s =
-            k.species ? make_src2<T, false, true>(Y[q], Y[nn + q], Y[2 * nn + q], Y[3 * nn + q], k, Y[4 * nn + q])
-            : k.rest_q > 0.0 ? make_src2<T, true>(Y[q], Y[nn + q], Y[2 * nn + q], Y[3 * nn + q], k)
-                             : make_src2<T, false>(Y[q], Y[nn + q], Y[2 * nn + q], Y[3 * nn + q], k);
+        const T m0 = Y[q], m1 = Y[nn + q], m2 = Y[2 * nn + q], m3 = Y[3 * nn + q];
+        const bool rest = k.rest_q > 0.0;
+        const Src2<T> s = k.species ? (rest ? make_src2<T, true, true>(m0, m1, m2, m3, k, Y[4 * nn + q])
+                                            : make_src2<T, false, true>(m0, m1, m2, m3, k, Y[4 * nn + q]))
+                                    : (rest ? make_src2<T, true>(m0, m1, m2, m3, k)
+                                            : make_src2<T, false>(m0, m1, m2, m3, k));
         fx[q] = s.fx;
         fy[q] = s.fy;
         c1[q] = s.c1;

@@ -155,9 +155,8 @@ class Solver:
     def __init__(self, dim: int, nx: int, ny: int = 1, *, gamma: float = 1.4, d0_frac=None,
                  precision: str = "fp64", bc_x="transmissive", bc_y="periodic", x_lo: float = 0.0,
                  x_hi: float = 1.0, device=None, stream=None, gamma2=None):
-        """gamma2: a second gas (lb_create_two_gas; the 1-D lattice or the
-        square dual-level set): gamma is gas 1's, and the state gains the
-        species field rho chi."""
+        """gamma2: a second gas (lb_create_two_gas): gamma is gas 1's, and
+        the state gains the species field rho chi."""
         import torch
 
         if d0_frac is None:

@@ -89,7 +89,10 @@ def test_two_gas_create_validation():
     assert rc == lbsd.LB_OK
     assert lbsd._lib.lb_state_bytes(h) >= 2 * 5 * 64 * 8
     lbsd._lib.lb_destroy(h)
-    for args in ((2, 1.4, 1.4, 8, 8, 3, 0.5), (2, 1.4, 2.5, 8, 8, 2, 0.0), (1, 1.4, 1.0), (1, 1.4, 3.5),
+    rc, h = make(2, 1.4, 5.0 / 3.0, 8, 8, 3, 0.5)  # and the square set with a rest level
+    assert rc == lbsd.LB_OK
+    lbsd._lib.lb_destroy(h)
+    for args in ((2, 1.4, 1.4, 8, 8, 3, 0.0), (2, 1.4, 2.5, 8, 8, 2, 0.0), (1, 1.4, 1.0), (1, 1.4, 3.5),
                  (1, 0.9, 1.4)):
         rc, h = make(*args)
         assert rc == lbsd.LB_EINVAL, args

@@ -173,3 +173,87 @@ def test_species_out_of_range_is_rejected(lbsd):
         s.init_moments(_with_species(Y, np.full((ny, nx), 1.5)), 1.0)
     assert ei.value.code == lbsd.LB_ESTATE
     s.close()
+
+
+# ------------------------------------------------ with the rest level (d_0 = delta0 rho)
+
+
+@pytest.mark.parametrize("delta0", [0.3, 0.5])
+@pytest.mark.parametrize("shape", [(1, 1), (129, 65), (300, 9)])
+@pytest.mark.parametrize("bcs", [(0, 1), (W, W)])
+def test_rest_level_random_fields(lbsd, delta0, shape, bcs):
+    nx, ny = shape
+    if W in bcs and min(nx, ny) < 5:
+        pytest.skip("walls need 5 nodes along the axis")
+    for smooth, seed in ((5, 67), (0, 68)):
+        Y = inputs.random_state(seed, 2, nx, ny, vel=(-1.1, 1.1), e=(0.0, 1.0), smooth=smooth if nx > 5 else 0)
+        chi = np.random.default_rng(seed).uniform(0.0, 1.0, size=(ny, nx))
+        P, ref, got, s = run_pair(lbsd, 2, _with_species(Y, chi), 1.0, 4, nx=nx, ny=ny, bcx=bcs[0], bcy=bcs[1],
+                                  delta0=delta0, gamma2=G2)
+        assert normwise_err(got, ref, 2) <= TOL64, (delta0, shape, bcs, smooth)
+        s.close()
+
+
+def test_rest_level_lanes_bit_exact(lbsd):
+    """c'_1 with the rest level: chi = 1/2, delta0 = 1/2, A = 2 (1/2) e / (1 -
+    1/2) = 2 e = c^2 for e = c^2 / 2."""
+    nx, ny, delta0 = 64, 40, 0.5
+    rng = np.random.default_rng(69)
+    Y = _with_species(inputs.random_state(70, 2, nx, ny, vel=(-2.0, 2.0), e=(0.0, 3.0)),
+                      rng.uniform(0.0, 1.0, size=(ny, nx)))
+    pick = rng.random((ny, nx)) < 0.3
+    v = np.round(rng.uniform(-2, 2, size=(2, ny, nx)))
+    c = rng.integers(0, 3, size=(ny, nx)).astype(float)
+    e = 0.5 * c * c
+    rho = Y[0]
+    Y[1] = np.where(pick, rho * v[0], Y[1])
+    Y[2] = np.where(pick, rho * v[1], Y[2])
+    Y[3] = np.where(pick, rho * (e + 0.5 * (v[0] ** 2 + v[1] ** 2)), Y[3])
+    Y[4] = np.where(pick, 0.5 * rho, Y[4])
+    P = oracle.Problem(2, nx, ny, gamma=G1, gamma2=G2, delta0=delta0)
+    s = lbsd.Solver(2, nx, ny, gamma=G1, gamma2=G2, d0_frac=delta0)
+    s.init_moments(Y, 1.0)
+    fx, fy, c1 = s.lanes()
+    ofx, ofy, oc1 = oracle.lanes(P, Y)
+    assert np.array_equal(fx.ravel(), ofx.ravel())
+    assert np.array_equal(fy.ravel(), ofy.ravel())
+    assert np.array_equal(c1.ravel(), oc1.ravel())
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rest_level_planar_sod(lbsd, prec):
+    """Two-gas Sod on 300 x 64 with the rest level (delta0 = 0.4): rows stay
+    bit-identical and match the oracle on a 300 x 4 strip."""
+    nx, ny, delta0 = 300, 64, 0.4
+    speeds = [abs(u) + np.sqrt(g * p / r) for (r, u, _, p), g in ((inputs.SOD_LEFT, G1), (inputs.SOD_RIGHT, G2))]
+    lam = 1.0 / max(speeds)
+    n = int(np.ceil(0.2 * nx / lam))
+    lam = 0.2 * nx / n
+    P = oracle.Problem(2, nx, 4, gamma=G1, gamma2=G2, bc_y=oracle.TRANSMISSIVE, delta0=delta0)
+    Y0 = oracle.riemann_moments(P, inputs.node_x(nx), inputs.SOD_LEFT, inputs.SOD_RIGHT, 0.5)
+    ref, st, _ = oracle.run(P, oracle.to_lattice(P, Y0, lam), n)
+    assert st == 0
+    ref = oracle.from_lattice(P, ref, lam)
+    s = lbsd.Solver(2, nx, ny, gamma=G1, gamma2=G2, precision=prec, d0_frac=delta0)
+    s.init_riemann(0.5, inputs.SOD_LEFT, inputs.SOD_RIGHT, lam=lam)
+    s.step(n)
+    got = s.moments()
+    assert np.all(got == got[:, :1, :])
+    if prec == "fp64":
+        assert normwise_err(got[:, :4, :], ref, 2) <= TOL64
+        assert s.species_total() == pytest.approx(oracle.totals(P, ref)[4] * ny / 4, rel=1e-13)
+    else:
+        assert _rel_l1(got[:, :4, :], ref) <= 1e-5
+        assert _rel_l1(got[:, :4, :], ref, 4) <= 1e-5
+    s.close()
+
+
+def test_rest_level_quadrant_closed_box(lbsd):
+    nx, ny, delta0 = 97, 83, 0.5
+    Y, lam = _two_gas_quadrant(nx, ny)
+    P, ref, got, s = run_pair(lbsd, 2, Y, lam, 10, nx=nx, ny=ny, bcx=W, bcy=W, delta0=delta0, gamma2=G2)
+    assert normwise_err(got, ref, 2) <= TOL64
+    t0 = oracle.totals(P, Y)
+    assert s.species_total() == pytest.approx(t0[4], rel=1e-13)
+    s.close()

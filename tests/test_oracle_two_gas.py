@@ -280,3 +280,30 @@ def test_two_gas_planar_tube_converges_to_exact():
     xc = 0.5 + rs.u_star * 0.2
     i = int(np.argmax(pr["chi"][0] < 0.5))
     assert abs(x[i] - xc) < 0.015
+
+
+def test_mixture_node_by_hand_square_rest_level():
+    """The square set with a rest level (d_0 = 0.4 rho), chi = 1/2 of gamma
+    7/5 and 5/3: rho = 1, v = 0, p = 1: e = 2, phi = 1, A = 2 (1/2) 2 / 0.6 =
+    10/3, c' = (1, 2), d_1 = (4 (0.6) - 2) / 12 = 1/30, d_2 = (2 - 0.6) / 12 =
+    7/60 (d_0 + 4 (d_1 + d_2) = rho, 2 (d_1 + 4 d_2) = p); the rest packets
+    carry chi like the others."""
+    P = oracle.Problem(2, 4, 4, gamma=G1, gamma2=G2, delta0=0.4)
+    node = [1.0, 0.0, 0.0, 2.0, 0.5]
+    L = oracle.levels(P, node)
+    assert L["gm1"] == pytest.approx(0.5, rel=1e-15)
+    assert L["phi"] == pytest.approx(1.0, rel=1e-15)
+    assert L["A"] == pytest.approx(10.0 / 3.0, rel=1e-15)
+    assert (L["c1"], L["c2"]) == (1, 2)
+    assert (L["d0"], L["d1"], L["d2"]) == pytest.approx((0.4, 1.0 / 30.0, 7.0 / 60.0), rel=1e-14)
+    rng = np.random.default_rng(48)
+    for _ in range(100):
+        rho, e, chi = rng.uniform(0.01, 5.0), rng.uniform(0.0, 6.0), rng.uniform()
+        v = rng.uniform(-2.5, 2.5, size=2)
+        node = [rho, rho * v[0], rho * v[1], rho * (e + 0.5 * v @ v), rho * chi]
+        off, pay = oracle.packets(P, node)
+        assert pay.shape == (36, 5)
+        vm = np.abs(v).max() + math.sqrt(e) + 1
+        scale = np.array([rho, rho * vm, rho * vm, node[3] + rho, rho])
+        assert np.all(np.abs(pay.sum(axis=0) - np.array(node)) <= 3e-14 * scale)
+        assert np.allclose(pay[:, 4], pay[:, 0] * chi, rtol=1e-15, atol=1e-300)
