@@ -69,6 +69,26 @@ __device__ __forceinline__ int isqrt_floor(T A)
     return c;
 }
 
+// a / b in the per-node primitives.  FAST = false (FP64 storage): the
+// correctly rounded quotient, so that floor(v) and c'_1 match the plain
+// definition bit for bit.  FAST = true (FP32 storage, whose results are
+// rounded to FP32 and whose decisions the step does not need bit for bit):
+// the hardware reciprocal refined by one Newton step, r (2 - b r), in two
+// FMAs, then a product; relative error near 1e-16, far below FP32 rounding,
+// for a few instructions instead of the IEEE division sequence.  b > 0, finite.
+template <bool FAST>
+__device__ __forceinline__ double pdiv(double a, double b)
+{
+    if constexpr (FAST) {
+        double r = __builtin_amdgcn_rcp(b);
+        r = __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
+        return a * r;
+    } else {
+#pragma clang fp contract(off)
+        return a / b;
+    }
+}
+
 // Internal energy, c'_1 and the weight split of one node.  rho > 0 required.
 //  e = E - |v|^2/2 (clamped at 0), A = D(gamma-1) e rho / (rho - b0 d0),
 //  c1 = floor(sqrt(A)); with w = (A - c1^2) / (c2^2 - c1^2) in [0, 1):
@@ -80,7 +100,7 @@ struct Levels {
     int c1;
 };
 
-template <typename T>
+template <typename T, bool FAST = false>
 __device__ __forceinline__ Levels<T> node_levels(T rho, T v2, T E, T d0, const Consts& k)
 {
 #pragma clang fp contract(off)
@@ -89,7 +109,7 @@ __device__ __forceinline__ Levels<T> node_levels(T rho, T v2, T E, T d0, const C
     if (e < (T)0) e = (T)0;
     L.e = e;
     L.rest = rho - (T)k.b0 * d0;
-    T A = (T)k.Dg1 * e * rho / L.rest;
+    T A = pdiv<FAST>((T)k.Dg1 * e * rho, L.rest);
     if (!(A >= (T)0)) A = (T)0;
     if (A > (T)kMaxC1 * (T)kMaxC1) A = (T)kMaxC1 * (T)kMaxC1;
     L.A = A;
@@ -118,7 +138,8 @@ __device__ __forceinline__ double level_w(double A, int c1)
 // source (eq. 15, 24-26, 28-29).  They are computed in FP64 whatever the
 // storage type T: in FP32 storage the per-node energy bookkeeping (E -> e, A,
 // the d_1 / d_2 split near a switch of c'_1) is where FP32 arithmetic would
-// lose the most, and FP64 costs the same VALU issue rate on this chip.  The
+// lose the most, and FP64 costs the same VALU issue rate on this chip (FP32
+// storage takes its quotients from a refined reciprocal, see pdiv).  The
 // staged results are rounded to T.  SP: two gases; m3t is the species moment
 // rho chi, and the node's gas is the mixture of the two by mass fraction
 // (c_v weighted, one gas constant): gamma - 1 = 1 / (chi / (gamma_1 - 1) +
@@ -137,11 +158,12 @@ __device__ __forceinline__ Src1<T> make_src1(T m0t, T m1t, T m2t, const Consts& 
         return s;
     }
     Consts k = kc;
+    constexpr bool FAST = sizeof(T) < 8;
     if constexpr (SP) {
 #pragma clang fp contract(off)
-        double chi = (double)m3t / m0;
+        double chi = pdiv<FAST>((double)m3t, m0);
         chi = chi < 0.0 ? 0.0 : (chi > 1.0 ? 1.0 : chi);
-        const double gm1 = 1.0 / (chi / k.g1m1 + (1.0 - chi) / k.g2m1);
+        const double gm1 = pdiv<FAST>(1.0, pdiv<FAST>(chi, k.g1m1) + pdiv<FAST>(1.0 - chi, k.g2m1));
         k.Dg1 = 1.0 * gm1;
         k.phi_coef = 1.0 - 0.5 * gm1;
         s.chi = (T)chi;
@@ -149,12 +171,12 @@ __device__ __forceinline__ Src1<T> make_src1(T m0t, T m1t, T m2t, const Consts& 
     double v, E, v2, d0;
     {
 #pragma clang fp contract(off)
-        v = m1 / m0;
-        E = m2 / m0;
+        v = pdiv<FAST>(m1, m0);
+        E = pdiv<FAST>(m2, m0);
         v2 = v * v;
         d0 = k.delta0 * m0;
     }
-    Levels<double> L = node_levels<double>(m0, v2, E, d0, k);
+    Levels<double> L = node_levels<double, FAST>(m0, v2, E, d0, k);
     const double fv = floor(v);
     s.f = (int)fv;
     s.r = (T)(v - fv);
@@ -181,11 +203,12 @@ __device__ __forceinline__ Src2<T> make_src2(T m0t, T m1t, T m2t, T m3t, const C
             (SP && !finite_val((double)m4t));
     s.chi = (T)0;
     Consts k = kc;
+    constexpr bool FAST = sizeof(T) < 8;
     if constexpr (SP) {
 #pragma clang fp contract(off)
-        double chi = (double)m4t / (m0 > 0.0 ? m0 : 1.0);
+        double chi = pdiv<FAST>((double)m4t, m0 > 0.0 ? m0 : 1.0);
         chi = chi < 0.0 ? 0.0 : (chi > 1.0 ? 1.0 : chi);
-        const double gm1 = 1.0 / (chi / k.g1m1 + (1.0 - chi) / k.g2m1);
+        const double gm1 = pdiv<FAST>(1.0, pdiv<FAST>(chi, k.g1m1) + pdiv<FAST>(1.0 - chi, k.g2m1));
         k.Dg1 = 2.0 * gm1;
         k.phi_coef = 1.0 - 1.0 * gm1;
         s.chi = (T)chi;
@@ -200,12 +223,12 @@ __device__ __forceinline__ Src2<T> make_src2(T m0t, T m1t, T m2t, T m3t, const C
     double vx, vy, E, v2;
     {
 #pragma clang fp contract(off)
-        vx = m1 / m0;
-        vy = m2 / m0;
-        E = m3 / m0;
+        vx = pdiv<FAST>(m1, m0);
+        vy = pdiv<FAST>(m2, m0);
+        E = pdiv<FAST>(m3, m0);
         v2 = vx * vx + vy * vy;
     }
-    Levels<double> L = node_levels<double>(m0, v2, E, REST ? k.delta0 * m0 : 0.0, k);
+    Levels<double> L = node_levels<double, FAST>(m0, v2, E, REST ? k.delta0 * m0 : 0.0, k);
     const double fvx = floor(vx), fvy = floor(vy);
     s.fx = (int)fvx;
     s.fy = (int)fvy;
