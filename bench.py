@@ -19,8 +19,9 @@ gather kernel plus its totals reduction.  Alongside, in the same JSON line:
   components of both signs) on 2048 x 2048 nodes, FP64;
 * rest_level: the headline tube on the square lattice with a rest level
   (d_0 = rho / 2), FP64, 100 steps;
-* tube1d / two_gas: one 1-D Sod tube of 2^24 nodes, FP64, 200 steps, with
-  one gas and with gamma 7/5 | 5/3 on the two sides (species field);
+* tube1d / tube1d_fp32 / two_gas: one 1-D Sod tube of 2^24 nodes, 200
+  steps: FP64 and FP32 with one gas, FP64 with gamma 7/5 | 5/3 on the two
+  sides (species field);
 * two_gas2d: the headline tube with gamma 5/3 on the right (species field
   on the square lattice), FP64, 100 steps;
 * batch2d: 48 planar square-lattice tubes of uneven sizes (nx log-uniform in
@@ -119,13 +120,13 @@ def run_nonplanar(steps: int = 200, n: int = 2048, seed: int = 1):
                 steps=steps, ms_per_step=round(total_ms / steps, 5), precision="fp64")
 
 
-def run_tube1d(gamma2=None, n: int = 1 << 24, steps: int = 200):
-    """One long 1-D Sod tube (FP64); with gamma2, gas 2 on the right."""
+def run_tube1d(gamma2=None, n: int = 1 << 24, steps: int = 200, precision: str = "fp64"):
+    """One long 1-D Sod tube; with gamma2, gas 2 on the right."""
     import torch
     from paper_1602_02675_amd import inputs
     from paper_1602_02675_amd.lbsd import Solver
 
-    s = Solver(1, n, gamma=1.4, gamma2=gamma2)
+    s = Solver(1, n, gamma=1.4, gamma2=gamma2, precision=precision)
     s.init_riemann(0.5, inputs.SOD_LEFT, inputs.SOD_RIGHT)
     s.step(5)
     s.sync()
@@ -133,9 +134,10 @@ def run_tube1d(gamma2=None, n: int = 1 << 24, steps: int = 200):
     kernel_ms, total_ms = s.step_profiled(steps)
     s.close()
     nf = 3 if gamma2 is None else 4
+    elem = 8 if precision == "fp64" else 4
     return dict(value=round(n * steps / (total_ms * 1e-3) / 1e6, 1), unit="MLUPS", nodes=n, steps=steps,
                 ms_per_step=round(total_ms / steps, 5),
-                achieved_GBs=round(2 * nf * 8 * n / (kernel_ms * 1e-3 / steps) / 1e9, 1), precision="fp64",
+                achieved_GBs=round(2 * nf * elem * n / (kernel_ms * 1e-3 / steps) / 1e9, 1), precision=precision,
                 gammas=[1.4] if gamma2 is None else [1.4, gamma2])
 
 
@@ -275,7 +277,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the walls, nonplanar, rest_level, tube1d, two_gas and two_gas2d legs")
+                    help="skip the walls, nonplanar, rest_level, tube1d(_fp32), two_gas and two_gas2d legs")
     ap.add_argument("--profile", action="store_true",
                     help="short run + a plain copy of known size, for rocprofv3 counters")
     ap.add_argument("--profile-batch", action="store_true",
@@ -355,6 +357,7 @@ def main():
                              "steps": 100, "ms_per_step": round(rr["total_ms"] / 100, 5), "d0_frac": 0.5,
                              "precision": "fp64"}
         out["tube1d"] = run_tube1d()
+        out["tube1d_fp32"] = run_tube1d(precision="fp32")
         out["two_gas"] = run_tube1d(gamma2=5.0 / 3.0)
         rg = run_gpu("fp64", 100, 5, gamma2=5.0 / 3.0)
         out["two_gas2d"] = {"value": round(nodes * 100 / (rg["total_ms"] / 1e3) / 1e6, 1), "unit": "MLUPS",

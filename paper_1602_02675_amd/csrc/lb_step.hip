@@ -164,11 +164,17 @@ finalize_kernel(const double* __restrict__ partials, int64_t nb, StepCtl* __rest
 
 // ------------------------------------------------------------------ 1-D ----
 
+// The staged sources of a 1-D tile.  Of the level weights only d_2 is staged,
+// with rho: d_0 = delta0 rho and d_1 = (rho - b_0 d_0) / b_1 - d_2 are formed
+// again where a packet needs them, with the source's own expressions (the
+// same values for FP64 storage), which keeps a tile's LDS small enough for a
+// fourth block per CU.
 template <typename T>
 struct Tile1 {
     int* pk;
-    T *r, *d0, *d1, *d2, *K;
+    T *r, *rho, *d2, *K;  // rho: 0 for a bad source (its packets are then empty)
     T* chi;  // two gases: mass fraction of gas 1 per source
+    T delta0, b0, inv_b1;
 };
 
 // One packet of a 1-D source s at displacement k + c' from its floor node:
@@ -178,9 +184,17 @@ template <typename T, bool SP>
 __device__ __forceinline__ void add_packet1(const Tile1<T>& tl, int s, int f, int k, int lane_c,
                                             int lev, T& R, T& P, T& En, T& X)
 {
+#pragma clang fp contract(off)
     const T r = tl.r[s];
     const T a = k ? r : (T)1 - r;
-    const T d = lev == 0 ? tl.d0[s] : (lev == 1 ? tl.d1[s] : tl.d2[s]);
+    T d;
+    if (lev == 2) {
+        d = tl.d2[s];
+    } else {
+        const T rho = tl.rho[s];
+        const T d0 = tl.delta0 * rho;
+        d = lev == 0 ? d0 : (rho - tl.b0 * d0) * tl.inv_b1 - tl.d2[s];
+    }
     const T m = a * d;
     const T v = (T)f + r;
     const T c = (T)lane_c;
@@ -322,7 +336,7 @@ __device__ __forceinline__ TileInfo tile1d_gather(const Tile1Src<T, H, TPB, J, W
     constexpr int W = S::W;
     constexpr int NW = TPB / 64;
     __shared__ int s_pk[W];
-    __shared__ T s_r[W], s_d0[W], s_d1[W], s_d2[W], s_K[W];
+    __shared__ T s_r[W], s_rho[W], s_d2[W], s_K[W];
     __shared__ T s_chi[SP ? W : 1];
     __shared__ int s_red[NW][8];
 
@@ -341,8 +355,7 @@ __device__ __forceinline__ TileInfo tile1d_gather(const Tile1Src<T, H, TPB, J, W
         if constexpr (SP) s_chi[i] = s.chi;
         s_pk[i] = pack_lane(s.f, 0, s.c1);
         s_r[i] = s.r;
-        s_d0[i] = s.d0;
-        s_d1[i] = s.d1;
+        s_rho[i] = s.bad ? (T)0 : src.ld[u][0];
         s_d2[i] = s.d2;
         s_K[i] = s.K;
         ti.fxmin = min(ti.fxmin, s.f);
@@ -353,7 +366,7 @@ __device__ __forceinline__ TileInfo tile1d_gather(const Tile1Src<T, H, TPB, J, W
         ti.bad |= s.bad ? 1 : 0;
     }
     ti = block_tile_info<NW>(ti, s_red);  // contains the barrier after staging
-    const Tile1<T> tl = {s_pk, s_r, s_d0, s_d1, s_d2, s_K, s_chi};
+    const Tile1<T> tl = {s_pk, s_r, s_rho, s_d2, s_K, s_chi, (T)k.delta0, (T)k.b0, (T)k.inv_b1};
     const bool uniform = ti.fxmin == ti.fxmax && ti.cmin == ti.cmax && ti.reach <= H;
     if (uniform && ti.cmin == 0)
         gather1_uniform<T, H, TPB, J, 0, SP, NF>(tl, ti.fxmin, x0, nx, Yn, acc);
