@@ -206,6 +206,12 @@ typedef struct lb_pool lb_pool; /* opaque */
  * sets (lb_pool_footprint per slot). */
 int lb_pool_create(int32_t dim, double gamma, const lb_velset* velset, int32_t precision,
                    int32_t max_slots, size_t arena_bytes, lb_pool** out);
+/* A pool of two-gas problems (as lb_create_two_gas: gas 1 gamma_1, gas 2
+ * gamma_2, a species field rho chi after rho E in every slot; admission by
+ * moments checks rho chi in [0, rho]).  lb_pool_totals reports the four
+ * one-gas totals. */
+int lb_pool_create_two_gas(int32_t dim, double gamma_1, double gamma_2, const lb_velset* velset,
+                           int32_t precision, int32_t max_slots, size_t arena_bytes, lb_pool** out);
 size_t lb_pool_bytes(const lb_pool* p);                   /* device bytes to bind (arena + tables) */
 size_t lb_pool_footprint(const lb_pool* p, int64_t nx, int64_t ny); /* arena bytes one problem takes */
 /* As lb_bind.  A non-default stream is required for lb_pool_use_graph. */

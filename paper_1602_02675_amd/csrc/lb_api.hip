@@ -147,6 +147,15 @@ int check_moments(const double* Y, int nf, int64_t nn)
     return LB_OK;
 }
 
+int check_species(const double* Y, int nf, int64_t nn)
+{
+    const double* chi = Y + (size_t)(nf - 1) * nn;  // the mass of gas 1 lies in [0, rho]
+    for (int64_t q = 0; q < nn; ++q)
+        if (!(chi[q] >= 0.0 && chi[q] <= Y[q] * (1.0 + 1e-12)))
+            return fail(LB_ESTATE, "rho chi outside [0, rho] at node %lld", (long long)q);
+    return LB_OK;
+}
+
 int upload_moments(void* dst, const double* Y, int nf, int ie, int64_t nn, double lambda, bool fp64,
                    hipStream_t stream)
 {
@@ -364,12 +373,7 @@ int lb_init_moments(lb_solver* s, const double* Y, double lambda)
     if (!(lambda > 0.0) || !isfinite(lambda)) return fail(LB_EINVAL, "lambda must be > 0");
     int rc = check_moments(Y, s->nf, s->nn);
     if (rc != LB_OK) return rc;
-    if (s->species) {  // the mass of gas 1 lies in [0, rho]
-        const double* chi = Y + (size_t)(s->nf - 1) * s->nn;
-        for (int64_t q = 0; q < s->nn; ++q)
-            if (!(chi[q] >= 0.0 && chi[q] <= Y[q] * (1.0 + 1e-12)))
-                return fail(LB_ESTATE, "rho chi outside [0, rho] at node %lld", (long long)q);
-    }
+    if (s->species && (rc = check_species(Y, s->nf, s->nn)) != LB_OK) return rc;
     rc = upload_moments(buf_ptr(s, 0), Y, s->nf, s->dim + 1, s->nn, lambda, s->precision == LB_FP64, s->stream);
     if (rc != LB_OK) return rc;
     s->lambda = lambda;

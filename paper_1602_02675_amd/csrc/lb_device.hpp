@@ -35,7 +35,7 @@ struct Consts {
     double rest_q;    // square lattice with a rest level: d_0 / (d_1 + d_2) = b_1 delta0 / (1 - delta0)
     double g1m1;      // two gases: gamma_1 - 1 (gas 1, the species field's gas)
     double g2m1;      // two gases: gamma_2 - 1
-    int species;      // 1: two gases, a species moment rho chi after rho E (1-D)
+    int species;      // 1: two gases, a species moment rho chi after rho E
 };
 
 template <typename T>

@@ -25,6 +25,8 @@ int riemann_sides(int dim, double gamma_l, double gamma_r, bool species, double 
                   const lb_prim* L, const lb_prim* R, double* lam_out, double side[2][5]);
 // rho > 0 and finite everywhere (LB_ESTATE otherwise).
 int check_moments(const double* Y, int nf, int64_t nn);
+// Two gases: the last field, rho chi, within [0, rho] (LB_ESTATE otherwise).
+int check_species(const double* Y, int nf, int64_t nn);
 // Physical FP64 SoA moments -> lattice units of the storage type, copied to
 // dst on `stream` (synchronously).  ie: index of the rho E field.
 int upload_moments(void* dst, const double* Y, int nf, int ie, int64_t nn, double lambda, bool fp64,

@@ -1,47 +1,11 @@
-// Square-lattice step as a column march: the one-gas kernel instances, the
-// pool form, the launch geometry (the kernel templates and how the march
-// works are in lb_march2d.hpp).
+// Square-lattice step as a column march: the one-gas kernel instances (plain
+// and pool form) and the launch geometry (the kernel templates and how the
+// march works are in lb_march2d.hpp).
 #include "lb_march2d.hpp"
 
 namespace lbsd {
 
 namespace {
-
-// Pool form: persistent blocks claim tiles of the tile table (see
-// pool1d_kernel).  The short-FIFO pass flags the tiles it could not complete;
-// the full-FIFO pass computes only those, and keeps the flags of the tiles
-// that still need it (as in march2d_kernel).
-template <typename T, int L, bool WALLS, bool REST>
-__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
-pool2d_kernel(PoolView v, Consts k)
-{
-    __shared__ int s_t;
-    if (L == kLFull && v.next[2] == 0) return;  // the short pass flagged no tile
-    const int nt = *v.ntiles;
-    T* arena = (T*)v.arena;
-    for (;;) {
-        const int t = claim_tile(&v.next[L < kLFull ? 0 : 1], &s_t);
-        if (t >= nt) break;
-        const int ts = v.tstate[t];
-        if (!(ts & kTileLive)) continue;  // the same for the whole block
-        const int flagged = v.flags[t];
-        if (L < kLFull && flagged) {  // needed the full FIFO last step: left to the full pass
-            if (threadIdx.x == 0) atomicAdd(&v.next[2], 1);
-            continue;
-        }
-        if (L == kLFull && !flagged) continue;
-        const PoolTile& tl = v.tiles[t];
-        const int64_t o0 = tl.off[0], o1 = tl.off[1];  // selected below, not indexed (keeps them in registers)
-        const int64_t from = (ts & kTileSet) ? o1 : o0, to = (ts & kTileSet) ? o0 : o1;
-        const Grid g{tl.nx, tl.ny, tl.bc_x, tl.bc_y};
-        const int far = march_tile<T, L, WALLS, REST, false>(arena + from, arena + to, g, k, tl.x0, tl.y0, tl.rows,
-                                                      v.partials + (int64_t)t * kPartialStride);
-        if (threadIdx.x == 0) {
-            v.flags[t] = far;
-            if (L < kLFull && far) atomicAdd(&v.next[2], 1);
-        }
-    }
-}
 
 int64_t x_strips(const Grid& g) { return (g.nx + (kMTPB - 2 * kMH) - 1) / (kMTPB - 2 * kMH); }
 
@@ -103,29 +67,20 @@ template <typename T>
 int pool2d_blocks_per_cu()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pool2d_kernel<T, kLSmall, false, false>, kMTPB, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pool2d_kernel<T, kLSmall, false, false, false>, kMTPB, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
-}
-
-template <typename T, bool WALLS, bool REST>
-hipError_t launch_pool2d_w(const PoolView& v, const Consts& k, int nblocks, hipStream_t stream)
-{
-    pool2d_kernel<T, kLSmall, WALLS, REST><<<nblocks, kMTPB, 0, stream>>>(v, k);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    pool2d_kernel<T, kLFull, WALLS, REST><<<nblocks, kMTPB, 0, stream>>>(v, k);
-    return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_pool2d(const PoolView& v, const Consts& k, int nblocks, bool walls, hipStream_t stream)
 {
+    if (k.species) return launch_pool2d_species<T>(v, k, nblocks, walls, stream);
     if (k.rest_q > 0.0)
-        return walls ? launch_pool2d_w<T, true, true>(v, k, nblocks, stream)
-                     : launch_pool2d_w<T, false, true>(v, k, nblocks, stream);
-    return walls ? launch_pool2d_w<T, true, false>(v, k, nblocks, stream)
-                 : launch_pool2d_w<T, false, false>(v, k, nblocks, stream);
+        return walls ? launch_pool2d_w<T, true, true, false>(v, k, nblocks, stream)
+                     : launch_pool2d_w<T, false, true, false>(v, k, nblocks, stream);
+    return walls ? launch_pool2d_w<T, true, false, false>(v, k, nblocks, stream)
+                 : launch_pool2d_w<T, false, false, false>(v, k, nblocks, stream);
 }
 
 template int march2d_blocks_per_cu<double>();

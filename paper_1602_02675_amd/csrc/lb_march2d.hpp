@@ -24,6 +24,11 @@
 // compile-time column offsets and FIFO slots; elsewhere candidate sources are
 // matched at run time.  The same packets are summed either way; only the
 // summation order differs from the scatter definition.
+//
+// The kernels and helpers below sit in an anonymous namespace: each
+// translation unit that includes this header instantiates its own kernels
+// (lb_march2d.hip the one-gas ones, lb_march2d_sp.hip the two-gas ones), and
+// no kernel is instantiated in both.
 #include <climits>
 
 #include "lb_kernels.hpp"
@@ -865,6 +870,42 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
     }
 }
 
+// Pool form: persistent blocks claim tiles of the tile table (see
+// pool1d_kernel).  The short-FIFO pass flags the tiles it could not complete;
+// the full-FIFO pass computes only those, and keeps the flags of the tiles
+// that still need it (as in march2d_kernel).
+template <typename T, int L, bool WALLS, bool REST, bool SP>
+__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
+pool2d_kernel(PoolView v, Consts k)
+{
+    __shared__ int s_t;
+    if (L == kLFull && v.next[2] == 0) return;  // the short pass flagged no tile
+    const int nt = *v.ntiles;
+    T* arena = (T*)v.arena;
+    for (;;) {
+        const int t = claim_tile(&v.next[L < kLFull ? 0 : 1], &s_t);
+        if (t >= nt) break;
+        const int ts = v.tstate[t];
+        if (!(ts & kTileLive)) continue;  // the same for the whole block
+        const int flagged = v.flags[t];
+        if (L < kLFull && flagged) {  // needed the full FIFO last step: left to the full pass
+            if (threadIdx.x == 0) atomicAdd(&v.next[2], 1);
+            continue;
+        }
+        if (L == kLFull && !flagged) continue;
+        const PoolTile& tl = v.tiles[t];
+        const int64_t o0 = tl.off[0], o1 = tl.off[1];  // selected below, not indexed (keeps them in registers)
+        const int64_t from = (ts & kTileSet) ? o1 : o0, to = (ts & kTileSet) ? o0 : o1;
+        const Grid g{tl.nx, tl.ny, tl.bc_x, tl.bc_y};
+        const int far = march_tile<T, L, WALLS, REST, SP>(arena + from, arena + to, g, k, tl.x0, tl.y0, tl.rows,
+                                                          v.partials + (int64_t)t * kPartialStride);
+        if (threadIdx.x == 0) {
+            v.flags[t] = far;
+            if (L < kLFull && far) atomicAdd(&v.next[2], 1);
+        }
+    }
+}
+
 // Both passes of one step: the short-FIFO pass over every tile, then the
 // full-FIFO pass over the tiles it flagged.
 template <typename T, bool WALLS, bool REST, bool SP>
@@ -883,6 +924,17 @@ hipError_t launch_march2d_w(const T* Y, T* Yn, const Grid& g, const MarchGeom& m
     return hipGetLastError();
 }
 
+// Both passes of one pool step.
+template <typename T, bool WALLS, bool REST, bool SP>
+hipError_t launch_pool2d_w(const PoolView& v, const Consts& k, int nblocks, hipStream_t stream)
+{
+    pool2d_kernel<T, kLSmall, WALLS, REST, SP><<<nblocks, kMTPB, 0, stream>>>(v, k);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    pool2d_kernel<T, kLFull, WALLS, REST, SP><<<nblocks, kMTPB, 0, stream>>>(v, k);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // Two gases (lb_march2d_sp.hip): the instances with the species field.
@@ -890,5 +942,7 @@ template <typename T>
 hipError_t launch_march2d_species(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
                                   StepCtl* ctl, double* partials, int* flags, long long step,
                                   hipStream_t stream);
+template <typename T>
+hipError_t launch_pool2d_species(const PoolView& v, const Consts& k, int nblocks, bool walls, hipStream_t stream);
 
 }  // namespace lbsd

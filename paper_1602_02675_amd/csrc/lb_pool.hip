@@ -34,7 +34,8 @@ struct SlotInfo {
 struct lb_pool {
     int dim = 0, nf = 0, precision = 0;
     size_t elem = 0;
-    double gamma = 0.0;
+    double gamma = 0.0, gamma2 = 0.0;  // gamma2: gas 2 (two gases), else gamma
+    bool species = false;              // two gases: a species field rho chi after rho E
     lb_velset vs{};
     Consts k{};
     int32_t max_slots = 0;
@@ -403,23 +404,29 @@ void* set_ptr(const lb_pool* p, int32_t slot, int set)
 
 extern "C" {
 
-int lb_pool_create(int32_t dim, double gamma, const lb_velset* vs, int32_t precision, int32_t max_slots,
-                   size_t arena_bytes, lb_pool** out)
+static int create_pool(int32_t dim, double gamma, double gamma2, bool species, const lb_velset* vs,
+                       int32_t precision, int32_t max_slots, size_t arena_bytes, lb_pool** out)
 {
     if (!vs || !out) return fail(LB_EINVAL, "null argument");
     int rc = check_model(dim, gamma, vs, precision);
     if (rc != LB_OK) return rc;
+    if (species && (rc = check_model(dim, gamma2, vs, precision)) != LB_OK) return rc;
     if (max_slots < 1 || max_slots > (1 << 20)) return fail(LB_EINVAL, "max_slots must lie in [1, 2^20]");
     if (arena_bytes < 256) return fail(LB_EINVAL, "arena too small");
     lb_pool* p = new (std::nothrow) lb_pool();
     if (!p) return fail(LB_ENOMEM, "host allocation failed");
     p->dim = dim;
-    p->nf = dim + 2;
+    p->species = species;
+    p->nf = dim + 2 + (species ? 1 : 0);
     p->precision = precision;
     p->elem = precision == LB_FP64 ? 8 : 4;
     p->gamma = gamma;
+    p->gamma2 = species ? gamma2 : gamma;
     p->vs = *vs;
     p->k = make_consts(dim, gamma, vs);
+    p->k.g1m1 = gamma - 1.0;
+    p->k.g2m1 = p->gamma2 - 1.0;
+    p->k.species = species ? 1 : 0;
     p->max_slots = max_slots;
     p->arena_bytes = arena_bytes & ~(size_t)255;
     // every live slot has at most one partly filled tile row/column per
@@ -447,6 +454,18 @@ int lb_pool_create(int32_t dim, double gamma, const lb_velset* vs, int32_t preci
     p->free_list[0] = p->arena_bytes;
     *out = p;
     return LB_OK;
+}
+
+int lb_pool_create(int32_t dim, double gamma, const lb_velset* vs, int32_t precision, int32_t max_slots,
+                   size_t arena_bytes, lb_pool** out)
+{
+    return create_pool(dim, gamma, gamma, false, vs, precision, max_slots, arena_bytes, out);
+}
+
+int lb_pool_create_two_gas(int32_t dim, double gamma_1, double gamma_2, const lb_velset* vs, int32_t precision,
+                           int32_t max_slots, size_t arena_bytes, lb_pool** out)
+{
+    return create_pool(dim, gamma_1, gamma_2, true, vs, precision, max_slots, arena_bytes, out);
 }
 
 size_t lb_pool_bytes(const lb_pool* p) { return p ? p->total : 0; }
@@ -493,7 +512,7 @@ int lb_pool_admit_riemann(lb_pool* p, const lb_grid* grid, double lambda, double
     if (!isfinite(x_d)) return fail(LB_EINVAL, "diaphragm position must be finite");
     if (!p) return fail(LB_EINVAL, "null pool");
     double lam = 0.0, side[2][5];
-    int rc = riemann_sides(p->dim, p->gamma, p->gamma, false, lambda, 1.0, L, R, &lam, side);
+    int rc = riemann_sides(p->dim, p->gamma, p->gamma2, p->species, lambda, 1.0, L, R, &lam, side);
     if (rc != LB_OK) return rc;
     int32_t s = -1;
     if ((rc = reserve(p, grid, steps, &s)) != LB_OK) return rc;
@@ -525,6 +544,7 @@ int lb_pool_admit_moments(lb_pool* p, const lb_grid* grid, const double* host_Y,
     int rc = check_grid(grid, p->dim);
     if (rc != LB_OK) return rc;
     if ((rc = check_moments(host_Y, p->nf, grid->nx * grid->ny)) != LB_OK) return rc;
+    if (p->species && (rc = check_species(host_Y, p->nf, grid->nx * grid->ny)) != LB_OK) return rc;
     int32_t s = -1;
     if ((rc = reserve(p, grid, steps, &s)) != LB_OK) return rc;
     rc = upload_moments(set_ptr(p, s, 0), host_Y, p->nf, p->dim + 1, grid->nx * grid->ny, lambda,

@@ -400,7 +400,7 @@ step1d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
 // same, so the hardware's block scheduling balances them and overlaps one
 // tile's loads with other tiles' work).  A tile belongs to one slot; its word
 // says whether the slot still steps and which moment set holds its state.
-template <typename T, int TPB, int J, bool WALLS>
+template <typename T, int TPB, int J, bool WALLS, bool SP>
 __global__ void __launch_bounds__(TPB) pool1d_kernel(PoolView v, Consts k)
 {
     const int t = blockIdx.x;
@@ -412,11 +412,12 @@ __global__ void __launch_bounds__(TPB) pool1d_kernel(PoolView v, Consts k)
     const int64_t o0 = tl.off[0], o1 = tl.off[1];  // selected below, not indexed (keeps them in registers)
     const int64_t from = (ts & kTileSet) ? o1 : o0, to = (ts & kTileSet) ? o0 : o1;
     const int64_t nx = tl.nx, x0 = tl.x0;
-    Tile1Src<T, kHalo, TPB, J, WALLS, false> src;
-    tile1d_load<T, kHalo, TPB, J, WALLS, false>(arena + from, nx, tl.bc_x, x0, src);
-    double acc[3] = {0.0, 0.0, 0.0};
-    const TileInfo ti = tile1d_gather<T, kHalo, TPB, J, WALLS, false>(src, arena + to, nx, x0, k, acc);
-    finish_step<TPB / 64, 3>(acc, ti, v.partials + (int64_t)t * kPartialStride, kHalo);
+    using S = Tile1Src<T, kHalo, TPB, J, WALLS, SP>;
+    S src;
+    tile1d_load<T, kHalo, TPB, J, WALLS, SP>(arena + from, nx, tl.bc_x, x0, src);
+    double acc[S::NF] = {};
+    const TileInfo ti = tile1d_gather<T, kHalo, TPB, J, WALLS, SP>(src, arena + to, nx, x0, k, acc);
+    finish_step<TPB / 64, S::NF>(acc, ti, v.partials + (int64_t)t * kPartialStride, kHalo);
 }
 
 // Per slot (one block each): the same fixed-order reduction as finalize_kernel
@@ -520,10 +521,15 @@ template <typename T, int S>
 static hipError_t pool1d_launch_shape(const PoolView& v, const Consts& k, int nblocks, bool walls,
                                       hipStream_t stream)
 {
-    if (walls)
-        pool1d_kernel<T, kPool1TPB[S], kPool1J[S], true><<<nblocks, kPool1TPB[S], 0, stream>>>(v, k);
-    else
-        pool1d_kernel<T, kPool1TPB[S], kPool1J[S], false><<<nblocks, kPool1TPB[S], 0, stream>>>(v, k);
+    constexpr int TPB = kPool1TPB[S], J = kPool1J[S];
+    if (k.species) {  // two gases: the instances that carry rho chi
+        if (walls) pool1d_kernel<T, TPB, J, true, true><<<nblocks, TPB, 0, stream>>>(v, k);
+        else pool1d_kernel<T, TPB, J, false, true><<<nblocks, TPB, 0, stream>>>(v, k);
+    } else if (walls) {
+        pool1d_kernel<T, TPB, J, true, false><<<nblocks, TPB, 0, stream>>>(v, k);
+    } else {
+        pool1d_kernel<T, TPB, J, false, false><<<nblocks, TPB, 0, stream>>>(v, k);
+    }
     return hipGetLastError();
 }
 

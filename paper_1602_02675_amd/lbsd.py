@@ -35,7 +35,7 @@ EXPORTED = ["lb_create", "lb_create_two_gas", "lb_species_total", "lb_state_byte
             "lb_init_riemann", "lb_init_moments", "lb_step", "lb_step_timed", "lb_step_profiled", "lb_sync",
             "lb_moments", "lb_totals", "lb_lambda", "lb_dt", "lb_steps_done", "lb_max_reach",
             "lb_debug_lanes", "lb_destroy", "lb_last_error",
-            "lb_pool_create", "lb_pool_bytes", "lb_pool_footprint", "lb_pool_bind", "lb_pool_admit_riemann",
+            "lb_pool_create", "lb_pool_create_two_gas", "lb_pool_bytes", "lb_pool_footprint", "lb_pool_bind", "lb_pool_admit_riemann",
             "lb_pool_admit_moments", "lb_pool_release", "lb_pool_advance", "lb_pool_advance_timed",
             "lb_pool_poll", "lb_pool_status", "lb_pool_moments", "lb_pool_totals", "lb_pool_lambda", "lb_pool_live",
             "lb_pool_shapes", "lb_pool_shape", "lb_pool_set_shape", "lb_pool_autotune", "lb_pool_use_graph",
@@ -97,6 +97,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lb_last_error": (ctypes.c_char_p, []),
         "lb_pool_create": (ctypes.c_int, [i32, dbl, ctypes.POINTER(lb_velset), i32, i32, ctypes.c_size_t,
                                           ctypes.POINTER(vp)]),
+        "lb_pool_create_two_gas": (ctypes.c_int, [i32, dbl, dbl, ctypes.POINTER(lb_velset), i32, i32,
+                                                  ctypes.c_size_t, ctypes.POINTER(vp)]),
         "lb_pool_bytes": (ctypes.c_size_t, [vp]),
         "lb_pool_footprint": (ctypes.c_size_t, [vp, i64, i64]),
         "lb_pool_bind": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
@@ -291,19 +293,26 @@ class Pool:
     a non-default stream)."""
 
     def __init__(self, dim: int, max_slots: int, arena_bytes: int, *, gamma: float = 1.4, d0_frac=None,
-                 precision: str = "fp32", device=None, stream=None):
+                 precision: str = "fp32", device=None, stream=None, gamma2=None):
+        """gamma2: a pool of two-gas problems (lb_pool_create_two_gas); every
+        slot's state then has the species field rho chi last."""
         import torch
 
         if d0_frac is None:
             d0_frac = 0.5 if dim == 1 else 0.0
-        self.dim, self.nf, self.precision = dim, dim + 2, precision
+        self.species = gamma2 is not None
+        self.dim, self.nf, self.precision = dim, dim + 2 + (1 if self.species else 0), precision
         self.max_slots = int(max_slots)
         self.arena_bytes = int(arena_bytes)
         vs = lb_velset(_lattice(dim, d0_frac), d0_frac)
         prec = {"fp64": LB_FP64, "fp32": LB_FP32}[precision]
         h = ctypes.c_void_p()
-        _check(_lib.lb_pool_create(dim, gamma, ctypes.byref(vs), prec, int(max_slots), int(arena_bytes),
-                                   ctypes.byref(h)))
+        if self.species:
+            _check(_lib.lb_pool_create_two_gas(dim, gamma, float(gamma2), ctypes.byref(vs), prec, int(max_slots),
+                                               int(arena_bytes), ctypes.byref(h)))
+        else:
+            _check(_lib.lb_pool_create(dim, gamma, ctypes.byref(vs), prec, int(max_slots), int(arena_bytes),
+                                       ctypes.byref(h)))
         self._h = h
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         nbytes = int(_lib.lb_pool_bytes(h))

@@ -96,6 +96,13 @@ def test_two_gas_create_validation():
                  (1, 0.9, 1.4)):
         rc, h = make(*args)
         assert rc == lbsd.LB_EINVAL, args
+    # pools of two gases: both gammas checked
+    g = lbsd.lb_velset(1, 0.5)
+    for g2, want in ((5.0 / 3.0, lbsd.LB_OK), (3.5, lbsd.LB_EINVAL), (1.0, lbsd.LB_EINVAL)):
+        hp = ctypes.c_void_p()
+        assert lbsd._lib.lb_pool_create_two_gas(1, 1.4, g2, ctypes.byref(g), 0, 4, 1 << 20, ctypes.byref(hp)) == want
+        if want == lbsd.LB_OK:
+            lbsd._lib.lb_pool_destroy(hp)
     # one gas: no species total
     rc, h = _create(lbsd)
     assert rc == lbsd.LB_OK
