@@ -583,9 +583,9 @@ template <typename T, int L, bool WALLS, bool REST, bool SP>
 __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict__ Yn, const Grid& g, const Consts& k,
                           int64_t X0, int64_t Y0, int sy, double* __restrict__ prow)
 {
-    // source rows staged per barrier: two in FP64 (fewer barriers, two
-    // independent per-source computations in flight); FP32 has no registers left
-    constexpr int RB = sizeof(T) == 8 ? 2 : 1;
+    // source rows staged per barrier: two (fewer barriers, two independent
+    // per-source computations in flight)
+    constexpr int RB = 2;
     constexpr int NF = SP ? 5 : 4;  // moment fields (two gases: rho chi after rho E)
     __shared__ MRow<T, SP> s_row[2][RB];
     __shared__ WaveInfo s_w[2][RB][kMNW];
