@@ -1,6 +1,7 @@
 // Square-lattice step as a column march with two gases: the instances (plain
-// and pool form) that carry the species moment rho chi (kernel templates in lb_march2d.hpp; a
-// translation unit of its own so that both halves compile in parallel).
+// and pool form) that carry the species moment rho chi.  The kernel templates
+// are in lb_march2d.hpp; this translation unit of its own lets the one-gas and
+// two-gas halves compile in parallel.
 #include "lb_march2d.hpp"
 
 namespace lbsd {
