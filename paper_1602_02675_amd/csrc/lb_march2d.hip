@@ -1,6 +1,8 @@
-// Square-lattice step as a column march: the one-gas kernel instances (plain
-// and pool form) and the launch geometry (the kernel templates and how the
-// march works are in lb_march2d.hpp).
+// Square-lattice step as a column march: the one-gas instances of the plain
+// form and the launch geometry (the kernel templates and how the march works
+// are in lb_march2d.hpp; the pool form's one-gas instances are in
+// lb_pool2d.hip, the two-gas instances in lb_march2d_sp.hip and
+// lb_pool2d_sp.hip).
 #include "lb_march2d.hpp"
 
 namespace lbsd {
@@ -63,32 +65,8 @@ hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, 
                  : launch_march2d_w<T, false, false, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
 }
 
-template <typename T>
-int pool2d_blocks_per_cu()
-{
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pool2d_kernel<T, kLSmall, false, false, false>, kMTPB, 0) != hipSuccess)
-        return 1;
-    return nb > 0 ? nb : 1;
-}
-
-template <typename T>
-hipError_t launch_pool2d(const PoolView& v, const Consts& k, int nblocks, bool walls, hipStream_t stream)
-{
-    if (k.species) return launch_pool2d_species<T>(v, k, nblocks, walls, stream);
-    if (k.rest_q > 0.0)
-        return walls ? launch_pool2d_w<T, true, true, false>(v, k, nblocks, stream)
-                     : launch_pool2d_w<T, false, true, false>(v, k, nblocks, stream);
-    return walls ? launch_pool2d_w<T, true, false, false>(v, k, nblocks, stream)
-                 : launch_pool2d_w<T, false, false, false>(v, k, nblocks, stream);
-}
-
 template int march2d_blocks_per_cu<double>();
 template int march2d_blocks_per_cu<float>();
-template int pool2d_blocks_per_cu<double>();
-template int pool2d_blocks_per_cu<float>();
-template hipError_t launch_pool2d<double>(const PoolView&, const Consts&, int, bool, hipStream_t);
-template hipError_t launch_pool2d<float>(const PoolView&, const Consts&, int, bool, hipStream_t);
 template hipError_t launch_march2d<double>(const double*, double*, const Grid&, const MarchGeom&,
                                            const Consts&, StepCtl*, double*, int*, long long, hipStream_t);
 template hipError_t launch_march2d<float>(const float*, float*, const Grid&, const MarchGeom&,

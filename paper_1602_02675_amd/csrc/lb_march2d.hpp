@@ -27,8 +27,9 @@
 //
 // The kernels and helpers below sit in an anonymous namespace: each
 // translation unit that includes this header instantiates its own kernels
-// (lb_march2d.hip the one-gas ones, lb_march2d_sp.hip the two-gas ones), and
-// no kernel is instantiated in both.
+// (lb_march2d.hip and lb_pool2d.hip the one-gas plain and pool forms,
+// lb_march2d_sp.hip and lb_pool2d_sp.hip the two-gas ones), and no kernel is
+// instantiated in two of them.
 #include <climits>
 
 #include "lb_kernels.hpp"
@@ -937,7 +938,8 @@ hipError_t launch_pool2d_w(const PoolView& v, const Consts& k, int nblocks, hipS
 
 }  // namespace
 
-// Two gases (lb_march2d_sp.hip): the instances with the species field.
+// Two gases (lb_march2d_sp.hip, lb_pool2d_sp.hip): the instances with the
+// species field.
 template <typename T>
 hipError_t launch_march2d_species(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
                                   StepCtl* ctl, double* partials, int* flags, long long step,
