@@ -10,8 +10,8 @@
  *
  * Conventions
  *  - Every call returns an int status (LB_OK = 0, negative on error) unless
- *    stated otherwise; out-parameters are written only on LB_OK; nothing
- *    throws across the ABI.  lb_last_error() gives a message for the calling
+ *    stated otherwise; out-parameters are written only on LB_OK (one
+ *    exception: lb_moments, see there); nothing throws across the ABI.  lb_last_error() gives a message for the calling
  *    thread's last failed call.
  *  - Device memory is owned by the caller: lb_state_bytes() says how much,
  *    lb_bind() hands over a device pointer (e.g. a PyTorch tensor's
@@ -154,7 +154,10 @@ int lb_step_profiled(lb_solver* s, int64_t n, float* kernel_ms, float* total_ms)
 int lb_sync(lb_solver* s);
 
 /* Current moments as FP64 SoA [nf][ny][nx] in physical units, into `out`
- * (host memory, or device memory when out_on_device != 0).  Synchronises. */
+ * (host memory, or device memory when out_on_device != 0).  Synchronises.
+ * After a failed step (LB_EREACH, LB_ESTATE) it still writes `out`: the
+ * state of the last good step, which the failed step left intact, and
+ * returns that step's error. */
 int lb_moments(lb_solver* s, double* out, int32_t out_on_device);
 
 /* Interior sums of rho, rho u, rho v (0 in 1-D), rho E of the current state
@@ -239,7 +242,9 @@ int lb_pool_poll(lb_pool* p, int32_t slot, int64_t* steps_done, int32_t* status)
  * slot reports 0 steps and status LB_POOL_FREE. */
 #define LB_POOL_FREE (-100)
 int lb_pool_status(lb_pool* p, int64_t* steps_done, int32_t* status);
-/* As lb_moments / lb_totals for one slot (lb_pool_totals: LB_EINVAL before its first step). */
+/* As lb_moments / lb_totals for one slot (lb_pool_totals: LB_EINVAL before its first step).
+ * A slot whose step failed exports its last good state and returns LB_OK;
+ * lb_pool_poll reports the failure. */
 int lb_pool_moments(lb_pool* p, int32_t slot, double* out, int32_t out_on_device);
 int lb_pool_totals(lb_pool* p, int32_t slot, double out[4]);
 double lb_pool_lambda(const lb_pool* p, int32_t slot);
