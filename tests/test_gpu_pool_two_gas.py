@@ -111,3 +111,23 @@ def test_pool_two_gas_admission_checks_species(lbsd):
     chi = pool.moments(sl)
     assert np.all(chi[4] >= 0) and np.all(chi[4] <= chi[0] * (1 + 1e-12))
     pool.close()
+
+
+def test_serve_loop_two_gas_results_match_alone(lbsd):
+    """The serving loop on a two-gas FP32 pool: requests admitted as slots
+    free up, each result bit-equal to its lb_solver run."""
+    from paper_1602_02675_amd import serve
+
+    reqs = inputs.serve_requests(12, 6, rate_per_s=200.0, side_lo=32, side_hi=160, steps_lo=5, steps_hi=50)
+    refs = [alone(lbsd, 2, r["side"], r["side"], r["x_d"], r["left"], r["right"],
+                  inputs.cfl_lambda([r["left"], r["right"]]), r["steps"], "fp32") for r in reqs]
+    pool = lbsd.Pool(2, 2, 3 * 2 * 5 * 160 * 160 * 4, precision="fp32", gamma=G1, gamma2=G2)
+    pool.use_graph(5)
+    got = {}
+    res = serve.run(pool, reqs, tick=5, fetch="moments", on_result=lambda i, m: got.__setitem__(i, m))
+    assert sorted(got) == list(range(len(reqs)))
+    for i, ref in enumerate(refs):
+        assert got[i].shape == (5, reqs[i]["side"], reqs[i]["side"])
+        assert np.array_equal(got[i], ref), i
+    assert res["nups"] > 0 and pool.live == 0
+    pool.close()
