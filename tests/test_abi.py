@@ -156,3 +156,16 @@ def test_pool_create_validation_and_sizes():
     assert rc == lbsd.LB_OK
     assert lbsd._lib.lb_pool_footprint(h, 64, 64) == 2 * 4 * 64 * 64 * 4
     lbsd._lib.lb_pool_destroy(h)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """No CPU fallback: with the HIP library missing, importing the binding
+    raises instead of running anything else."""
+    import subprocess
+    import sys
+
+    env = dict(os.environ, LBSD_LIBRARY=str(tmp_path / "absent" / "liblbsd.so"))
+    code = "import paper_1602_02675_amd.lbsd"
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "is missing" in r.stderr
