@@ -66,7 +66,7 @@ hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, 
 
 // Reduce nb per-block partial rows of one step into ctl (fixed order);
 // species2d: also the rho chi sums of the square lattice with two gases.
-hipError_t launch_finalize(const double* partials, int64_t nb, StepCtl* ctl, long long step,
+hipError_t launch_finalize(double* partials, int64_t nb, StepCtl* ctl, long long step,
                            hipStream_t stream, bool species2d = false);
 constexpr int kHalo = 5;
 

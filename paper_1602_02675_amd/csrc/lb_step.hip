@@ -104,12 +104,63 @@ __device__ void finish_step(double (&acc)[NF], const TileInfo& ti, double* __res
     }
 }
 
+// First stage of the reduction of many partial rows (a 1-D step has one row
+// per 1024 nodes, 16 K rows at 2^24 nodes, too many for one block to read
+// quickly): block g folds rows [g kChunk, (g + 1) kChunk) in a fixed order
+// (sums, largest reach, error bits) into row g kChunk, the first of its own
+// chunk, so that blocks never touch each other's rows.
+constexpr int kChunk = 256;
+__global__ void __launch_bounds__(kChunk)
+partials_chunk_kernel(double* __restrict__ partials, int64_t nb, const StepCtl* __restrict__ ctl, long long step)
+{
+    __shared__ double s_sum[kChunk / 64][5];
+    __shared__ int s_ir[kChunk / 64][2];
+    if (ctl->err_step < step) return;  // an earlier step failed: the rows are not this step's
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t b0 = (int64_t)blockIdx.x * kChunk, b = b0 + tid;
+    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    int reach = 0, err = 0;
+    if (b < nb) {
+        const double* p = partials + b * kPartialStride;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) s[f] = p[f];
+        s[4] = p[6];
+        reach = (int)p[4];
+        err = (int)p[5];
+    }
+#pragma unroll
+    for (int f = 0; f < 5; ++f) s[f] = wave_sum(s[f]);
+    reach = wave_max(reach);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) err |= __shfl_xor(err, o, 64);
+    if (lane == 0) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) s_sum[wid][f] = s[f];
+        s_ir[wid][0] = reach;
+        s_ir[wid][1] = err;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double* q = partials + b0 * kPartialStride;
+        for (int f = 0; f < 5; ++f) {
+            double t = s_sum[0][f];
+            for (int w = 1; w < kChunk / 64; ++w) t += s_sum[w][f];
+            q[f < 4 ? f : 6] = t;
+        }
+        int r = s_ir[0][0], e = s_ir[0][1];
+        for (int w = 1; w < kChunk / 64; ++w) { r = max(r, s_ir[w][0]); e |= s_ir[w][1]; }
+        q[4] = (double)r;
+        q[5] = (double)e;
+    }
+}
+
 // Sum the per-block partials of one step in a fixed order (deterministic),
-// record the totals, the largest reach and the first failed step.
+// record the totals, the largest reach and the first failed step.  Rows b
+// stride for b < nb (stride > 1: the chunk heads of partials_chunk_kernel).
 constexpr int kFinTPB = 256;
 __global__ void __launch_bounds__(kFinTPB)
-finalize_kernel(const double* __restrict__ partials, int64_t nb, StepCtl* __restrict__ ctl,
-                long long step, int H, int sp2)
+finalize_kernel(const double* __restrict__ partials, int64_t nb, int64_t stride, StepCtl* __restrict__ ctl,
+                long long step, int sp2)
 {
     __shared__ double s_sum[kFinTPB / 64][5];
     __shared__ int s_ir[kFinTPB / 64][2];
@@ -125,7 +176,7 @@ finalize_kernel(const double* __restrict__ partials, int64_t nb, StepCtl* __rest
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     int reach = 0, err = 0;
     for (int64_t b = tid; b < nb; b += kFinTPB) {
-        const double* p = partials + b * kPartialStride;
+        const double* p = partials + b * stride * kPartialStride;
 #pragma unroll
         for (int f = 0; f < 4; ++f) s[f] += p[f];
         if (sp2) s[4] += p[6];  // rho chi (square lattice, two gases)
@@ -553,10 +604,18 @@ hipError_t launch_pool_finalize(const PoolView& v, int nslots, int commit, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double* partials, int64_t nb, StepCtl* ctl, long long step,
+hipError_t launch_finalize(double* partials, int64_t nb, StepCtl* ctl, long long step,
                            hipStream_t stream, bool species2d)
 {
-    finalize_kernel<<<1, kFinTPB, 0, stream>>>(partials, nb, ctl, step, kHalo, species2d ? 1 : 0);
+    if (nb > 16 * kChunk) {  // many rows: fold each chunk first, on many CUs
+        const int64_t g = (nb + kChunk - 1) / kChunk;
+        partials_chunk_kernel<<<(unsigned)g, kChunk, 0, stream>>>(partials, nb, ctl, step);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        finalize_kernel<<<1, kFinTPB, 0, stream>>>(partials, g, kChunk, ctl, step, species2d ? 1 : 0);
+        return hipGetLastError();
+    }
+    finalize_kernel<<<1, kFinTPB, 0, stream>>>(partials, nb, 1, ctl, step, species2d ? 1 : 0);
     return hipGetLastError();
 }
 
