@@ -56,10 +56,11 @@ MarchGeom march2d_geometry(const Grid& g, int resident_blocks);
 int64_t march2d_max_blocks(const Grid& g);
 template <typename T>
 int march2d_blocks_per_cu();
-// The short-FIFO kernel runs every tile and flags (flags[tile] != 0) those
-// whose packets reach past its FIFO; the full-FIFO kernel then recomputes only
-// the flagged tiles (it returns at once when there are none).  flags holds
-// one int per tile.
+// The short-FIFO kernel runs every tile and flags those it could not
+// complete, and those with sources that reach past its FIFO; the full-FIFO
+// kernel then recomputes the incomplete tiles and the row-chunk neighbours of
+// the far-reaching ones (it returns at once when nothing was flagged).  flags
+// holds one int of flag bits per tile.
 template <typename T>
 hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
                           StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream);
@@ -130,7 +131,7 @@ struct PoolView {
     int32_t* tstate;        // kTileSet | kTileLive per tile
     const int32_t* ntiles;  // tiles in the table (read by the kernels, so admissions need no new launch shape)
     double* partials;       // kPartialStride doubles per tile
-    int32_t* flags;         // square lattice: tile needs the full-FIFO pass
+    int32_t* flags;         // square lattice: per-tile flag bits of the short- and full-FIFO passes
     int32_t* next;          // [0], [1]: tile claim counters of the step and full-FIFO passes; [2]: tiles
                             // flagged for the full-FIFO pass; reset by finalize
     void* arena;            // moment sets of all slots (T elements)

@@ -569,16 +569,54 @@ __device__ __forceinline__ void load_node(const T* __restrict__ Y, int64_t nn, i
     if constexpr (NF > 4) m[4] = Y[4 * nn + q];
 }
 
+// Per-tile flag bits of the square-lattice passes.  The short pass writes
+// kFlagFar and kFlagReach of every tile it claims (a tile it leaves to the
+// full pass gets both: its sources are not looked at); the full pass reads
+// them and rewrites only kFlagKeep, the tile still needs the full FIFO, which
+// the next step's short pass reads.
+constexpr int kFlagFar = 1, kFlagReach = 2, kFlagKeep = 4;
+
+// Whether the full pass must compute the tile of destination rows
+// [Y0, ylast) whose row chunk ty0 = Y0 / sy starts at flag index tbase +
+// ty0 * tiles_x + tx (row chunks of sy rows, column strips tiles_x wide).  The
+// short pass stages the L = kLSmall rows on each side of a tile, but a source
+// up to H rows away can reach it: the rows [Y0 - H, Y0 - L) and
+// [ylast + L, ylast + H), mapped by the y boundary, belong to other row chunks
+// (or the same one).  A source there that reaches the tile has a y-reach
+// beyond L, so the chunk owning its row raised kFlagReach: a periodic or
+// clamped halo row is the very source it stands for, and a mirror image
+// beyond a wall reaches inside only with packets whose mirror images, from
+// the node inside, reach as far out (zero-mass corners aside, which add
+// nothing).  The tile is computed again if its own short pass was incomplete
+// or any such chunk raised kFlagReach.
+__device__ __forceinline__ bool needs_full(const int* __restrict__ flags, int64_t tbase, int64_t tiles_x,
+                                           int64_t tx, int64_t Y0, int64_t ylast, int sy, int64_t ny, int bc_y)
+{
+    if (flags[tbase + (Y0 / sy) * tiles_x + tx] & kFlagFar) return true;
+#pragma unroll
+    for (int i = 0; i < 2 * (kMH - kLSmall); ++i) {
+        const int d = i % (kMH - kLSmall);
+        const int64_t row = i < kMH - kLSmall ? Y0 - kMH + d : ylast + kLSmall + d;
+        bool mir = false;
+        const int64_t src = source_idx(row, ny, bc_y, &mir);
+        if (flags[tbase + (src / sy) * tiles_x + tx] & kFlagReach) return true;
+    }
+    return false;
+}
+
 // One tile: destination columns [X0, X0 + 256 - 2H) and rows [Y0, Y0 + sy)
 // (clipped to the grid) of grid g, marched from row Y0 - L to Y0 + sy + L - 1.
 // Writes Yn and one row of per-tile partials (field sums, reach, error bits).
-// Returns 1 (the same in every thread) when the short pass cannot take some
-// window of the tile: a y-displacement beyond the short FIFO (kLSmall), or a
-// non-planar window (floor(v_y) not uniform, and the mixes the row path does
-// not take), which only the full pass's paths handle.  With L = kLSmall the
-// tile's output is then incomplete and must be recomputed with L = kLFull,
-// which sums in the same order (bit-identical); with L = kLFull it tells that
-// the tile still needs the full pass.
+// Returns kFlag* bits (the same in every thread).  kFlagFar: the short pass
+// cannot take some window of the tile: a y-displacement beyond the short FIFO
+// (kLSmall), or a non-planar window (floor(v_y) not uniform, and the mixes
+// the row path does not take), which only the full pass's paths handle.  With
+// L = kLSmall the tile's output is then incomplete and must be recomputed
+// with L = kLFull, which sums in the same order (bit-identical); with
+// L = kLFull it tells that the tile still needs the full pass.  kFlagReach: a
+// source in the tile's own destination rows has a y-reach beyond kLSmall, so
+// it may reach destination rows of the neighbouring row chunks that their
+// short passes complete without staging it (see needs_full).
 // Contains block-wide barriers: every thread of the block must call it.
 template <typename T, int L, bool WALLS, bool REST, bool SP>
 __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict__ Yn, const Grid& g, const Consts& k,
@@ -612,7 +650,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
         if constexpr (SP) f.x[o] = (A)0;
     }
     double tot[NF] = {};
-    int reach = 0, bad = 0, yfar = 0;
+    int reach = 0, bad = 0, yfar = 0, yreach = 0;
 
     // moments of this thread's source column in row gy (halo rows and
     // columns mapped by the boundaries); *mir_y tells whether the row is a
@@ -659,6 +697,10 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
             const int yr = axis_reach(s.fy, s.c1);
             reach = max(reach, max(axis_reach(s.fx, s.c1), yr));
             yfar |= yr > kLSmall ? 1 : 0;
+            // a source of the tile's own destination rows that reaches past
+            // the short FIFO: the neighbouring tiles' short passes, which do
+            // not stage this row, may miss its packets
+            yreach |= (yr > kLSmall && r0 + u >= L && r0 + u < nrows - L) ? 1 : 0;
             bad |= s.bad ? 1 : 0;
             {
                 const int ry0 = __all(s.ry == (T)0) ? 1 : 0;
@@ -801,7 +843,8 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
         s_ir[wid][0] = reach;
         s_ir[wid][1] = bad;
     }
-    const int far = __syncthreads_or(yfar);
+    // (__syncthreads_or returns whether any value is non-zero, not their OR)
+    const int far = (__syncthreads_or(yfar) ? kFlagFar : 0) | (__syncthreads_or(yreach) ? kFlagReach : 0);
     if (tid == 0) {
         int rr = 0, bb = 0;
         for (int c = 0; c < NF; ++c) {
@@ -849,21 +892,28 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
     for (;;) {
         const int t = claim_tile(&ctl->next[L < kLFull ? 0 : 1], &s_t);
         if (t >= ntiles) break;
+        const int64_t tx = t % tiles_x, ty = t / tiles_x;
         if (L < kLFull) {
-            if (kept && flags[t]) {  // needed the full pass last step: left to it
-                if (threadIdx.x == 0) atomicAdd(&ctl->next[2], 1);
+            if (kept && (flags[t] & kFlagKeep)) {  // needed the full pass last step: left to it
+                if (threadIdx.x == 0) {
+                    flags[t] = kFlagFar | kFlagReach | kFlagKeep;
+                    atomicAdd(&ctl->next[2], 1);
+                }
                 continue;
             }
-        } else if (!flags[t]) {
+        } else if (!needs_full(flags, 0, tiles_x, tx, ty * sy, min((ty + 1) * sy, g.ny), sy, g.ny, g.bc_y)) {
             continue;
         }
-        const int64_t tx = t % tiles_x, ty = t / tiles_x;
-        const int far = march_tile<T, L, WALLS, REST, SP>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
-                                                      partials + (int64_t)t * kPartialStride);
+        const int bits = march_tile<T, L, WALLS, REST, SP>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
+                                                       partials + (int64_t)t * kPartialStride);
         if (threadIdx.x == 0) {
-            flags[t] = far;
-            if (L < kLFull && far) atomicAdd(&ctl->next[2], 1);
-            if (L == kLFull) {
+            const int far = bits & kFlagFar;
+            if (L < kLFull) {
+                flags[t] = bits;
+                if (far) atomicAdd(&ctl->next[2], 1);
+            } else {
+                // keep the short pass's bits, which other blocks of this pass read
+                flags[t] = (flags[t] & (kFlagFar | kFlagReach)) | (far ? kFlagKeep : 0);
                 atomicAdd(&ctl->redo_tiles, 1);
                 if (far) atomicAdd(&ctl->keep[0], 1);
             }
@@ -888,21 +938,36 @@ pool2d_kernel(PoolView v, Consts k)
         if (t >= nt) break;
         const int ts = v.tstate[t];
         if (!(ts & kTileLive)) continue;  // the same for the whole block
-        const int flagged = v.flags[t];
-        if (L < kLFull && flagged) {  // needed the full FIFO last step: left to the full pass
-            if (threadIdx.x == 0) atomicAdd(&v.next[2], 1);
-            continue;
-        }
-        if (L == kLFull && !flagged) continue;
         const PoolTile& tl = v.tiles[t];
+        if (L < kLFull) {
+            if (v.flags[t] & kFlagKeep) {  // needed the full FIFO last step: left to the full pass
+                if (threadIdx.x == 0) {
+                    v.flags[t] = kFlagFar | kFlagReach | kFlagKeep;
+                    atomicAdd(&v.next[2], 1);
+                }
+                continue;
+            }
+        } else {
+            // a slot's tiles are its row chunks, then column strips, from t0
+            const int64_t tiles_x = (tl.nx + kPool2Cols - 1) / kPool2Cols;
+            if (!needs_full(v.flags, v.probs[tl.prob].t0, tiles_x, tl.x0 / kPool2Cols, tl.y0,
+                            min(tl.y0 + (int64_t)tl.rows, tl.ny), tl.rows, tl.ny, tl.bc_y))
+                continue;
+        }
         const int64_t o0 = tl.off[0], o1 = tl.off[1];  // selected below, not indexed (keeps them in registers)
         const int64_t from = (ts & kTileSet) ? o1 : o0, to = (ts & kTileSet) ? o0 : o1;
         const Grid g{tl.nx, tl.ny, tl.bc_x, tl.bc_y};
-        const int far = march_tile<T, L, WALLS, REST, SP>(arena + from, arena + to, g, k, tl.x0, tl.y0, tl.rows,
-                                                          v.partials + (int64_t)t * kPartialStride);
+        const int bits = march_tile<T, L, WALLS, REST, SP>(arena + from, arena + to, g, k, tl.x0, tl.y0, tl.rows,
+                                                           v.partials + (int64_t)t * kPartialStride);
         if (threadIdx.x == 0) {
-            v.flags[t] = far;
-            if (L < kLFull && far) atomicAdd(&v.next[2], 1);
+            const int far = bits & kFlagFar;
+            if (L < kLFull) {
+                v.flags[t] = bits;
+                if (far) atomicAdd(&v.next[2], 1);
+            } else {
+                // keep the short pass's bits, which other blocks of this pass read
+                v.flags[t] = (v.flags[t] & (kFlagFar | kFlagReach)) | (far ? kFlagKeep : 0);
+            }
         }
     }
 }
