@@ -182,6 +182,29 @@ int lb_debug_lanes(lb_solver* s, int32_t* floor_x, int32_t* floor_y, int32_t* c1
 void lb_destroy(lb_solver* s);
 const char* lb_last_error(void);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one step
+ * of solver s's problem (grid, gamma, velocity set, precision; s needs no
+ * lb_bind) from the moment fields Y_in to Y_out, without the bound buffer.
+ * Y_in and Y_out are device SoA arrays [nf][ny][nx] in the storage type
+ * (double for LB_FP64, float for LB_FP32) in lattice units: rho,
+ * rho u lambda, (rho v lambda), rho E lambda^2 (, rho chi); each 256-byte
+ * aligned, not overlapping.  The caller owns both; Y_in is only read.  The
+ * step's scratch (control block, per-tile partial sums, tile flags) is a
+ * static device array of 2 MiB per GPU, which the library holds until the
+ * process ends; grids that need more are rejected with LB_EINVAL (1-D tubes
+ * above about 33 M nodes; a 2-D grid is cut into about three tiles per
+ * resident block whatever its size, and only grids wider than about 7 M
+ * columns need more).
+ * The call queues kernels on hip_stream and returns; it calls no hipMalloc,
+ * hipFree or allocating library routine.  If status_dev (a device int32, may
+ * be NULL) is given, the stream writes LB_OK, LB_EREACH or LB_ESTATE to it
+ * after the step; after a failure Y_out is unspecified and Y_in is the last
+ * good state.  All calls on one GPU share its scratch array and reset it at
+ * their start: calls whose work overlaps on one GPU (other streams, other
+ * threads) race and must be serialised by the caller. */
+int lb_step_static(lb_solver* s, const void* Y_in, void* Y_out, void* hip_stream, int32_t* status_dev);
+
 /* ---- pools: many independent problems, one persistent launch per step ----
  *
  * The batching and serving forms.  A pool holds up to max_slots problems of one

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <climits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -632,6 +633,129 @@ int lb_debug_lanes(lb_solver* s, int32_t* fx, int32_t* fy, int32_t* c1)
         if (e != hipSuccess) return hip_fail(e, "copy out");
     }
     if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return hip_fail(e, "sync");
+    return LB_OK;
+}
+
+// ---- allocation-free stepping: lb_step_static ----
+//
+// The step kernels' scratch (control block, per-tile partial rows, tile flags)
+// lives in the file-scope device array below instead of a bound buffer.  In
+// host code `scratch` only stands in for the symbol: its device address, which
+// differs per GPU, comes from hipGetSymbolAddress, taken once per device with
+// that device current and kept in g_static.
+
+}  // extern "C"
+
+namespace {
+
+constexpr size_t kStaticScratchBytes = (size_t)2 << 20;  // per device
+constexpr size_t kStaticCtlBytes = 256;                  // the StepCtl at the front
+static_assert(sizeof(StepCtl) <= kStaticCtlBytes, "control block must fit its slot");
+constexpr int kStaticMaxDevices = 64;
+
+struct StaticDevice {
+    char* ptr = nullptr;  // device address of `scratch` on this device
+    int cus = 0;          // compute units
+    int per_cu[2] = {0, 0};  // resident square-lattice blocks per CU, FP64 and FP32
+    bool ready = false;
+};
+
+std::mutex g_static_mu;
+StaticDevice g_static[kStaticMaxDevices];
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+// Set-up of the current device (its first lb_step_static call): the address
+// of its copy of `scratch`, its CU count and the march's occupancy.
+int static_device(StaticDevice** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kStaticMaxDevices) return fail(LB_EINVAL, "device %d beyond %d", dev, kStaticMaxDevices);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticDevice& d = g_static[dev];
+    if (!d.ready) {
+        void* p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess)
+            return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if ((e = hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+            return hip_fail(e, "hipDeviceGetAttribute");
+        d.per_cu[0] = march2d_blocks_per_cu<double>();
+        d.per_cu[1] = march2d_blocks_per_cu<float>();
+        d.ptr = (char*)p;
+        d.ready = true;
+    }
+    *out = &d;
+    return LB_OK;
+}
+
+bool is_device_ptr(const void* p)
+{
+    hipPointerAttribute_t attr;
+    const hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lb_step_static(lb_solver* s, const void* Y_in, void* Y_out, void* hip_stream, int32_t* status_dev)
+{
+    if (!s || !Y_in || !Y_out) return fail(LB_EINVAL, "null argument");
+    const size_t set = (size_t)s->nf * (size_t)s->nn * s->elem;
+    const uintptr_t a = (uintptr_t)Y_in, b = (uintptr_t)Y_out;
+    if (a % 256 != 0 || b % 256 != 0) return fail(LB_EINVAL, "moment buffers must be 256-byte aligned");
+    if (a < b + set && b < a + set) return fail(LB_EINVAL, "input and output moment buffers overlap");
+    if (!is_device_ptr(Y_in) || !is_device_ptr(Y_out) || (status_dev && !is_device_ptr(status_dev)))
+        return fail(LB_EINVAL, "buffers must be device memory");
+    StaticDevice* d = nullptr;
+    int rc = static_device(&d);
+    if (rc != LB_OK) return rc;
+    // scratch layout: control block, partial rows (one per block / tile), tile flags
+    MarchGeom m{};
+    int64_t rows = 0;
+    if (s->dim == 1) {
+        rows = step_blocks_1d(s->g);
+    } else {
+        m = march2d_geometry(s->g, d->cus * d->per_cu[s->precision == LB_FP64 ? 0 : 1]);
+        rows = m.blocks();
+    }
+    const size_t part_bytes = align256((size_t)rows * kPartialStride * 8);
+    const size_t need = kStaticCtlBytes + part_bytes + (s->dim == 2 ? align256((size_t)rows * 4) : 0);
+    if (need > kStaticScratchBytes)
+        return fail(LB_EINVAL, "grid %lld x %lld needs %zu bytes of step scratch, more than the %zu of lb_step_static",
+                    (long long)s->g.nx, (long long)s->g.ny, need, kStaticScratchBytes);
+    StepCtl* ctl = (StepCtl*)d->ptr;
+    double* partials = (double*)(d->ptr + kStaticCtlBytes);
+    int* flags = (int*)(d->ptr + kStaticCtlBytes + part_bytes);
+    const hipStream_t st = (hipStream_t)hip_stream;
+    // the last call's control block is stale: a fill kernel resets it (no
+    // memset, so the call can be captured into a graph)
+    hipError_t e = launch_reset_ctl(ctl, st);
+    if (e != hipSuccess) return hip_fail(e, "reset");
+    if (s->dim == 1) {
+        e = s->precision == LB_FP64
+            ? launch_step1d<double>((const double*)Y_in, (double*)Y_out, s->g, s->k, ctl, partials, 1, st)
+            : launch_step1d<float>((const float*)Y_in, (float*)Y_out, s->g, s->k, ctl, partials, 1, st);
+    } else {
+        e = s->precision == LB_FP64
+            ? launch_march2d<double>((const double*)Y_in, (double*)Y_out, s->g, m, s->k, ctl, partials, flags, 1, st)
+            : launch_march2d<float>((const float*)Y_in, (float*)Y_out, s->g, m, s->k, ctl, partials, flags, 1, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    if ((e = launch_finalize(partials, rows, ctl, 1, st, s->dim == 2 && s->species)) != hipSuccess)
+        return hip_fail(e, "finalize launch");
+    if (status_dev && (e = launch_status(ctl, status_dev, st)) != hipSuccess) return hip_fail(e, "status launch");
     return LB_OK;
 }
 

@@ -90,6 +90,11 @@ hipError_t launch_lanes(const T* Y, const Grid& g, int dim, const Consts& k, int
 
 hipError_t launch_reset_ctl(StepCtl* ctl, hipStream_t stream);
 
+// *out := the outcome of the step(s) recorded in ctl: kStatusOk, or the
+// status code of the first failure (the values of LB_OK, LB_ESTATE, LB_EREACH).
+constexpr int kStatusOk = 0, kStatusState = -4, kStatusReach = -5;
+hipError_t launch_status(const StepCtl* ctl, int32_t* out, hipStream_t stream);
+
 // ---- pools: many independent problems advanced by one persistent launch per
 // step over a device-resident tile table (lb_pool.hip) ----
 

@@ -79,6 +79,15 @@ __global__ void reset_ctl_kernel(StepCtl* ctl)
     }
 }
 
+// The step's outcome as an lbsd status code (LB_OK, LB_EREACH, LB_ESTATE).
+__global__ void status_kernel(const StepCtl* __restrict__ ctl, int32_t* __restrict__ out)
+{
+    if (threadIdx.x == 0) {
+        const int e = ctl->err_code;
+        *out = e == 0 ? 0 : ((e & kErrState) ? kStatusState : kStatusReach);
+    }
+}
+
 unsigned blocks_for(int64_t n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
 
 }  // namespace
@@ -113,6 +122,12 @@ hipError_t launch_lanes(const T* Y, const Grid& g, int dim, const Consts& k, int
 hipError_t launch_reset_ctl(StepCtl* ctl, hipStream_t stream)
 {
     reset_ctl_kernel<<<1, 64, 0, stream>>>(ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_status(const StepCtl* ctl, int32_t* out, hipStream_t stream)
+{
+    status_kernel<<<1, 64, 0, stream>>>(ctl, out);
     return hipGetLastError();
 }
 

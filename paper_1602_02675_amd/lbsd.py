@@ -34,7 +34,7 @@ EXPORTED = ["lb_create", "lb_create_two_gas", "lb_species_total", "lb_state_byte
             "lb_set_cfl",
             "lb_init_riemann", "lb_init_moments", "lb_step", "lb_step_timed", "lb_step_profiled", "lb_sync",
             "lb_moments", "lb_totals", "lb_lambda", "lb_dt", "lb_steps_done", "lb_max_reach",
-            "lb_debug_lanes", "lb_destroy", "lb_last_error",
+            "lb_debug_lanes", "lb_destroy", "lb_last_error", "lb_step_static",
             "lb_pool_create", "lb_pool_create_two_gas", "lb_pool_bytes", "lb_pool_footprint", "lb_pool_bind", "lb_pool_admit_riemann",
             "lb_pool_admit_moments", "lb_pool_release", "lb_pool_advance", "lb_pool_advance_timed",
             "lb_pool_poll", "lb_pool_status", "lb_pool_moments", "lb_pool_totals", "lb_pool_lambda", "lb_pool_live",
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lb_debug_lanes": (ctypes.c_int, [vp, I32P, I32P, I32P]),
         "lb_destroy": (None, [vp]),
         "lb_last_error": (ctypes.c_char_p, []),
+        "lb_step_static": (ctypes.c_int, [vp, vp, vp, vp, I32P]),
         "lb_pool_create": (ctypes.c_int, [i32, dbl, ctypes.POINTER(lb_velset), i32, i32, ctypes.c_size_t,
                                           ctypes.POINTER(vp)]),
         "lb_pool_create_two_gas": (ctypes.c_int, [i32, dbl, dbl, ctypes.POINTER(lb_velset), i32, i32,
@@ -237,6 +238,18 @@ class Solver:
 
     def sync(self):
         _check(_lib.lb_sync(self._h))
+
+    def step_static(self, y_in, y_out, status=None, stream=None):
+        """One step from the device moment fields y_in to y_out (torch tensors
+        of the storage dtype, [nf, ny, nx], lattice units) with the library's
+        static scratch (lb_step_static); status: optional int32 device tensor
+        that receives the step's status code.  Queued on `stream` (default:
+        the solver's)."""
+        st = self.stream if stream is None else stream
+        sp = ctypes.cast(ctypes.c_void_p(status.data_ptr()), ctypes.POINTER(ctypes.c_int32)) if status is not None \
+            else None
+        _check(_lib.lb_step_static(self._h, ctypes.c_void_p(y_in.data_ptr()), ctypes.c_void_p(y_out.data_ptr()),
+                                   ctypes.c_void_p(st.cuda_stream), sp))
 
     # -- outputs ---------------------------------------------------------------
     def moments(self) -> np.ndarray:
