@@ -67,7 +67,8 @@ extern "C" {
 typedef struct lb_solver lb_solver; /* opaque */
 
 /* Grid: dim 1 -> ny must be 1.  Nodes are cell centres x_i = x_lo + (i + 1/2) dx,
- * dx = (x_hi - x_lo) / nx; the square lattice has dy = dx. */
+ * dx = (x_hi - x_lo) / nx; the square lattice has dy = dx.  Limits: nx, ny
+ * <= 2^40, nx ny <= 2^36, and nx <= 2^28 on the square lattice (LB_EINVAL). */
 typedef struct {
     int32_t dim;
     int64_t nx, ny;

@@ -66,6 +66,8 @@ int check_grid(const lb_grid* grid, int dim)
     if (grid->nx > (int64_t)1 << 40 || grid->ny > (int64_t)1 << 40 ||
         grid->nx * grid->ny > (int64_t)1 << 36)
         return fail(LB_EINVAL, "grid too large");
+    // the square-lattice kernels address a row's nodes with 32-bit byte offsets
+    if (dim == 2 && grid->nx > (int64_t)1 << 28) return fail(LB_EINVAL, "nx must be <= 2^28 on the square lattice");
     if (!(grid->x_hi > grid->x_lo) || !isfinite(grid->x_lo) || !isfinite(grid->x_hi))
         return fail(LB_EINVAL, "need x_lo < x_hi");
     for (int b : {grid->bc_x, grid->bc_y})
@@ -267,7 +269,8 @@ static int create_solver(const lb_grid* grid, double gamma, double gamma2, bool 
     s->off_ctl = s->off_export + align256((size_t)s->nf * (size_t)s->nn * 8);
     s->off_partials = s->off_ctl + align256(sizeof(StepCtl));
     s->off_flags = s->off_partials + align256((size_t)s->nblocks * kPartialStride * 8);
-    s->total = s->off_flags + align256((size_t)(dim == 2 ? s->nblocks : 1) * 4);
+    // square lattice: two flag words per tile (short and full passes, lean pass)
+    s->total = s->off_flags + align256((size_t)(dim == 2 ? 2 * s->nblocks : 1) * 4);
     s->cfl = 1.0;
     s->lambda_set = 0.0;
     *out = s;
@@ -311,9 +314,10 @@ int lb_bind(lb_solver* s, void* dev_ptr, size_t bytes, void* hip_stream)
         if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
         if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
             return hip_fail(e, "hipDeviceGetAttribute");
-        const int per_cu = s->precision == LB_FP64 ? march2d_blocks_per_cu<double>()
-                                                   : march2d_blocks_per_cu<float>();
-        s->march = march2d_geometry(s->g, cus * per_cu);
+        const bool fp64 = s->precision == LB_FP64;
+        const int per_cu = fp64 ? march2d_blocks_per_cu<double>(false) : march2d_blocks_per_cu<float>(false);
+        const int per_cu_lean = fp64 ? march2d_blocks_per_cu<double>(true) : march2d_blocks_per_cu<float>(true);
+        s->march = march2d_geometry(s->g, cus, per_cu, per_cu_lean);
         s->nblocks = s->march.blocks();
     }
     s->bound = true;
@@ -656,7 +660,8 @@ constexpr int kStaticMaxDevices = 64;
 struct StaticDevice {
     char* ptr = nullptr;  // device address of `scratch` on this device
     int cus = 0;          // compute units
-    int per_cu[2] = {0, 0};  // resident square-lattice blocks per CU, FP64 and FP32
+    int per_cu[2] = {0, 0};       // resident blocks per CU of the square lattice's short pass, FP64 and FP32
+    int per_cu_lean[2] = {0, 0};  // and of its lean pass
     bool ready = false;
 };
 
@@ -685,8 +690,10 @@ int static_device(StaticDevice** out)
             return hip_fail(e, "hipGetSymbolAddress(scratch)");
         if ((e = hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
             return hip_fail(e, "hipDeviceGetAttribute");
-        d.per_cu[0] = march2d_blocks_per_cu<double>();
-        d.per_cu[1] = march2d_blocks_per_cu<float>();
+        d.per_cu[0] = march2d_blocks_per_cu<double>(false);
+        d.per_cu[1] = march2d_blocks_per_cu<float>(false);
+        d.per_cu_lean[0] = march2d_blocks_per_cu<double>(true);
+        d.per_cu_lean[1] = march2d_blocks_per_cu<float>(true);
         d.ptr = (char*)p;
         d.ready = true;
     }
@@ -721,17 +728,18 @@ int lb_step_static(lb_solver* s, const void* Y_in, void* Y_out, void* hip_stream
     StaticDevice* d = nullptr;
     int rc = static_device(&d);
     if (rc != LB_OK) return rc;
-    // scratch layout: control block, partial rows (one per block / tile), tile flags
+    // scratch layout: control block, partial rows (one per block / tile), tile flags (two words per tile)
     MarchGeom m{};
     int64_t rows = 0;
     if (s->dim == 1) {
         rows = step_blocks_1d(s->g);
     } else {
-        m = march2d_geometry(s->g, d->cus * d->per_cu[s->precision == LB_FP64 ? 0 : 1]);
+        const int pi = s->precision == LB_FP64 ? 0 : 1;
+        m = march2d_geometry(s->g, d->cus, d->per_cu[pi], d->per_cu_lean[pi]);
         rows = m.blocks();
     }
     const size_t part_bytes = align256((size_t)rows * kPartialStride * 8);
-    const size_t need = kStaticCtlBytes + part_bytes + (s->dim == 2 ? align256((size_t)rows * 4) : 0);
+    const size_t need = kStaticCtlBytes + part_bytes + (s->dim == 2 ? align256((size_t)rows * 2 * 4) : 0);
     if (need > kStaticScratchBytes)
         return fail(LB_EINVAL, "grid %lld x %lld needs %zu bytes of step scratch, more than the %zu of lb_step_static",
                     (long long)s->g.nx, (long long)s->g.ny, need, kStaticScratchBytes);

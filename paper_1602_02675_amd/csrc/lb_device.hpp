@@ -193,8 +193,10 @@ __device__ __forceinline__ Src1<T> make_src1(T m0t, T m1t, T m2t, const Consts& 
 // REST: the square set with a rest level (d_0 = delta0 rho); the staged level
 // masses then carry (rho - d_0) / b_1 between them.  SP: two gases; m4t is
 // the species moment rho chi and the node's gas the mixture (as in make_src1,
-// with D = 2).
-template <typename T, bool REST = false, bool SP = false>
+// with D = 2).  VY0: for callers that use the result only where rho v_y is
+// +-0: v_y is then taken as rho v_y itself, the same +-0 as the quotient
+// (elsewhere v_y = rho v_y, and floor(v_y) and r_y tell that it is not 0).
+template <typename T, bool REST = false, bool SP = false, bool VY0 = false>
 __device__ __forceinline__ Src2<T> make_src2(T m0t, T m1t, T m2t, T m3t, const Consts& kc, T m4t = (T)0)
 {
     const double m0 = m0t, m1 = m1t, m2 = m2t, m3 = m3t;
@@ -224,7 +226,7 @@ __device__ __forceinline__ Src2<T> make_src2(T m0t, T m1t, T m2t, T m3t, const C
     {
 #pragma clang fp contract(off)
         vx = pdiv<FAST>(m1, m0);
-        vy = pdiv<FAST>(m2, m0);
+        vy = VY0 ? m2 : pdiv<FAST>(m2, m0);
         E = pdiv<FAST>(m3, m0);
         v2 = vx * vx + vy * vy;
     }

@@ -12,8 +12,9 @@ constexpr int kErrState = 2;  // rho <= 0 or a non-finite moment
 
 // Per-solver control block in device memory (written by the step kernels).
 struct StepCtl {
-    int next[3];            // square lattice: tile claim counters of the short- and full-FIFO passes,
-                            // and the number of tiles the short pass flagged (reset by finalize)
+    int next[5];            // square lattice: tile claim counters of the short- and full-FIFO passes,
+                            // tiles the short pass flagged, claim counter of the lean pass, tiles the
+                            // lean pass gave up (reset by finalize)
     int err_code;           // kErr* bits of the first failed step
     long long err_step;     // first failed step (LLONG_MAX if none)
     long long totals_step;  // step whose totals are in `totals`
@@ -49,13 +50,17 @@ int64_t step_blocks_1d(const Grid& g);
 struct MarchGeom {
     int sy;                   // destination rows per tile
     int64_t grid_x, grid_y;   // tiles along x (column strips) and y (row chunks)
-    int nblocks;              // persistent blocks (resident at once)
+    int nblocks;              // persistent blocks of the short and full passes (resident at once)
+    int nblocks_lean;         // persistent blocks of the lean pass
     int64_t blocks() const { return grid_x * grid_y; }  // tiles (= rows of partials)
 };
-MarchGeom march2d_geometry(const Grid& g, int resident_blocks);
+// cus: compute units; per_cu / per_cu_lean: resident blocks per CU of the
+// short and the lean pass (march2d_blocks_per_cu).
+MarchGeom march2d_geometry(const Grid& g, int cus, int per_cu, int per_cu_lean);
 int64_t march2d_max_blocks(const Grid& g);
+// Resident blocks per CU of the short pass (lean = false) or the lean pass.
 template <typename T>
-int march2d_blocks_per_cu();
+int march2d_blocks_per_cu(bool lean = false);
 // The short-FIFO kernel runs every tile and flags those it could not
 // complete, and those with sources that reach past its FIFO; the full-FIFO
 // kernel then recomputes the incomplete tiles and the row-chunk neighbours of
@@ -137,8 +142,8 @@ struct PoolView {
     const int32_t* ntiles;  // tiles in the table (read by the kernels, so admissions need no new launch shape)
     double* partials;       // kPartialStride doubles per tile
     int32_t* flags;         // square lattice: per-tile flag bits of the short- and full-FIFO passes
-    int32_t* next;          // [0], [1]: tile claim counters of the step and full-FIFO passes; [2]: tiles
-                            // flagged for the full-FIFO pass; reset by finalize
+    int32_t* flags_lean;    // square lattice: per-tile flag bits of the lean pass
+    int32_t* next;          // 5 counters, as StepCtl::next; reset by finalize
     void* arena;            // moment sets of all slots (T elements)
 };
 
@@ -163,9 +168,11 @@ template <typename T>
 hipError_t launch_pool1d(const PoolView& v, const Consts& k, int shape, int nblocks, bool walls,
                          hipStream_t stream);
 template <typename T>
-hipError_t launch_pool2d(const PoolView& v, const Consts& k, int nblocks, bool walls, hipStream_t stream);
+hipError_t launch_pool2d(const PoolView& v, const Consts& k, int nblocks_lean, int nblocks, bool walls,
+                         hipStream_t stream);
+// Resident blocks per CU of the pool's short pass (lean = false) or lean pass.
 template <typename T>
-int pool2d_blocks_per_cu();
+int pool2d_blocks_per_cu(bool lean = false);
 // Per slot: reduce its tiles' partial rows (fixed order) into its state and,
 // when commit != 0 and the step succeeded, count the step.
 hipError_t launch_pool_finalize(const PoolView& v, int nslots, int commit, hipStream_t stream);

@@ -3,6 +3,8 @@
 // are in lb_march2d.hpp; the pool form's one-gas instances are in
 // lb_pool2d.hip, the two-gas instances in lb_march2d_sp.hip and
 // lb_pool2d_sp.hip).
+#include <algorithm>
+
 #include "lb_march2d.hpp"
 
 namespace lbsd {
@@ -14,25 +16,30 @@ int64_t x_strips(const Grid& g) { return (g.nx + (kMTPB - 2 * kMH) - 1) / (kMTPB
 }  // namespace
 
 #ifndef LB_MARCH_TILES_X10
-#define LB_MARCH_TILES_X10 30  // tiles per resident block, times 10
+#define LB_MARCH_TILES_X10 10  // tiles per resident block of the lean pass, times 10
 #endif
-MarchGeom march2d_geometry(const Grid& g, int resident_blocks)
+MarchGeom march2d_geometry(const Grid& g, int cus, int per_cu, int per_cu_lean)
 {
     MarchGeom m;
     const int64_t xs = x_strips(g);
-    // strips short enough for about LB_MARCH_TILES_X10 / 10 tiles per resident
-    // block (claim-order balance), but not below kMinRows (the 2L halo rows of
-    // each tile are marched again)
-    const int64_t want = ((int64_t)LB_MARCH_TILES_X10 * (resident_blocks > 0 ? resident_blocks : 1) + 9) / 10;
-    int64_t chunks = (want + xs - 1) / xs;
+    const int64_t resident = (int64_t)(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+    const int64_t resident_lean = (int64_t)(cus > 0 ? cus : 1) * (per_cu_lean > 0 ? per_cu_lean : 1);
+    // about LB_MARCH_TILES_X10 / 10 tiles per resident block of the lean
+    // pass, which does the bulk of a planar step (its tiles cost about the
+    // same; taller tiles march fewer halo rows again), but strips no shorter
+    // than kMinRows
+    // (rounded down: one tile more than the resident blocks would cost the
+    // step a second round for that tile)
+    const int64_t want = (int64_t)LB_MARCH_TILES_X10 * resident_lean / 10;
+    int64_t chunks = want / xs;
     if (chunks < 1) chunks = 1;
     int64_t sy = (g.ny + chunks - 1) / chunks;
     if (sy < kMinRows) sy = kMinRows;
     m.sy = (int)sy;
     m.grid_x = xs;
     m.grid_y = (g.ny + sy - 1) / sy;
-    m.nblocks = resident_blocks > 0 ? resident_blocks : 1;
-    if (m.nblocks > m.blocks()) m.nblocks = (int)m.blocks();
+    m.nblocks = (int)std::min<int64_t>(resident, m.blocks());
+    m.nblocks_lean = (int)std::min<int64_t>(resident_lean, m.blocks());
     return m;
 }
 
@@ -42,11 +49,13 @@ int64_t march2d_max_blocks(const Grid& g)
 }
 
 template <typename T>
-int march2d_blocks_per_cu()
+int march2d_blocks_per_cu(bool lean)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, march2d_kernel<T, kLSmall, false, false, false>, kMTPB, 0) != hipSuccess)
-        return 1;
+    const hipError_t e = lean
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, march2d_lean_kernel<T, false, false, false>, kMTPB, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, march2d_kernel<T, kLSmall, false, false, false>, kMTPB, 0);
+    if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 
@@ -65,8 +74,8 @@ hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, 
                  : launch_march2d_w<T, false, false, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
 }
 
-template int march2d_blocks_per_cu<double>();
-template int march2d_blocks_per_cu<float>();
+template int march2d_blocks_per_cu<double>(bool);
+template int march2d_blocks_per_cu<float>(bool);
 template hipError_t launch_march2d<double>(const double*, double*, const Grid&, const MarchGeom&,
                                            const Consts&, StepCtl*, double*, int*, long long, hipStream_t);
 template hipError_t launch_march2d<float>(const float*, float*, const Grid&, const MarchGeom&,

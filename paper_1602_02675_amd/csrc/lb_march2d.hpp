@@ -48,12 +48,12 @@ constexpr int kLFull = kMH, kLSmall = 3;
 constexpr int kMinRows = 16;      // smallest strip height (bounds the y-halo overhead)
 
 // FIFO values per slot.  The y-momentum is kept as two parts: what packets
-// carry as m v_y, and the m c' of the y-lanes, summed in double-length
-// (TwoSum) arithmetic.  A y-lane packet and its mirror (opposite sign) reach a
-// destination from two different source rows, after other terms; the
-// double-length sum makes them cancel exactly when those rows are equal, so a
-// planar flow keeps v_y = 0 exactly and floor(v_y) stays uniform.
-enum { kR = 0, kPx = 1, kPyv = 2, kGh = 3, kGl = 4, kE = 5, kNV = 6 };
+// carry as m v_y, and the m c' of the y-lanes (YLaneSum).  A y-lane packet
+// and its mirror (opposite sign) reach a destination from two different
+// source rows, after other terms; the y-lane sum makes them cancel exactly
+// when those rows are equal, so a planar flow keeps v_y = 0 exactly and
+// floor(v_y) stays uniform.
+enum { kR = 0, kPx = 1, kPyv = 2, kE = 3, kNV = 4 };
 
 // (h, l) += x with the rounding error of h + x carried into l (TwoSum).
 template <typename T>
@@ -66,6 +66,21 @@ __device__ __forceinline__ void dd_add(T& h, T& l, T x)
     h = s;
     l = l + e;
 }
+
+// Sum of the y-lane momenta m c' of one FIFO slot, in double-length
+// (TwoSum) arithmetic: FP64 pairs for both storage types.  The terms of one
+// destination can span some 80 binades (near rest, a corner weight 1 - r_x
+// of 1e-24 next to one of 1), and the row path adds one term per packet
+// class; only a double-length sum cancels such mirrored terms from equal rows
+// exactly.  In FP32 storage the terms are FP32 products, so an FP64 pair is
+// exact where an FP32 pair leaves the rounding of its low part behind.
+template <typename T>
+struct YLaneSum {
+    double h, l;
+    __device__ __forceinline__ void zero() { h = l = 0.0; }
+    __device__ __forceinline__ void add(T x) { dd_add<double>(h, l, (double)x); }
+    __device__ __forceinline__ double total() const { return h + l; }
+};
 
 __device__ __forceinline__ int mpack(int fx, int fy, int c1)
 {
@@ -85,20 +100,36 @@ struct MRowSpecies {  // two gases: mass fraction of gas 1 per source
 template <typename T>
 struct MRowSpecies<T, false> {};  // one gas: empty (the row keeps its layout)
 
-template <typename T, bool SP = false>
-struct MRow : MRowSpecies<T, SP> {  // one staged source row (per source, see Src2)
-    T vx[kMTPB], ry[kMTPB];
+template <typename T, bool RYS>
+struct MRowRy {  // the y fraction r_y per source
+    T ry[kMTPB];
+};
+template <typename T>
+struct MRowRy<T, false> {};  // rows of the lean pass: every source has v_y = 0 (r_y = 0)
+
+template <typename T, bool SP = false, bool RYS = true>
+struct MRow : MRowSpecies<T, SP>, MRowRy<T, RYS> {  // one staged source row (per source, see Src2)
+    static constexpr bool kSP = SP, kRYS = RYS;
+    using value_type = T;
+    T vx[kMTPB];
     T m[2][2][kMTPB];  // [level][x corner]
     T kk[2][kMTPB];    // [level]
     int pk[kMTPB];
 };
 
 // chi of the source in column s (0 with one gas)
-template <typename T, bool SP>
-__device__ __forceinline__ T chi_of(const MRow<T, SP>& R, int s)
+template <typename Row>
+__device__ __forceinline__ typename Row::value_type chi_of(const Row& R, int s)
 {
-    if constexpr (SP) return R.chi[s];
-    else return (T)0;
+    if constexpr (Row::kSP) return R.chi[s];
+    else return (typename Row::value_type)0;
+}
+// r_y of the source in column s (0 in the lean pass's rows)
+template <typename Row>
+__device__ __forceinline__ typename Row::value_type ry_of(const Row& R, int s)
+{
+    if constexpr (Row::kRYS) return R.ry[s];
+    else return (typename Row::value_type)0;
 }
 
 struct WaveInfo {  // per wavefront and staged row: ranges over its 64 sources
@@ -124,7 +155,36 @@ template <typename T, int L, bool SP = false>
 struct Fifo {
     static constexpr int NS = 2 * L + 1;
     T a[NS][kNV];        // slot o + L: destination row (current source row) + o
+    YLaneSum<T> g[NS];   // y-lane momenta per slot
     T x[SP ? NS : 1];    // two gases: the species moment m chi per slot
+
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int o = 0; o < NS; ++o) {
+#pragma unroll
+            for (int c = 0; c < kNV; ++c) a[o][c] = (T)0;
+            g[o].zero();
+            if constexpr (SP) x[o] = (T)0;
+        }
+    }
+    // the oldest slot is written out: every slot moves down by one
+    __device__ __forceinline__ void shift()
+    {
+#pragma unroll
+        for (int o = 0; o + 1 < NS; ++o) {
+#pragma unroll
+            for (int c = 0; c < kNV; ++c) a[o][c] = a[o + 1][c];
+            g[o] = g[o + 1];
+            if constexpr (SP) x[o] = x[o + 1];
+        }
+#pragma unroll
+        for (int c = 0; c < kNV; ++c) a[NS - 1][c] = (T)0;
+        g[NS - 1].zero();
+        if constexpr (SP) x[NS - 1] = (T)0;
+    }
+    // y-momentum of the oldest slot
+    __device__ __forceinline__ T py0() const { return (T)(a[0][kPyv] + g[0].total()); }
 };
 
 // Add to the FIFO slot `slot` (differs between lanes) for slots in the
@@ -153,7 +213,7 @@ __device__ __forceinline__ void fifo_add_g(Fifo<A, L, SP>& f, int slot, int lo, 
 #pragma unroll
     for (int o = 0; o < 2 * L + 1; ++o) {
         if (o < lo || o > hi) continue;
-        dd_add<A>(f.a[o][kGh], f.a[o][kGl], (A)(slot == o ? v : (T)0));
+        f.g[o].add((A)(slot == o ? v : (T)0));
     }
 }
 
@@ -232,7 +292,7 @@ __device__ __forceinline__ void add_ylanes(Fifo<A, L, SP>& f, int op, int om, co
         f.a[o][kR] += (A)msum;
         f.a[o][kPx] += (A)pr;
         if (!NOVY) f.a[o][kPyv] += (A)py;
-        dd_add<A>(f.a[o][kGh], f.a[o][kGl], (A)(sg > 0 ? gm : -gm));
+        f.g[o].add((A)(sg > 0 ? gm : -gm));
         f.a[o][kE] += (A)pe;
         if constexpr (SP) f.x[o] += (A)xsum;
     }
@@ -268,13 +328,13 @@ __device__ __forceinline__ void add_rest(Fifo<A, L, SP>& f, int o, const T (&m)[
 
 // Rest-group mass at x corner kc of the source in column s: d_0 = rq (d_1 +
 // d_2) of the staged level masses; and its energy per unit mass, K.
-template <typename T, bool SP>
-__device__ __forceinline__ T rest_mass(const MRow<T, SP>& R, int kc, int s, T rq)
+template <typename T, bool SP, bool RYS>
+__device__ __forceinline__ T rest_mass(const MRow<T, SP, RYS>& R, int kc, int s, T rq)
 {
     return rq * (R.m[0][kc][s] + R.m[1][kc][s]);
 }
-template <typename T, bool SP>
-__device__ __forceinline__ T rest_k(const MRow<T, SP>& R, int s)
+template <typename T, bool SP, bool RYS>
+__device__ __forceinline__ T rest_k(const MRow<T, SP, RYS>& R, int s)
 {
     const int c1 = mc1(R.pk[s]);
     return R.kk[0][s] - (T)0.5 * (T)(c1 * c1);
@@ -292,8 +352,9 @@ __device__ __forceinline__ T rest_k(const MRow<T, SP>& R, int s)
 // sums are the same, term for term.  REST: the rest group's packets (from the
 // sources at x displacement floor(v_x) + k_x, into row FY + k_y) follow the
 // lanes.
-template <typename T, int L, int FY, int S0, int NSP, int NKX, bool RY0, bool REST, bool SP>
-__device__ __forceinline__ void gather_fast(const MRow<T, SP>& R, int lane, int fx, Fifo<Acc<T>, L, SP>& f, T rq)
+template <typename T, int L, int FY, int S0, int NSP, int NKX, bool RY0, bool REST, bool SP, bool RYS>
+__device__ __forceinline__ void gather_fast(const MRow<T, SP, RYS>& R, int lane, int fx, Fifo<Acc<T>, L, SP>& f,
+                                            T rq)
 {
 #pragma clang fp contract(off)
     constexpr bool UNI = NSP == 2;
@@ -330,7 +391,7 @@ __device__ __forceinline__ void gather_fast(const MRow<T, SP>& R, int lane, int 
             const int sp = base - (kx + c), sm = base - (kx - c);
             const T bp = mass(sp, j, kx), bm = mass(sm, j, kx);
             const T vxp = R.vx[sp], vxm = R.vx[sm];
-            const T ryp = R.ry[sp], rym = R.ry[sm];
+            const T ryp = ry_of(R, sp), rym = ry_of(R, sm);
             const T vyp = (T)FY + ryp, vym = (T)FY + rym;
             const T zp = fmaT(cc, vxp, kkof(sp, j)), zm = fmaT(-cc, vxm, kkof(sm, j));
 #pragma unroll
@@ -350,7 +411,7 @@ __device__ __forceinline__ void gather_fast(const MRow<T, SP>& R, int lane, int 
         for (int q = 0; q < NKX; ++q) {
             const int kx = K0 + q, sq = base - kx;
             b[q] = mass(sq, j, kx);
-            ry[q] = R.ry[sq];
+            ry[q] = ry_of(R, sq);
             vx[q] = R.vx[sq];
             vy[q] = (T)FY + ry[q];
             kk[q] = kkof(sq, j);
@@ -372,7 +433,7 @@ __device__ __forceinline__ void gather_fast(const MRow<T, SP>& R, int lane, int 
             const int kc = NKX == 2 ? kx : kx + fx - mfx(R.pk[sq]);  // the source's own corner
             const T v = rest_mass(R, kc < 0 ? 0 : (kc > 1 ? 1 : kc), sq, rq);
             b[q] = (kc >= 0 && kc <= 1) ? v : (T)0;
-            ry[q] = R.ry[sq];
+            ry[q] = ry_of(R, sq);
             vx[q] = R.vx[sq];
             vy[q] = (T)FY + ry[q];
             kr[q] = rest_k(R, sq);
@@ -398,11 +459,17 @@ __device__ __forceinline__ void gather_fast(const MRow<T, SP>& R, int lane, int 
 // source counts only if its floor(v_y) is FY as well: two such calls, for FY
 // and FY + 1, take a window whose floor(v_y) has two adjacent values.  REST:
 // the rest group's packets follow the lanes, in the fast path's order.
-template <typename T, int L, int FY, bool REST, bool SP>
-__device__ __forceinline__ void gather_rows(const MRow<T, SP>& R, int lane, Fifo<Acc<T>, L, SP>& f, int fxlo,
+template <typename T, int L, int FY, bool REST, bool SP, bool RYS, bool RY0 = false>
+__device__ __forceinline__ void gather_rows(const MRow<T, SP, RYS>& R, int lane, Fifo<Acc<T>, L, SP>& f, int fxlo,
                                             int fxhi, int clo, int chi, bool chk, T rq)
 {
 #pragma clang fp contract(off)
+    // RY0 (FY = 0, every source with v_y = 0): the k_y = 1 corners carry no
+    // mass and are skipped, and no packet carries m v_y; the other packets
+    // are added in the same order, so the sums are bit for bit those of the
+    // full form (which adds exact zeros for the skipped ones)
+    constexpr bool NOVY = RY0 && FY == 0;
+    constexpr int NKY = RY0 ? 1 : 2;
     const int nfx = fxhi - fxlo;
 #pragma unroll
     for (int lev = 0; lev < 2; ++lev) {
@@ -418,18 +485,18 @@ __device__ __forceinline__ void gather_rows(const MRow<T, SP>& R, int lane, Fifo
                     const bool okm = mfx(pkm) == F && mc1(pkm) + lev == C && (!chk || mfy(pkm) == FY);
                     const T bp = okp ? R.m[lev][kx][sp] : (T)0, bm = okm ? R.m[lev][kx][sm] : (T)0;
                     const T vxp = R.vx[sp], vxm = R.vx[sm];
-                    const T ryp = R.ry[sp], rym = R.ry[sm];
+                    const T ryp = ry_of(R, sp), rym = ry_of(R, sm);
                     const T vyp = (T)FY + ryp, vym = (T)FY + rym;
                     const T cc = (T)C;
                     const T zp = fmaT(cc, vxp, R.kk[lev][sp]), zm = fmaT(-cc, vxm, R.kk[lev][sm]);
 #pragma unroll
-                    for (int ky = 0; ky < 2; ++ky) {
+                    for (int ky = 0; ky < NKY; ++ky) {
                         const T mp = bp * (ky ? ryp : (T)1 - ryp), mm = bm * (ky ? rym : (T)1 - rym);
                         if constexpr (SP)
-                            add_xpair<Acc<T>, T, L, false>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm,
-                                                           chi_of(R, sp), chi_of(R, sm));
+                            add_xpair<Acc<T>, T, L, NOVY>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm,
+                                                          chi_of(R, sp), chi_of(R, sm));
                         else
-                            add_xpair<Acc<T>, T, L, false>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm);
+                            add_xpair<Acc<T>, T, L, NOVY>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm);
                     }
                 }
             }
@@ -443,7 +510,7 @@ __device__ __forceinline__ void gather_rows(const MRow<T, SP>& R, int lane, Fifo
             const bool ok0 = mfx(pk0) == F && (!chk || mfy(pk0) == FY);
             const bool ok1 = mfx(pk1) == F && (!chk || mfy(pk1) == FY);
             const int c0 = mc1(pk0) + lev, c1 = mc1(pk1) + lev;
-            const T ry[2] = {R.ry[s0], R.ry[s1]};
+            const T ry[2] = {ry_of(R, s0), ry_of(R, s1)};
             const T b0 = ok0 ? R.m[lev][0][s0] : (T)0, b1 = ok1 ? R.m[lev][1][s1] : (T)0;
             const T vx[2] = {R.vx[s0], R.vx[s1]};
             const T vy[2] = {(T)FY + ry[0], (T)FY + ry[1]};
@@ -452,13 +519,13 @@ __device__ __forceinline__ void gather_rows(const MRow<T, SP>& R, int lane, Fifo
 #pragma unroll
             for (int C = 0; C <= 3 + 1; ++C) {  // speed of this level, static
                 if (C < cl || C > ch) continue;
-                if (FY + 1 + C > L || FY - C < -L) continue;  // out of the FIFO: redone / reported
+                if (FY + NKY - 1 + C > L || FY - C < -L) continue;  // out of the FIFO: redone / reported
                 const T w0 = c0 == C ? b0 : (T)0, w1 = c1 == C ? b1 : (T)0;
                 const T cc = (T)C;
 #pragma unroll
-                for (int ky = 0; ky < 2; ++ky) {
+                for (int ky = 0; ky < NKY; ++ky) {
                     const T m[2] = {w0 * (ky ? ry[0] : (T)1 - ry[0]), w1 * (ky ? ry[1] : (T)1 - ry[1])};
-                    add_ylanes<Acc<T>, T, L, 2, false>(f, FY + ky + C + L, FY + ky - C + L, m, vx, vy, kk, cc, xq);
+                    add_ylanes<Acc<T>, T, L, 2, NOVY>(f, FY + ky + C + L, FY + ky - C + L, m, vx, vy, kk, cc, xq);
                 }
             }
         }
@@ -470,16 +537,16 @@ __device__ __forceinline__ void gather_rows(const MRow<T, SP>& R, int lane, Fifo
             const int pk0 = R.pk[s0], pk1 = R.pk[s1];
             const bool ok0 = mfx(pk0) == F && (!chk || mfy(pk0) == FY);
             const bool ok1 = mfx(pk1) == F && (!chk || mfy(pk1) == FY);
-            const T ry[2] = {R.ry[s0], R.ry[s1]};
+            const T ry[2] = {ry_of(R, s0), ry_of(R, s1)};
             const T b0 = ok0 ? rest_mass(R, 0, s0, rq) : (T)0, b1 = ok1 ? rest_mass(R, 1, s1, rq) : (T)0;
             const T vx[2] = {R.vx[s0], R.vx[s1]};
             const T vy[2] = {(T)FY + ry[0], (T)FY + ry[1]};
             const T kr[2] = {rest_k(R, s0), rest_k(R, s1)};
             const T xq[2] = {chi_of(R, s0), chi_of(R, s1)};
 #pragma unroll
-            for (int ky = 0; ky < 2; ++ky) {
+            for (int ky = 0; ky < NKY; ++ky) {
                 const T m[2] = {b0 * (ky ? ry[0] : (T)1 - ry[0]), b1 * (ky ? ry[1] : (T)1 - ry[1])};
-                add_rest<Acc<T>, T, L, 2, false>(f, FY + ky + L, m, vx, vy, kr, xq);
+                add_rest<Acc<T>, T, L, 2, NOVY>(f, FY + ky + L, m, vx, vy, kr, xq);
             }
         }
     }
@@ -576,27 +643,28 @@ __device__ __forceinline__ void load_node(const T* __restrict__ Y, int64_t nn, i
 // the next step's short pass reads.
 constexpr int kFlagFar = 1, kFlagReach = 2, kFlagKeep = 4;
 
-// Whether the full pass must compute the tile of destination rows
+// Whether the next pass must compute the tile of destination rows
 // [Y0, ylast) whose row chunk ty0 = Y0 / sy starts at flag index tbase +
-// ty0 * tiles_x + tx (row chunks of sy rows, column strips tiles_x wide).  The
-// short pass stages the L = kLSmall rows on each side of a tile, but a source
-// up to H rows away can reach it: the rows [Y0 - H, Y0 - L) and
-// [ylast + L, ylast + H), mapped by the y boundary, belong to other row chunks
-// (or the same one).  A source there that reaches the tile has a y-reach
-// beyond L, so the chunk owning its row raised kFlagReach: a periodic or
-// clamped halo row is the very source it stands for, and a mirror image
-// beyond a wall reaches inside only with packets whose mirror images, from
-// the node inside, reach as far out (zero-mass corners aside, which add
-// nothing).  The tile is computed again if its own short pass was incomplete
-// or any such chunk raised kFlagReach.
-__device__ __forceinline__ bool needs_full(const int* __restrict__ flags, int64_t tbase, int64_t tiles_x,
+// ty0 * tiles_x + tx (row chunks of sy rows, column strips tiles_x wide),
+// after a pass that staged LP rows on each side of its tiles and wrote
+// `flags`.  A source up to H rows away can reach the tile: the rows
+// [Y0 - H, Y0 - LP) and [ylast + LP, ylast + H), mapped by the y boundary,
+// belong to other row chunks (or the same one).  A source there that reaches
+// the tile has a y-reach beyond LP, so the chunk owning its row raised
+// kFlagReach: a periodic or clamped halo row is the very source it stands
+// for, and a mirror image beyond a wall reaches inside only with packets
+// whose mirror images, from the node inside, reach as far out (zero-mass
+// corners aside, which add nothing).  The tile is computed again if its own
+// pass was incomplete or any such chunk raised kFlagReach.
+template <int LP>
+__device__ __forceinline__ bool needs_pass(const int* __restrict__ flags, int64_t tbase, int64_t tiles_x,
                                            int64_t tx, int64_t Y0, int64_t ylast, int sy, int64_t ny, int bc_y)
 {
     if (flags[tbase + (Y0 / sy) * tiles_x + tx] & kFlagFar) return true;
 #pragma unroll
-    for (int i = 0; i < 2 * (kMH - kLSmall); ++i) {
-        const int d = i % (kMH - kLSmall);
-        const int64_t row = i < kMH - kLSmall ? Y0 - kMH + d : ylast + kLSmall + d;
+    for (int i = 0; i < 2 * (kMH - LP); ++i) {
+        const int d = i % (kMH - LP);
+        const int64_t row = i < kMH - LP ? Y0 - kMH + d : ylast + LP + d;
         bool mir = false;
         const int64_t src = source_idx(row, ny, bc_y, &mir);
         if (flags[tbase + (src / sy) * tiles_x + tx] & kFlagReach) return true;
@@ -616,7 +684,7 @@ __device__ __forceinline__ bool needs_full(const int* __restrict__ flags, int64_
 // L = kLFull it tells that the tile still needs the full pass.  kFlagReach: a
 // source in the tile's own destination rows has a y-reach beyond kLSmall, so
 // it may reach destination rows of the neighbouring row chunks that their
-// short passes complete without staging it (see needs_full).
+// short passes complete without staging it (see needs_pass).
 // Contains block-wide barriers: every thread of the block must call it.
 template <typename T, int L, bool WALLS, bool REST, bool SP>
 __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict__ Yn, const Grid& g, const Consts& k,
@@ -643,12 +711,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
 
     using A = Acc<T>;
     Fifo<A, L, SP> f;
-#pragma unroll
-    for (int o = 0; o < NS; ++o) {
-#pragma unroll
-        for (int c = 0; c < kNV; ++c) f.a[o][c] = (A)0;
-        if constexpr (SP) f.x[o] = (A)0;
-    }
+    f.zero();
     double tot[NF] = {};
     int reach = 0, bad = 0, yfar = 0, yreach = 0;
 
@@ -799,7 +862,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
             if (r >= 2 * L && dest) {
                 const int64_t ty = Y0 + r - 2 * L;
                 const int64_t q = ty * nx + gx;
-                const T py = (T)(f.a[0][kPyv] + (f.a[0][kGh] + f.a[0][kGl]));
+                const T py = f.py0();
                 Yn[q] = (T)f.a[0][kR];
                 Yn[nn + q] = (T)f.a[0][kPx];
                 Yn[2 * nn + q] = py;
@@ -813,15 +876,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                     tot[NF - 1] += (double)f.x[0];
                 }
             }
-    #pragma unroll
-            for (int o = 0; o + 1 < NS; ++o) {
-    #pragma unroll
-                for (int c = 0; c < kNV; ++c) f.a[o][c] = f.a[o + 1][c];
-                if constexpr (SP) f.x[o] = f.x[o + 1];
-            }
-    #pragma unroll
-            for (int c = 0; c < kNV; ++c) f.a[NS - 1][c] = (A)0;
-            if constexpr (SP) f.x[NS - 1] = (A)0;
+            f.shift();
         }
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
@@ -862,55 +917,313 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
     return far;
 }
 
-// Wavefronts per SIMD the short-FIFO kernels are compiled for: FP64 keeps its
-// FIFO in registers at two; FP32 fits four with a few spilled registers.
+// The lean first pass: one tile, as march_tile, for x-planar flows.  It takes
+// a tile only if every source it stages has v_y = 0 exactly (floor(v_y) = 0,
+// r_y = 0) and c'_1 <= 1, and every window is one of the fast path's uniform
+// or one-step-mixed cases: then a packet moves at most c'_2 <= 2 rows (the
+// k_y = 1 corners carry no mass and are skipped, eq. 29 with r_y = 0), a FIFO
+// of 2 kLLean + 1 = 5 slots holds every pending destination row, no packet
+// carries m v_y, and r_y need not be staged.  Those savings, and one staged
+// row per barrier, keep the registers and LDS of four wavefronts per SIMD.
+// The packets go through the same gather_fast instances in the same source
+// row order as in march_tile, so a tile it completes is bit-identical to the
+// short pass's result.  At the first row that breaks these conditions the
+// whole block gives the tile up (the decision rides on the row's barrier) and
+// returns kFlagFar | kFlagReach: the short pass then computes it, and the
+// tiles around it (see needs_pass).  Returns 0 when the tile is complete.
+// Contains block-wide barriers: every thread of the block must call it.
+constexpr int kLLean = 2;
+
+// The element at byte offset `off` from p (p wave-uniform, off per lane):
+// the form the hardware's scalar-base global loads and stores take.
+template <typename T>
+__device__ __forceinline__ T& at_byte(T* p, uint32_t off)
+{
+    return *(T*)((char*)p + off);
+}
+template <typename T>
+__device__ __forceinline__ const T& at_byte(const T* p, uint32_t off)
+{
+    return *(const T*)((const char*)p + off);
+}
+
+// A wavefront's summary of one staged row in the lean pass, one int: its
+// ranges of floor(v_x) (biased by 128, as mpack clamps them) and c'_1 (at
+// most 15 is kept: the pass gives up any tile with c'_1 > 1), and kLeanStop.
+constexpr int kLeanStop = 1 << 24;
+__device__ __forceinline__ int lean_word(int fxmin, int fxmax, int c1min, int c1max, int stop)
+{
+    return (fxmin + 128) | ((fxmax + 128) << 8) | (min(c1min, 15) << 16) | (min(c1max, 15) << 20) | stop;
+}
+__device__ __forceinline__ int lean_fxmin(int w) { return (w & 255) - 128; }
+__device__ __forceinline__ int lean_fxmax(int w) { return ((w >> 8) & 255) - 128; }
+__device__ __forceinline__ int lean_c1min(int w) { return (w >> 16) & 15; }
+__device__ __forceinline__ int lean_c1max(int w) { return (w >> 20) & 15; }
+
+template <typename T, bool WALLS, bool REST, bool SP>
+__device__ __forceinline__ int march_tile_lean(const T* __restrict__ Y, T* __restrict__ Yn, const Grid& g,
+                                               const Consts& k, int64_t X0, int64_t Y0, int sy,
+                                               double* __restrict__ prow)
+{
+    constexpr int L = kLLean;
+    constexpr int NF = SP ? 5 : 4;
+    __shared__ MRow<T, SP, false> s_row[2];
+    // per wavefront and staged row: its ranges of floor(v_x) and c'_1, and
+    // whether the tile must be given up (lean_word)
+    __shared__ int4 s_wave[2];
+    const int tid = threadIdx.x, lane64 = tid & 63, wid = tid >> 6;
+    const T rq = REST ? (T)k.rest_q : (T)0;
+    const int64_t nx = g.nx, ny = g.ny, nn = nx * ny;
+    const int64_t gx = X0 - kMH + tid;
+    bool mir_x = false;
+    int64_t sx;
+    if constexpr (WALLS) sx = source_idx(gx, nx, g.bc_x, &mir_x);
+    else sx = g.bc_x == kBcPeriodic ? wrap_near(gx, nx) : clamp_idx(gx, nx);
+    // byte offsets of the columns within a row: 32 bits (a square-lattice
+    // grid is at most 2^28 nodes wide), added to a wave-uniform row address
+    const uint32_t sxb = (uint32_t)sx * (uint32_t)sizeof(T), gxb = (uint32_t)gx * (uint32_t)sizeof(T);
+    const bool dest = tid >= kMH && tid < kMTPB - kMH && gx < nx;
+    const int64_t ylast = min(Y0 + (int64_t)sy, ny);
+    const int nrows = Y0 < ny ? (int)(ylast - Y0) + 2 * L : 0;
+    constexpr int NS = 2 * L + 1;
+
+    using A = Acc<T>;
+    Fifo<A, L, SP> f;
+    f.zero();
+    double tot[NF] = {};
+    int reach = 0, far = 0;
+
+    auto load_src = [&](int64_t gy, T (&m)[NF], bool* mir_y) {
+        int64_t yy;
+        if constexpr (WALLS) yy = source_idx(gy, ny, g.bc_y, mir_y);
+        else yy = g.bc_y == kBcPeriodic ? wrap_near(gy, ny) : clamp_idx(gy, ny);
+#pragma unroll
+        for (int c = 0; c < NF; ++c) m[c] = at_byte(Y + (int64_t)c * nn + yy * nx, sxb);  // uniform row + column
+    };
+    // one source row in registers: row r + 1 is loaded into them as soon as
+    // row r's primitives have read them, and arrives while row r is staged
+    // and gathered (no copy of registers with loads in flight, which would
+    // wait for them)
+    T cur[NF];
+    bool cur_my = false;
+    if (nrows > 0) load_src(Y0 - L, cur, &cur_my);
+
+    for (int r = 0; r < nrows; ++r) {
+        const int b = r & 1;
+        T mx = cur[1], my = cur[2];
+        if constexpr (WALLS) {
+            mx = mir_x ? -mx : mx;
+            my = cur_my ? -my : my;
+        }
+        const Src2<T> s = make_src2<T, REST, SP, true>(cur[0], mx, my, cur[3], k, cur[NF - 1]);
+        if (r + 1 < nrows) load_src(Y0 - L + r + 1, cur, &cur_my);
+        const int pk = mpack(s.fx, s.fy, s.c1);
+        MRow<T, SP, false>& R = s_row[b];
+        R.vx[tid] = s.vx;
+        R.m[0][0][tid] = s.m[0][0];
+        R.m[0][1][tid] = s.m[0][1];
+        R.m[1][0][tid] = s.m[1][0];
+        R.m[1][1][tid] = s.m[1][1];
+        R.kk[0][tid] = s.kk[0];
+        R.kk[1][tid] = s.kk[1];
+        R.pk[tid] = pk;
+        if constexpr (SP) R.chi[tid] = s.chi;
+        reach = max(reach, max(axis_reach(s.fx, s.c1), axis_reach(s.fy, s.c1)));  // as march_tile reports it
+        // v_y = 0 exactly and c'_1 <= 1 (and a good state: bad ones are the short pass's to report)
+        const bool ok = !s.bad && s.fy == 0 && s.ry == (T)0 && s.c1 <= 1;
+        {
+            const int pk0 = __builtin_amdgcn_readfirstlane(pk);
+            int word;
+            if (__all(pk == pk0))
+                word = lean_word(mfx(pk0), mfx(pk0), mc1(pk0), mc1(pk0), 0);
+            else
+                word = lean_word(wave_min(s.fx), wave_max(s.fx), wave_min(s.c1), wave_max(s.c1), 0);
+            // this row's sources, or the previous row's window (far), rule the tile out
+            if (__any(!ok) || far) word |= kLeanStop;
+            if (lane64 == 0) (&s_wave[b].x)[wid] = word;
+        }
+        __syncthreads();
+        const int4 wv = s_wave[b];
+        if ((wv.x | wv.y | wv.z | wv.w) & kLeanStop) return kFlagFar | kFlagReach;  // the same in every thread
+        // the window: this wavefront's sources and its neighbours'
+        const int wm = wid == 0 ? wv.x : (wid == 1 ? wv.y : (wid == 2 ? wv.z : wv.w));
+        const int wl = wid == 0 ? wm : (wid == 1 ? wv.x : (wid == 2 ? wv.y : wv.z));
+        const int wr = wid == 3 ? wm : (wid == 0 ? wv.y : (wid == 1 ? wv.z : wv.w));
+        WaveInfo w;
+        w.fxmin = min(lean_fxmin(wm), min(lean_fxmin(wl), lean_fxmin(wr)));
+        w.fxmax = max(lean_fxmax(wm), max(lean_fxmax(wl), lean_fxmax(wr)));
+        w.c1min = min(lean_c1min(wm), min(lean_c1min(wl), lean_c1min(wr)));
+        w.c1max = max(lean_c1max(wm), max(lean_c1max(wl), lean_c1max(wr)));
+        const bool fits_x = w.fxmin - (w.c1max + 1) >= -kMH && w.fxmax + 1 + (w.c1max + 1) <= kMH;
+        const bool cmix = w.c1max == w.c1min + 1, xmix = w.fxmax == w.fxmin + 1;
+        const bool fastw = fits_x && (w.c1max == w.c1min || cmix) && (w.fxmax == w.fxmin || xmix) && !(cmix && xmix);
+        // FP32 storage: the row path (as the short pass takes them) for the
+        // windows that mix both, or span three values of floor(v_x): at rest,
+        // FP32 rounding leaves v_x a hair either side of 0.  In FP64 such
+        // windows are rare, and the row path's registers would cost the pass
+        // its occupancy: it gives those tiles up.
+        constexpr bool kRows = sizeof(T) == 4;
+        const bool rowsw = kRows && !fastw && fits_x && w.fxmax - w.fxmin <= 2;
+        if (!fastw && !rowsw) far = 1;  // given up at the next barrier
+        if constexpr (kRows) {
+            if (dest && rowsw)
+                gather_rows<T, L, 0, REST, SP, false, true>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, false, rq);
+        }
+        if (dest && fastw) {
+            const int fx0 = w.fxmax;
+            const int sel = (xmix ? 8 : 0) + (cmix ? 4 : 0) + w.c1min;
+            switch (sel) {
+                case 0: gather_fast<T, L, 0, 0, 2, 2, true, REST>(R, tid, fx0, f, rq); break;
+                case 1: gather_fast<T, L, 0, 1, 2, 2, true, REST>(R, tid, fx0, f, rq); break;
+                case 4: gather_fast<T, L, 0, 0, 3, 2, true, REST>(R, tid, fx0, f, rq); break;
+                case 8: gather_fast<T, L, 0, 0, 2, 3, true, REST>(R, tid, fx0, f, rq); break;
+                case 9: gather_fast<T, L, 0, 1, 2, 3, true, REST>(R, tid, fx0, f, rq); break;
+                default: break;  // not reached: c'_1 <= 1, and cmix excludes xmix
+            }
+        }
+        if (r >= 2 * L && dest) {
+            T* __restrict__ orow = Yn + (Y0 + r - 2 * L) * nx;  // wave-uniform
+            const T py = f.py0();
+            at_byte(orow, gxb) = (T)f.a[0][kR];
+            at_byte(orow + nn, gxb) = (T)f.a[0][kPx];
+            at_byte(orow + 2 * nn, gxb) = py;
+            at_byte(orow + 3 * nn, gxb) = (T)f.a[0][kE];
+            tot[0] += (double)f.a[0][kR];
+            tot[1] += (double)f.a[0][kPx];
+            tot[2] += (double)py;
+            tot[3] += (double)f.a[0][kE];
+            if constexpr (SP) {
+                at_byte(orow + 4 * nn, gxb) = (T)f.x[0];
+                tot[NF - 1] += (double)f.x[0];
+            }
+        }
+        f.shift();
+    }
+    // the last row's window decision has no later barrier to ride on
+    __shared__ double s_sum[kMNW][NF];
+    __shared__ int s_ir[kMNW][2];
+#pragma unroll
+    for (int c = 0; c < NF; ++c) tot[c] = wave_sum(tot[c]);
+    reach = wave_max(reach);
+    if (lane64 == 0) {
+#pragma unroll
+        for (int c = 0; c < NF; ++c) s_sum[wid][c] = tot[c];
+        s_ir[wid][0] = reach;
+        s_ir[wid][1] = far;
+    }
+    __syncthreads();
+    int stop = 0;
+#pragma unroll
+    for (int w = 0; w < kMNW; ++w) stop |= s_ir[w][1];
+    if (stop) return kFlagFar | kFlagReach;
+    if (tid == 0) {
+        int rr = 0;
+        for (int c = 0; c < NF; ++c) {
+            double t = s_sum[0][c];
+            for (int w = 1; w < kMNW; ++w) t += s_sum[w][c];
+            prow[c < 4 ? c : 6] = t;
+        }
+        for (int w = 0; w < kMNW; ++w) rr = max(rr, s_ir[w][0]);
+        prow[4] = (double)rr;
+        prow[5] = (double)(rr > kMH ? kErrReach : 0);
+    }
+    return 0;
+}
+
+// Wavefronts per SIMD the kernels are compiled for.  Short pass: FP64 keeps
+// its FIFO in registers at two; FP32 fits four with a few spilled registers.
+// Lean pass: four in FP64 (its 5-slot FIFO and one staged row per barrier
+// leave the registers and LDS for them), more in FP32.
 #ifndef LB_MARCH_WPE
 #define LB_MARCH_WPE 2
 #endif
 #ifndef LB_MARCH_WPE_F32
-#define LB_MARCH_WPE_F32 4
+#define LB_MARCH_WPE_F32 3
 #endif
-// L = kLSmall: the short-FIFO pass; a tile whose sources reach beyond its FIFO
-// is flagged.  L = kLFull: computes the flagged tiles (bit-identically: the
-// summation order does not depend on L) and keeps the flag of each that still
-// needs the full FIFO; the next step's short pass leaves such tiles to the
-// full pass instead of computing them twice (flows change little per step).
-// Persistent blocks claim the tiles (tiles_x column strips x row chunks of sy
-// rows, row chunk major) from the control block's counter of the pass.
+#ifndef LB_LEAN_WPE
+#define LB_LEAN_WPE 4
+#endif
+#ifndef LB_LEAN_WPE_F32
+#define LB_LEAN_WPE_F32 4
+#endif
+
+// Counters of StepCtl::next / PoolView::next: tile claims of each pass, and
+// the tiles the lean and short passes left to the next pass (reset by the
+// step's reduction kernel).
+enum { kNextShort = 0, kNextFull = 1, kNextShortFlagged = 2, kNextLean = 3, kNextLeanFlagged = 4 };
+
+// The lean pass (first of a step): persistent blocks claim the tiles (tiles_x
+// column strips x row chunks of sy rows, row chunk major).  A tile it
+// completes gets flags[t] = 0 (no bit of the short or full pass); one it
+// gives up gets kFlagFar | kFlagReach in flags_lean[t], and flags[t] is left
+// for the short pass (a kFlagKeep bit there from the previous step's full
+// pass still counts).
+template <typename T, bool WALLS, bool REST, bool SP>
+__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? LB_LEAN_WPE_F32 : LB_LEAN_WPE)))
+march2d_lean_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k, StepCtl* __restrict__ ctl,
+                    double* __restrict__ partials, int* __restrict__ flags, int* __restrict__ flags_lean,
+                    long long step, int sy, int tiles_x, int ntiles)
+{
+    __shared__ int s_t;
+    if (ctl->err_step < step) return;
+    for (;;) {
+        const int t = claim_tile(&ctl->next[kNextLean], &s_t);
+        if (t >= ntiles) break;
+        const int64_t tx = t % tiles_x, ty = t / tiles_x;
+        const int bits = march_tile_lean<T, WALLS, REST, SP>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
+                                                             partials + (int64_t)t * kPartialStride);
+        if (threadIdx.x == 0) {
+            flags_lean[t] = bits;
+            if (bits) atomicAdd(&ctl->next[kNextLeanFlagged], 1);
+            else flags[t] = 0;
+        }
+    }
+}
+
+// L = kLSmall: the short-FIFO pass over the tiles the lean pass gave up and
+// their row-chunk neighbours (needs_pass on the lean pass's flags); it flags
+// those it cannot complete itself.  L = kLFull: computes the tiles the short
+// pass flagged and their neighbours (bit-identically: the summation order
+// does not depend on L) and keeps the flag of each that still needs the full
+// FIFO; the next step's short pass leaves such tiles to the full pass instead
+// of computing them twice (flows change little per step).  Each returns at
+// once when the previous pass flagged nothing.
 template <typename T, int L, bool WALLS, bool REST, bool SP>
 __global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
 march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
                StepCtl* __restrict__ ctl, double* __restrict__ partials, int* __restrict__ flags,
-               long long step, int sy, int tiles_x, int ntiles)
+               const int* __restrict__ flags_lean, long long step, int sy, int tiles_x, int ntiles)
 {
     __shared__ int s_t;
     if (ctl->err_step < step) return;
-    if (L == kLFull && ctl->next[2] == 0) return;  // the short pass flagged no tile
-    // some tile kept its flag in the previous step's full pass (else every
-    // flag is clear and the short pass need not read them)
+    if (ctl->next[L < kLFull ? kNextLeanFlagged : kNextShortFlagged] == 0) return;  // nothing left to it
+    // some tile kept its flag in the previous step's full pass (else no flag
+    // holds kFlagKeep and the short pass need not look)
     const bool kept = L < kLFull && ctl->keep[1] != 0;
     for (;;) {
-        const int t = claim_tile(&ctl->next[L < kLFull ? 0 : 1], &s_t);
+        const int t = claim_tile(&ctl->next[L < kLFull ? kNextShort : kNextFull], &s_t);
         if (t >= ntiles) break;
         const int64_t tx = t % tiles_x, ty = t / tiles_x;
+        const int64_t Y0 = ty * sy, ylast = min(Y0 + sy, g.ny);
         if (L < kLFull) {
+            if (!needs_pass<kLLean>(flags_lean, 0, tiles_x, tx, Y0, ylast, sy, g.ny, g.bc_y)) continue;
             if (kept && (flags[t] & kFlagKeep)) {  // needed the full pass last step: left to it
                 if (threadIdx.x == 0) {
                     flags[t] = kFlagFar | kFlagReach | kFlagKeep;
-                    atomicAdd(&ctl->next[2], 1);
+                    atomicAdd(&ctl->next[kNextShortFlagged], 1);
                 }
                 continue;
             }
-        } else if (!needs_full(flags, 0, tiles_x, tx, ty * sy, min((ty + 1) * sy, g.ny), sy, g.ny, g.bc_y)) {
+        } else if (!needs_pass<kLSmall>(flags, 0, tiles_x, tx, Y0, ylast, sy, g.ny, g.bc_y)) {
             continue;
         }
-        const int bits = march_tile<T, L, WALLS, REST, SP>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
+        const int bits = march_tile<T, L, WALLS, REST, SP>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), Y0, sy,
                                                        partials + (int64_t)t * kPartialStride);
         if (threadIdx.x == 0) {
             const int far = bits & kFlagFar;
             if (L < kLFull) {
                 flags[t] = bits;
-                if (far) atomicAdd(&ctl->next[2], 1);
+                if (far) atomicAdd(&ctl->next[kNextShortFlagged], 1);
             } else {
                 // keep the short pass's bits, which other blocks of this pass read
                 flags[t] = (flags[t] & (kFlagFar | kFlagReach)) | (far ? kFlagKeep : 0);
@@ -921,38 +1234,64 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
     }
 }
 
-// Pool form: persistent blocks claim tiles of the tile table (see
-// pool1d_kernel).  The short-FIFO pass flags the tiles it could not complete;
-// the full-FIFO pass computes only those, and keeps the flags of the tiles
-// that still need it (as in march2d_kernel).
+// Pool form of the three passes: persistent blocks claim tiles of the tile
+// table (see pool1d_kernel); a slot's tiles are its row chunks, then column
+// strips, from its t0, which is how needs_pass finds a tile's neighbours.
+template <typename T, bool WALLS, bool REST, bool SP>
+__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? LB_LEAN_WPE_F32 : LB_LEAN_WPE)))
+pool2d_lean_kernel(PoolView v, Consts k)
+{
+    __shared__ int s_t;
+    const int nt = *v.ntiles;
+    T* arena = (T*)v.arena;
+    for (;;) {
+        const int t = claim_tile(&v.next[kNextLean], &s_t);
+        if (t >= nt) break;
+        const int ts = v.tstate[t];
+        if (!(ts & kTileLive)) continue;  // the same for the whole block
+        const PoolTile& tl = v.tiles[t];
+        const int64_t o0 = tl.off[0], o1 = tl.off[1];
+        const int64_t from = (ts & kTileSet) ? o1 : o0, to = (ts & kTileSet) ? o0 : o1;
+        const Grid g{tl.nx, tl.ny, tl.bc_x, tl.bc_y};
+        const int bits = march_tile_lean<T, WALLS, REST, SP>(arena + from, arena + to, g, k, tl.x0, tl.y0,
+                                                             tl.rows, v.partials + (int64_t)t * kPartialStride);
+        if (threadIdx.x == 0) {
+            v.flags_lean[t] = bits;
+            if (bits) atomicAdd(&v.next[kNextLeanFlagged], 1);
+            else v.flags[t] = 0;
+        }
+    }
+}
+
 template <typename T, int L, bool WALLS, bool REST, bool SP>
 __global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
 pool2d_kernel(PoolView v, Consts k)
 {
     __shared__ int s_t;
-    if (L == kLFull && v.next[2] == 0) return;  // the short pass flagged no tile
+    if (v.next[L < kLFull ? kNextLeanFlagged : kNextShortFlagged] == 0) return;  // nothing left to it
     const int nt = *v.ntiles;
     T* arena = (T*)v.arena;
     for (;;) {
-        const int t = claim_tile(&v.next[L < kLFull ? 0 : 1], &s_t);
+        const int t = claim_tile(&v.next[L < kLFull ? kNextShort : kNextFull], &s_t);
         if (t >= nt) break;
         const int ts = v.tstate[t];
         if (!(ts & kTileLive)) continue;  // the same for the whole block
         const PoolTile& tl = v.tiles[t];
+        const int64_t tiles_x = (tl.nx + kPool2Cols - 1) / kPool2Cols;
+        const int64_t tbase = v.probs[tl.prob].t0, tx = tl.x0 / kPool2Cols;
+        const int64_t ylast = min(tl.y0 + (int64_t)tl.rows, tl.ny);
         if (L < kLFull) {
+            if (!needs_pass<kLLean>(v.flags_lean, tbase, tiles_x, tx, tl.y0, ylast, tl.rows, tl.ny, tl.bc_y))
+                continue;
             if (v.flags[t] & kFlagKeep) {  // needed the full FIFO last step: left to the full pass
                 if (threadIdx.x == 0) {
                     v.flags[t] = kFlagFar | kFlagReach | kFlagKeep;
-                    atomicAdd(&v.next[2], 1);
+                    atomicAdd(&v.next[kNextShortFlagged], 1);
                 }
                 continue;
             }
-        } else {
-            // a slot's tiles are its row chunks, then column strips, from t0
-            const int64_t tiles_x = (tl.nx + kPool2Cols - 1) / kPool2Cols;
-            if (!needs_full(v.flags, v.probs[tl.prob].t0, tiles_x, tl.x0 / kPool2Cols, tl.y0,
-                            min(tl.y0 + (int64_t)tl.rows, tl.ny), tl.rows, tl.ny, tl.bc_y))
-                continue;
+        } else if (!needs_pass<kLSmall>(v.flags, tbase, tiles_x, tx, tl.y0, ylast, tl.rows, tl.ny, tl.bc_y)) {
+            continue;
         }
         const int64_t o0 = tl.off[0], o1 = tl.off[1];  // selected below, not indexed (keeps them in registers)
         const int64_t from = (ts & kTileSet) ? o1 : o0, to = (ts & kTileSet) ? o0 : o1;
@@ -963,7 +1302,7 @@ pool2d_kernel(PoolView v, Consts k)
             const int far = bits & kFlagFar;
             if (L < kLFull) {
                 v.flags[t] = bits;
-                if (far) atomicAdd(&v.next[2], 1);
+                if (far) atomicAdd(&v.next[kNextShortFlagged], 1);
             } else {
                 // keep the short pass's bits, which other blocks of this pass read
                 v.flags[t] = (v.flags[t] & (kFlagFar | kFlagReach)) | (far ? kFlagKeep : 0);
@@ -972,31 +1311,38 @@ pool2d_kernel(PoolView v, Consts k)
     }
 }
 
-// Both passes of one step: the short-FIFO pass over every tile, then the
-// full-FIFO pass over the tiles it flagged.
+// The three passes of one step: lean over every tile, short over what the
+// lean pass gave up (and its neighbours), full over what the short pass
+// flagged (and its neighbours).  nblocks_lean persistent blocks for the lean
+// pass, m.nblocks for the others.  flags holds 2 ntiles ints: the short and
+// full passes' flags, then the lean pass's.
 template <typename T, bool WALLS, bool REST, bool SP>
 hipError_t launch_march2d_w(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
                             StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream)
 {
     const int nt = (int)m.blocks();
-    march2d_kernel<T, kLSmall, WALLS, REST, SP><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials,
-                                                                                 flags, step, m.sy,
-                                                                                 (int)m.grid_x, nt);
+    int* flags_lean = flags + nt;
+    march2d_lean_kernel<T, WALLS, REST, SP><<<m.nblocks_lean, kMTPB, 0, stream>>>(
+        Y, Yn, g, k, ctl, partials, flags, flags_lean, step, m.sy, (int)m.grid_x, nt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    march2d_kernel<T, kLFull, WALLS, REST, SP><<<m.nblocks, kMTPB, 0, stream>>>(Y, Yn, g, k, ctl, partials,
-                                                                                flags, step, m.sy,
-                                                                                (int)m.grid_x, nt);
+    march2d_kernel<T, kLSmall, WALLS, REST, SP><<<m.nblocks, kMTPB, 0, stream>>>(
+        Y, Yn, g, k, ctl, partials, flags, flags_lean, step, m.sy, (int)m.grid_x, nt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    march2d_kernel<T, kLFull, WALLS, REST, SP><<<m.nblocks, kMTPB, 0, stream>>>(
+        Y, Yn, g, k, ctl, partials, flags, flags_lean, step, m.sy, (int)m.grid_x, nt);
     return hipGetLastError();
 }
 
-// Both passes of one pool step.
+// The three passes of one pool step.
 template <typename T, bool WALLS, bool REST, bool SP>
-hipError_t launch_pool2d_w(const PoolView& v, const Consts& k, int nblocks, hipStream_t stream)
+hipError_t launch_pool2d_w(const PoolView& v, const Consts& k, int nblocks_lean, int nblocks, hipStream_t stream)
 {
-    pool2d_kernel<T, kLSmall, WALLS, REST, SP><<<nblocks, kMTPB, 0, stream>>>(v, k);
+    pool2d_lean_kernel<T, WALLS, REST, SP><<<nblocks_lean, kMTPB, 0, stream>>>(v, k);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    pool2d_kernel<T, kLSmall, WALLS, REST, SP><<<nblocks, kMTPB, 0, stream>>>(v, k);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     pool2d_kernel<T, kLFull, WALLS, REST, SP><<<nblocks, kMTPB, 0, stream>>>(v, k);
     return hipGetLastError();
 }
@@ -1010,6 +1356,7 @@ hipError_t launch_march2d_species(const T* Y, T* Yn, const Grid& g, const MarchG
                                   StepCtl* ctl, double* partials, int* flags, long long step,
                                   hipStream_t stream);
 template <typename T>
-hipError_t launch_pool2d_species(const PoolView& v, const Consts& k, int nblocks, bool walls, hipStream_t stream);
+hipError_t launch_pool2d_species(const PoolView& v, const Consts& k, int nblocks_lean, int nblocks, bool walls,
+                                 hipStream_t stream);
 
 }  // namespace lbsd

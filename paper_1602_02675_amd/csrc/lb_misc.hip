@@ -64,9 +64,7 @@ __global__ void lanes_kernel(const T* __restrict__ Y, int64_t nn, int dim, Const
 __global__ void reset_ctl_kernel(StepCtl* ctl)
 {
     if (threadIdx.x == 0) {
-        ctl->next[0] = 0;
-        ctl->next[1] = 0;
-        ctl->next[2] = 0;
+        for (int i = 0; i < 5; ++i) ctl->next[i] = 0;
         ctl->err_code = 0;
         ctl->err_step = LLONG_MAX;
         ctl->totals_step = -1;

@@ -54,7 +54,8 @@ struct lb_pool {
     std::map<size_t, size_t> free_list;  // arena byte offset -> size
     std::vector<PoolTile> tiles;
     int shape = 0;    // 1-D: kernel tile shape; 2-D: strip height index
-    int nblocks = 0;  // persistent blocks of the current shape
+    int nblocks = 0;  // persistent blocks of the current shape (square lattice: short and full passes)
+    int nblocks_lean = 0;  // square lattice: persistent blocks of the lean pass
     bool walls = false;  // a live slot has reflecting walls: run the kernels that handle them
     // graph of `graph_steps` steps (0: plain launches)
     int graph_steps = 0;
@@ -75,6 +76,7 @@ PoolView view_of(const lb_pool* p)
     v.ntiles = (const int32_t*)(p->base + p->off_ntiles);
     v.partials = (double*)(p->base + p->off_partials);
     v.flags = (int32_t*)(p->base + p->off_flags);
+    v.flags_lean = v.flags + p->max_tiles;
     v.next = (int32_t*)(p->base + p->off_ntiles + 64);
     v.arena = p->base + p->off_arena;
     return v;
@@ -92,7 +94,7 @@ int64_t tiles_of(const lb_pool* p, int64_t nx, int64_t ny, int shape)
     return ((nx + kPool2Cols - 1) / kPool2Cols) * ((ny + kPool2MinRows - 1) / kPool2MinRows);  // at most
 }
 
-int launch_blocks(const lb_pool* p, int64_t ntiles);
+int launch_blocks(const lb_pool* p, int64_t ntiles, bool lean = false);
 
 // Rows per tile: 1 in 1-D; on the square lattice about
 // kPool2TilesPerBlock[shape] tiles per resident block over the live problems.
@@ -104,7 +106,7 @@ int64_t tile_rows(const lb_pool* p)
         const PoolProb& q = p->probs[(size_t)i];
         if (q.active) strip_rows += ((q.nx + kPool2Cols - 1) / kPool2Cols) * q.ny;
     }
-    const int64_t want = (int64_t)kPool2TilesPerBlock[p->shape] * launch_blocks(p, 0);
+    const int64_t want = (int64_t)kPool2TilesPerBlock[p->shape] * launch_blocks(p, 0, true);
     const int64_t rows = (strip_rows + want - 1) / std::max<int64_t>(want, 1);
     return std::max<int64_t>(rows, kPool2MinRows);
 }
@@ -130,10 +132,10 @@ int64_t live_max_tiles(const lb_pool* p)
 // are resident at once) that claim tiles, so that slow tiles spread out.  1-D:
 // one block per tile (tiles cost about the same, and the hardware then
 // overlaps one tile's loads with other tiles' work).
-int launch_blocks(const lb_pool* p, int64_t ntiles)
+int launch_blocks(const lb_pool* p, int64_t ntiles, bool lean)
 {
     if (p->dim == 1) return (int)std::max<int64_t>(1, ntiles);
-    const int per_cu = p->precision == LB_FP64 ? pool2d_blocks_per_cu<double>() : pool2d_blocks_per_cu<float>();
+    const int per_cu = p->precision == LB_FP64 ? pool2d_blocks_per_cu<double>(lean) : pool2d_blocks_per_cu<float>(lean);
     return std::max(1, p->cus * per_cu);
 }
 
@@ -174,16 +176,17 @@ int upload_tables(lb_pool* p)
     }
     if ((int64_t)p->tiles.size() > p->max_tiles) return fail(LB_ENOMEM, "tile table full");
     const int32_t nt = (int32_t)p->tiles.size();
-    const int nb = launch_blocks(p, nt);
+    const int nb = launch_blocks(p, nt), nb_lean = launch_blocks(p, nt, true);
     bool walls = false;
     for (const PoolProb& q : p->probs)
         walls |= q.active && (q.bc_x == kBcReflecting || (p->dim == 2 && q.bc_y == kBcReflecting));
-    if (nb != p->nblocks || walls != p->walls) {  // other kernels or launch shape: a captured graph is stale
+    if (nb != p->nblocks || nb_lean != p->nblocks_lean || walls != p->walls) {  // a captured graph is stale
         drop_graph(p);
         p->nblocks = nb;
+        p->nblocks_lean = nb_lean;
         p->walls = walls;
     }
-    std::vector<int32_t> zeros((size_t)std::max<int32_t>(nt, 3), 0);
+    std::vector<int32_t> zeros((size_t)std::max<int32_t>(nt, 5), 0);
     // tile words from the slots' device states
     std::vector<PoolState> st((size_t)p->max_slots);
     hipError_t e = hipStreamSynchronize(p->stream);
@@ -207,7 +210,7 @@ int upload_tables(lb_pool* p)
     if ((e = hipMemcpyAsync(p->base + p->off_ntiles, &nt, sizeof nt, hipMemcpyHostToDevice, p->stream)) !=
         hipSuccess)
         return hip_fail(e, "upload tile count");
-    if ((e = hipMemcpyAsync(p->base + p->off_ntiles + 64, zeros.data(), 3 * sizeof(int32_t),
+    if ((e = hipMemcpyAsync(p->base + p->off_ntiles + 64, zeros.data(), 5 * sizeof(int32_t),
                             hipMemcpyHostToDevice, p->stream)) != hipSuccess)
         return hip_fail(e, "clear claim counters");
     if (nt > 0 && (e = hipMemcpyAsync(p->base + p->off_flags, zeros.data(), (size_t)nt * 4,
@@ -238,8 +241,9 @@ int queue_step(lb_pool* p, int commit)
         e = p->precision == LB_FP64 ? launch_pool1d<double>(v, p->k, p->shape, p->nblocks, p->walls, p->stream)
                                     : launch_pool1d<float>(v, p->k, p->shape, p->nblocks, p->walls, p->stream);
     else
-        e = p->precision == LB_FP64 ? launch_pool2d<double>(v, p->k, p->nblocks, p->walls, p->stream)
-                                    : launch_pool2d<float>(v, p->k, p->nblocks, p->walls, p->stream);
+        e = p->precision == LB_FP64
+            ? launch_pool2d<double>(v, p->k, p->nblocks_lean, p->nblocks, p->walls, p->stream)
+            : launch_pool2d<float>(v, p->k, p->nblocks_lean, p->nblocks, p->walls, p->stream);
     if (e != hipSuccess) return hip_fail(e, "pool step launch");
     if ((e = launch_pool_finalize(v, p->max_slots, commit, p->stream)) != hipSuccess)
         return hip_fail(e, "pool finalize launch");
@@ -449,7 +453,7 @@ static int create_pool(int32_t dim, double gamma, double gamma2, bool species, c
     p->off_ntiles = p->off_tstate + align256((size_t)p->max_tiles * 4);
     p->off_partials = p->off_ntiles + 256;  // tile count at +0, claim counters at +64
     p->off_flags = p->off_partials + align256((size_t)p->max_tiles * kPartialStride * 8);
-    p->off_arena = p->off_flags + align256((size_t)p->max_tiles * 4);
+    p->off_arena = p->off_flags + align256((size_t)p->max_tiles * 2 * 4);  // two flag words per tile
     p->total = p->off_arena + p->arena_bytes;
     p->free_list[0] = p->arena_bytes;
     *out = p;

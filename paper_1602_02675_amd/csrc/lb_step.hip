@@ -165,9 +165,7 @@ finalize_kernel(const double* __restrict__ partials, int64_t nb, int64_t stride,
     __shared__ double s_sum[kFinTPB / 64][5];
     __shared__ int s_ir[kFinTPB / 64][2];
     if (threadIdx.x == 0) {  // the step kernels of this step are done with their counters
-        ctl->next[0] = 0;
-        ctl->next[1] = 0;
-        ctl->next[2] = 0;
+        for (int i = 0; i < 5; ++i) ctl->next[i] = 0;
         ctl->keep[1] = ctl->keep[0];
         ctl->keep[0] = 0;
     }
@@ -479,9 +477,7 @@ __global__ void __launch_bounds__(kFinTPB) pool_finalize_kernel(PoolView v, int 
     __shared__ int s_ir[kFinTPB / 64][2];
     const int p = blockIdx.x;
     if (p == 0 && threadIdx.x == 0) {  // the step kernels of this step are done with their counters
-        v.next[0] = 0;
-        v.next[1] = 0;
-        v.next[2] = 0;
+        for (int i = 0; i < 5; ++i) v.next[i] = 0;
     }
     const PoolProb& P = v.probs[p];
     PoolState& S = v.state[p];

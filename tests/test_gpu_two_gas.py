@@ -47,6 +47,25 @@ def _sensitivity(P, Yl, n, seed=0):
     return normwise_err(b, a, 1)
 
 
+def _fp32_movement(P, Yl, n, seeds=8):
+    """How far the oracle itself moves after n steps when every field is
+    perturbed by a relative +-2^-24 (the FP32 unit roundoff, uniform) after
+    each step: the largest relative L1 change of rho and of rho chi over
+    `seeds` seeded runs.  Storing the state in FP32 alone perturbs it this
+    much per step."""
+    ref, _, _ = oracle.run(P, Yl, n)
+    worst = [0.0, 0.0]
+    for seed in range(seeds):
+        rng = np.random.default_rng(seed)
+        b = Yl.copy()
+        for _ in range(n):
+            b, _, _ = oracle.step(P, b)
+            b = b * (1.0 + 2.0 ** -24 * rng.uniform(-1.0, 1.0, size=b.shape))
+        for i, f in enumerate((0, 3)):
+            worst[i] = max(worst[i], np.sum(np.abs(b[f] - ref[f])) / np.sum(np.abs(ref[f])))
+    return worst
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("bc", [0, W])
 def test_two_gas_sod(lbsd, prec, bc):
@@ -54,15 +73,17 @@ def test_two_gas_sod(lbsd, prec, bc):
     t = 0.2; with walls also 400 and 600 steps (the shock reflects and crosses
     the contact).  Where the reflected shock meets the contact the oracle
     itself moves by ~1e-12 after 600 steps under a 1e-16 change of its input
-    (2e-14 with one gas): that FP64 run is held to 4x this movement."""
+    (2e-14 with one gas): that FP64 run is held to 4x this movement.  The same
+    amplification makes the FP32 bar of 1e-5 ill-conditioned there: under
+    FP32-sized perturbations after each step the oracle's density moves by
+    0.7 .. 3.6e-5 at 600 steps (8 seeds), so that FP32 run is held to twice
+    the largest of these movements."""
     nx = 1000
     n, lam = _lam(nx)
     P = oracle.Problem(1, nx, gamma=G1, gamma2=G2, bc_x=bc)
     Y0 = oracle.riemann_moments(P, inputs.node_x(nx), inputs.SOD_LEFT, inputs.SOD_RIGHT, 0.5)
     Yl = oracle.to_lattice(P, Y0, lam)
-    # FP32 stops at 400 steps: the ~1e4 amplification at 600 steps takes FP32
-    # rounding past the 1e-5 density bar (as it would take any FP32 run)
-    for steps in ((n,) if bc != W else ((n, 400, 600) if prec == "fp64" else (n, 400))):
+    for steps in ((n,) if bc != W else (n, 400, 600)):
         ref, st, _ = oracle.run(P, Yl, steps)
         assert st == 0
         ref = oracle.from_lattice(P, ref, lam)
@@ -78,8 +99,9 @@ def test_two_gas_sod(lbsd, prec, bc):
             assert normwise_err(got, ref, 1) <= bar, steps
             assert s.species_total() == pytest.approx(oracle.totals(P, ref)[3], rel=1e-13)
         else:
-            assert np.sum(np.abs(got[0] - ref[0])) / np.sum(np.abs(ref[0])) <= 1e-5
-            assert np.sum(np.abs(got[3] - ref[3])) / np.sum(np.abs(ref[3])) <= 1e-5
+            bars = [1e-5, 1e-5] if steps < 600 else [max(1e-5, 2.0 * m) for m in _fp32_movement(P, Yl, steps)]
+            assert np.sum(np.abs(got[0] - ref[0])) / np.sum(np.abs(ref[0])) <= bars[0], (steps, bars)
+            assert np.sum(np.abs(got[3] - ref[3])) / np.sum(np.abs(ref[3])) <= bars[1], (steps, bars)
         # chi = (rho chi) / rho stays in [0, 1] up to the storage's rounding
         chi, eps = got[3] / got[0], (1e-12 if prec == "fp64" else 1e-6)
         assert np.all(chi >= -eps) and np.all(chi <= 1 + eps)
