@@ -33,7 +33,14 @@ gather kernel plus its totals reduction.  Alongside, in the same JSON line:
   measured capacity, continuously batched on an FP32 pool: p50 / p99
   latency and aggregate node-updates/s; and the same requests all queued at
   once (the served throughput at saturation);
-* cpu_baseline: the FP64 oracle on a bounded sample, one host thread.
+* cpu_baseline: the FP64 oracle on a bounded sample, one host thread (host
+  CPU model and usable cores stated); cpu_baseline_batch: the oracle over the
+  512 independent tubes of the batch workload on all usable cores (at most
+  16), one process per core.
+* fp32.rel_l1_density_vs_fp64_2000_steps: the FP32 form's density error
+  against FP64 after the 2000 steps the FP32-versus-FP64 comparison is
+  stated at (a 4096 x 16 strip of the headline tube: planar rows evolve
+  bit-identically), whatever --steps is.
 
 `--profile` runs a short headline plus a plain device copy of known size,
 for rocprofv3 counter runs.
@@ -141,6 +148,105 @@ def run_tube1d(gamma2=None, n: int = 1 << 24, steps: int = 200, precision: str =
                 gammas=[1.4] if gamma2 is None else [1.4, gamma2])
 
 
+def host_info():
+    """CPU model and the cores this process may use (the GPU machine grants a
+    share of its host, whatever os.cpu_count() reports)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, usable
+
+
+def _oracle_tubes(job):
+    """Worker of cpu_baseline_batch (a spawned process): the 1-D oracle on
+    the given seeded tubes for `steps` steps; returns (node-updates, seconds)."""
+    import oracle
+    from paper_1602_02675_amd import inputs
+
+    tubes, steps = job
+    work, busy = 0, 0.0
+    for L, i, seed in tubes:
+        left, right, xd = inputs.riemann_instance(seed * 100000 + i)
+        P = oracle.Problem(1, L)
+        Y = oracle.to_lattice(P, oracle.riemann_moments(P, inputs.node_x(L), left, right, xd),
+                              inputs.cfl_lambda([left, right]))
+        t0 = time.perf_counter()
+        oracle.run(P, Y, steps)
+        busy += time.perf_counter() - t0
+        work += L * steps
+    return work, busy
+
+
+def cpu_baseline_batch(seconds_target: float = 15.0, n_tubes: int = 512, seed: int = 0):
+    """The oracle over the independent tubes of the batch workload (512 seeded
+    1-D tubes, lengths log-uniform in [256, 65536]) on all usable host cores,
+    one process per core, each taking whole tubes (balanced by length)."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+
+    from paper_1602_02675_amd import inputs
+
+    model, usable = host_info()
+    cores = max(1, min(16, usable))
+    lens = [int(L) for L in inputs.tube_lengths(seed, n_tubes)]
+    order = sorted(range(n_tubes), key=lambda i: -lens[i])
+    shares = [[] for _ in range(cores)]
+    load = [0] * cores
+    for i in order:  # longest first onto the least loaded core
+        c = load.index(min(load))
+        shares[c].append((lens[i], i, seed))
+        load[c] += lens[i]
+    ctx = multiprocessing.get_context("spawn")
+    with ProcessPoolExecutor(max_workers=cores, mp_context=ctx) as ex:
+        # calibration: the workers start (and load the oracle) on a first
+        # step of everything, a timed second pass of 2 steps sets the step
+        # count for the target
+        list(ex.map(_oracle_tubes, [(sh, 1) for sh in shares]))
+        t0 = time.perf_counter()
+        list(ex.map(_oracle_tubes, [(sh, 2) for sh in shares]))
+        per_step = (time.perf_counter() - t0) / 2
+        steps = int(min(1000, max(5, seconds_target / max(per_step, 1e-6))))
+        t0 = time.perf_counter()
+        res = list(ex.map(_oracle_tubes, [(sh, steps) for sh in shares]))
+        wall = time.perf_counter() - t0
+    work = sum(r[0] for r in res)
+    return dict(value=work / wall / 1e6, unit="MLUPS", cores=cores, kind="oracle", host_cpu=model, nproc=usable,
+                sample=f"all {n_tubes} tubes of the batch workload ({sum(lens)} nodes), {steps} steps, FP64, "
+                       f"{cores} processes (whole tubes each, balanced by length)")
+
+
+def fp32_accuracy(steps: int = 2000, ny: int = 16):
+    """Relative L1 density error of the FP32 form against FP64 on the headline
+    tube after `steps` steps, on a 4096 x ny periodic strip: a planar flow's
+    rows evolve bit-identically, so every row of the 4096 x 4096 run is one of
+    these rows."""
+    import torch
+    from paper_1602_02675_amd.lbsd import Solver
+
+    left, right, x_d, lam = workload()
+    rho = {}
+    for prec in ("fp64", "fp32"):
+        s = Solver(2, NX, ny, precision=prec, bc_x="transmissive", bc_y="periodic")
+        s.init_riemann(x_d, left, right, lam=lam)
+        s.step(steps)
+        y = s.moments()
+        assert np.all(y == y[:, :1, :]), "planar rows differ"
+        rho[prec] = y[0, 0]
+        s.close()
+    torch.cuda.synchronize()
+    return float(np.sum(np.abs(rho["fp32"] - rho["fp64"])) / np.sum(np.abs(rho["fp64"])))
+
+
 def cpu_baseline(seconds_target: float = 15.0):
     """The oracle, single-threaded, on a bounded sample of the same workload."""
     import oracle
@@ -159,8 +265,9 @@ def cpu_baseline(seconds_target: float = 15.0):
     t0 = time.perf_counter()
     Y, st, _ = oracle.run(P, Y, more)
     dt = time.perf_counter() - t0
-    return dict(value=n * n * more / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
-                sample=f"{n}x{n} nodes of the same seeded planar tube, {more} steps, FP64, 1 thread")
+    model, usable = host_info()
+    return dict(value=n * n * more / dt / 1e6, unit="MLUPS", cores=1, kind="oracle", host_cpu=model,
+                nproc=usable, sample=f"{n}x{n} nodes of the same seeded planar tube, {more} steps, FP64, 1 thread")
 
 
 def run_batch(precision: str, steps: int = 1000, n_tubes: int = 512, seed: int = 0, shape=None,
@@ -335,7 +442,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "march2d_kernel<double>",
+                     "kernel": "march2d step: lean, short and full passes (march2d_lean_kernel<double>, "
+                               "march2d_kernel<double, 3>, march2d_kernel<double, 5>)",
                      "kernel_us_per_launch": round(kernel_s_per_launch * 1e6, 2),
                      "algorithmic_bytes_per_launch": BYTES_PER_NODE["fp64"] * nodes},
     }
@@ -346,6 +454,8 @@ def main():
         out["fp32"] = {"value": round(nodes * args.steps / (r32["total_ms"] / 1e3) / 1e6, 1), "unit": "MLUPS",
                        "ms_per_step": round(r32["total_ms"] / args.steps, 5),
                        "rel_l1_density_vs_fp64": rel_l1,
+                       "rel_l1_density_vs_fp64_steps": args.warmup + args.steps,
+                       "rel_l1_density_vs_fp64_2000_steps": fp32_accuracy(2000),
                        "achieved_GBs": round(BYTES_PER_NODE["fp32"] * nodes /
                                              (r32["kernel_ms"] / 1e3 / args.steps) / 1e9, 1)}
     if not args.no_extra:
@@ -382,6 +492,7 @@ def main():
         out["serve"] = run_serve()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline_batch"] = cpu_baseline_batch()
     print(json.dumps(out), flush=True)
 
 

@@ -348,6 +348,8 @@ static int start_state(lb_solver* s)
     s->pending_err = 0;
     s->initialized = true;
     hipError_t e = launch_reset_ctl(ctl_ptr(s), s->stream);
+    // square lattice: the passes' per-tile flag words start clear
+    if (e == hipSuccess && s->dim == 2) e = launch_fill_i32(flags_ptr(s), 2 * s->nblocks, 0, s->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "reset");
 }
 
@@ -750,6 +752,7 @@ int lb_step_static(lb_solver* s, const void* Y_in, void* Y_out, void* hip_stream
     // the last call's control block is stale: a fill kernel resets it (no
     // memset, so the call can be captured into a graph)
     hipError_t e = launch_reset_ctl(ctl, st);
+    if (e == hipSuccess && s->dim == 2) e = launch_fill_i32(flags, 2 * rows, 0, st);  // the last call's flags
     if (e != hipSuccess) return hip_fail(e, "reset");
     if (s->dim == 1) {
         e = s->precision == LB_FP64

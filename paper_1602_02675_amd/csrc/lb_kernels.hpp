@@ -95,6 +95,9 @@ hipError_t launch_lanes(const T* Y, const Grid& g, int dim, const Consts& k, int
 
 hipError_t launch_reset_ctl(StepCtl* ctl, hipStream_t stream);
 
+// p[0 .. n) := v (a kernel, not a memset: it may be captured into a graph).
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t stream);
+
 // *out := the outcome of the step(s) recorded in ctl: kStatusOk, or the
 // status code of the first failure (the values of LB_OK, LB_ESTATE, LB_EREACH).
 constexpr int kStatusOk = 0, kStatusState = -4, kStatusReach = -5;

@@ -24,13 +24,24 @@ MarchGeom march2d_geometry(const Grid& g, int cus, int per_cu, int per_cu_lean)
     const int64_t xs = x_strips(g);
     const int64_t resident = (int64_t)(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
     const int64_t resident_lean = (int64_t)(cus > 0 ? cus : 1) * (per_cu_lean > 0 ? per_cu_lean : 1);
-    // about LB_MARCH_TILES_X10 / 10 tiles per resident block of the lean
-    // pass, which does the bulk of a planar step (its tiles cost about the
-    // same; taller tiles march fewer halo rows again), but strips no shorter
-    // than kMinRows
-    // (rounded down: one tile more than the resident blocks would cost the
-    // step a second round for that tile)
-    const int64_t want = (int64_t)LB_MARCH_TILES_X10 * resident_lean / 10;
+    // a whole number of tiles per resident block of both the lean pass, which
+    // does the bulk of a planar step, and the short pass, which does it where
+    // the flow is not planar: the least common multiple of the two block
+    // counts when that is at most twice the larger, else about
+    // LB_MARCH_TILES_X10 / 10 tiles per lean block (its tiles cost about the
+    // same; taller tiles march fewer halo rows again); strips no shorter than
+    // kMinRows.  Rounded down: one tile more than a multiple of the resident
+    // blocks would cost a pass a second round for that tile.
+    int64_t a = resident_lean, b = resident;
+    while (b != 0) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    const int64_t lcm = resident_lean / a * resident;
+    const int64_t want = lcm <= 2 * std::max(resident, resident_lean)
+                             ? lcm
+                             : (int64_t)LB_MARCH_TILES_X10 * resident_lean / 10;
     int64_t chunks = want / xs;
     if (chunks < 1) chunks = 1;
     int64_t sy = (g.ny + chunks - 1) / chunks;

@@ -351,16 +351,37 @@ __device__ __forceinline__ T rest_k(const MRow<T, SP, RYS>& R, int s)
 // and are skipped; with FY = 0 also v_y = 0 and the m v_y terms vanish.  The
 // sums are the same, term for term.  REST: the rest group's packets (from the
 // sources at x displacement floor(v_x) + k_x, into row FY + k_y) follow the
-// lanes.
-template <typename T, int L, int FY, int S0, int NSP, int NKX, bool RY0, bool REST, bool SP, bool RYS>
+// lanes.  YM: floor(v_y) is FY or FY + 1 per source (where v_y changes
+// sign); the corners k_y = 0, 1 of a source then sit at rows FY + d with d =
+// floor(v_y) - FY + k_y in 0 .. 2, and each packet class is taken once per d
+// with the source's weight for that row (zero for the row it does not reach).
+template <typename T, int L, int FY, int S0, int NSP, int NKX, bool RY0, bool REST, bool YM = false, bool SP,
+          bool RYS>
 __device__ __forceinline__ void gather_fast(const MRow<T, SP, RYS>& R, int lane, int fx, Fifo<Acc<T>, L, SP>& f,
                                             T rq)
 {
 #pragma clang fp contract(off)
+    static_assert(!(YM && RY0), "a y-mixed window has sources with r_y != 0");
     constexpr bool UNI = NSP == 2;
     constexpr bool NOVY = RY0 && FY == 0;
+    constexpr int NKY = YM ? 3 : (RY0 ? 1 : 2);  // row offsets d of the packets (k_y, plus 1 if YM)
     constexpr int K0 = NKX == 3 ? -1 : 0;  // first x corner relative to floor(v_x) = fx
     const int base = lane - fx;  // staged column of x displacement fx + a is base - a
+    // weight of row offset d for the source in column s with y fraction ry
+    // (1 - r_y at its k_y = 0, r_y at k_y = 1)
+    auto ywt = [&](int s, T ry, int d) -> T {
+        if constexpr (YM) {
+            const int k = d - (mfy(R.pk[s]) - FY);
+            return k == 0 ? (T)1 - ry : (k == 1 ? ry : (T)0);
+        } else {
+            return d ? ry : (T)1 - ry;
+        }
+    };
+    // v_y of the source in column s
+    auto vyof = [&](int s, T ry) -> T {
+        if constexpr (YM) return (T)mfy(R.pk[s]) + ry;
+        else return (T)FY + ry;
+    };
     // level (0: c'_1, 1: c'_2) that the source in column s has at speed
     // S0 + j, or -1 (no lane of that speed)
     auto level = [&](int s, int j) -> int {
@@ -392,12 +413,12 @@ __device__ __forceinline__ void gather_fast(const MRow<T, SP, RYS>& R, int lane,
             const T bp = mass(sp, j, kx), bm = mass(sm, j, kx);
             const T vxp = R.vx[sp], vxm = R.vx[sm];
             const T ryp = ry_of(R, sp), rym = ry_of(R, sm);
-            const T vyp = (T)FY + ryp, vym = (T)FY + rym;
+            const T vyp = vyof(sp, ryp), vym = vyof(sm, rym);
             const T zp = fmaT(cc, vxp, kkof(sp, j)), zm = fmaT(-cc, vxm, kkof(sm, j));
 #pragma unroll
-            for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
-                const T mp = RY0 ? bp : bp * (ky ? ryp : (T)1 - ryp);
-                const T mm = RY0 ? bm : bm * (ky ? rym : (T)1 - rym);
+            for (int ky = 0; ky < NKY; ++ky) {
+                const T mp = RY0 ? bp : bp * ywt(sp, ryp, ky);
+                const T mm = RY0 ? bm : bm * ywt(sm, rym, ky);
                 if constexpr (SP)
                     add_xpair<Acc<T>, T, L, NOVY>(f, FY + ky + L, mp, mm, vxp, vxm, vyp, vym, cc, zp, zm,
                                                   chi_of(R, sp), chi_of(R, sm));
@@ -413,15 +434,15 @@ __device__ __forceinline__ void gather_fast(const MRow<T, SP, RYS>& R, int lane,
             b[q] = mass(sq, j, kx);
             ry[q] = ry_of(R, sq);
             vx[q] = R.vx[sq];
-            vy[q] = (T)FY + ry[q];
+            vy[q] = vyof(sq, ry[q]);
             kk[q] = kkof(sq, j);
             xq[q] = chi_of(R, sq);
         }
 #pragma unroll
-        for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
+        for (int ky = 0; ky < NKY; ++ky) {
             T m[NKX];
 #pragma unroll
-            for (int q = 0; q < NKX; ++q) m[q] = RY0 ? b[q] : b[q] * (ky ? ry[q] : (T)1 - ry[q]);
+            for (int q = 0; q < NKX; ++q) m[q] = RY0 ? b[q] : b[q] * ywt(base - (K0 + q), ry[q], ky);
             add_ylanes<Acc<T>, T, L, NKX, NOVY>(f, FY + ky + c + L, FY + ky - c + L, m, vx, vy, kk, cc, xq);
         }
     }
@@ -435,15 +456,15 @@ __device__ __forceinline__ void gather_fast(const MRow<T, SP, RYS>& R, int lane,
             b[q] = (kc >= 0 && kc <= 1) ? v : (T)0;
             ry[q] = ry_of(R, sq);
             vx[q] = R.vx[sq];
-            vy[q] = (T)FY + ry[q];
+            vy[q] = vyof(sq, ry[q]);
             kr[q] = rest_k(R, sq);
             xq[q] = chi_of(R, sq);
         }
 #pragma unroll
-        for (int ky = 0; ky < (RY0 ? 1 : 2); ++ky) {
+        for (int ky = 0; ky < NKY; ++ky) {
             T m[NKX];
 #pragma unroll
-            for (int q = 0; q < NKX; ++q) m[q] = RY0 ? b[q] : b[q] * (ky ? ry[q] : (T)1 - ry[q]);
+            for (int q = 0; q < NKX; ++q) m[q] = RY0 ? b[q] : b[q] * ywt(base - (K0 + q), ry[q], ky);
             add_rest<Acc<T>, T, L, NKX, NOVY>(f, FY + ky + L, m, vx, vy, kr, xq);
         }
     }
@@ -640,8 +661,11 @@ __device__ __forceinline__ void load_node(const T* __restrict__ Y, int64_t nn, i
 // kFlagFar and kFlagReach of every tile it claims (a tile it leaves to the
 // full pass gets both: its sources are not looked at); the full pass reads
 // them and rewrites only kFlagKeep, the tile still needs the full FIFO, which
-// the next step's short pass reads.
-constexpr int kFlagFar = 1, kFlagReach = 2, kFlagKeep = 4;
+// the next step's short pass reads.  In the lean pass's flag words the short
+// pass keeps kFlagKeep for the tiles it computed whose sources the lean pass
+// cannot take (march_tile's kFlagNotLean), and the next step's lean pass
+// leaves those to it at once.
+constexpr int kFlagFar = 1, kFlagReach = 2, kFlagKeep = 4, kFlagNotLean = 8;
 
 // Whether the next pass must compute the tile of destination rows
 // [Y0, ylast) whose row chunk ty0 = Y0 / sy starts at flag index tbase +
@@ -682,9 +706,12 @@ __device__ __forceinline__ bool needs_pass(const int* __restrict__ flags, int64_
 // L = kLSmall the tile's output is then incomplete and must be recomputed
 // with L = kLFull, which sums in the same order (bit-identical); with
 // L = kLFull it tells that the tile still needs the full pass.  kFlagReach: a
-// source in the tile's own destination rows has a y-reach beyond kLSmall, so
-// it may reach destination rows of the neighbouring row chunks that their
-// short passes complete without staging it (see needs_pass).
+// source in the first or last H of the tile's own destination rows has a
+// y-reach beyond kLSmall, so it may reach destination rows of the
+// neighbouring row chunks that their short passes complete without staging
+// it (see needs_pass).  kFlagNotLean:
+// some staged source has v_y != 0, c'_1 > 1 or a bad state (the lean pass
+// would give the tile up).
 // Contains block-wide barriers: every thread of the block must call it.
 template <typename T, int L, bool WALLS, bool REST, bool SP>
 __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict__ Yn, const Grid& g, const Consts& k,
@@ -713,7 +740,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
     Fifo<A, L, SP> f;
     f.zero();
     double tot[NF] = {};
-    int reach = 0, bad = 0, yfar = 0, yreach = 0;
+    int reach = 0, bad = 0, yfar = 0, yreach = 0, unlean = 0;
 
     // moments of this thread's source column in row gy (halo rows and
     // columns mapped by the boundaries); *mir_y tells whether the row is a
@@ -760,11 +787,15 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
             const int yr = axis_reach(s.fy, s.c1);
             reach = max(reach, max(axis_reach(s.fx, s.c1), yr));
             yfar |= yr > kLSmall ? 1 : 0;
-            // a source of the tile's own destination rows that reaches past
-            // the short FIFO: the neighbouring tiles' short passes, which do
-            // not stage this row, may miss its packets
-            yreach |= (yr > kLSmall && r0 + u >= L && r0 + u < nrows - L) ? 1 : 0;
+            // a source in the first or last H of the tile's own destination
+            // rows that reaches past the short FIFO: the neighbouring tiles'
+            // short passes, which do not stage this row, may miss its packets
+            // (every source row another tile's pass does not stage lies within
+            // H rows of an edge of its own tile, after the boundary map)
+            yreach |= (yr > kLSmall && r0 + u >= L && r0 + u < nrows - L &&
+                       (r0 + u < L + kMH || r0 + u >= nrows - L - kMH)) ? 1 : 0;
             bad |= s.bad ? 1 : 0;
+            unlean |= (s.bad || s.fy != 0 || s.ry != (T)0 || s.c1 > 1) ? 1 : 0;
             {
                 const int ry0 = __all(s.ry == (T)0) ? 1 : 0;
                 const int pk0 = __builtin_amdgcn_readfirstlane(pk);
@@ -798,52 +829,54 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
             const bool planar = fits_x && w.fymin == w.fymax && (w.fymin == 0 || w.fymin == -1) &&
                                 w.c1max <= 3 && w.fxmax - w.fxmin <= 2;
             const bool rows_ok = planar && fits_y;
-            // the short pass takes planar windows within its FIFO; a tile with
-            // any other window is flagged for the full pass
-            if (!(planar && fits_small)) yfar = 1;
-            // full pass, floor(v_y) in {-1, 0} (where v_y changes sign): the row
-            // path once per value (other pairs of values take the general path:
-            // their instances made the compiler spill the FIFO on every path)
+            // floor(v_y) in {-1, 0} (where v_y changes sign): the row path
+            // once per value (other pairs of values take the full pass's
+            // general path: their instances made the compiler spill the FIFO
+            // on every path)
             const bool ymix_ok = fits_x && fits_y && w.fymin == -1 && w.fymax == 0 && w.c1max <= 3 &&
                                  w.fxmax - w.fxmin <= 2;
+            // the short pass takes these windows and the planar ones within
+            // its FIFO; a tile with any other window is flagged for the full pass
+            if (!((planar || ymix_ok) && fits_small)) yfar = 1;
             if (dest && (fits_y || L == kLFull)) {
                 // two adjacent values of c'_1 or of floor(v_x) keep compile-time
                 // offsets; a window mixing both (rare in planar flows) takes the
                 // row path, whose extra registers would otherwise cost occupancy
                 const bool cmix = w.c1max == w.c1min + 1, xmix = w.fxmax == w.fxmin + 1;
-                const bool fastw = rows_ok && (w.c1max == w.c1min || cmix) && (w.fxmax == w.fxmin || xmix) &&
+                const bool mixes = (w.c1max == w.c1min || cmix) && (w.fxmax == w.fxmin || xmix) &&
                                    !(cmix && xmix) && (!cmix || w.c1min <= 2) && (!xmix || w.c1min <= 1);
-                if (fastw) {
+                const bool fastw = rows_ok && mixes;
+                // floor(v_y) in {-1, 0} with the same mixes: the y-mixed
+                // instances (three row offsets per packet class)
+                const bool ymixw = ymix_ok && mixes && !xmix && w.c1max <= 1;
+                if (fastw || ymixw) {
                     const auto& R = s_row[b][u];
                     const int fx0 = w.fxmax;
-                    const int sel = ((w.fymin == 0 ? (w.ry0 ? 0 : 1) : 2) * 2 + (xmix ? 1 : 0)) * 8 +
+                    const int sel = ((ymixw ? 3 : (w.fymin == 0 ? (w.ry0 ? 0 : 1) : 2)) * 2 + (xmix ? 1 : 0)) * 8 +
                                     (cmix ? 4 : 0) + w.c1min;
                     switch (sel) {
-    #define LB_FAST(S, FYV, S0, NSP, NKX, RY)                                                   \
-        case S:                                                                                 \
-            if constexpr ((FYV) - (S0) - (NSP) + 1 >= -L && (FYV) + 1 + (S0) + (NSP) - 1 <= L)  \
-                gather_fast<T, L, FYV, S0, NSP, NKX, RY, REST>(R, tid, fx0, f, rq);             \
+    #define LB_FAST(S, FYV, S0, NSP, NKX, RY, YM)                                                           \
+        case S:                                                                                             \
+            if constexpr ((FYV) - (S0) - (NSP) + 1 >= -L && (FYV) + ((YM) ? 2 : 1) + (S0) + (NSP) - 1 <= L) \
+                gather_fast<T, L, FYV, S0, NSP, NKX, RY, REST, YM>(R, tid, fx0, f, rq);                     \
             break;
-    #define LB_FAST_SET(B, FYV, RY)                                                              \
-        LB_FAST(B + 0, FYV, 0, 2, 2, RY) LB_FAST(B + 1, FYV, 1, 2, 2, RY) LB_FAST(B + 2, FYV, 2, 2, 2, RY) \
-        LB_FAST(B + 3, FYV, 3, 2, 2, RY) LB_FAST(B + 4, FYV, 0, 3, 2, RY) LB_FAST(B + 5, FYV, 1, 3, 2, RY) \
-        LB_FAST(B + 6, FYV, 2, 3, 2, RY)                                                        \
-        LB_FAST(B + 8, FYV, 0, 2, 3, RY) LB_FAST(B + 9, FYV, 1, 2, 3, RY)
-                        LB_FAST_SET(0, 0, true)
-                        LB_FAST_SET(16, 0, false)
-                        LB_FAST_SET(32, -1, false)
+    #define LB_FAST_SET(B, FYV, RY, YM)                                                                      \
+        LB_FAST(B + 0, FYV, 0, 2, 2, RY, YM) LB_FAST(B + 1, FYV, 1, 2, 2, RY, YM)                            \
+        LB_FAST(B + 2, FYV, 2, 2, 2, RY, YM) LB_FAST(B + 3, FYV, 3, 2, 2, RY, YM)                            \
+        LB_FAST(B + 4, FYV, 0, 3, 2, RY, YM) LB_FAST(B + 5, FYV, 1, 3, 2, RY, YM)                            \
+        LB_FAST(B + 6, FYV, 2, 3, 2, RY, YM)                                                                 \
+        LB_FAST(B + 8, FYV, 0, 2, 3, RY, YM) LB_FAST(B + 9, FYV, 1, 2, 3, RY, YM)
+                        LB_FAST_SET(0, 0, true, false)
+                        LB_FAST_SET(16, 0, false, false)
+                        LB_FAST_SET(32, -1, false, false)
+                        // y-mixed: uniform c'_1 0 or 1 and c'_1 in {0, 1} (the other
+                        // instances made the compiler spill the short pass's FIFO)
+                        LB_FAST(48 + 0, -1, 0, 2, 2, false, true) LB_FAST(48 + 1, -1, 1, 2, 2, false, true)
+                        LB_FAST(48 + 4, -1, 0, 3, 2, false, true)
     #undef LB_FAST_SET
     #undef LB_FAST
-                        default: break;  // not reached: fastw admits only the cases above
+                        default: break;  // not reached: fastw and ymixw admit only the cases above
                     }
-                } else if (L < kLFull) {
-                    if (rows_ok) {
-                        const auto& R = s_row[b][u];
-                        if (w.fymin == -1)
-                            gather_rows<T, L, -1, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, false, rq);
-                        else
-                            gather_rows<T, L, 0, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, false, rq);
-                    }  // other windows: the tile is flagged (above)
                 } else if (rows_ok || ymix_ok) {
                     // one call per value of floor(v_y) in the window (one
                     // call site per instance keeps the kernel's code compact)
@@ -852,7 +885,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                         gather_rows<T, L, -1, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, ymix_ok, rq);
                     if (w.fymax == 0)
                         gather_rows<T, L, 0, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, ymix_ok, rq);
-                } else {
+                } else if (L == kLFull) {  // other windows: the short pass flags the tile (above)
                     gather_general<T, L, REST>(s_row[b][u], tid, f, max(-kMH, w.fxmin - c2max),
                                                min(kMH, w.fxmax + 1 + c2max), w.fymin, w.fymax, w.c1min, w.c1max,
                                                rq);
@@ -899,7 +932,8 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
         s_ir[wid][1] = bad;
     }
     // (__syncthreads_or returns whether any value is non-zero, not their OR)
-    const int far = (__syncthreads_or(yfar) ? kFlagFar : 0) | (__syncthreads_or(yreach) ? kFlagReach : 0);
+    const int far = (__syncthreads_or(yfar) ? kFlagFar : 0) | (__syncthreads_or(yreach) ? kFlagReach : 0) |
+                    (__syncthreads_or(unlean) ? kFlagNotLean : 0);
     if (tid == 0) {
         int rr = 0, bb = 0;
         for (int c = 0; c < NF; ++c) {
@@ -1140,11 +1174,17 @@ __device__ __forceinline__ int march_tile_lean(const T* __restrict__ Y, T* __res
 #ifndef LB_MARCH_WPE_F32
 #define LB_MARCH_WPE_F32 3
 #endif
+#ifndef LB_MARCH_WPE_FULL
+#define LB_MARCH_WPE_FULL 1
+#endif
 #ifndef LB_LEAN_WPE
 #define LB_LEAN_WPE 4
 #endif
 #ifndef LB_LEAN_WPE_F32
 #define LB_LEAN_WPE_F32 4
+#endif
+#ifndef LB_LEAN_WPE_EXT
+#define LB_LEAN_WPE_EXT 3  // FP64 with a rest level or two gases: more packets or fields per source
 #endif
 
 // Counters of StepCtl::next / PoolView::next: tile claims of each pass, and
@@ -1159,7 +1199,7 @@ enum { kNextShort = 0, kNextFull = 1, kNextShortFlagged = 2, kNextLean = 3, kNex
 // for the short pass (a kFlagKeep bit there from the previous step's full
 // pass still counts).
 template <typename T, bool WALLS, bool REST, bool SP>
-__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? LB_LEAN_WPE_F32 : LB_LEAN_WPE)))
+__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? LB_LEAN_WPE_F32 : ((REST || SP) ? LB_LEAN_WPE_EXT : LB_LEAN_WPE))))
 march2d_lean_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k, StepCtl* __restrict__ ctl,
                     double* __restrict__ partials, int* __restrict__ flags, int* __restrict__ flags_lean,
                     long long step, int sy, int tiles_x, int ntiles)
@@ -1169,6 +1209,13 @@ march2d_lean_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts 
     for (;;) {
         const int t = claim_tile(&ctl->next[kNextLean], &s_t);
         if (t >= ntiles) break;
+        if (flags_lean[t] & kFlagKeep) {  // the short pass found it beyond this pass last step
+            if (threadIdx.x == 0) {
+                flags_lean[t] = kFlagFar | kFlagReach | kFlagKeep;
+                atomicAdd(&ctl->next[kNextLeanFlagged], 1);
+            }
+            continue;
+        }
         const int64_t tx = t % tiles_x, ty = t / tiles_x;
         const int bits = march_tile_lean<T, WALLS, REST, SP>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), ty * sy, sy,
                                                              partials + (int64_t)t * kPartialStride);
@@ -1189,10 +1236,10 @@ march2d_lean_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts 
 // of computing them twice (flows change little per step).  Each returns at
 // once when the previous pass flagged nothing.
 template <typename T, int L, bool WALLS, bool REST, bool SP>
-__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
+__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : LB_MARCH_WPE_FULL)))
 march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
                StepCtl* __restrict__ ctl, double* __restrict__ partials, int* __restrict__ flags,
-               const int* __restrict__ flags_lean, long long step, int sy, int tiles_x, int ntiles)
+               int* __restrict__ flags_lean, long long step, int sy, int tiles_x, int ntiles)
 {
     __shared__ int s_t;
     if (ctl->err_step < step) return;
@@ -1222,8 +1269,10 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
         if (threadIdx.x == 0) {
             const int far = bits & kFlagFar;
             if (L < kLFull) {
-                flags[t] = bits;
+                flags[t] = bits & (kFlagFar | kFlagReach);
                 if (far) atomicAdd(&ctl->next[kNextShortFlagged], 1);
+                // keep the lean pass's bits, which other blocks of this pass read
+                flags_lean[t] = (flags_lean[t] & (kFlagFar | kFlagReach)) | ((bits & kFlagNotLean) ? kFlagKeep : 0);
             } else {
                 // keep the short pass's bits, which other blocks of this pass read
                 flags[t] = (flags[t] & (kFlagFar | kFlagReach)) | (far ? kFlagKeep : 0);
@@ -1238,7 +1287,7 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
 // table (see pool1d_kernel); a slot's tiles are its row chunks, then column
 // strips, from its t0, which is how needs_pass finds a tile's neighbours.
 template <typename T, bool WALLS, bool REST, bool SP>
-__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? LB_LEAN_WPE_F32 : LB_LEAN_WPE)))
+__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? LB_LEAN_WPE_F32 : ((REST || SP) ? LB_LEAN_WPE_EXT : LB_LEAN_WPE))))
 pool2d_lean_kernel(PoolView v, Consts k)
 {
     __shared__ int s_t;
@@ -1249,6 +1298,13 @@ pool2d_lean_kernel(PoolView v, Consts k)
         if (t >= nt) break;
         const int ts = v.tstate[t];
         if (!(ts & kTileLive)) continue;  // the same for the whole block
+        if (v.flags_lean[t] & kFlagKeep) {  // the short pass found it beyond this pass last step
+            if (threadIdx.x == 0) {
+                v.flags_lean[t] = kFlagFar | kFlagReach | kFlagKeep;
+                atomicAdd(&v.next[kNextLeanFlagged], 1);
+            }
+            continue;
+        }
         const PoolTile& tl = v.tiles[t];
         const int64_t o0 = tl.off[0], o1 = tl.off[1];
         const int64_t from = (ts & kTileSet) ? o1 : o0, to = (ts & kTileSet) ? o0 : o1;
@@ -1264,7 +1320,7 @@ pool2d_lean_kernel(PoolView v, Consts k)
 }
 
 template <typename T, int L, bool WALLS, bool REST, bool SP>
-__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : 1)))
+__global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : LB_MARCH_WPE_FULL)))
 pool2d_kernel(PoolView v, Consts k)
 {
     __shared__ int s_t;
@@ -1301,8 +1357,11 @@ pool2d_kernel(PoolView v, Consts k)
         if (threadIdx.x == 0) {
             const int far = bits & kFlagFar;
             if (L < kLFull) {
-                v.flags[t] = bits;
+                v.flags[t] = bits & (kFlagFar | kFlagReach);
                 if (far) atomicAdd(&v.next[kNextShortFlagged], 1);
+                // keep the lean pass's bits, which other blocks of this pass read
+                v.flags_lean[t] = (v.flags_lean[t] & (kFlagFar | kFlagReach)) |
+                                  ((bits & kFlagNotLean) ? kFlagKeep : 0);
             } else {
                 // keep the short pass's bits, which other blocks of this pass read
                 v.flags[t] = (v.flags[t] & (kFlagFar | kFlagReach)) | (far ? kFlagKeep : 0);

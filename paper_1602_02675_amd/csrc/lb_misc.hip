@@ -86,6 +86,12 @@ __global__ void status_kernel(const StepCtl* __restrict__ ctl, int32_t* __restri
     }
 }
 
+__global__ void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 unsigned blocks_for(int64_t n, int tpb) { return (unsigned)((n + tpb - 1) / tpb); }
 
 }  // namespace
@@ -120,6 +126,13 @@ hipError_t launch_lanes(const T* Y, const Grid& g, int dim, const Consts& k, int
 hipError_t launch_reset_ctl(StepCtl* ctl, hipStream_t stream)
 {
     reset_ctl_kernel<<<1, 64, 0, stream>>>(ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    fill_i32_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(p, n, v);
     return hipGetLastError();
 }
 

@@ -216,6 +216,10 @@ int upload_tables(lb_pool* p)
     if (nt > 0 && (e = hipMemcpyAsync(p->base + p->off_flags, zeros.data(), (size_t)nt * 4,
                                       hipMemcpyHostToDevice, p->stream)) != hipSuccess)
         return hip_fail(e, "clear flags");
+    if (nt > 0 && p->dim == 2 &&
+        (e = hipMemcpyAsync(p->base + p->off_flags + (size_t)p->max_tiles * 4, zeros.data(), (size_t)nt * 4,
+                            hipMemcpyHostToDevice, p->stream)) != hipSuccess)
+        return hip_fail(e, "clear lean flags");
     if (nt > 0 && (e = hipMemcpyAsync(p->base + p->off_tstate, words.data(), (size_t)nt * 4,
                                       hipMemcpyHostToDevice, p->stream)) != hipSuccess)
         return hip_fail(e, "upload tile words");
