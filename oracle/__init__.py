@@ -45,7 +45,7 @@ class _Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_long), ("ny", ctypes.c_long),
                 ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
                 ("gamma", ctypes.c_double), ("delta0", ctypes.c_double),
-                ("species", ctypes.c_int), ("gamma2", ctypes.c_double)]
+                ("species", ctypes.c_int), ("gamma2", ctypes.c_double), ("hex", ctypes.c_int)]
 
 
 class _Levels(ctypes.Structure):
@@ -56,7 +56,8 @@ class _Levels(ctypes.Structure):
                 ("d0", ctypes.c_double), ("d1", ctypes.c_double), ("d2", ctypes.c_double),
                 ("b0", ctypes.c_int), ("b1", ctypes.c_int), ("b2", ctypes.c_int),
                 ("f", ctypes.c_int * 2), ("vp0", ctypes.c_double * 2),
-                ("vp1", ctypes.c_double * 2), ("chi", ctypes.c_double), ("gm1", ctypes.c_double)]
+                ("vp1", ctypes.c_double * 2), ("chi", ctypes.c_double), ("gm1", ctypes.c_double),
+                ("r", ctypes.c_double * 2), ("tri", ctypes.c_int)]
 
 
 def _load():
@@ -88,17 +89,21 @@ class Problem:
 
     def __init__(self, dim: int, nx: int, ny: int = 1, *, gamma: float = 1.4,
                  delta0: float | None = None, bc_x: int = TRANSMISSIVE, bc_y: int = PERIODIC,
-                 gamma2: float | None = None):
+                 gamma2: float | None = None, hex: bool = False):
         """gamma2: a second gas (gamma of gas 2, gamma of gas 1); the state
-        then has a species field rho chi (mass of gas 1) after rho E."""
+        then has a species field rho chi (mass of gas 1) after rho E.
+        hex (dim 2): the hexagonal lattice of Fig. 1, nodes at i e_1 + j e_2
+        with e_1 = (1, 0), e_2 = (1/2, sqrt(3)/2), stored [.][j][i]; bc_x and
+        bc_y then apply to the axial indices i and j."""
         if delta0 is None:
             delta0 = 0.5 if dim == 1 else 0.0
         self.dim, self.nx, self.ny = dim, int(nx), int(ny if dim == 2 else 1)
         self.gamma, self.delta0, self.bc_x, self.bc_y = float(gamma), float(delta0), bc_x, bc_y
         self.species = gamma2 is not None
         self.gamma2 = float(gamma2) if self.species else self.gamma
+        self.hex = bool(hex) and dim == 2
         self._c = _Problem(dim, self.nx, self.ny, bc_x, bc_y, self.gamma, self.delta0,
-                           1 if self.species else 0, self.gamma2)
+                           1 if self.species else 0, self.gamma2, 1 if self.hex else 0)
 
     @property
     def ie(self) -> int:
@@ -131,15 +136,15 @@ def levels(P: Problem, node) -> dict:
     return dict(valid=L.valid, rho=L.rho, v=tuple(L.v[: P.dim]), E=L.E, e=L.e, phi=L.phi,
                 A=L.A, c1=L.c1, c2=L.c2, d0=L.d0, d1=L.d1, d2=L.d2, b=(L.b0, L.b1, L.b2),
                 f=tuple(L.f[: P.dim]), vp0=tuple(L.vp0[: P.dim]), vp1=tuple(L.vp1[: P.dim]),
-                chi=L.chi, gm1=L.gm1)
+                chi=L.chi, gm1=L.gm1, r=tuple(L.r[: P.dim]), tri=L.tri)
 
 
 def packets(P: Problem, node):
     """All packets of one node: (offsets [n, 2] int, payload [n, nf] = m, m*xi, m*zeta)."""
     lib = _load()
     y = np.ascontiguousarray(node, dtype=np.float64)
-    off = np.zeros((36, 2), dtype=np.int32)  # at most 36 packets (2-D with a rest level)
-    pay = np.zeros(36 * 5, dtype=np.float64)
+    off = np.zeros((40, 2), dtype=np.int32)  # at most 39 packets (hexagonal lattice with a rest level)
+    pay = np.zeros(40 * 5, dtype=np.float64)
     n = lib.oc_packets(ctypes.byref(P._c), _dptr(y), _iptr(off), _dptr(pay))
     return off[:n].copy(), pay[: n * P.nf].reshape(n, P.nf).copy()
 

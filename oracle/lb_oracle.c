@@ -53,6 +53,21 @@
  *     whose figures show only the dual-level set): one rest particle group,
  *     b_0 = 1, d_0 = delta0 * rho, next to the four directions at c'_1, c'_2
  *     (b_1 = b_2 = 4).  delta0 = 0 is the paper's dual-level set.
+ *   - the hexagonal lattice (Fig. 1; Sec. III.B with b_v = 6): nodes at
+ *     i e_1 + j e_2 with e_1 = (1, 0), e_2 = (1/2, sqrt(3)/2) (unit spacing),
+ *     stored as Y[.][j][i]; velocities and momenta are Cartesian.  Its six
+ *     directions are the unit vectors at multiples of 60 degrees, axial
+ *     (1,0), (0,1), (-1,1), (-1,0), (0,-1), (1,-1), each at c'_1 and c'_2
+ *     (b_1 = b_2 = 6; eq. 16-18 hold with b_v / D = 3), plus a rest group
+ *     when delta0 > 0.  The end point of v, v = a e_1 + b e_2, lies in the
+ *     lattice triangle with vertices (f_a, f_b) + {(1,0), (0,1)} and either
+ *     (0,0) (when r_a + r_b <= 1, r = (a,b) - f) or (1,1); "the nodes that
+ *     surround the end point of v" are these three, and alpha_k (eq. 23) is
+ *     the barycentric weight of vertex k: the only split of the unit mass on
+ *     three nodes with sum alpha_k v'_k = 0.  tri 0: alpha = (1 - r_a - r_b,
+ *     r_a, r_b) at (0,0), (1,0), (0,1); tri 1: alpha = (r_a + r_b - 1, 1 - r_b,
+ *     1 - r_a) at (1,1), (1,0), (0,1).  Boundaries along both axial
+ *     directions: transmissive or periodic (no walls).
  *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC.
  */
@@ -61,7 +76,7 @@
 #include <string.h>
 
 #define OC_GHOSTS 8       /* ghost nodes per transmissive end (>= any reach) */
-#define OC_MAX_PACKETS 36 /* 10 in 1-D, 32 in 2-D (36 with the rest level) */
+#define OC_MAX_PACKETS 40 /* 10 in 1-D, 32 square (36 with the rest level), 36 hexagonal (39) */
 
 typedef struct {
     int dim;        /* 1: 1-D triple-level lattice; 2: square dual-level lattice */
@@ -72,6 +87,7 @@ typedef struct {
     double delta0;  /* d_0 = delta0 * rho; in 2-D, delta0 > 0 adds the rest level */
     int species;    /* 1: two gases, a species field rho chi after rho E */
     double gamma2;  /* ratio of specific heats of gas 2 (species only) */
+    int hex;        /* dim 2 only: 1 for the hexagonal lattice, 0 for the square one */
 } oc_problem;
 
 typedef struct {
@@ -85,6 +101,10 @@ typedef struct {
     double vp1[2]; /* v'_2 = (x + f + 1) - (x + v): towards corner 1 */
     double chi;    /* mass fraction of gas 1 (two gases) */
     double gm1;    /* gamma - 1 of the node's gas */
+    /* hexagonal lattice: f = floor of the axial coordinates (a, b) of v,
+     * r = (a, b) - f, tri = which triangle of the cell holds the end point */
+    double r[2];
+    int tri;
 } oc_levels;
 
 /* Number of moment fields: rho, rho*v (dim components), rho*E. */
@@ -133,14 +153,15 @@ int oc_levels_of(const oc_problem* P, const double* Yn, oc_levels* L)
     L->phi = (1.0 - ((double)D / 2.0) * L->gm1) * L->e;
     /* velocity set (Sec. IV): 1-D b0=1, b1=b2=2; square lattice b0=0, b1=b2=4
      * (dual level), or b0=1 with d0 = delta0 rho (triple level) */
+    const int bdir = (D == 2 && P->hex) ? 6 : 2 * D; /* directions per level */
     if (D == 1) {
         L->b0 = 1; L->b1 = 2; L->b2 = 2;
         L->d0 = P->delta0 * L->rho;
     } else if (P->delta0 > 0.0) {
-        L->b0 = 1; L->b1 = 4; L->b2 = 4;
+        L->b0 = 1; L->b1 = bdir; L->b2 = bdir;
         L->d0 = P->delta0 * L->rho;
     } else {
-        L->b0 = 0; L->b1 = 4; L->b2 = 4;
+        L->b0 = 0; L->b1 = bdir; L->b2 = bdir;
         L->d0 = 0.0;
     }
     /* level speeds (eq. 26) */
@@ -158,6 +179,17 @@ int oc_levels_of(const oc_problem* P, const double* Yn, oc_levels* L)
     L->d1 = (c2s * rest - Dp) / ((double)L->b1 * (c2s - c1s));
     L->d2 = (Dp - c1s * rest) / ((double)L->b1 * (c2s - c1s));
     /* nodes surrounding the end point of v (eq. 13, 28-29) */
+    if (D == 2 && P->hex) {
+        /* axial coordinates of v: v_y = b sqrt(3)/2, v_x = a + b/2 */
+        const double b = 2.0 * L->v[1] / sqrt(3.0);
+        const double a = L->v[0] - 0.5 * b;
+        L->f[0] = (int)floor(a);
+        L->f[1] = (int)floor(b);
+        L->r[0] = a - (double)L->f[0];
+        L->r[1] = b - (double)L->f[1];
+        L->tri = L->r[0] + L->r[1] > 1.0 ? 1 : 0;
+        return 1;
+    }
     for (int a = 0; a < D; ++a) {
         L->f[a] = (int)floor(L->v[a]);
         L->vp0[a] = (double)L->f[a] - L->v[a];
@@ -173,11 +205,65 @@ int oc_levels_of(const oc_problem* P, const double* Yn, oc_levels* L)
  * level; 0 if rho <= 0).
  * off: [n][2] integer displacement; pay: [n][nf].
  */
+/* Packets of one node of the hexagonal lattice (see oc_packets): lanes in
+ * the order rest group, six directions at c'_1, six at c'_2; per lane the
+ * three vertices of the triangle around the end point of v. */
+static int oc_packets_hex(const oc_problem* P, const oc_levels* L, int* off, double* pay)
+{
+    const int nf = oc_nf(P);
+    /* the six directions: axial steps and Cartesian unit vectors */
+    const int dir[6][2] = {{1, 0}, {0, 1}, {-1, 1}, {-1, 0}, {0, -1}, {1, -1}};
+    const double h = sqrt(3.0) / 2.0;
+    const double unit[6][2] = {{1.0, 0.0}, {0.5, h}, {-0.5, h}, {-1.0, 0.0}, {-0.5, -h}, {0.5, -h}};
+    /* triangle vertices relative to f and their barycentric weights */
+    int vert[3][2];
+    double alpha[3];
+    const double ra = L->r[0], rb = L->r[1];
+    if (L->tri == 0) {
+        vert[0][0] = 0; vert[0][1] = 0; alpha[0] = (1.0 - ra) - rb;
+    } else {
+        vert[0][0] = 1; vert[0][1] = 1; alpha[0] = (ra + rb) - 1.0;
+    }
+    vert[1][0] = 1; vert[1][1] = 0; alpha[1] = L->tri == 0 ? ra : 1.0 - rb;
+    vert[2][0] = 0; vert[2][1] = 1; alpha[2] = L->tri == 0 ? rb : 1.0 - ra;
+    /* lanes: speed, direction (-1: rest) and weight d_v */
+    int lane_s[13], lane_j[13];
+    double lane_d[13];
+    int nl = 0;
+    if (L->b0 == 1) { lane_s[nl] = 0; lane_j[nl] = -1; lane_d[nl++] = L->d0; }
+    for (int lev = 1; lev <= 2; ++lev)
+        for (int j = 0; j < 6; ++j) {
+            lane_s[nl] = lev == 1 ? L->c1 : L->c2;
+            lane_j[nl] = j;
+            lane_d[nl++] = lev == 1 ? L->d1 : L->d2;
+        }
+    int n = 0;
+    for (int l = 0; l < nl; ++l) {
+        const int c = lane_s[l], j = lane_j[l];
+        /* molecular velocity v + c' (eq. 12) and zeta (eq. 14) */
+        const double xi0 = L->v[0] + (j < 0 ? 0.0 : (double)c * unit[j][0]);
+        const double xi1 = L->v[1] + (j < 0 ? 0.0 : (double)c * unit[j][1]);
+        const double zeta = 0.5 * (xi0 * xi0 + xi1 * xi1) + L->phi;
+        for (int t = 0; t < 3; ++t) {
+            const double m = alpha[t] * lane_d[l]; /* eq. 23 */
+            off[2 * n + 0] = L->f[0] + vert[t][0] + (j < 0 ? 0 : c * dir[j][0]);
+            off[2 * n + 1] = L->f[1] + vert[t][1] + (j < 0 ? 0 : c * dir[j][1]);
+            pay[nf * n + 0] = m;
+            pay[nf * n + 1] = m * xi0;
+            pay[nf * n + 2] = m * xi1;
+            pay[nf * n + 3] = m * zeta;
+            ++n;
+        }
+    }
+    return n;
+}
+
 int oc_packets(const oc_problem* P, const double* Yn, int* off, double* pay)
 {
     oc_levels L;
     const int D = P->dim, nf = oc_nf(P);
     if (!oc_levels_of(P, Yn, &L)) return 0;
+    if (D == 2 && P->hex) return oc_packets_hex(P, &L, off, pay);
     /* lanes: c' per axis and weight d_v */
     int lane_c[9][2];
     double lane_d[9];
@@ -263,6 +349,8 @@ int oc_step(const oc_problem* P, const double* Y, double* Ynew, int* max_reach)
         if (!(Y[q] > 0.0)) status = -4;
     memset(Ynew, 0, sizeof(double) * (size_t)nf * (size_t)nn);
     if (P->bc_x < 0 || P->bc_x > 2 || (D == 2 && (P->bc_y < 0 || P->bc_y > 2))) return -1;
+    /* the hexagonal lattice has no walls (nor a second gas) */
+    if (D == 2 && P->hex && (P->bc_x == 2 || P->bc_y == 2 || P->species)) return -1;
     /* source range: ghosts beyond transmissive ends only (Sec. V.B) */
     const long gx = P->bc_x == 0 ? OC_GHOSTS : 0;
     const long gy = (D == 2 && P->bc_y == 0) ? OC_GHOSTS : 0;
