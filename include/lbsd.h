@@ -58,6 +58,13 @@ extern "C" {
 #define LB_LATTICE_D2_SQUARE_TRIPLE 3 /* square set with a rest level: the dual-level set plus one rest group,
                                        * b0=1, d0 = d0_frac rho, d0_frac in (0, 1) (eq. 24-26 with b_0 d_0;
                                        * the paper's square lattice takes d0 = 0) */
+#define LB_LATTICE_D2_HEX_DUAL 4     /* hexagonal lattice (Fig. 1, Sec. III.B with b_v = 6): six directions 60 degrees
+                                      * apart at c'_1 and c'_2, d0 = 0, b1 = b2 = 6.  Nodes at i e_1 + j e_2 with
+                                      * e_1 = (1, 0), e_2 = (1/2, sqrt(3)/2) (x spacing dx), stored [f][j][i];
+                                      * momenta are Cartesian; bc_x / bc_y apply to the axial indices i / j
+                                      * (transmissive or periodic; no walls, one gas).  A velocity's end point
+                                      * lies in a lattice triangle whose three nodes take its barycentric weights */
+#define LB_LATTICE_D2_HEX_TRIPLE 5   /* the hexagonal set plus one rest group, b0 = 1, d0 = d0_frac rho, d0_frac in (0, 1) */
 
 #define LB_FP64 0 /* FP64 storage and arithmetic */
 #define LB_FP32 1 /* FP32 storage and arithmetic, FP64 conservation totals */
@@ -67,8 +74,10 @@ extern "C" {
 typedef struct lb_solver lb_solver; /* opaque */
 
 /* Grid: dim 1 -> ny must be 1.  Nodes are cell centres x_i = x_lo + (i + 1/2) dx,
- * dx = (x_hi - x_lo) / nx; the square lattice has dy = dx.  Limits: nx, ny
- * <= 2^40, nx ny <= 2^36, and nx <= 2^28 on the square lattice (LB_EINVAL). */
+ * dx = (x_hi - x_lo) / nx; the square lattice has dy = dx (the hexagonal one
+ * rows sqrt(3)/2 dx apart, row j shifted by j dx / 2; lb_init_riemann splits it
+ * by the axial index i, i.e. along lines parallel to e_2).  Limits: nx, ny
+ * <= 2^40, nx ny <= 2^36, and nx <= 2^28 on the 2-D lattices (LB_EINVAL). */
 typedef struct {
     int32_t dim;
     int64_t nx, ny;

@@ -44,8 +44,13 @@ int check_model(int dim, double gamma, const lb_velset* vs, int precision)
     if (!(gamma > 1.0) || !(gamma <= 1.0 + 2.0 / dim))
         return fail(LB_EINVAL, "gamma must lie in (1, 1 + 2/D] (phi >= 0, eq. 15); got %g", gamma);
     if ((dim == 1 && vs->lattice != LB_LATTICE_D1_TRIPLE) ||
-        (dim == 2 && vs->lattice != LB_LATTICE_D2_SQUARE_DUAL && vs->lattice != LB_LATTICE_D2_SQUARE_TRIPLE))
+        (dim == 2 && vs->lattice != LB_LATTICE_D2_SQUARE_DUAL && vs->lattice != LB_LATTICE_D2_SQUARE_TRIPLE &&
+         vs->lattice != LB_LATTICE_D2_HEX_DUAL && vs->lattice != LB_LATTICE_D2_HEX_TRIPLE))
         return fail(LB_EINVAL, "lattice %d does not match dim %d", vs->lattice, dim);
+    if (vs->lattice == LB_LATTICE_D2_HEX_DUAL && vs->d0_frac != 0.0)
+        return fail(LB_EINVAL, "the hexagonal dual-level set has d0 = 0");
+    if (vs->lattice == LB_LATTICE_D2_HEX_TRIPLE && !(vs->d0_frac > 0.0 && vs->d0_frac < 1.0))
+        return fail(LB_EINVAL, "the hexagonal set with a rest group needs d0_frac in (0, 1); got %g", vs->d0_frac);
     if (dim == 1 && !(vs->d0_frac >= 0.0 && vs->d0_frac < 1.0))
         return fail(LB_EINVAL, "d0_frac must lie in [0, 1); got %g", vs->d0_frac);
     if (vs->lattice == LB_LATTICE_D2_SQUARE_DUAL && vs->d0_frac != 0.0)
@@ -67,7 +72,7 @@ int check_grid(const lb_grid* grid, int dim)
         grid->nx * grid->ny > (int64_t)1 << 36)
         return fail(LB_EINVAL, "grid too large");
     // the square-lattice kernels address a row's nodes with 32-bit byte offsets
-    if (dim == 2 && grid->nx > (int64_t)1 << 28) return fail(LB_EINVAL, "nx must be <= 2^28 on the square lattice");
+    if (dim == 2 && grid->nx > (int64_t)1 << 28) return fail(LB_EINVAL, "nx must be <= 2^28 on the 2-D lattices");
     if (!(grid->x_hi > grid->x_lo) || !isfinite(grid->x_lo) || !isfinite(grid->x_hi))
         return fail(LB_EINVAL, "need x_lo < x_hi");
     for (int b : {grid->bc_x, grid->bc_y})
@@ -81,18 +86,24 @@ int check_grid(const lb_grid* grid, int dim)
     return LB_OK;
 }
 
+bool is_hex(const lb_velset* vs)
+{
+    return vs->lattice == LB_LATTICE_D2_HEX_DUAL || vs->lattice == LB_LATTICE_D2_HEX_TRIPLE;
+}
+
 Consts make_consts(int dim, double gamma, const lb_velset* vs)
 {
     Consts k;
     k.Dg1 = (double)dim * (gamma - 1.0);
     k.phi_coef = 1.0 - ((double)dim / 2.0) * (gamma - 1.0);
-    const bool rest = dim == 1 || vs->lattice == LB_LATTICE_D2_SQUARE_TRIPLE;
+    k.hex = is_hex(vs) ? 1 : 0;
+    const bool rest = dim == 1 || vs->lattice == LB_LATTICE_D2_SQUARE_TRIPLE || vs->lattice == LB_LATTICE_D2_HEX_TRIPLE;
     k.delta0 = rest ? vs->d0_frac : 0.0;
     k.b0 = rest ? 1.0 : 0.0;
-    k.inv_b1 = dim == 1 ? 0.5 : 0.25;
+    k.inv_b1 = dim == 1 ? 0.5 : (k.hex ? 1.0 / 6.0 : 0.25);
     // square lattice with a rest level: d_0 = q (d_1 + d_2), q = b_1 delta0 / (1 - delta0),
     // so that a rest packet's mass follows from the staged level masses
-    k.rest_q = (dim == 2 && rest) ? 4.0 * vs->d0_frac / (1.0 - vs->d0_frac) : 0.0;
+    k.rest_q = (dim == 2 && rest && !k.hex) ? 4.0 * vs->d0_frac / (1.0 - vs->d0_frac) : 0.0;
     return k;
 }
 
@@ -203,6 +214,7 @@ struct lb_solver {
     int dim, nf, precision;
     double gamma, gamma2;  // gamma2: gas 2 (two gases), else gamma
     bool species;          // two gases: a species field rho chi after rho E
+    bool hex;              // the hexagonal lattice
     lb_velset vs;
     Consts k;
     int64_t nn;
@@ -243,6 +255,10 @@ static int create_solver(const lb_grid* grid, double gamma, double gamma2, bool 
         if ((rc = check_model(dim, gamma2, vs, precision)) != LB_OK) return rc;
     }
     if ((rc = check_grid(grid, dim)) != LB_OK) return rc;
+    const bool hex = is_hex(vs);
+    if (hex && species) return fail(LB_EINVAL, "the hexagonal lattice runs one gas");
+    if (hex && (grid->bc_x == LB_BC_REFLECTING || grid->bc_y == LB_BC_REFLECTING))
+        return fail(LB_EINVAL, "the hexagonal lattice has transmissive or periodic boundaries");
 
     lb_solver* s = new (std::nothrow) lb_solver();
     if (!s) return fail(LB_ENOMEM, "host allocation failed");
@@ -262,7 +278,8 @@ static int create_solver(const lb_grid* grid, double gamma, double gamma2, bool 
     s->nn = grid->nx * grid->ny;
     s->elem = precision == LB_FP64 ? 8 : 4;
     const size_t field_bytes = align256((size_t)s->nf * (size_t)s->nn * s->elem);
-    s->nblocks = dim == 1 ? step_blocks_1d(s->g) : march2d_max_blocks(s->g);
+    s->hex = hex;
+    s->nblocks = dim == 1 ? step_blocks_1d(s->g) : (hex ? hex_blocks(s->g) : march2d_max_blocks(s->g));
     s->off_buf[0] = 0;
     s->off_buf[1] = field_bytes;
     s->off_export = 2 * field_bytes;
@@ -309,7 +326,7 @@ int lb_bind(lb_solver* s, void* dev_ptr, size_t bytes, void* hip_stream)
         if ((e = hipEventCreate(&s->ev1)) != hipSuccess) return hip_fail(e, "hipEventCreate");
         s->events = true;
     }
-    if (s->dim == 2) {
+    if (s->dim == 2 && !s->hex) {
         int dev = 0, cus = 0;
         if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
         if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
@@ -403,6 +420,13 @@ static int queue_steps(lb_solver* s, int64_t n, hipEvent_t* ev = nullptr)
             else
                 e = launch_step1d<float>((const float*)buf_ptr(s, in), (float*)buf_ptr(s, out), s->g,
                                          s->k, ctl_ptr(s), partials_ptr(s), step, s->stream);
+        } else if (s->hex) {
+            if (s->precision == LB_FP64)
+                e = launch_hex<double>((const double*)buf_ptr(s, in), (double*)buf_ptr(s, out), s->g, s->k,
+                                       ctl_ptr(s), partials_ptr(s), step, s->stream);
+            else
+                e = launch_hex<float>((const float*)buf_ptr(s, in), (float*)buf_ptr(s, out), s->g, s->k,
+                                      ctl_ptr(s), partials_ptr(s), step, s->stream);
         } else {
             if (s->precision == LB_FP64)
                 e = launch_march2d<double>((const double*)buf_ptr(s, in), (double*)buf_ptr(s, out), s->g,
@@ -733,15 +757,18 @@ int lb_step_static(lb_solver* s, const void* Y_in, void* Y_out, void* hip_stream
     // scratch layout: control block, partial rows (one per block / tile), tile flags (two words per tile)
     MarchGeom m{};
     int64_t rows = 0;
+    const bool march = s->dim == 2 && !s->hex;  // the square lattice's passes (tile flags)
     if (s->dim == 1) {
         rows = step_blocks_1d(s->g);
+    } else if (s->hex) {
+        rows = hex_blocks(s->g);
     } else {
         const int pi = s->precision == LB_FP64 ? 0 : 1;
         m = march2d_geometry(s->g, d->cus, d->per_cu[pi], d->per_cu_lean[pi]);
         rows = m.blocks();
     }
     const size_t part_bytes = align256((size_t)rows * kPartialStride * 8);
-    const size_t need = kStaticCtlBytes + part_bytes + (s->dim == 2 ? align256((size_t)rows * 2 * 4) : 0);
+    const size_t need = kStaticCtlBytes + part_bytes + (march ? align256((size_t)rows * 2 * 4) : 0);
     if (need > kStaticScratchBytes)
         return fail(LB_EINVAL, "grid %lld x %lld needs %zu bytes of step scratch, more than the %zu of lb_step_static",
                     (long long)s->g.nx, (long long)s->g.ny, need, kStaticScratchBytes);
@@ -752,12 +779,16 @@ int lb_step_static(lb_solver* s, const void* Y_in, void* Y_out, void* hip_stream
     // the last call's control block is stale: a fill kernel resets it (no
     // memset, so the call can be captured into a graph)
     hipError_t e = launch_reset_ctl(ctl, st);
-    if (e == hipSuccess && s->dim == 2) e = launch_fill_i32(flags, 2 * rows, 0, st);  // the last call's flags
+    if (e == hipSuccess && march) e = launch_fill_i32(flags, 2 * rows, 0, st);  // the last call's flags
     if (e != hipSuccess) return hip_fail(e, "reset");
     if (s->dim == 1) {
         e = s->precision == LB_FP64
             ? launch_step1d<double>((const double*)Y_in, (double*)Y_out, s->g, s->k, ctl, partials, 1, st)
             : launch_step1d<float>((const float*)Y_in, (float*)Y_out, s->g, s->k, ctl, partials, 1, st);
+    } else if (s->hex) {
+        e = s->precision == LB_FP64
+            ? launch_hex<double>((const double*)Y_in, (double*)Y_out, s->g, s->k, ctl, partials, 1, st)
+            : launch_hex<float>((const float*)Y_in, (float*)Y_out, s->g, s->k, ctl, partials, 1, st);
     } else {
         e = s->precision == LB_FP64
             ? launch_march2d<double>((const double*)Y_in, (double*)Y_out, s->g, m, s->k, ctl, partials, flags, 1, st)

@@ -36,6 +36,7 @@ struct Consts {
     double g1m1;      // two gases: gamma_1 - 1 (gas 1, the species field's gas)
     double g2m1;      // two gases: gamma_2 - 1
     int species;      // 1: two gases, a species moment rho chi after rho E
+    int hex;          // 1: the hexagonal lattice (2-D)
 };
 
 template <typename T>
@@ -248,6 +249,71 @@ __device__ __forceinline__ Src2<T> make_src2(T m0t, T m1t, T m2t, T m3t, const C
     const double c1 = (double)L.c1;
     s.kk[0] = (T)(K + 0.5 * c1 * c1);
     s.kk[1] = (T)(K + 0.5 * (c1 + 1.0) * (c1 + 1.0));
+    return s;
+}
+
+template <typename T>
+struct SrcHex {   // one source node of the hexagonal lattice
+    int fa, fb;   // floor of the axial coordinates (a, b) of v = a e_1 + b e_2
+    int c1;
+    int tri;      // triangle of the cell that holds the end point of v: 0 has
+                  // the vertex (0, 0), 1 the vertex (1, 1) (both (1,0), (0,1))
+    T ra, rb;     // (a, b) - (f_a, f_b)
+    T vx, vy;     // Cartesian v (lattice units)
+    T K;          // |v|^2 / 2 + phi
+    T d0, d1, d2; // level weights (d0 = 0 without the rest group)
+    bool bad;
+};
+
+constexpr double kSqrt3 = 1.7320508075688772;  // sqrt(3), correctly rounded
+
+// Per-node primitives of a source of the hexagonal lattice (Fig. 1; eq. 15,
+// 24-26 with b_1 = b_2 = 6, Consts::inv_b1 = 1/6): as make_src2, and the end
+// point of v in axial coordinates, b = 2 v_y / sqrt(3), a = v_x - b / 2 (e_1 =
+// (1, 0), e_2 = (1/2, sqrt(3)/2)), whose cell (f_a, f_b) + [0, 1]^2 splits
+// into the triangles below and above the diagonal r_a + r_b = 1.  REST: the
+// set with a rest group, d_0 = delta0 rho.
+template <typename T, bool REST>
+__device__ __forceinline__ SrcHex<T> make_srchex(T m0t, T m1t, T m2t, T m3t, const Consts& k)
+{
+    const double m0 = m0t, m1 = m1t, m2 = m2t, m3 = m3t;
+    SrcHex<T> s;
+    s.bad = !(m0 > 0.0) || !finite_val(m0) || !finite_val(m1) || !finite_val(m2) || !finite_val(m3);
+    if (s.bad) {
+        s.fa = 0; s.fb = 0; s.c1 = 0; s.tri = 0;
+        s.ra = s.rb = s.vx = s.vy = s.K = s.d0 = s.d1 = s.d2 = (T)0;
+        return s;
+    }
+    constexpr bool FAST = sizeof(T) < 8;
+    double vx, vy, E, v2, a, b;
+    {
+#pragma clang fp contract(off)
+        vx = pdiv<FAST>(m1, m0);
+        vy = pdiv<FAST>(m2, m0);
+        E = pdiv<FAST>(m3, m0);
+        v2 = vx * vx + vy * vy;
+        b = pdiv<FAST>(2.0 * vy, kSqrt3);
+        a = vx - 0.5 * b;
+    }
+    const double d0 = REST ? k.delta0 * m0 : 0.0;
+    Levels<double> L = node_levels<double, FAST>(m0, v2, E, d0, k);
+    // floors clamped far beyond any admissible reach (the step reports those)
+    const double fa = fmin(fmax(floor(a), -32.0), 31.0), fb = fmin(fmax(floor(b), -32.0), 31.0);
+    s.fa = (int)fa;
+    s.fb = (int)fb;
+    const double ra = a - fa, rb = b - fb;
+    s.tri = ra + rb > 1.0 ? 1 : 0;
+    s.ra = (T)ra;
+    s.rb = (T)rb;
+    s.vx = (T)vx;
+    s.vy = (T)vy;
+    s.c1 = L.c1;
+    const double per = L.rest * k.inv_b1;
+    const double d2 = per * level_w(L.A, L.c1);
+    s.d2 = (T)d2;
+    s.d1 = (T)(per - d2);
+    s.d0 = (T)d0;
+    s.K = (T)(0.5 * v2 + k.phi_coef * L.e);
     return s;
 }
 

@@ -15,6 +15,7 @@ size_t align256(size_t n);
 int check_model(int dim, double gamma, const lb_velset* vs, int precision);
 int check_grid(const lb_grid* grid, int dim);
 Consts make_consts(int dim, double gamma, const lb_velset* vs);
+bool is_hex(const lb_velset* vs);  // one of the hexagonal sets
 
 // Riemann states in lattice units: lambda = lam_set if > 0, else cfl over
 // the largest |u| + sqrt(gamma p / rho) of the two states; side[i] holds

@@ -70,6 +70,13 @@ template <typename T>
 hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
                           StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream);
 
+// Hexagonal lattice (lb_hex.hip): one block per tile of 64 x 4 nodes (axial
+// i x j), hex_blocks(g) blocks and partial rows per step.
+template <typename T>
+hipError_t launch_hex(const T* Y, T* Yn, const Grid& g, const Consts& k, StepCtl* ctl, double* partials,
+                      long long step, hipStream_t stream);
+int64_t hex_blocks(const Grid& g);
+
 // Reduce nb per-block partial rows of one step into ctl (fixed order);
 // species2d: also the rho chi sums of the square lattice with two gases.
 hipError_t launch_finalize(double* partials, int64_t nb, StepCtl* ctl, long long step,

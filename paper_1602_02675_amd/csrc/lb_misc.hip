@@ -47,6 +47,14 @@ __global__ void lanes_kernel(const T* __restrict__ Y, int64_t nn, int dim, Const
         fx[q] = s.f;
         fy[q] = 0;
         c1[q] = s.c1;
+    } else if (k.hex) {
+        // hexagonal lattice: the floors of the axial coordinates of v
+        const T m0 = Y[q], m1 = Y[nn + q], m2 = Y[2 * nn + q], m3 = Y[3 * nn + q];
+        const SrcHex<T> s = k.b0 > 0.0 ? make_srchex<T, true>(m0, m1, m2, m3, k)
+                                       : make_srchex<T, false>(m0, m1, m2, m3, k);
+        fx[q] = s.fa;
+        fy[q] = s.fb;
+        c1[q] = s.c1;
     } else {
         // the same device function the step uses (with or without the rest group)
         const T m0 = Y[q], m1 = Y[nn + q], m2 = Y[2 * nn + q], m3 = Y[3 * nn + q];

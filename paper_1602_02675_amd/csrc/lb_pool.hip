@@ -419,6 +419,7 @@ static int create_pool(int32_t dim, double gamma, double gamma2, bool species, c
     int rc = check_model(dim, gamma, vs, precision);
     if (rc != LB_OK) return rc;
     if (species && (rc = check_model(dim, gamma2, vs, precision)) != LB_OK) return rc;
+    if (is_hex(vs)) return fail(LB_EINVAL, "pools run the 1-D and square lattices");
     if (max_slots < 1 || max_slots > (1 << 20)) return fail(LB_EINVAL, "max_slots must lie in [1, 2^20]");
     if (arena_bytes < 256) return fail(LB_EINVAL, "arena too small");
     lb_pool* p = new (std::nothrow) lb_pool();

@@ -23,6 +23,7 @@ LIB_PATH = os.environ.get("LBSD_LIBRARY") or os.path.join(_PKG, "liblbsd.so")
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ESTATE, LB_EREACH = 0, -1, -2, -3, -4, -5
 LB_BC_TRANSMISSIVE, LB_BC_PERIODIC, LB_BC_REFLECTING = 0, 1, 2
 LB_LATTICE_D1_TRIPLE, LB_LATTICE_D2_SQUARE_DUAL, LB_LATTICE_D2_SQUARE_TRIPLE = 1, 2, 3
+LB_LATTICE_D2_HEX_DUAL, LB_LATTICE_D2_HEX_TRIPLE = 4, 5
 LB_FP64, LB_FP32 = 0, 1
 LB_HALO = 5
 LB_POOL_FREE = -100
@@ -137,11 +138,15 @@ def _check(rc: int):
         raise LBError(rc, _lib.lb_last_error().decode())
 
 
-def _lattice(dim: int, d0_frac: float) -> int:
-    """The 1-D triple-level set, or on the square lattice the dual-level set
-    (d0_frac = 0) or the set with a rest level (d0_frac > 0)."""
+def _lattice(dim: int, d0_frac: float, lattice: str = "square") -> int:
+    """The 1-D triple-level set, or on the square (or hexagonal) lattice the
+    dual-level set (d0_frac = 0) or the set with a rest level (d0_frac > 0)."""
     if dim == 1:
         return LB_LATTICE_D1_TRIPLE
+    if lattice == "hex":
+        return LB_LATTICE_D2_HEX_TRIPLE if d0_frac > 0.0 else LB_LATTICE_D2_HEX_DUAL
+    if lattice != "square":
+        raise ValueError(f"lattice must be 'square' or 'hex', not {lattice!r}")
     return LB_LATTICE_D2_SQUARE_TRIPLE if d0_frac > 0.0 else LB_LATTICE_D2_SQUARE_DUAL
 
 
@@ -157,9 +162,11 @@ class Solver:
 
     def __init__(self, dim: int, nx: int, ny: int = 1, *, gamma: float = 1.4, d0_frac=None,
                  precision: str = "fp64", bc_x="transmissive", bc_y="periodic", x_lo: float = 0.0,
-                 x_hi: float = 1.0, device=None, stream=None, gamma2=None):
+                 x_hi: float = 1.0, device=None, stream=None, gamma2=None, lattice: str = "square"):
         """gamma2: a second gas (lb_create_two_gas): gamma is gas 1's, and
-        the state gains the species field rho chi."""
+        the state gains the species field rho chi.  lattice (dim 2): "square"
+        or "hex" (the hexagonal lattice, nodes at i e_1 + j e_2, stored
+        [f][j][i], Cartesian momenta)."""
         import torch
 
         if d0_frac is None:
@@ -169,7 +176,8 @@ class Solver:
         self.nf = dim + 2 + (1 if self.species else 0)
         self.precision = precision
         g = lb_grid(dim, self.nx, self.ny, x_lo, x_hi, _bc(bc_x), _bc(bc_y))
-        vs = lb_velset(_lattice(dim, d0_frac), d0_frac)
+        self.lattice = lattice if dim == 2 else "line"
+        vs = lb_velset(_lattice(dim, d0_frac, lattice), d0_frac)
         prec = {"fp64": LB_FP64, "fp32": LB_FP32}[precision]
         h = ctypes.c_void_p()
         if self.species:
@@ -317,7 +325,8 @@ class Pool:
         self.dim, self.nf, self.precision = dim, dim + 2 + (1 if self.species else 0), precision
         self.max_slots = int(max_slots)
         self.arena_bytes = int(arena_bytes)
-        vs = lb_velset(_lattice(dim, d0_frac), d0_frac)
+        self.lattice = lattice if dim == 2 else "line"
+        vs = lb_velset(_lattice(dim, d0_frac, lattice), d0_frac)
         prec = {"fp64": LB_FP64, "fp32": LB_FP32}[precision]
         h = ctypes.c_void_p()
         if self.species:
