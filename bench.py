@@ -17,6 +17,8 @@ gather kernel plus its totals reduction.  Alongside, in the same JSON line:
   the kernel instances that handle walls);
 * nonplanar: a seeded four-state 2-D Riemann problem (both velocity
   components of both signs) on 2048 x 2048 nodes, FP64;
+* hex: the headline tube on the hexagonal lattice (4096 x 4096 nodes, state
+  along the axial index i), FP64, 100 steps;
 * rest_level: the headline tube on the square lattice with a rest level
   (d_0 = rho / 2), FP64, 100 steps;
 * tube1d / tube1d_fp32 / two_gas: one 1-D Sod tube of 2^24 nodes, 200
@@ -125,6 +127,28 @@ def run_nonplanar(steps: int = 200, n: int = 2048, seed: int = 1):
     s.close()
     return dict(value=round(n * n * steps / (total_ms * 1e-3) / 1e6, 1), unit="MLUPS", nx=n, ny=n, seed=seed,
                 steps=steps, ms_per_step=round(total_ms / steps, 5), precision="fp64")
+
+
+def run_hex(steps: int = 100, precision: str = "fp64"):
+    """The headline tube on the hexagonal lattice (nodes at i e_1 + j e_2;
+    the state depends on the axial index i, transmissive along i, periodic
+    along j), 4096 x 4096."""
+    import torch
+    from paper_1602_02675_amd.lbsd import Solver
+
+    left, right, x_d, lam = workload()
+    s = Solver(2, NX, NY, precision=precision, bc_x="transmissive", bc_y="periodic", lattice="hex")
+    s.init_riemann(x_d, left, right, lam=lam)
+    s.step(5)
+    s.sync()
+    torch.cuda.synchronize()
+    kernel_ms, total_ms = s.step_profiled(steps)
+    s.close()
+    nodes = NX * NY
+    return dict(value=round(nodes * steps / (total_ms * 1e-3) / 1e6, 1), unit="MLUPS", nx=NX, ny=NY, steps=steps,
+                ms_per_step=round(total_ms / steps, 5),
+                achieved_GBs=round(BYTES_PER_NODE[precision] * nodes / (kernel_ms * 1e-3 / steps) / 1e9, 1),
+                precision=precision, lattice="hexagonal")
 
 
 def run_tube1d(gamma2=None, n: int = 1 << 24, steps: int = 200, precision: str = "fp64"):
@@ -464,6 +488,7 @@ def main():
                         "steps": 500, "ms_per_step": round(rw["total_ms"] / 500, 5),
                         "bc": "reflecting x / periodic y", "precision": "fp64"}
         out["nonplanar"] = run_nonplanar()
+        out["hex"] = run_hex()
         rr = run_gpu("fp64", 100, 5, d0_frac=0.5)
         out["rest_level"] = {"value": round(nodes * 100 / (rr["total_ms"] / 1e3) / 1e6, 1), "unit": "MLUPS",
                              "steps": 100, "ms_per_step": round(rr["total_ms"] / 100, 5), "d0_frac": 0.5,

@@ -12,19 +12,19 @@
 // One block computes a tile of kHX x kHY destination nodes.  It stages the
 // per-node records (make_srchex) of the tile and a halo of H = kHalo nodes
 // along both axial directions in LDS, then each thread sums, for its
-// destination, every packet that lands there: it walks the packet classes
-// (floor of the axial velocity, triangle vertex, lane) the block's sources can
-// have, and takes a class from the one source that would emit it, if that
-// source has the class's floor, speed and triangle.  The order of the sum is
-// fixed (deterministic results), and a window of uniform floors and speeds
-// costs one candidate per lane and vertex.
+// destination, every packet that lands there: it walks the lanes and, per
+// lane, the packet classes (floor of the axial velocity, triangle vertex) the
+// block's sources can have, and takes a class from the one source that would
+// emit it, if that source has the class's floor, speed and triangle.  The
+// order of the sum is fixed (deterministic results), and a window of uniform
+// floors and speeds costs four candidates per lane.
 #include "lb_kernels.hpp"
 
 namespace lbsd {
 namespace {
 
-constexpr int kHX = 64, kHY = 4, kHH = kHalo;  // tile (axial i x j) and halo
-constexpr int kHTPB = kHX * kHY;               // one destination per thread
+constexpr int kHX = 64, kHY = 16, kHH = kHalo;  // tile (axial i x j) and halo
+constexpr int kHTPB = kHX * kHY;                // one destination per thread
 constexpr int kSW = kHX + 2 * kHH, kSH = kHY + 2 * kHH, kSN = kSW * kSH;  // staged sources
 constexpr int kHNW = kHTPB / 64;
 
@@ -42,11 +42,19 @@ __device__ __forceinline__ int hk_fa(int p) { return (p & 127) - 64; }
 __device__ __forceinline__ int hk_fb(int p) { return ((p >> 7) & 127) - 64; }
 __device__ __forceinline__ int hk_c1(int p) { return (p >> 14) & 1023; }
 constexpr int kHkTri = 1 << 24, kHkBad = 1 << 25;
+constexpr int kHkC1 = 1023 << 14;
 
+__device__ __forceinline__ double hfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float hfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Staged records.  w[t]: barycentric weight of vertex t of the source's
+// triangle: t = 0 the vertex (0,0) or (1,1) (by the triangle), t = 1 (1,0),
+// t = 2 (0,1).
 template <typename T, bool REST>
 struct HexStage {
     int pk[kSN];
-    T vx[kSN], vy[kSN], K[kSN], d1[kSN], d2[kSN], ra[kSN], rb[kSN];
+    T vx[kSN], vy[kSN], K[kSN], d1[kSN], d2[kSN];
+    T w[3][kSN];
     T d0[REST ? kSN : 1];
 };
 
@@ -68,7 +76,7 @@ hex_step_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k, S
     // stage the records of the tile and its halo (boundaries map the halo)
     int falo = 1 << 20, fahi = -(1 << 20), fblo = 1 << 20, fbhi = -(1 << 20), clo = 1 << 20, chi = -1;
     for (int q = tid; q < kSN; q += kHTPB) {
-        const int li = q % kSW, lj = q / kSW;
+        const int lj = q / kSW, li = q - lj * kSW;
         const int64_t gi = X0 - kHH + li, gj = Y0 - kHH + lj;
         const int64_t si = g.bc_x == kBcPeriodic ? wrap_near(gi, nx) : clamp_idx(gi, nx);
         const int64_t sj = g.bc_y == kBcPeriodic ? wrap_near(gj, ny) : clamp_idx(gj, ny);
@@ -81,8 +89,13 @@ hex_step_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k, S
         st.K[q] = s.K;
         st.d1[q] = s.d1;
         st.d2[q] = s.d2;
-        st.ra[q] = s.ra;
-        st.rb[q] = s.rb;
+        {
+#pragma clang fp contract(off)
+            const T ra = s.ra, rb = s.rb;
+            st.w[0][q] = s.tri ? (ra + rb) - (T)1 : ((T)1 - ra) - rb;
+            st.w[1][q] = s.tri ? (T)1 - rb : ra;
+            st.w[2][q] = s.tri ? (T)1 - ra : rb;
+        }
         if constexpr (REST) st.d0[q] = s.d0;
         if (!s.bad) {
             falo = min(falo, s.fa); fahi = max(fahi, s.fa);
@@ -98,7 +111,6 @@ hex_step_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k, S
         s_rng[wid][3] = fbhi; s_rng[wid][4] = clo; s_rng[wid][5] = chi;
     }
     __syncthreads();
-#pragma unroll
     for (int w = 0; w < kHNW; ++w) {
         falo = min(falo, s_rng[w][0]); fahi = max(fahi, s_rng[w][1]);
         fblo = min(fblo, s_rng[w][2]); fbhi = max(fbhi, s_rng[w][3]);
@@ -110,66 +122,66 @@ hex_step_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k, S
     fblo = max(fblo, -kHH - 1); fbhi = min(fbhi, kHH);
     chi = min(chi, kHH);
 
-    // gather the packets that land on this thread's destination
+    // Gather the packets that land on this thread's destination, lane by
+    // lane: for each lane (c', u), sum over its sources m, m v_x, m v_y, m K,
+    // then add the lane's packets at once: m (v + c' u) and m (K + c' u . v
+    // + c'^2 / 2) (eq. 14, 21).  Within a lane the candidates are taken by
+    // floor of the axial velocity and by triangle vertex; the source of a
+    // candidate emits it if it has that floor, speed and triangle.
     const int li = tid % kHX, lj = tid / kHX;
     const int cidx = (lj + kHH) * kSW + (li + kHH);  // staged index of the destination node
     double R = 0.0, PX = 0.0, PY = 0.0, E = 0.0;
-    {
-#pragma clang fp contract(off)
-        // one packet of mass m of the source at staged index s on lane (c, u)
-        auto add = [&](int s, T m, T c, T ux, T uy) {
-            const T vx = st.vx[s], vy = st.vy[s];
-            const T xx = vx + c * ux, xy = vy + c * uy;
-            const T z = st.K[s] + c * (vx * ux + vy * uy) + (T)0.5 * c * c;
-            R += (double)m;
-            PX += (double)(m * xx);
-            PY += (double)(m * xy);
-            E += (double)(m * z);
-        };
-        // barycentric weight of vertex kc ((0,0), (1,0), (0,1), (1,1)) of the source at s
-        auto alpha = [&](int s, int kc, bool tri) -> T {
-            const T ra = st.ra[s], rb = st.rb[s];
-            if (kc == 0) return ((T)1 - ra) - rb;
-            if (kc == 3) return (ra + rb) - (T)1;
-            if (kc == 1) return tri ? (T)1 - rb : ra;
-            return tri ? (T)1 - ra : rb;
-        };
+    // sources of vertex kc at displacement (dx, dy) with key `want` (under
+    // `mask`), weight of that vertex times the level weight dl
+    auto take = [&](int dx, int dy, int mask, int want, int t, const T* dl, T& s0, T& s1, T& s2, T& s3) {
+        if (dx < -kHH || dx > kHH || dy < -kHH || dy > kHH) return;
+        const int s = cidx - dy * kSW - dx;
+        if ((st.pk[s] & mask) != want) return;
+        const T m = st.w[t][s] * dl[s];
+        s0 += m;
+        s1 = hfma(m, st.vx[s], s1);
+        s2 = hfma(m, st.vy[s], s2);
+        s3 = hfma(m, st.K[s], s3);
+    };
+    // the candidates of one lane (speed c, axial step (da, db)); lev: level
+    // of the speed (-1: rest group)
+    auto lane_sum = [&](int lev, int c, int da, int db, T& s0, T& s1, T& s2, T& s3) {
+        const T* dl = lev < 0 ? st.d0 : (lev == 0 ? st.d1 : st.d2);
+        const int cmask = lev < 0 ? 0 : kHkC1;  // the rest group moves at any c'_1
         for (int fa = falo; fa <= fahi; ++fa) {
             for (int fb = fblo; fb <= fbhi; ++fb) {
+                const int base = hkey(fa, fb, lev < 0 ? 0 : c - lev) & (0x3FFF | cmask);
+                const int dx = fa + c * da, dy = fb + c * db;
+                // vertex (0,0) of triangle 0, (1,1) of triangle 1, (1,0), (0,1) of either
+                take(dx, dy, 0x3FFF | cmask | kHkTri | kHkBad, base, 0, dl, s0, s1, s2, s3);
+                take(dx + 1, dy + 1, 0x3FFF | cmask | kHkTri | kHkBad, base | kHkTri, 0, dl, s0, s1, s2, s3);
+                take(dx + 1, dy, 0x3FFF | cmask | kHkBad, base, 1, dl, s0, s1, s2, s3);
+                take(dx, dy + 1, 0x3FFF | cmask | kHkBad, base, 2, dl, s0, s1, s2, s3);
+            }
+        }
+    };
+    if constexpr (REST) {
+        T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        lane_sum(-1, 0, 0, 0, s0, s1, s2, s3);
+        R += (double)s0;
+        PX += (double)s1;
+        PY += (double)s2;
+        E += (double)s3;
+    }
 #pragma unroll
-                for (int kc = 0; kc < 4; ++kc) {
-                    const int ax = fa + (kc & 1), ay = fb + (kc >> 1);  // displacement of the vertex
-                    // the key a source must have (floors, and the triangle that holds vertex kc)
-                    const int mask = kc == 0 || kc == 3 ? (0xFFFFFF | kHkTri | kHkBad) : (0xFFFFFF | kHkBad);
-                    const int tri_bits = kc == 3 ? kHkTri : 0;
-                    if constexpr (REST) {
-                        if (ax >= -kHH && ax <= kHH && ay >= -kHH && ay <= kHH) {
-                            const int s = cidx - ay * kSW - ax;
-                            const int p = st.pk[s];
-                            if ((p & mask & ~0xFFC000) == (hkey(fa, fb, 0) | tri_bits)) {
-                                add(s, alpha(s, kc, (p & kHkTri) != 0) * st.d0[s], (T)0, (T)0, (T)0);
-                            }
-                        }
-                    }
+    for (int lev = 0; lev < 2; ++lev) {
+        for (int c = clo + lev; c <= chi + lev; ++c) {
+            if (c > kHH) break;
+            const T cc = (T)c, hc2 = (T)0.5 * cc * cc;
 #pragma unroll
-                    for (int lev = 0; lev < 2; ++lev) {
-                        for (int c = clo + lev; c <= chi + lev; ++c) {
-                            if (c > kHH) break;
-                            const int want = hkey(fa, fb, c - lev) | tri_bits;
-                            const T cc = (T)c;
-#pragma unroll
-                            for (int d = 0; d < 6; ++d) {
-                                const int dx = ax + c * kDA[d], dy = ay + c * kDB[d];
-                                if (dx < -kHH || dx > kHH || dy < -kHH || dy > kHH) continue;
-                                const int s = cidx - dy * kSW - dx;
-                                const int p = st.pk[s];
-                                if ((p & mask) != want) continue;
-                                const T m = alpha(s, kc, (p & kHkTri) != 0) * (lev ? st.d2[s] : st.d1[s]);
-                                add(s, m, cc, (T)kUX[d], (T)kUY[d]);
-                            }
-                        }
-                    }
-                }
+            for (int d = 0; d < 6; ++d) {
+                T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+                lane_sum(lev, c, kDA[d], kDB[d], s0, s1, s2, s3);
+                const T cux = cc * (T)kUX[d], cuy = cc * (T)kUY[d];
+                R += (double)s0;
+                PX += (double)hfma(cux, s0, s1);
+                PY += (double)hfma(cuy, s0, s2);
+                E += (double)(hfma(hc2, s0, s3) + hfma(cux, s1, cuy * s2));
             }
         }
     }
