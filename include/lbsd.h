@@ -127,9 +127,13 @@ size_t lb_state_bytes(const lb_solver* s);
  * stream (hipStream_t, NULL = default stream) all later work is queued on. */
 int lb_bind(lb_solver* s, void* dev_ptr, size_t bytes, void* hip_stream);
 
-/* lambda = dt/dx used by the next lb_init_* call.  lb_set_lambda fixes it
- * (> 0); lb_set_cfl (> 0, default 1) makes lb_init_riemann take
- * lambda = cfl / max(|u| + sqrt(gamma p / rho)) over the two states. */
+/* lambda = dt/dx used by the next lb_init_* call: the kernel works in lattice
+ * units (dx = dt = 1, Sec. III), so velocities scale by lambda and energies per
+ * unit mass by lambda^2.  The paper states no time step; lb_set_lambda fixes
+ * it (> 0); lb_set_cfl (> 0, default 1) makes lb_init_riemann take
+ * lambda = cfl / max(|u| + sqrt(gamma p / rho)) over the two states, the
+ * reading that a CFL number of 1 on the initial states sets dt (the fastest
+ * initial signal then moves at most one node per step). */
 int lb_set_lambda(lb_solver* s, double lambda);
 int lb_set_cfl(lb_solver* s, double cfl);
 
@@ -145,10 +149,14 @@ int lb_init_riemann(lb_solver* s, double x_diaphragm, const lb_prim* left, const
  * non-finite value, or (two gases) rho chi outside [0, rho]. */
 int lb_init_moments(lb_solver* s, const double* host_Y, double lambda);
 
-/* Queue n >= 0 steps (eq. 10 / eq. 30 with tau = 1, Sec. V.A).  Each step is
- * one kernel that also forms the interior conservation totals and checks the
- * reach.  If a step fails, it and every later queued step leave the state at
- * the last good step; the error is reported at the next synchronising call. */
+/* Queue n >= 0 steps (eq. 10 / eq. 30 with tau = 1, Sec. V.A).  Each step
+ * queues its step launches on the bound stream -- one kernel in 1-D and on the
+ * hexagonal lattice; on the square lattice a first pass over the tiles, and
+ * two further passes that return at once unless the earlier pass left tiles
+ * to them -- and then a small kernel that reduces the per-tile partial
+ * results into the interior conservation totals and the largest reach.  If a
+ * step fails, it and every later queued step leave the state at the last good
+ * step; the error is reported at the next synchronising call. */
 int lb_step(lb_solver* s, int64_t n);
 
 /* As lb_step, bracketed by HIP events on the bound stream; waits and writes
@@ -163,15 +171,21 @@ int lb_step_profiled(lb_solver* s, int64_t n, float* kernel_ms, float* total_ms)
 /* Wait for queued work; returns LB_EREACH / LB_ESTATE if a step failed. */
 int lb_sync(lb_solver* s);
 
-/* Current moments as FP64 SoA [nf][ny][nx] in physical units, into `out`
- * (host memory, or device memory when out_on_device != 0).  Synchronises.
+/* Current moments (eq. 6-7: rho, rho v and rho E, the sums of eq. 22 over
+ * the packets that landed on each node) as FP64 SoA [nf][ny][nx] in physical
+ * units, into `out` (host memory, or device memory when out_on_device != 0);
+ * the primitives of Sec. V.D follow from them (u = rho u / rho, e = E - u^2/2,
+ * p by eq. 27).  Synchronises.
  * After a failed step (LB_EREACH, LB_ESTATE) it still writes `out`: the
  * state of the last good step, which the failed step left intact, and
  * returns that step's error. */
 int lb_moments(lb_solver* s, double* out, int32_t out_on_device);
 
 /* Interior sums of rho, rho u, rho v (0 in 1-D), rho E of the current state
- * in physical units per node (multiply by dx for integrals).  The step
+ * in physical units per node (multiply by dx for integrals).  Each node's
+ * packets carry its mass, momentum and energy exactly (eq. 22), so these are
+ * conserved to rounding while nothing crosses a boundary (periodic, walls),
+ * and change only by the flux through transmissive ends (Sec. V.B).  The step
  * kernels form them in FP64 with a fixed reduction order.  Synchronises. */
 int lb_totals(lb_solver* s, double out[4]);
 
