@@ -31,10 +31,11 @@ gather kernel plus its totals reduction.  Alongside, in the same JSON line:
   HIP-graph steps, 250 steps, FP32 and FP64 (and the FP32 density error
   against FP64);
 * serve: square-lattice requests (sides log-uniform in [64, 2048], steps in
-  [100, 5000], seeded states) arriving as a Poisson process at 0.8 x the
-  measured capacity, continuously batched on an FP32 pool: p50 / p99
-  latency and aggregate node-updates/s; and the same requests all queued at
-  once (the served throughput at saturation);
+  [100, 5000], seeded states) arriving as a Poisson process at 0.5, 0.8 and
+  1.0 x the measured capacity, continuously batched on an FP32 pool: p50 /
+  p99 latency and served node-updates/s at each load (the headline figures
+  at 0.8); and the same requests all queued at once (the served throughput
+  at saturation);
 * cpu_baseline: the FP64 oracle on a bounded sample, one host thread (host
   CPU model and usable cores stated); cpu_baseline_batch: the oracle over the
   512 independent tubes of the batch workload on all usable cores (at most
@@ -364,7 +365,8 @@ def run_batch2d(precision: str, n: int = 48, steps: int = 250, seed: int = 5, ke
 
 
 def run_serve(n_requests: int = 100, seed: int = 0):
-    """Poisson arrivals at 0.8 x measured capacity on an FP32 square-lattice pool."""
+    """Poisson arrivals at 0.5, 0.8 and 1.0 x measured capacity on an FP32
+    square-lattice pool (the headline figures at 0.8)."""
     from paper_1602_02675_amd import inputs, serve
     from paper_1602_02675_amd.lbsd import Pool
 
@@ -373,18 +375,24 @@ def run_serve(n_requests: int = 100, seed: int = 0):
     pool.use_graph(25)
     cap_nups, shape = serve.calibrate(pool, probe)
     mean_work = sum(r["side"] ** 2 * r["steps"] for r in probe) / len(probe)
-    rate = 0.8 * cap_nups / mean_work
-    reqs = inputs.serve_requests(seed, n_requests, rate_per_s=rate)
-    res = serve.run(pool, reqs, tick=25)
+    loads = {}
+    for load in (0.5, 0.8, 1.0):
+        rate = load * cap_nups / mean_work
+        reqs = inputs.serve_requests(seed, n_requests, rate_per_s=rate)
+        res = serve.run(pool, reqs, tick=25)
+        offered = sum(r["side"] ** 2 * r["steps"] for r in reqs) / max(reqs[-1]["arrival"], 1e-9)
+        loads[str(load)] = dict(rate_per_s=round(rate, 3), offered_MLUPS=round(offered / 1e6, 1),
+                                served_MLUPS=round(res["nups"] / 1e6, 1), p50_latency_s=round(res["p50_s"], 4),
+                                p99_latency_s=round(res["p99_s"], 4), makespan_s=round(res["makespan_s"], 3))
     # the same requests all queued at once: the served throughput at saturation
     sat = serve.run(pool, inputs.serve_requests(seed, n_requests, rate_per_s=1e9), tick=25)
     pool.close()
-    return dict(value=round(res["nups"] / 1e6, 1), unit="MLUPS", requests=n_requests,
-                rate_per_s=round(rate, 3), capacity_MLUPS=round(cap_nups / 1e6, 1),
-                p50_latency_s=round(res["p50_s"], 4), p99_latency_s=round(res["p99_s"], 4),
-                makespan_s=round(res["makespan_s"], 3), tile_shape=shape,
-                saturated_MLUPS=round(sat["nups"] / 1e6, 1), saturated_makespan_s=round(sat["makespan_s"], 3),
-                precision="fp32")
+    at = loads["0.8"]
+    return dict(value=at["served_MLUPS"], unit="MLUPS", requests=n_requests, load=0.8,
+                rate_per_s=at["rate_per_s"], capacity_MLUPS=round(cap_nups / 1e6, 1),
+                p50_latency_s=at["p50_latency_s"], p99_latency_s=at["p99_latency_s"], makespan_s=at["makespan_s"],
+                loads=loads, tile_shape=shape, saturated_MLUPS=round(sat["nups"] / 1e6, 1),
+                saturated_makespan_s=round(sat["makespan_s"], 3), precision="fp32")
 
 
 def traffic_per_launch():

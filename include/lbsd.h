@@ -239,17 +239,22 @@ int lb_step_static(lb_solver* s, const void* Y_in, void* Y_out, void* hip_stream
  * pass that redoes the tiles whose packets reached past the short FIFO; 1-D:
  * one block per tile) and a per-slot reduction kernel; every live, unfinished
  * slot advances by one step (eq. 10 / 30 with tau = 1, as lb_step).
- * Admissions and releases rewrite the tables between launches; on the square
- * lattice the launch shape, and so a captured HIP graph, stays valid while
- * problems come and go (1-D re-captures when the number of tiles changes).
+ * Admissions and releases rewrite the tables between launches, in stream
+ * order: steps queued before them run with the old tables, steps queued
+ * after with the new ones, and the host does not wait for the device (so a
+ * serving loop can keep the next steps queued while it admits and releases).
+ * On the square lattice the launch shape, and so a captured HIP graph, stays
+ * valid while problems come and go (1-D re-captures when the number of tiles
+ * changes).
  * A slot's results do not depend on what else is in the pool, the tile shape
  * or graph use: they are bit-identical to an lb_solver run of the same
  * problem.
  *
  * Slot status (lb_pool_poll): 0 running, 1 reached its step target, or
  * LB_EREACH / LB_ESTATE if one of its steps failed (it then stops at its last
- * good step; other slots go on).  Calls that synchronise: poll, moments,
- * totals, release, set_shape, autotune, the admit calls. */
+ * good step; other slots go on).  Calls that synchronise: poll, status,
+ * moments, totals, set_shape, autotune, admit_moments; snapshot_read waits
+ * only for its snapshot. */
 typedef struct lb_pool lb_pool; /* opaque */
 
 /* max_slots in [1, 2^20]; arena_bytes: device memory for the slots' moment
@@ -275,7 +280,9 @@ int lb_pool_admit_riemann(lb_pool* p, const lb_grid* grid, double lambda, double
 /* Admit a general state (as lb_init_moments). */
 int lb_pool_admit_moments(lb_pool* p, const lb_grid* grid, const double* host_Y, double lambda,
                           int64_t steps, int32_t* slot);
-/* Free a slot and its arena space (waits for queued steps first). */
+/* Free a slot and its arena space.  Does not wait: steps queued before the
+ * release still advance the slot (into its own memory), and anything that
+ * reuses that memory is queued after them. */
 int lb_pool_release(lb_pool* p, int32_t slot);
 
 /* Queue n >= 0 pool steps (async; graph launches when lb_pool_use_graph is on). */
@@ -289,6 +296,17 @@ int lb_pool_poll(lb_pool* p, int32_t slot, int64_t* steps_done, int32_t* status)
  * slot reports 0 steps and status LB_POOL_FREE. */
 #define LB_POOL_FREE (-100)
 int lb_pool_status(lb_pool* p, int64_t* steps_done, int32_t* status);
+/* Progress snapshots for serving loops that keep steps queued: snapshot
+ * queues, behind the work queued so far, a copy of every slot's progress
+ * into host buffer `buf` (0 or 1) and returns at once; snapshot_read waits
+ * for that copy only and gives, per slot (arrays of max_slots entries, totals
+ * [max_slots][4] or NULL), steps done, the status of lb_pool_poll, and the
+ * totals of lb_pool_totals (NaN before a slot's first step).  A slot that was
+ * free when the snapshot was queued, or was released and admitted again
+ * since, reports LB_POOL_FREE.  Queuing into a buffer whose previous snapshot
+ * is still in flight waits for it. */
+int lb_pool_snapshot(lb_pool* p, int32_t buf);
+int lb_pool_snapshot_read(lb_pool* p, int32_t buf, int64_t* steps_done, int32_t* status, double* totals);
 /* As lb_moments / lb_totals for one slot (lb_pool_totals: LB_EINVAL before its first step).
  * A slot whose step failed exports its last good state and returns LB_OK;
  * lb_pool_poll reports the failure. */

@@ -29,6 +29,26 @@ struct SlotInfo {
     int64_t target = 0;
 };
 
+// Pinned staging of one table upload; `ev` marks when the copies out of it
+// have run.
+struct Stage {
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+
+// One progress snapshot (lb_pool_snapshot): the slot states copied behind the
+// queued work into pinned memory, and the host's view of the slots when it
+// was queued (admission count, target, lambda).
+struct Snap {
+    PoolState* host = nullptr;
+    hipEvent_t ev = nullptr;
+    bool queued = false;
+    std::vector<int64_t> gen, target;
+    std::vector<double> lambda;
+};
+
 }  // namespace
 
 struct lb_pool {
@@ -62,6 +82,12 @@ struct lb_pool {
     bool graph_ready = false;
     hipGraphExec_t graph_exec = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // stream-ordered table uploads (two stagings used in turn) and snapshots
+    Stage stage[2];
+    int stage_next = 0;
+    Snap snap[2];
+    std::vector<int64_t> gen;  // admissions per slot
+    bool dirty = false;        // the tables changed since the last upload (sent before the next step)
 };
 
 namespace {
@@ -146,8 +172,28 @@ void drop_graph(lb_pool* p)
     p->graph_ready = false;
 }
 
+// Per-tile word from the device's slot states: the set holding the slot's
+// moments, and whether the slot still steps.
+__global__ void pool_tile_words_kernel(PoolView v, int32_t nt)
+{
+    const int32_t t = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= nt) return;
+    const int32_t i = v.tiles[t].prob;
+    const PoolState& q = v.state[i];
+    v.tstate[t] = (int32_t)(q.done & 1) | (q.err_step == 0 && q.done < v.probs[i].target ? kTileLive : 0);
+}
+
+// A fresh state record for a slot being admitted.
+__global__ void pool_reset_state_kernel(PoolState* st)
+{
+    if (threadIdx.x == 0) *st = PoolState{};
+}
+
 // Rebuild the tile table of the live slots (slot order, then rows, then
-// columns) and upload it with the slot table; synchronous.
+// columns) and queue its upload with the slot table on the pool's stream:
+// the kernels of steps queued earlier still see the old tables, those queued
+// later the new ones.  The host returns at once (it waits only when both
+// pinned stagings still have copies in flight).
 int upload_tables(lb_pool* p)
 {
     p->tiles.clear();
@@ -186,44 +232,48 @@ int upload_tables(lb_pool* p)
         p->nblocks_lean = nb_lean;
         p->walls = walls;
     }
-    std::vector<int32_t> zeros((size_t)std::max<int32_t>(nt, 5), 0);
-    // tile words from the slots' device states
-    std::vector<PoolState> st((size_t)p->max_slots);
-    hipError_t e = hipStreamSynchronize(p->stream);
-    if (e != hipSuccess) return hip_fail(e, "sync");
-    if ((e = hipMemcpy(st.data(), p->base + p->off_state, st.size() * sizeof(PoolState), hipMemcpyDeviceToHost)) !=
-        hipSuccess)
-        return hip_fail(e, "read slot states");
-    std::vector<int32_t> words((size_t)std::max<int32_t>(nt, 1), 0);
-    for (int32_t t = 0; t < nt; ++t) {
-        const int i = p->tiles[(size_t)t].prob;
-        const PoolState& q = st[(size_t)i];
-        words[(size_t)t] = (int32_t)(q.done & 1) |
-                           (q.err_step == 0 && q.done < p->probs[(size_t)i].target ? kTileLive : 0);
+    // probs, tile count and tiles through a pinned staging
+    const size_t pb = p->probs.size() * sizeof(PoolProb), tb = (size_t)nt * sizeof(PoolTile);
+    const size_t at_nt = align256(pb), at_tiles = at_nt + 256, need = at_tiles + tb;
+    Stage& sg = p->stage[p->stage_next];
+    p->stage_next ^= 1;
+    hipError_t e;
+    if (sg.pending) {
+        if ((e = hipEventSynchronize(sg.ev)) != hipSuccess) return hip_fail(e, "staging wait");
+        sg.pending = false;
     }
-    if ((e = hipMemcpyAsync(p->base + p->off_probs, p->probs.data(), p->probs.size() * sizeof(PoolProb),
-                            hipMemcpyHostToDevice, p->stream)) != hipSuccess)
+    if (sg.cap < need) {
+        if (sg.host) (void)hipHostFree(sg.host);
+        sg.host = nullptr;
+        sg.cap = 0;
+        if ((e = hipHostMalloc(&sg.host, need, hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(e, "pinned staging");
+        sg.cap = need;
+    }
+    char* h = (char*)sg.host;
+    memcpy(h, p->probs.data(), pb);
+    memcpy(h + at_nt, &nt, sizeof nt);
+    if (nt > 0) memcpy(h + at_tiles, p->tiles.data(), tb);
+    if ((e = hipMemcpyAsync(p->base + p->off_probs, h, pb, hipMemcpyHostToDevice, p->stream)) != hipSuccess)
         return hip_fail(e, "upload slots");
-    if (nt > 0 && (e = hipMemcpyAsync(p->base + p->off_tiles, p->tiles.data(), (size_t)nt * sizeof(PoolTile),
-                                      hipMemcpyHostToDevice, p->stream)) != hipSuccess)
+    if (nt > 0 && (e = hipMemcpyAsync(p->base + p->off_tiles, h + at_tiles, tb, hipMemcpyHostToDevice,
+                                      p->stream)) != hipSuccess)
         return hip_fail(e, "upload tiles");
-    if ((e = hipMemcpyAsync(p->base + p->off_ntiles, &nt, sizeof nt, hipMemcpyHostToDevice, p->stream)) !=
+    if ((e = hipMemcpyAsync(p->base + p->off_ntiles, h + at_nt, sizeof nt, hipMemcpyHostToDevice, p->stream)) !=
         hipSuccess)
         return hip_fail(e, "upload tile count");
-    if ((e = hipMemcpyAsync(p->base + p->off_ntiles + 64, zeros.data(), 5 * sizeof(int32_t),
-                            hipMemcpyHostToDevice, p->stream)) != hipSuccess)
-        return hip_fail(e, "clear claim counters");
-    if (nt > 0 && (e = hipMemcpyAsync(p->base + p->off_flags, zeros.data(), (size_t)nt * 4,
-                                      hipMemcpyHostToDevice, p->stream)) != hipSuccess)
-        return hip_fail(e, "clear flags");
-    if (nt > 0 && p->dim == 2 &&
-        (e = hipMemcpyAsync(p->base + p->off_flags + (size_t)p->max_tiles * 4, zeros.data(), (size_t)nt * 4,
-                            hipMemcpyHostToDevice, p->stream)) != hipSuccess)
+    if ((e = hipEventRecord(sg.ev, p->stream)) != hipSuccess) return hip_fail(e, "staging event");
+    sg.pending = true;
+    // claim counters and tile flags cleared; tile words from the slots' device states
+    const PoolView v = view_of(p);
+    if ((e = launch_fill_i32(v.next, 5, 0, p->stream)) != hipSuccess) return hip_fail(e, "clear claim counters");
+    if (nt > 0 && (e = launch_fill_i32(v.flags, nt, 0, p->stream)) != hipSuccess) return hip_fail(e, "clear flags");
+    if (nt > 0 && p->dim == 2 && (e = launch_fill_i32(v.flags_lean, nt, 0, p->stream)) != hipSuccess)
         return hip_fail(e, "clear lean flags");
-    if (nt > 0 && (e = hipMemcpyAsync(p->base + p->off_tstate, words.data(), (size_t)nt * 4,
-                                      hipMemcpyHostToDevice, p->stream)) != hipSuccess)
-        return hip_fail(e, "upload tile words");
-    if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_fail(e, "sync");
+    if (nt > 0) {
+        pool_tile_words_kernel<<<(unsigned)((nt + 255) / 256), 256, 0, p->stream>>>(v, nt);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "tile words");
+    }
     return LB_OK;
 }
 
@@ -233,7 +283,9 @@ int set_shape(lb_pool* p, int shape)
     if (shape < 0 || shape >= ns) return fail(LB_EINVAL, "shape must lie in [0, %d)", ns);
     if (shape != p->shape) drop_graph(p);
     p->shape = shape;
-    return upload_tables(p);
+    const int rc = upload_tables(p);
+    if (rc == LB_OK) p->dirty = false;
+    return rc;
 }
 
 // One step of every live slot: step kernel(s), then the per-slot reduction.
@@ -278,8 +330,12 @@ int capture_graph(lb_pool* p)
     return LB_OK;
 }
 
+int flush_tables(lb_pool* p);
+
 int queue_steps(lb_pool* p, int64_t n)
 {
+    int rc0 = flush_tables(p);  // never inside a captured graph
+    if (rc0 != LB_OK) return rc0;
     int64_t left = n;
     if (p->graph_steps > 0 && left >= p->graph_steps) {
         if (!p->graph_ready) {
@@ -390,16 +446,25 @@ void unreserve(lb_pool* p, int32_t slot)
     q = PoolProb{};
 }
 
-// Make a reserved slot live: fresh state record, tables uploaded.
+// Make a reserved slot live: fresh state record, tables uploaded (both
+// stream-ordered behind the work queued so far).
 int activate(lb_pool* p, int32_t slot)
 {
-    PoolState st{};
-    hipError_t e = hipMemcpyAsync(p->base + p->off_state + (size_t)slot * sizeof(PoolState), &st, sizeof st,
-                                  hipMemcpyHostToDevice, p->stream);
+    pool_reset_state_kernel<<<1, 64, 0, p->stream>>>((PoolState*)(p->base + p->off_state) + slot);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "reset slot state");
     p->probs[(size_t)slot].active = 1;
-    const int rc = upload_tables(p);  // synchronises (st is on this stack frame)
-    if (rc != LB_OK) p->probs[(size_t)slot].active = 0;
+    p->gen[(size_t)slot] += 1;
+    p->dirty = true;
+    return LB_OK;
+}
+
+// Send the tables if admissions or releases changed them (before a step).
+int flush_tables(lb_pool* p)
+{
+    if (!p->dirty) return LB_OK;
+    const int rc = upload_tables(p);
+    if (rc == LB_OK) p->dirty = false;
     return rc;
 }
 
@@ -446,6 +511,7 @@ static int create_pool(int32_t dim, double gamma, double gamma2, bool species, c
     try {
         p->probs.assign((size_t)max_slots, PoolProb{});
         p->info.assign((size_t)max_slots, SlotInfo{});
+        p->gen.assign((size_t)max_slots, 0);
     } catch (...) {
         delete p;
         return fail(LB_ENOMEM, "host allocation failed");
@@ -503,15 +569,26 @@ int lb_pool_bind(lb_pool* p, void* dev_ptr, size_t bytes, void* hip_stream)
         return hip_fail(e, "hipDeviceGetAttribute");
     if ((e = hipEventCreate(&p->ev0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
     if ((e = hipEventCreate(&p->ev1)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    for (Stage& sg : p->stage)
+        if ((e = hipEventCreateWithFlags(&sg.ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    for (Snap& sn : p->snap) {
+        if ((e = hipEventCreateWithFlags(&sn.ev, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+        if ((e = hipHostMalloc((void**)&sn.host, (size_t)p->max_slots * sizeof(PoolState), hipHostMallocDefault)) !=
+            hipSuccess)
+            return hip_fail(e, "pinned snapshot");
+    }
     p->base = (char*)dev_ptr;
     p->stream = (hipStream_t)hip_stream;
     p->bound = true;
     // zero slot states, then the (empty) tables
-    std::vector<PoolState> st((size_t)p->max_slots, PoolState{});
-    if ((e = hipMemcpyAsync(p->base + p->off_state, st.data(), st.size() * sizeof(PoolState),
-                            hipMemcpyHostToDevice, p->stream)) != hipSuccess)
+    static_assert(sizeof(PoolState) % 4 == 0, "slot states are cleared as 32-bit words");
+    if ((e = launch_fill_i32((int32_t*)(p->base + p->off_state), (int64_t)p->max_slots * sizeof(PoolState) / 4, 0,
+                             p->stream)) != hipSuccess)
         return hip_fail(e, "clear slot states");
-    return set_shape(p, p->shape);  // synchronises
+    const int rc = set_shape(p, p->shape);
+    if (rc != LB_OK) return rc;
+    if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return hip_fail(e, "sync");
+    return LB_OK;
 }
 
 int lb_pool_admit_riemann(lb_pool* p, const lb_grid* grid, double lambda, double x_d, const lb_prim* L,
@@ -571,12 +648,13 @@ int lb_pool_admit_moments(lb_pool* p, const lb_grid* grid, const double* host_Y,
     return LB_OK;
 }
 
+// No wait: steps queued earlier still run the released slot with the old
+// tables; whatever reuses its memory (an admission's initial state) is
+// queued after them on the same stream.
 int lb_pool_release(lb_pool* p, int32_t slot)
 {
     int rc = check_slot(p, slot);
     if (rc != LB_OK) return rc;
-    hipError_t e = hipStreamSynchronize(p->stream);  // no queued step may still use its memory
-    if (e != hipSuccess) return hip_fail(e, "sync");
     unreserve(p, slot);
     return upload_tables(p);
 }
@@ -592,6 +670,10 @@ int lb_pool_advance_timed(lb_pool* p, int64_t n, float* ms)
 {
     if (!p || !p->bound || !ms) return fail(LB_EINVAL, "null argument or pool not bound");
     if (n < 0) return fail(LB_EINVAL, "n must be >= 0");
+    {
+        const int rc = flush_tables(p);  // outside the timed region
+        if (rc != LB_OK) return rc;
+    }
     if (p->graph_steps > 0 && !p->graph_ready && n >= p->graph_steps) {
         const int rc = capture_graph(p);  // outside the timed region
         if (rc != LB_OK) return rc;
@@ -785,6 +867,69 @@ int lb_pool_use_graph(lb_pool* p, int32_t steps_per_graph)
     return LB_OK;
 }
 
+int lb_pool_snapshot(lb_pool* p, int32_t buf)
+{
+    if (!p || !p->bound) return fail(LB_EINVAL, "pool not bound");
+    if (buf < 0 || buf > 1) return fail(LB_EINVAL, "snapshot buffer must be 0 or 1");
+    Snap& sn = p->snap[buf];
+    hipError_t e;
+    if (sn.queued && (e = hipEventSynchronize(sn.ev)) != hipSuccess) return hip_fail(e, "snapshot wait");
+    if ((e = hipMemcpyAsync(sn.host, p->base + p->off_state, (size_t)p->max_slots * sizeof(PoolState),
+                            hipMemcpyDeviceToHost, p->stream)) != hipSuccess)
+        return hip_fail(e, "snapshot copy");
+    if ((e = hipEventRecord(sn.ev, p->stream)) != hipSuccess) return hip_fail(e, "snapshot event");
+    sn.gen = p->gen;
+    sn.target.assign((size_t)p->max_slots, 0);
+    sn.lambda.assign((size_t)p->max_slots, 0.0);
+    for (int32_t i = 0; i < p->max_slots; ++i) {
+        if (!p->probs[(size_t)i].active) sn.gen[(size_t)i] = -1;
+        sn.target[(size_t)i] = p->probs[(size_t)i].target;
+        sn.lambda[(size_t)i] = p->info[(size_t)i].lambda;
+    }
+    sn.queued = true;
+    return LB_OK;
+}
+
+int lb_pool_snapshot_read(lb_pool* p, int32_t buf, int64_t* steps_done, int32_t* status, double* totals)
+{
+    if (!p || !p->bound) return fail(LB_EINVAL, "pool not bound");
+    if (buf < 0 || buf > 1) return fail(LB_EINVAL, "snapshot buffer must be 0 or 1");
+    if (!steps_done || !status) return fail(LB_EINVAL, "null argument");
+    Snap& sn = p->snap[buf];
+    if (!sn.queued) return fail(LB_EINVAL, "no snapshot queued in buffer %d", buf);
+    hipError_t e = hipEventSynchronize(sn.ev);
+    if (e != hipSuccess) return hip_fail(e, "snapshot wait");
+    for (int32_t i = 0; i < p->max_slots; ++i) {
+        const size_t u = (size_t)i;
+        double* out = totals ? totals + 4 * u : nullptr;
+        if (out) out[0] = out[1] = out[2] = out[3] = NAN;
+        // free when queued, or admitted again since: not this occupant's progress
+        if (sn.gen[u] < 0 || !p->probs[u].active || p->gen[u] != sn.gen[u]) {
+            steps_done[i] = 0;
+            status[i] = LB_POOL_FREE;
+            continue;
+        }
+        const PoolState& q = sn.host[u];
+        steps_done[i] = q.done;
+        if (q.err_step != 0) status[i] = (q.err_code & kErrState) ? LB_ESTATE : LB_EREACH;
+        else status[i] = q.done >= sn.target[u] ? 1 : 0;
+        if (out && q.done > 0 && q.totals_step == q.done) {
+            double sc[5];
+            field_scales(p->nf, p->dim + 1, sn.lambda[u], sc);
+            out[0] = q.totals[0] / sc[0];
+            out[1] = q.totals[1] / sc[1];
+            if (p->dim == 2) {
+                out[2] = q.totals[2] / sc[2];
+                out[3] = q.totals[3] / sc[3];
+            } else {
+                out[2] = 0.0;
+                out[3] = q.totals[2] / sc[2];
+            }
+        }
+    }
+    return LB_OK;
+}
+
 void lb_pool_destroy(lb_pool* p)
 {
     if (!p) return;
@@ -792,6 +937,14 @@ void lb_pool_destroy(lb_pool* p)
     drop_graph(p);
     if (p->ev0) (void)hipEventDestroy(p->ev0);
     if (p->ev1) (void)hipEventDestroy(p->ev1);
+    for (Stage& sg : p->stage) {
+        if (sg.host) (void)hipHostFree(sg.host);
+        if (sg.ev) (void)hipEventDestroy(sg.ev);
+    }
+    for (Snap& sn : p->snap) {
+        if (sn.host) (void)hipHostFree(sn.host);
+        if (sn.ev) (void)hipEventDestroy(sn.ev);
+    }
     delete p;
 }
 

@@ -38,7 +38,7 @@ EXPORTED = ["lb_create", "lb_create_two_gas", "lb_species_total", "lb_state_byte
             "lb_debug_lanes", "lb_destroy", "lb_last_error", "lb_step_static",
             "lb_pool_create", "lb_pool_create_two_gas", "lb_pool_bytes", "lb_pool_footprint", "lb_pool_bind", "lb_pool_admit_riemann",
             "lb_pool_admit_moments", "lb_pool_release", "lb_pool_advance", "lb_pool_advance_timed",
-            "lb_pool_poll", "lb_pool_status", "lb_pool_moments", "lb_pool_totals", "lb_pool_lambda", "lb_pool_live",
+            "lb_pool_poll", "lb_pool_status", "lb_pool_snapshot", "lb_pool_snapshot_read", "lb_pool_moments", "lb_pool_totals", "lb_pool_lambda", "lb_pool_live",
             "lb_pool_shapes", "lb_pool_shape", "lb_pool_set_shape", "lb_pool_autotune", "lb_pool_use_graph",
             "lb_pool_destroy"]
 
@@ -112,6 +112,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lb_pool_advance_timed": (ctypes.c_int, [vp, i64, ctypes.POINTER(ctypes.c_float)]),
         "lb_pool_poll": (ctypes.c_int, [vp, i32, ctypes.POINTER(ctypes.c_int64), I32P]),
         "lb_pool_status": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int64), I32P]),
+        "lb_pool_snapshot": (ctypes.c_int, [vp, i32]),
+        "lb_pool_snapshot_read": (ctypes.c_int, [vp, i32, ctypes.POINTER(ctypes.c_int64), I32P,
+                                                 ctypes.POINTER(ctypes.c_double)]),
         "lb_pool_moments": (ctypes.c_int, [vp, i32, vp, i32]),
         "lb_pool_totals": (ctypes.c_int, [vp, i32, D]),
         "lb_pool_lambda": (dbl, [vp, i32]),
@@ -325,8 +328,7 @@ class Pool:
         self.dim, self.nf, self.precision = dim, dim + 2 + (1 if self.species else 0), precision
         self.max_slots = int(max_slots)
         self.arena_bytes = int(arena_bytes)
-        self.lattice = lattice if dim == 2 else "line"
-        vs = lb_velset(_lattice(dim, d0_frac, lattice), d0_frac)
+        vs = lb_velset(_lattice(dim, d0_frac), d0_frac)  # pools run the 1-D and square lattices
         prec = {"fp64": LB_FP64, "fp32": LB_FP32}[precision]
         h = ctypes.c_void_p()
         if self.species:
@@ -416,6 +418,22 @@ class Pool:
         _check(_lib.lb_pool_status(self._h, done.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                    st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return done, st
+
+    def snapshot(self, buf: int):
+        """Queue a copy of every slot's progress into host buffer buf (0 or 1)
+        behind the queued work; returns at once (lb_pool_snapshot)."""
+        _check(_lib.lb_pool_snapshot(self._h, int(buf)))
+
+    def snapshot_read(self, buf: int):
+        """Wait for snapshot buf: (steps done, status, totals [max_slots, 4]
+        physical units, NaN before a slot's first step)."""
+        done = np.zeros(self.max_slots, dtype=np.int64)
+        st = np.zeros(self.max_slots, dtype=np.int32)
+        tot = np.zeros((self.max_slots, 4), dtype=np.float64)
+        _check(_lib.lb_pool_snapshot_read(self._h, int(buf), done.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                          st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                          tot.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return done, st, tot
 
     def moments(self, slot: int) -> np.ndarray:
         out = np.empty(self._shape[int(slot)], dtype=np.float64)

@@ -8,6 +8,11 @@ solves together by `tick` pool steps (one persistent launch per step, HIP-graph
 captured), then collects the finished ones, whose slots and memory go to the
 next arrivals.  Work of different requests overlaps inside each launch.
 
+The device never waits for the host: each tick is queued with a progress
+snapshot behind it, and the host reads the previous tick's snapshot (finished
+slots, their totals) while the next tick runs.  Admissions and releases are
+stream-ordered, so they take effect from the next tick queued.
+
 Latency of a request = completion (its result collected) - arrival.
 Aggregate throughput = sum over requests of nodes x steps / makespan.
 """
@@ -18,7 +23,7 @@ import time
 import numpy as np
 
 from . import inputs
-from .lbsd import Pool
+from .lbsd import LB_POOL_FREE, Pool
 
 
 def request_footprint(pool: Pool, side: int) -> int:
@@ -43,9 +48,11 @@ def run(pool: Pool, requests, *, tick: int = 25, fetch: str = "totals", time_sca
     nxt = 0
     t0 = time.perf_counter()
     ticks = 0
-    while nxt < n or live:
+    pending = []  # snapshots queued and not read yet (sequence numbers; buffer = seq % 2)
+    seq = 0
+    while nxt < n or live or pending:
         now = time.perf_counter() - t0
-        if not live and nxt < n and arrival[nxt] > now:
+        if not live and not pending and nxt < n and arrival[nxt] > now:
             time.sleep(arrival[nxt] - now)  # idle until the next arrival
             now = time.perf_counter() - t0
         while nxt < n and arrival[nxt] <= now:
@@ -57,17 +64,26 @@ def run(pool: Pool, requests, *, tick: int = 25, fetch: str = "totals", time_sca
             live[slot] = nxt
             admitted[nxt] = time.perf_counter() - t0
             nxt += 1
-        if not live:
+        queued = False
+        if live and len(pending) < 2:
+            pool.advance(tick)
+            pool.snapshot(seq % 2)
+            pending.append(seq)
+            seq += 1
+            ticks += 1
+            queued = True
+        if not pending:
             continue
-        pool.advance(tick)
-        ticks += 1
-        done, status = pool.status()
-        for slot in [s for s in live if status[s] != 0]:
+        if queued and len(pending) < 2:
+            continue  # keep one tick queued ahead before waiting for a snapshot
+        s = pending.pop(0)
+        done, status, tot = pool.snapshot_read(s % 2)
+        for slot in [q for q in live if status[q] not in (0, LB_POOL_FREE)]:
             i = live.pop(slot)
             if status[slot] != 1:
                 raise RuntimeError(f"request {i} failed with status {status[slot]} after {done[slot]} steps")
             if fetch == "totals":
-                res = pool.totals(slot)
+                res = tot[slot].copy()
             elif fetch == "moments":
                 res = pool.moments(slot)
             else:
