@@ -835,6 +835,11 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
             // on every path)
             const bool ymix_ok = fits_x && fits_y && w.fymin == -1 && w.fymax == 0 && w.c1max <= 3 &&
                                  w.fxmax - w.fxmin <= 2;
+            // full pass: floor(v_y) taking two or three values in [-2, 1] (a
+            // region moving at |v_y| >= 1 next to one at rest): the row path
+            // once per value, as for {-1, 0}
+            const bool ymulti_ok = L == kLFull && fits_x && fits_y && w.fymin >= -2 && w.fymax <= 1 &&
+                                   w.fymax - w.fymin <= 2 && w.c1max <= 3 && w.fxmax - w.fxmin <= 2;
             // the short pass takes these windows and the planar ones within
             // its FIFO; a tile with any other window is flagged for the full pass
             if (!((planar || ymix_ok) && fits_small)) yfar = 1;
@@ -877,14 +882,23 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
     #undef LB_FAST
                         default: break;  // not reached: fastw and ymixw admit only the cases above
                     }
-                } else if (rows_ok || ymix_ok) {
+                } else if (rows_ok || ymix_ok || ymulti_ok) {
                     // one call per value of floor(v_y) in the window (one
                     // call site per instance keeps the kernel's code compact)
                     const auto& R = s_row[b][u];
-                    if (w.fymin == -1)
-                        gather_rows<T, L, -1, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, ymix_ok, rq);
-                    if (w.fymax == 0)
-                        gather_rows<T, L, 0, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, ymix_ok, rq);
+                    const bool chk = w.fymin != w.fymax;
+                    if constexpr (L == kLFull) {
+                        if (w.fymin <= -2)
+                            gather_rows<T, L, -2, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, chk, rq);
+                    }
+                    if (w.fymin <= -1 && w.fymax >= -1)
+                        gather_rows<T, L, -1, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, chk, rq);
+                    if (w.fymin <= 0 && w.fymax >= 0)
+                        gather_rows<T, L, 0, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, chk, rq);
+                    if constexpr (L == kLFull) {
+                        if (w.fymax >= 1)
+                            gather_rows<T, L, 1, REST>(R, tid, f, w.fxmin, w.fxmax, w.c1min, w.c1max, chk, rq);
+                    }
                 } else if (L == kLFull) {  // other windows: the short pass flags the tile (above)
                     gather_general<T, L, REST>(s_row[b][u], tid, f, max(-kMH, w.fxmin - c2max),
                                                min(kMH, w.fxmax + 1 + c2max), w.fymin, w.fymax, w.c1min, w.c1max,
