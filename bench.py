@@ -47,7 +47,8 @@ gather kernel plus its totals reduction.  Alongside, in the same JSON line:
   seeds 0-7 of the family.
 
 `--profile` runs a short headline plus a plain device copy of known size,
-for rocprofv3 counter runs.
+for rocprofv3 counter runs (`--profile-batch`, `--profile-hex`: the same for
+the FP64 tube batch and the hexagonal-lattice tube).
 """
 from __future__ import annotations
 
@@ -424,6 +425,8 @@ def main():
                     help="short run + a plain copy of known size, for rocprofv3 counters")
     ap.add_argument("--profile-batch", action="store_true",
                     help="as --profile, for the FP64 tube batch (tile shape 2, --steps steps)")
+    ap.add_argument("--profile-hex", action="store_true",
+                    help="as --profile, for the hexagonal-lattice tube (FP64, --steps steps)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path "
@@ -433,7 +436,7 @@ def main():
     import torch
 
     torch.cuda.set_device(0)
-    if args.profile or args.profile_batch:
+    if args.profile or args.profile_batch or args.profile_hex:
         # plain device copy of 1 GiB, three times (counter calibration)
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
         b = torch.empty_like(a)
@@ -443,6 +446,9 @@ def main():
         del a, b
         if args.profile_batch:
             print(json.dumps({"profile": True, "batch": run_batch("fp64", steps=args.steps, shape=2, graph=False)}), flush=True)
+            return
+        if args.profile_hex:
+            print(json.dumps({"profile": True, "hex": run_hex(args.steps)}), flush=True)
             return
         r = run_gpu("fp64", args.steps, args.warmup)
         print(json.dumps({"profile": True, "steps": args.steps, "kernel_ms": r["kernel_ms"],
