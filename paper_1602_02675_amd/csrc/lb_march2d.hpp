@@ -355,13 +355,14 @@ __device__ __forceinline__ T rest_k(const MRow<T, SP, RYS>& R, int s)
 // sign); the corners k_y = 0, 1 of a source then sit at rows FY + d with d =
 // floor(v_y) - FY + k_y in 0 .. 2, and each packet class is taken once per d
 // with the source's weight for that row (zero for the row it does not reach).
-template <typename T, int L, int FY, int S0, int NSP, int NKX, bool RY0, bool REST, bool YM = false, bool SP,
-          bool RYS>
+template <typename T, int L, int FY, int S0, int NSP, int NKX, bool RY0, bool REST, bool YM = false,
+          bool XCHK = false, bool SP, bool RYS>
 __device__ __forceinline__ void gather_fast(const MRow<T, SP, RYS>& R, int lane, int fx, Fifo<Acc<T>, L, SP>& f,
                                             T rq)
 {
 #pragma clang fp contract(off)
     static_assert(!(YM && RY0), "a y-mixed window has sources with r_y != 0");
+    static_assert(!XCHK || NKX == 2, "XCHK takes one value of floor(v_x) per call");
     constexpr bool UNI = NSP == 2;
     constexpr bool NOVY = RY0 && FY == 0;
     constexpr int NKY = YM ? 3 : (RY0 ? 1 : 2);  // row offsets d of the packets (k_y, plus 1 if YM)
@@ -393,8 +394,9 @@ __device__ __forceinline__ void gather_fast(const MRow<T, SP, RYS>& R, int lane,
     // speed S0 + j; with NKX = 3 a source may have floor(v_x) = fx - 1
     auto mass = [&](int s, int j, int k) -> T {
         const int l = level(s, j);
-        const int kc = NKX == 2 ? k : k + fx - mfx(R.pk[s]);  // the source's own corner
-        if (UNI && NKX == 2) return R.m[l][kc][s];
+        // the source's own corner (XCHK: only sources with floor(v_x) = fx count)
+        const int kc = XCHK ? (mfx(R.pk[s]) == fx ? k : -1) : (NKX == 2 ? k : k + fx - mfx(R.pk[s]));
+        if (UNI && NKX == 2 && !XCHK) return R.m[l][kc][s];
         const T v = R.m[l < 0 ? 0 : l][kc < 0 ? 0 : (kc > 1 ? 1 : kc)][s];
         return (l >= 0 && kc >= 0 && kc <= 1) ? v : (T)0;
     };
@@ -451,7 +453,8 @@ __device__ __forceinline__ void gather_fast(const MRow<T, SP, RYS>& R, int lane,
 #pragma unroll
         for (int q = 0; q < NKX; ++q) {
             const int kx = K0 + q, sq = base - kx;
-            const int kc = NKX == 2 ? kx : kx + fx - mfx(R.pk[sq]);  // the source's own corner
+            // the source's own corner (XCHK: only sources with floor(v_x) = fx count)
+            const int kc = XCHK ? (mfx(R.pk[sq]) == fx ? kx : -1) : (NKX == 2 ? kx : kx + fx - mfx(R.pk[sq]));
             const T v = rest_mass(R, kc < 0 ? 0 : (kc > 1 ? 1 : kc), sq, rq);
             b[q] = (kc >= 0 && kc <= 1) ? v : (T)0;
             ry[q] = ry_of(R, sq);
@@ -851,10 +854,30 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                 const bool mixes = (w.c1max == w.c1min || cmix) && (w.fxmax == w.fxmin || xmix) &&
                                    !(cmix && xmix) && (!cmix || w.c1min <= 2) && (!xmix || w.c1min <= 1);
                 const bool fastw = rows_ok && mixes;
+                // planar, c'_1 in {0, 1} or {1, 2} and floor(v_x) in {fx - 1, fx}:
+                // the c'_1-mixed instance once per value of floor(v_x)
+                const bool xsplitw = rows_ok && cmix && xmix && w.c1min <= 1;
                 // floor(v_y) in {-1, 0} with the same mixes: the y-mixed
                 // instances (three row offsets per packet class)
                 const bool ymixw = ymix_ok && mixes && !xmix && w.c1max <= 1;
-                if (fastw || ymixw) {
+                if (xsplitw) {
+                    const auto& R = s_row[b][u];
+                    const int sel = (w.fymin == 0 ? (w.ry0 ? 0 : 1) : 2) * 2 + w.c1min;
+                    switch (sel) {
+    #define LB_XSPLIT(S, FYV, S0, RY)                                                                      \
+        case S:                                                                                            \
+            if constexpr ((FYV) - (S0) - 2 >= -L && (FYV) + 1 + (S0) + 2 <= L) {                            \
+                gather_fast<T, L, FYV, S0, 3, 2, RY, REST, false, true>(R, tid, w.fxmin, f, rq);          \
+                gather_fast<T, L, FYV, S0, 3, 2, RY, REST, false, true>(R, tid, w.fxmax, f, rq);          \
+            }                                                                                              \
+            break;
+                        LB_XSPLIT(0, 0, 0, true) LB_XSPLIT(1, 0, 1, true)
+                        LB_XSPLIT(2, 0, 0, false) LB_XSPLIT(3, 0, 1, false)
+                        LB_XSPLIT(4, -1, 0, false) LB_XSPLIT(5, -1, 1, false)
+    #undef LB_XSPLIT
+                        default: break;  // not reached
+                    }
+                } else if (fastw || ymixw) {
                     const auto& R = s_row[b][u];
                     const int fx0 = w.fxmax;
                     const int sel = ((ymixw ? 3 : (w.fymin == 0 ? (w.ry0 ? 0 : 1) : 2)) * 2 + (xmix ? 1 : 0)) * 8 +
