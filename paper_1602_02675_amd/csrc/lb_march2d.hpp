@@ -860,7 +860,24 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                 // floor(v_y) in {-1, 0} with the same mixes: the y-mixed
                 // instances (three row offsets per packet class)
                 const bool ymixw = ymix_ok && mixes && !xmix && w.c1max <= 1;
-                if (xsplitw) {
+                // floor(v_y) in {-1, 0} and floor(v_x) in {fx - 1, fx} as well
+                // (c'_1 <= 1): the y-mixed instance once per value of floor(v_x)
+                const bool yxsplitw = ymix_ok && xmix && w.c1max <= 1;
+                if (yxsplitw) {
+                    const auto& R = s_row[b][u];
+                    if (w.c1min == w.c1max) {
+                        if (w.c1min == 0) {
+                            gather_fast<T, L, -1, 0, 2, 2, false, REST, true, true>(R, tid, w.fxmin, f, rq);
+                            gather_fast<T, L, -1, 0, 2, 2, false, REST, true, true>(R, tid, w.fxmax, f, rq);
+                        } else {
+                            gather_fast<T, L, -1, 1, 2, 2, false, REST, true, true>(R, tid, w.fxmin, f, rq);
+                            gather_fast<T, L, -1, 1, 2, 2, false, REST, true, true>(R, tid, w.fxmax, f, rq);
+                        }
+                    } else {
+                        gather_fast<T, L, -1, 0, 3, 2, false, REST, true, true>(R, tid, w.fxmin, f, rq);
+                        gather_fast<T, L, -1, 0, 3, 2, false, REST, true, true>(R, tid, w.fxmax, f, rq);
+                    }
+                } else if (xsplitw) {
                     const auto& R = s_row[b][u];
                     const int sel = (w.fymin == 0 ? (w.ry0 ? 0 : 1) : 2) * 2 + w.c1min;
                     switch (sel) {

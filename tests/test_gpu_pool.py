@@ -266,3 +266,46 @@ def test_serve_loop_results_match_alone(lbsd):
     assert np.all(lat > 0) and res["p99_s"] >= res["p50_s"] > 0
     assert res["nups"] > 0 and pool.live == 0
     pool.close()
+
+
+def test_snapshots_follow_stream_order(lbsd):
+    """lb_pool_snapshot / lb_pool_snapshot_read: a snapshot shows the slots
+    as they were when it was queued (steps done, status, totals equal to
+    lb_pool_totals once synchronised); a slot released and admitted again
+    after a snapshot was queued reads as free in it; releases and admissions
+    queued behind running steps leave the others' results unchanged."""
+    L, R = (1.0, 0.0, 0.0, 1.0), (0.125, 0.0, 0.0, 0.1)
+    lam = inputs.cfl_lambda([L, R])
+    pool = lbsd.Pool(2, 3, 3 * 2 * 4 * 120 * 60 * 8, precision="fp64")
+    a = pool.admit_riemann(120, 0.5, L, R, 6, ny=60, lam=lam)
+    b = pool.admit_riemann(100, 0.4, L, R, 20, ny=40, lam=lam)
+    pool.advance(4)
+    pool.snapshot(0)
+    pool.advance(4)  # a finishes at 6
+    pool.snapshot(1)
+    done0, st0, tot0 = pool.snapshot_read(0)
+    assert (done0[a], st0[a], done0[b], st0[b]) == (4, 0, 4, 0)
+    assert st0[2] == lbsd.LB_POOL_FREE and np.all(np.isnan(tot0[2]))
+    done1, st1, tot1 = pool.snapshot_read(1)
+    assert (done1[a], st1[a], done1[b], st1[b]) == (6, 1, 8, 0)
+    np.testing.assert_array_equal(tot1[a], pool.totals(a))
+    ref_a = alone(lbsd, 2, 120, 60, 0.5, L, R, lam, 6, "fp64")
+    np.testing.assert_array_equal(pool.moments(a), ref_a)
+    # release a and admit another problem into its slot while b's steps are queued
+    pool.advance(4)
+    pool.snapshot(0)  # queued before the release and the admission
+    pool.release(a)
+    c = pool.admit_riemann(80, 0.6, L, R, 3, ny=30, lam=lam)
+    assert c == a  # the freed slot is reused
+    pool.advance(8)
+    pool.snapshot(1)
+    done0, st0, _ = pool.snapshot_read(0)
+    assert st0[c] == lbsd.LB_POOL_FREE  # the new occupant is not in the older snapshot
+    assert (done0[b], st0[b]) == (12, 0)
+    done1, st1, _ = pool.snapshot_read(1)
+    assert (done1[c], st1[c], done1[b], st1[b]) == (3, 1, 20, 1)
+    np.testing.assert_array_equal(pool.moments(b), alone(lbsd, 2, 100, 40, 0.4, L, R, lam, 20, "fp64"))
+    np.testing.assert_array_equal(pool.moments(c), alone(lbsd, 2, 80, 30, 0.6, L, R, lam, 3, "fp64"))
+    with pytest.raises(lbsd.LBError):
+        pool.snapshot(2)
+    pool.close()
