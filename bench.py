@@ -176,8 +176,8 @@ def run_tube1d(gamma2=None, n: int = 1 << 24, steps: int = 200, precision: str =
 
 
 def host_info():
-    """CPU model and the cores this process may use (the GPU machine grants a
-    share of its host, whatever os.cpu_count() reports)."""
+    """CPU model and the cores this process may use (a host may grant it a
+    share of its cores, whatever os.cpu_count() reports)."""
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:

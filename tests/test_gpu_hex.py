@@ -1,7 +1,7 @@
 """Hexagonal lattice (Fig. 1; Sec. III.B with b_v = 6): HIP path against the
 oracle on the same seeded inputs.
 
-Grids span several 64 x 4 tiles with ragged tails in both axial directions;
+Grids span several 64 x 16 tiles with ragged tails in both axial directions;
 fields range from pure noise (every window mixes floors, speeds and
 triangles) to smooth and planar data; boundaries transmissive and periodic
 along either axis; the dual-level set and the one with a rest group.  FP64
@@ -51,7 +51,7 @@ CASES = [  # nx, ny, bc_x, bc_y, d0_frac, seed, smoothing, steps
     (150, 22, "transmissive", "periodic", 0.0, 2, 5, 4),
     (97, 13, "transmissive", "transmissive", 0.0, 3, 3, 3),
     (130, 9, "periodic", "transmissive", 0.4, 4, 0, 3),
-    (64, 4, "periodic", "periodic", 0.5, 5, 2, 5),   # exactly one tile
+    (64, 16, "periodic", "periodic", 0.5, 5, 2, 5),  # exactly one tile
     (7, 3, "periodic", "periodic", 0.0, 6, 0, 2),    # smaller than the halo: wrapped many times
 ]
 
