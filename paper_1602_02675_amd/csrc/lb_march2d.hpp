@@ -351,11 +351,14 @@ __device__ __forceinline__ T rest_k(const MRow<T, SP, RYS>& R, int s)
 // and are skipped; with FY = 0 also v_y = 0 and the m v_y terms vanish.  The
 // sums are the same, term for term.  REST: the rest group's packets (from the
 // sources at x displacement floor(v_x) + k_x, into row FY + k_y) follow the
-// lanes.  YM: floor(v_y) is FY or FY + 1 per source (where v_y changes
-// sign); the corners k_y = 0, 1 of a source then sit at rows FY + d with d =
-// floor(v_y) - FY + k_y in 0 .. 2, and each packet class is taken once per d
-// with the source's weight for that row (zero for the row it does not reach).
-template <typename T, int L, int FY, int S0, int NSP, int NKX, bool RY0, bool REST, bool YM = false,
+// lanes.  YM > 0: floor(v_y) is one of FY .. FY + YM per source (where v_y
+// changes sign, YM = 1, or next to a region moving at |v_y| >= 1); the
+// corners k_y = 0, 1 of a source then sit at rows FY + d with d =
+// floor(v_y) - FY + k_y in 0 .. YM + 1, and each packet class is taken once
+// per d with the source's weight for that row (zero for the rows it does not
+// reach).  XCHK: only the sources with floor(v_x) = fx count (a window that
+// mixes floor(v_x) takes one call per value).
+template <typename T, int L, int FY, int S0, int NSP, int NKX, bool RY0, bool REST, int YM = 0,
           bool XCHK = false, bool SP, bool RYS>
 __device__ __forceinline__ void gather_fast(const MRow<T, SP, RYS>& R, int lane, int fx, Fifo<Acc<T>, L, SP>& f,
                                             T rq)
@@ -365,13 +368,13 @@ __device__ __forceinline__ void gather_fast(const MRow<T, SP, RYS>& R, int lane,
     static_assert(!XCHK || NKX == 2, "XCHK takes one value of floor(v_x) per call");
     constexpr bool UNI = NSP == 2;
     constexpr bool NOVY = RY0 && FY == 0;
-    constexpr int NKY = YM ? 3 : (RY0 ? 1 : 2);  // row offsets d of the packets (k_y, plus 1 if YM)
+    constexpr int NKY = YM ? YM + 2 : (RY0 ? 1 : 2);  // row offsets d of the packets (k_y, plus YM)
     constexpr int K0 = NKX == 3 ? -1 : 0;  // first x corner relative to floor(v_x) = fx
     const int base = lane - fx;  // staged column of x displacement fx + a is base - a
     // weight of row offset d for the source in column s with y fraction ry
     // (1 - r_y at its k_y = 0, r_y at k_y = 1)
     auto ywt = [&](int s, T ry, int d) -> T {
-        if constexpr (YM) {
+        if constexpr (YM > 0) {
             const int k = d - (mfy(R.pk[s]) - FY);
             return k == 0 ? (T)1 - ry : (k == 1 ? ry : (T)0);
         } else {
@@ -380,7 +383,7 @@ __device__ __forceinline__ void gather_fast(const MRow<T, SP, RYS>& R, int lane,
     };
     // v_y of the source in column s
     auto vyof = [&](int s, T ry) -> T {
-        if constexpr (YM) return (T)mfy(R.pk[s]) + ry;
+        if constexpr (YM > 0) return (T)mfy(R.pk[s]) + ry;
         else return (T)FY + ry;
     };
     // level (0: c'_1, 1: c'_2) that the source in column s has at speed
@@ -841,6 +844,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
             // full pass: floor(v_y) taking two or three values in [-2, 1] (a
             // region moving at |v_y| >= 1 next to one at rest): the row path
             // once per value, as for {-1, 0}
+            constexpr bool kWide = L == kLFull && sizeof(T) == 8;
             const bool ymulti_ok = L == kLFull && fits_x && fits_y && w.fymin >= -2 && w.fymax <= 1 &&
                                    w.fymax - w.fymin <= 2 && w.c1max <= 3 && w.fxmax - w.fxmin <= 2;
             // the short pass takes these windows and the planar ones within
@@ -867,15 +871,15 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                     const auto& R = s_row[b][u];
                     if (w.c1min == w.c1max) {
                         if (w.c1min == 0) {
-                            gather_fast<T, L, -1, 0, 2, 2, false, REST, true, true>(R, tid, w.fxmin, f, rq);
-                            gather_fast<T, L, -1, 0, 2, 2, false, REST, true, true>(R, tid, w.fxmax, f, rq);
+                            gather_fast<T, L, -1, 0, 2, 2, false, REST, 1, true>(R, tid, w.fxmin, f, rq);
+                            gather_fast<T, L, -1, 0, 2, 2, false, REST, 1, true>(R, tid, w.fxmax, f, rq);
                         } else {
-                            gather_fast<T, L, -1, 1, 2, 2, false, REST, true, true>(R, tid, w.fxmin, f, rq);
-                            gather_fast<T, L, -1, 1, 2, 2, false, REST, true, true>(R, tid, w.fxmax, f, rq);
+                            gather_fast<T, L, -1, 1, 2, 2, false, REST, 1, true>(R, tid, w.fxmin, f, rq);
+                            gather_fast<T, L, -1, 1, 2, 2, false, REST, 1, true>(R, tid, w.fxmax, f, rq);
                         }
                     } else {
-                        gather_fast<T, L, -1, 0, 3, 2, false, REST, true, true>(R, tid, w.fxmin, f, rq);
-                        gather_fast<T, L, -1, 0, 3, 2, false, REST, true, true>(R, tid, w.fxmax, f, rq);
+                        gather_fast<T, L, -1, 0, 3, 2, false, REST, 1, true>(R, tid, w.fxmin, f, rq);
+                        gather_fast<T, L, -1, 0, 3, 2, false, REST, 1, true>(R, tid, w.fxmax, f, rq);
                     }
                 } else if (xsplitw) {
                     const auto& R = s_row[b][u];
@@ -884,8 +888,8 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
     #define LB_XSPLIT(S, FYV, S0, RY)                                                                      \
         case S:                                                                                            \
             if constexpr ((FYV) - (S0) - 2 >= -L && (FYV) + 1 + (S0) + 2 <= L) {                            \
-                gather_fast<T, L, FYV, S0, 3, 2, RY, REST, false, true>(R, tid, w.fxmin, f, rq);          \
-                gather_fast<T, L, FYV, S0, 3, 2, RY, REST, false, true>(R, tid, w.fxmax, f, rq);          \
+                gather_fast<T, L, FYV, S0, 3, 2, RY, REST, 0, true>(R, tid, w.fxmin, f, rq);          \
+                gather_fast<T, L, FYV, S0, 3, 2, RY, REST, 0, true>(R, tid, w.fxmax, f, rq);          \
             }                                                                                              \
             break;
                         LB_XSPLIT(0, 0, 0, true) LB_XSPLIT(1, 0, 1, true)
@@ -902,7 +906,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                     switch (sel) {
     #define LB_FAST(S, FYV, S0, NSP, NKX, RY, YM)                                                           \
         case S:                                                                                             \
-            if constexpr ((FYV) - (S0) - (NSP) + 1 >= -L && (FYV) + ((YM) ? 2 : 1) + (S0) + (NSP) - 1 <= L) \
+            if constexpr ((FYV) - (S0) - (NSP) + 1 >= -L && (FYV) + (YM) + 1 + (S0) + (NSP) - 1 <= L)       \
                 gather_fast<T, L, FYV, S0, NSP, NKX, RY, REST, YM>(R, tid, fx0, f, rq);                     \
             break;
     #define LB_FAST_SET(B, FYV, RY, YM)                                                                      \
@@ -911,16 +915,34 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
         LB_FAST(B + 4, FYV, 0, 3, 2, RY, YM) LB_FAST(B + 5, FYV, 1, 3, 2, RY, YM)                            \
         LB_FAST(B + 6, FYV, 2, 3, 2, RY, YM)                                                                 \
         LB_FAST(B + 8, FYV, 0, 2, 3, RY, YM) LB_FAST(B + 9, FYV, 1, 2, 3, RY, YM)
-                        LB_FAST_SET(0, 0, true, false)
-                        LB_FAST_SET(16, 0, false, false)
-                        LB_FAST_SET(32, -1, false, false)
+                        LB_FAST_SET(0, 0, true, 0)
+                        LB_FAST_SET(16, 0, false, 0)
+                        LB_FAST_SET(32, -1, false, 0)
                         // y-mixed: uniform c'_1 0 or 1 and c'_1 in {0, 1} (the other
                         // instances made the compiler spill the short pass's FIFO)
-                        LB_FAST(48 + 0, -1, 0, 2, 2, false, true) LB_FAST(48 + 1, -1, 1, 2, 2, false, true)
-                        LB_FAST(48 + 4, -1, 0, 3, 2, false, true)
+                        LB_FAST(48 + 0, -1, 0, 2, 2, false, 1) LB_FAST(48 + 1, -1, 1, 2, 2, false, 1)
+                        LB_FAST(48 + 4, -1, 0, 3, 2, false, 1)
     #undef LB_FAST_SET
     #undef LB_FAST
                         default: break;  // not reached: fastw and ymixw admit only the cases above
+                    }
+                } else if (kWide && fits_x && fits_y && w.c1max <= 1 && w.fxmax - w.fxmin <= 1 &&
+                           w.fymax == 1 && (w.fymin == 0 || w.fymin == -1)) {
+                    // full pass: floor(v_y) in {0, 1} or {-1, 0, 1} (next to a
+                    // region moving at v_y >= 1), c'_1 <= 1: the y-mixed
+                    // instances (YM = 1 from 0, YM = 2 from -1; speeds 0 .. 2,
+                    // which also take a uniform c'_1), once per value of
+                    // floor(v_x).  FP64 only: in FP32 their registers would
+                    // cost the pass its second wavefront per SIMD.
+                    if constexpr (kWide) {
+                        const auto& R = s_row[b][u];
+                        for (int fxq = w.fxmin; fxq <= w.fxmax; ++fxq) {
+                            if (w.fymin == 0) {
+                                gather_fast<T, L, 0, 0, 3, 2, false, REST, 1, true>(R, tid, fxq, f, rq);
+                            } else {
+                                gather_fast<T, L, -1, 0, 3, 2, false, REST, 2, true>(R, tid, fxq, f, rq);
+                            }
+                        }
                     }
                 } else if (rows_ok || ymix_ok || ymulti_ok) {
                     // one call per value of floor(v_y) in the window (one
