@@ -286,8 +286,10 @@ static int create_solver(const lb_grid* grid, double gamma, double gamma2, bool 
     s->off_ctl = s->off_export + align256((size_t)s->nf * (size_t)s->nn * 8);
     s->off_partials = s->off_ctl + align256(sizeof(StepCtl));
     s->off_flags = s->off_partials + align256((size_t)s->nblocks * kPartialStride * 8);
-    // square lattice: two flag words per tile (short and full passes, lean pass)
-    s->total = s->off_flags + align256((size_t)(dim == 2 ? 2 * s->nblocks : 1) * 4);
+    // square lattice: two flag words per tile (short and full passes, lean
+    // pass) and the state of the passes' row chunks; hexagonal: unused
+    const size_t flag_bytes = dim == 2 ? (hex ? (size_t)2 * s->nblocks * 4 : march2d_flag_bytes(s->nblocks, true)) : 4;
+    s->total = s->off_flags + align256(flag_bytes);
     s->cfl = 1.0;
     s->lambda_set = 0.0;
     *out = s;
@@ -365,8 +367,10 @@ static int start_state(lb_solver* s)
     s->pending_err = 0;
     s->initialized = true;
     hipError_t e = launch_reset_ctl(ctl_ptr(s), s->stream);
-    // square lattice: the passes' per-tile flag words start clear
-    if (e == hipSuccess && s->dim == 2) e = launch_fill_i32(flags_ptr(s), 2 * s->nblocks, 0, s->stream);
+    // square lattice: the passes' per-tile flag words, work words and chunk
+    // counters start clear
+    if (e == hipSuccess && s->dim == 2)
+        e = launch_fill_i32(flags_ptr(s), (s->hex ? 2 : 5) * s->nblocks, 0, s->stream);
     return e == hipSuccess ? LB_OK : hip_fail(e, "reset");
 }
 
@@ -431,11 +435,11 @@ static int queue_steps(lb_solver* s, int64_t n, hipEvent_t* ev = nullptr)
             if (s->precision == LB_FP64)
                 e = launch_march2d<double>((const double*)buf_ptr(s, in), (double*)buf_ptr(s, out), s->g,
                                            s->march, s->k, ctl_ptr(s), partials_ptr(s), flags_ptr(s), step,
-                                           s->stream);
+                                           s->stream, true);
             else
                 e = launch_march2d<float>((const float*)buf_ptr(s, in), (float*)buf_ptr(s, out), s->g,
                                           s->march, s->k, ctl_ptr(s), partials_ptr(s), flags_ptr(s), step,
-                                          s->stream);
+                                          s->stream, true);
         }
         if (e != hipSuccess) return hip_fail(e, "step launch");
         if (ev && (e = hipEventRecord(ev[2 * i + 1], s->stream)) != hipSuccess) return hip_fail(e, "event");
@@ -791,8 +795,10 @@ int lb_step_static(lb_solver* s, const void* Y_in, void* Y_out, void* hip_stream
             : launch_hex<float>((const float*)Y_in, (float*)Y_out, s->g, s->k, ctl, partials, 1, st);
     } else {
         e = s->precision == LB_FP64
-            ? launch_march2d<double>((const double*)Y_in, (double*)Y_out, s->g, m, s->k, ctl, partials, flags, 1, st)
-            : launch_march2d<float>((const float*)Y_in, (float*)Y_out, s->g, m, s->k, ctl, partials, flags, 1, st);
+            ? launch_march2d<double>((const double*)Y_in, (double*)Y_out, s->g, m, s->k, ctl, partials, flags, 1, st,
+                                     false)
+            : launch_march2d<float>((const float*)Y_in, (float*)Y_out, s->g, m, s->k, ctl, partials, flags, 1, st,
+                                    false);
     }
     if (e != hipSuccess) return hip_fail(e, "step launch");
     if ((e = launch_finalize(partials, rows, ctl, 1, st, s->dim == 2 && s->species)) != hipSuccess)

@@ -24,6 +24,8 @@ struct StepCtl {
     int keep[2];            // square lattice: tiles the full-FIFO pass left flagged in this step [0]
                             // and in the previous step [1] (finalize moves [0] to [1])
     double totals_sp;       // square lattice with two gases: interior sum of rho chi
+    int split_n[2];         // square lattice: tiles listed for row chunks in the steps of each parity
+                            // (finalize clears the next step's)
 };
 
 // Per-block partial results: 4 field sums, reach, error bits; the square
@@ -65,10 +67,28 @@ int march2d_blocks_per_cu(bool lean = false);
 // complete, and those with sources that reach past its FIFO; the full-FIFO
 // kernel then recomputes the incomplete tiles and the row-chunk neighbours of
 // the far-reaching ones (it returns at once when nothing was flagged).  flags
-// holds one int of flag bits per tile.
+// holds two ints of flag bits per tile (march2d_flag_bytes(tiles, false)
+// bytes); with split, the state of the passes' row chunks follows them
+// (march2d_flag_bytes(tiles, true) bytes, zero before the first step).
 template <typename T>
 hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
-                          StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream);
+                          StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream,
+                          bool split);
+
+// Row chunks of the square lattice's short and full passes: at most
+// kSplitMax per tile.  Their state follows the two flag words per tile
+// (flags, flags_lean): two work words per tile (written in the steps of
+// each parity), one counter of finished chunks per tile (zero between
+// passes), two lists of tiles to cut (written in the steps of each parity),
+// then kSplitMax partial rows per tile (chunk p of tile t at row
+// p * tiles + t), 8-byte aligned.  The first 5 words per tile start at zero.
+constexpr int kSplitMax = 4;
+__host__ __device__ inline int64_t split_slots_offset(int64_t ntiles) { return (7 * ntiles + 1) / 2 * 2; }
+inline size_t march2d_flag_bytes(int64_t ntiles, bool split)
+{
+    return split ? (size_t)split_slots_offset(ntiles) * 4 + (size_t)kSplitMax * ntiles * kPartialStride * 8
+                 : (size_t)2 * ntiles * 4;
+}
 
 // Hexagonal lattice (lb_hex.hip): one block per tile of 64 x 4 nodes (axial
 // i x j), hex_blocks(g) blocks and partial rows per step.

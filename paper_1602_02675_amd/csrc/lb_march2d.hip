@@ -74,22 +74,23 @@ int march2d_blocks_per_cu(bool lean)
 // the dual-level set those without the rest group.
 template <typename T>
 hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
-                          StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream)
+                          StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream,
+                          bool split)
 {
     const bool walls = g.bc_x == kBcReflecting || g.bc_y == kBcReflecting, rest = k.rest_q > 0.0;
-    if (k.species) return launch_march2d_species<T>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
+    if (k.species) return launch_march2d_species<T>(Y, Yn, g, m, k, ctl, partials, flags, step, stream, split);
     if (rest)
-        return walls ? launch_march2d_w<T, true, true, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream)
-                     : launch_march2d_w<T, false, true, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
-    return walls ? launch_march2d_w<T, true, false, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream)
-                 : launch_march2d_w<T, false, false, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream);
+        return walls ? launch_march2d_w<T, true, true, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream, split)
+                     : launch_march2d_w<T, false, true, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream, split);
+    return walls ? launch_march2d_w<T, true, false, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream, split)
+                 : launch_march2d_w<T, false, false, false>(Y, Yn, g, m, k, ctl, partials, flags, step, stream, split);
 }
 
 template int march2d_blocks_per_cu<double>(bool);
 template int march2d_blocks_per_cu<float>(bool);
 template hipError_t launch_march2d<double>(const double*, double*, const Grid&, const MarchGeom&,
-                                           const Consts&, StepCtl*, double*, int*, long long, hipStream_t);
+                                           const Consts&, StepCtl*, double*, int*, long long, hipStream_t, bool);
 template hipError_t launch_march2d<float>(const float*, float*, const Grid&, const MarchGeom&,
-                                          const Consts&, StepCtl*, double*, int*, long long, hipStream_t);
+                                          const Consts&, StepCtl*, double*, int*, long long, hipStream_t, bool);
 
 }  // namespace lbsd

@@ -673,6 +673,33 @@ __device__ __forceinline__ void load_node(const T* __restrict__ Y, int64_t nn, i
 // leaves those to it at once.
 constexpr int kFlagFar = 1, kFlagReach = 2, kFlagKeep = 4, kFlagNotLean = 8;
 
+// Work of one window of a wavefront on the paths of march_tile, in units of
+// about half a uniform window (the fast instances' packet classes: speeds x
+// x corners x row offsets), summed over a tile's staged rows per wavefront;
+// a tile's work is its busiest wavefront's (the row barriers wait for it).
+constexpr int kUnitFast = 2, kUnitFastMix = 3, kUnitXSplit = 5, kUnitYMix = 3, kUnitYXSplit = 9,
+              kUnitWide = 14, kUnitRows = 9, kUnitGeneral = 32;
+
+// Row chunks of heavy tiles (plain form of the short and full passes).  A
+// tile whose windows take the slow paths costs the pass up to several times
+// the mean tile, and a pass lasts as long as its slowest block: such a tile
+// is cut into up to kSplitMax chunks of rows, which other blocks claim, each
+// marching its own rows plus the L halo rows on each side.  The short pass
+// cuts a tile by the work the last pass that computed it measured there (one
+// chunk more per kSplitWork units for the rows of a whole tile: about three
+// times a uniform tile's, so that only tiles that would outlast the pass's
+// mean load per block are cut, each chunk adding 2 L halo rows); the full
+// pass, which takes few tiles, cuts each of its tiles into as many chunks as
+// leave every resident block about one.  A chunk's per-tile results (field
+// sums, reach, error and flag bits) go to a slot of their own; the tile's
+// last chunk to finish adds the slots in chunk order into the tile's row of
+// partials, so the totals do not depend on which block ran which chunk.
+// Every node of a chunk is summed exactly as in the whole tile (the FIFO adds
+// a destination row's packets in source-row order whatever row the march
+// starts from).
+constexpr int kSplitWork = 150;
+constexpr int kWorkListed = 1 << 30;  // work word: the tile is in this step's list
+
 // Whether the next pass must compute the tile of destination rows
 // [Y0, ylast) whose row chunk ty0 = Y0 / sy starts at flag index tbase +
 // ty0 * tiles_x + tx (row chunks of sy rows, column strips tiles_x wide),
@@ -721,7 +748,7 @@ __device__ __forceinline__ bool needs_pass(const int* __restrict__ flags, int64_
 // Contains block-wide barriers: every thread of the block must call it.
 template <typename T, int L, bool WALLS, bool REST, bool SP>
 __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict__ Yn, const Grid& g, const Consts& k,
-                          int64_t X0, int64_t Y0, int sy, double* __restrict__ prow)
+                          int64_t X0, int64_t Y0, int sy, double* __restrict__ prow, int* cost = nullptr)
 {
     // source rows staged per barrier: two (fewer barriers, two independent
     // per-source computations in flight)
@@ -747,6 +774,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
     f.zero();
     double tot[NF] = {};
     int reach = 0, bad = 0, yfar = 0, yreach = 0, unlean = 0;
+    int units = 0;  // work of this thread's wavefront's windows (see kUnit*)
 
     // moments of this thread's source column in row gy (halo rows and
     // columns mapped by the boundaries); *mir_y tells whether the row is a
@@ -867,6 +895,15 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
                 // floor(v_y) in {-1, 0} and floor(v_x) in {fx - 1, fx} as well
                 // (c'_1 <= 1): the y-mixed instance once per value of floor(v_x)
                 const bool yxsplitw = ymix_ok && xmix && w.c1max <= 1;
+                const bool widew = kWide && fits_x && fits_y && w.c1max <= 1 && w.fxmax - w.fxmin <= 1 &&
+                                   w.fymax == 1 && (w.fymin == 0 || w.fymin == -1);
+                units += yxsplitw ? kUnitYXSplit
+                       : xsplitw ? kUnitXSplit
+                       : fastw ? (cmix ? kUnitFastMix : kUnitFast)
+                       : ymixw ? kUnitYMix
+                       : widew ? kUnitWide
+                       : (rows_ok || ymix_ok || ymulti_ok) ? kUnitRows * (w.fymax - w.fymin + 1)
+                       : (L == kLFull ? kUnitGeneral : 0);
                 if (yxsplitw) {
                     const auto& R = s_row[b][u];
                     if (w.c1min == w.c1max) {
@@ -926,8 +963,7 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
     #undef LB_FAST
                         default: break;  // not reached: fastw and ymixw admit only the cases above
                     }
-                } else if (kWide && fits_x && fits_y && w.c1max <= 1 && w.fxmax - w.fxmin <= 1 &&
-                           w.fymax == 1 && (w.fymin == 0 || w.fymin == -1)) {
+                } else if (widew) {
                     // full pass: floor(v_y) in {0, 1} or {-1, 0, 1} (next to a
                     // region moving at v_y >= 1), c'_1 <= 1: the y-mixed
                     // instances (YM = 1 from 0, YM = 2 from -1; speeds 0 .. 2,
@@ -996,16 +1032,18 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
     }
     // per-tile partials: field sums (a fifth, rho chi, at index 6), reach, error bits
     __shared__ double s_sum[kMNW][NF];
-    __shared__ int s_ir[kMNW][2];
+    __shared__ int s_ir[kMNW][3];
 #pragma unroll
     for (int c = 0; c < NF; ++c) tot[c] = wave_sum(tot[c]);
     reach = wave_max(reach);
     bad = wave_max(bad);
+    units = wave_max(units);
     if (lane64 == 0) {
 #pragma unroll
         for (int c = 0; c < NF; ++c) s_sum[wid][c] = tot[c];
         s_ir[wid][0] = reach;
         s_ir[wid][1] = bad;
+        s_ir[wid][2] = units;
     }
     // (__syncthreads_or returns whether any value is non-zero, not their OR)
     const int far = (__syncthreads_or(yfar) ? kFlagFar : 0) | (__syncthreads_or(yreach) ? kFlagReach : 0) |
@@ -1017,12 +1055,15 @@ __device__ __forceinline__ int march_tile(const T* __restrict__ Y, T* __restrict
             for (int w = 1; w < kMNW; ++w) t += s_sum[w][c];
             prow[c < 4 ? c : 6] = t;
         }
+        int uu = 0;
         for (int w = 0; w < kMNW; ++w) {
             rr = max(rr, s_ir[w][0]);
             bb |= s_ir[w][1];
+            uu = max(uu, s_ir[w][2]);
         }
         prow[4] = (double)rr;
         prow[5] = (double)((rr > kMH ? kErrReach : 0) | (bb ? kErrState : 0));
+        if (cost) *cost = uu;
     }
     return far;
 }
@@ -1278,7 +1319,7 @@ template <typename T, bool WALLS, bool REST, bool SP>
 __global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? LB_LEAN_WPE_F32 : ((REST || SP) ? LB_LEAN_WPE_EXT : LB_LEAN_WPE))))
 march2d_lean_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k, StepCtl* __restrict__ ctl,
                     double* __restrict__ partials, int* __restrict__ flags, int* __restrict__ flags_lean,
-                    long long step, int sy, int tiles_x, int ntiles)
+                    long long step, int sy, int tiles_x, int ntiles, int split)
 {
     __shared__ int s_t;
     if (ctl->err_step < step) return;
@@ -1289,6 +1330,7 @@ march2d_lean_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts 
             if (threadIdx.x == 0) {
                 flags_lean[t] = kFlagFar | kFlagReach | kFlagKeep;
                 atomicAdd(&ctl->next[kNextLeanFlagged], 1);
+                if (split) flags[(2 + (step & 1)) * (int64_t)ntiles + t] = 0;
             }
             continue;
         }
@@ -1297,8 +1339,14 @@ march2d_lean_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts 
                                                              partials + (int64_t)t * kPartialStride);
         if (threadIdx.x == 0) {
             flags_lean[t] = bits;
-            if (bits) atomicAdd(&ctl->next[kNextLeanFlagged], 1);
-            else flags[t] = 0;
+            if (bits) {
+                atomicAdd(&ctl->next[kNextLeanFlagged], 1);
+            } else {
+                flags[t] = 0;
+            }
+            // the work word of this step starts clear (the short and full
+            // passes set it for the tiles they compute)
+            if (split) flags[(2 + (step & 1)) * (int64_t)ntiles + t] = 0;
         }
     }
 }
@@ -1310,28 +1358,76 @@ march2d_lean_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts 
 // does not depend on L) and keeps the flag of each that still needs the full
 // FIFO; the next step's short pass leaves such tiles to the full pass instead
 // of computing them twice (flows change little per step).  Each returns at
-// once when the previous pass flagged nothing.
+// once when the previous pass flagged nothing.  With split (flags then holds
+// the split state after its two words per tile, march2d_flag_bytes), a
+// block claims a row chunk of a tile at a time (see kSplitMax).
 template <typename T, int L, bool WALLS, bool REST, bool SP>
 __global__ void __launch_bounds__(kMTPB) __attribute__((amdgpu_waves_per_eu(L < kLFull ? (sizeof(T) == 4 ? LB_MARCH_WPE_F32 : LB_MARCH_WPE) : LB_MARCH_WPE_FULL)))
 march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
                StepCtl* __restrict__ ctl, double* __restrict__ partials, int* __restrict__ flags,
-               int* __restrict__ flags_lean, long long step, int sy, int tiles_x, int ntiles)
+               int* __restrict__ flags_lean, long long step, int sy, int tiles_x, int ntiles, int split)
 {
     __shared__ int s_t;
     if (ctl->err_step < step) return;
-    if (ctl->next[L < kLFull ? kNextLeanFlagged : kNextShortFlagged] == 0) return;  // nothing left to it
+    const int nflag = ctl->next[L < kLFull ? kNextLeanFlagged : kNextShortFlagged];
+    if (nflag == 0) return;  // nothing left to it
     // some tile kept its flag in the previous step's full pass (else no flag
     // holds kFlagKeep and the short pass need not look)
     const bool kept = L < kLFull && ctl->keep[1] != 0;
+    // row chunks (see kSplitMax): work measured in the previous step and its
+    // list of tiles to cut, work and list of this step, finished chunks per
+    // tile, per-chunk partial slots
+    const int nsx = split ? kSplitMax : 1;
+    const int* __restrict__ work_in = flags + (2 + ((step - 1) & 1)) * (int64_t)ntiles;
+    int* __restrict__ work_out = flags + (2 + (step & 1)) * (int64_t)ntiles;
+    int* __restrict__ done = flags + 4 * (int64_t)ntiles;
+    const int* __restrict__ list_in = flags + (5 + ((step - 1) & 1)) * (int64_t)ntiles;
+    int* __restrict__ list_out = flags + (5 + (step & 1)) * (int64_t)ntiles;
+    double* __restrict__ slots = reinterpret_cast<double*>(flags + split_slots_offset(ntiles));
+    // the short pass cuts the listed tiles (by their work); the full pass,
+    // which takes the flagged tiles and their row-chunk neighbours, cuts
+    // every tile alike
+    const int nlist = (L < kLFull && split) ? ctl->split_n[(step - 1) & 1] : 0;
+    const int ns_full = min(nsx, max(1, (int)gridDim.x / (3 * nflag)));
+    const int nclaim = L < kLFull ? nlist * nsx + ntiles : ntiles * nsx;
+    auto chunks_of = [&](int t) -> int {
+        if (nsx == 1) return 1;
+        if (L == kLFull) return ns_full;
+        return min(nsx, 1 + (work_in[t] & ~kWorkListed) / kSplitWork);
+    };
     for (;;) {
-        const int t = claim_tile(&ctl->next[L < kLFull ? kNextShort : kNextFull], &s_t);
-        if (t >= ntiles) break;
+        const int c = claim_tile(&ctl->next[L < kLFull ? kNextShort : kNextFull], &s_t);
+        if (c >= nclaim) break;
+        // short pass: the chunks of the listed tiles (they start with the
+        // pass), then every tile not cut; full pass: nsx rounds over the
+        // tiles, round q taking chunk q of each.  Other claims are skipped at once.
+        int t, q;
+        if (L < kLFull) {
+            const bool listed = c < nlist * nsx;
+            t = listed ? list_in[c / nsx] : c - nlist * nsx;
+            q = listed ? c % nsx : -1;
+        } else {
+            q = c / ntiles;
+            t = c - q * ntiles;
+        }
         const int64_t tx = t % tiles_x, ty = t / tiles_x;
         const int64_t Y0 = ty * sy, ylast = min(Y0 + sy, g.ny);
+        const int rows = (int)(ylast - Y0);
+        int ns = chunks_of(t);
+        const int h = (rows + ns - 1) / ns;  // rows per chunk; the last may be shorter
+        ns = (rows + h - 1) / h;             // chunks with rows
+        int p = 0;
+        if (L < kLFull) {
+            if (ns > 1 ? (q < 0 || q >= ns) : q >= 0) continue;  // cut: its chunks' claims; whole: its own
+            p = ns > 1 ? q : 0;
+        } else {
+            if (ns > 1 ? q >= ns : q != 0) continue;
+            p = q;
+        }
         if (L < kLFull) {
             if (!needs_pass<kLLean>(flags_lean, 0, tiles_x, tx, Y0, ylast, sy, g.ny, g.bc_y)) continue;
             if (kept && (flags[t] & kFlagKeep)) {  // needed the full pass last step: left to it
-                if (threadIdx.x == 0) {
+                if (p == 0 && threadIdx.x == 0) {
                     flags[t] = kFlagFar | kFlagReach | kFlagKeep;
                     atomicAdd(&ctl->next[kNextShortFlagged], 1);
                 }
@@ -1340,20 +1436,73 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
         } else if (!needs_pass<kLSmall>(flags, 0, tiles_x, tx, Y0, ylast, sy, g.ny, g.bc_y)) {
             continue;
         }
-        const int bits = march_tile<T, L, WALLS, REST, SP>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), Y0, sy,
-                                                       partials + (int64_t)t * kPartialStride);
+        const int64_t c0 = Y0 + (int64_t)p * h;
+        const int hc = (int)min((int64_t)h, ylast - c0);
+        double* const prow = ns > 1 ? slots + ((int64_t)p * ntiles + t) * kPartialStride
+                                    : partials + (int64_t)t * kPartialStride;
+        int work = 0;
+        const int bits = march_tile<T, L, WALLS, REST, SP>(Y, Yn, g, k, tx * (kMTPB - 2 * kMH), c0, hc, prow, &work);
         if (threadIdx.x == 0) {
-            const int far = bits & kFlagFar;
-            if (L < kLFull) {
-                flags[t] = bits & (kFlagFar | kFlagReach);
-                if (far) atomicAdd(&ctl->next[kNextShortFlagged], 1);
-                // keep the lean pass's bits, which other blocks of this pass read
-                flags_lean[t] = (flags_lean[t] & (kFlagFar | kFlagReach)) | ((bits & kFlagNotLean) ? kFlagKeep : 0);
-            } else {
-                // keep the short pass's bits, which other blocks of this pass read
-                flags[t] = (flags[t] & (kFlagFar | kFlagReach)) | (far ? kFlagKeep : 0);
-                atomicAdd(&ctl->redo_tiles, 1);
-                if (far) atomicAdd(&ctl->keep[0], 1);
+            int tb = bits, tw = work;
+            bool last = true;
+            if (ns > 1) {
+                // this chunk's flag bits and work beside its sums; count it in,
+                // and the last chunk adds the slots in chunk order
+                prow[7] = (double)(work * 16 + bits);
+                __threadfence();
+                last = atomicAdd(&done[t], 1) == ns - 1;
+                if (last) {
+                    __threadfence();
+                    done[t] = 0;
+                    double sum[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+                    int rr = 0, ee = 0;
+                    tb = 0;
+                    tw = 0;
+                    for (int i = 0; i < ns; ++i) {
+                        const double* sr = slots + ((int64_t)i * ntiles + t) * kPartialStride;
+                        double v[8];
+#pragma unroll
+                        for (int f = 0; f < 8; ++f)
+                            v[f] = __hip_atomic_load(sr + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) sum[f] += v[f];
+                        sum[4] += v[6];
+                        rr = max(rr, (int)v[4]);
+                        ee |= (int)v[5];
+                        const int wb = (int)v[7];
+                        tb |= wb & 15;
+                        tw += wb >> 4;
+                    }
+                    double* const row = partials + (int64_t)t * kPartialStride;
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) row[f] = sum[f];
+                    row[4] = (double)rr;
+                    row[5] = (double)ee;
+                    row[6] = sum[4];
+                    // the chunks' work over the rows of one whole tile
+                    tw = (int)((int64_t)tw * (rows + 2 * L) / (rows + ns * 2 * L));
+                }
+            }
+            if (last) {
+                const int far = tb & kFlagFar;
+                if (L < kLFull) {
+                    flags[t] = tb & (kFlagFar | kFlagReach);
+                    if (far) atomicAdd(&ctl->next[kNextShortFlagged], 1);
+                    // keep the lean pass's bits, which other blocks of this pass read
+                    flags_lean[t] = (flags_lean[t] & (kFlagFar | kFlagReach)) | ((tb & kFlagNotLean) ? kFlagKeep : 0);
+                } else {
+                    // keep the short pass's bits, which other blocks of this pass read
+                    flags[t] = (flags[t] & (kFlagFar | kFlagReach)) | (far ? kFlagKeep : 0);
+                    atomicAdd(&ctl->redo_tiles, 1);
+                    if (far) atomicAdd(&ctl->keep[0], 1);
+                }
+                if (nsx > 1) {
+                    // this step's work; a tile worth cutting is listed once
+                    const int was = work_out[t];
+                    const bool list = tw >= kSplitWork && !(was & kWorkListed);
+                    work_out[t] = min(tw, kWorkListed - 1) | ((list || (was & kWorkListed)) ? kWorkListed : 0);
+                    if (list) list_out[atomicAdd(&ctl->split_n[step & 1], 1)] = t;
+                }
             }
         }
     }
@@ -1453,19 +1602,21 @@ pool2d_kernel(PoolView v, Consts k)
 // full passes' flags, then the lean pass's.
 template <typename T, bool WALLS, bool REST, bool SP>
 hipError_t launch_march2d_w(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
-                            StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream)
+                            StepCtl* ctl, double* partials, int* flags, long long step, hipStream_t stream,
+                            bool split)
 {
     const int nt = (int)m.blocks();
     int* flags_lean = flags + nt;
+    const int sp = split ? 1 : 0;
     march2d_lean_kernel<T, WALLS, REST, SP><<<m.nblocks_lean, kMTPB, 0, stream>>>(
-        Y, Yn, g, k, ctl, partials, flags, flags_lean, step, m.sy, (int)m.grid_x, nt);
+        Y, Yn, g, k, ctl, partials, flags, flags_lean, step, m.sy, (int)m.grid_x, nt, sp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     march2d_kernel<T, kLSmall, WALLS, REST, SP><<<m.nblocks, kMTPB, 0, stream>>>(
-        Y, Yn, g, k, ctl, partials, flags, flags_lean, step, m.sy, (int)m.grid_x, nt);
+        Y, Yn, g, k, ctl, partials, flags, flags_lean, step, m.sy, (int)m.grid_x, nt, sp);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     march2d_kernel<T, kLFull, WALLS, REST, SP><<<m.nblocks, kMTPB, 0, stream>>>(
-        Y, Yn, g, k, ctl, partials, flags, flags_lean, step, m.sy, (int)m.grid_x, nt);
+        Y, Yn, g, k, ctl, partials, flags, flags_lean, step, m.sy, (int)m.grid_x, nt, sp);
     return hipGetLastError();
 }
 
@@ -1489,7 +1640,7 @@ hipError_t launch_pool2d_w(const PoolView& v, const Consts& k, int nblocks_lean,
 template <typename T>
 hipError_t launch_march2d_species(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, const Consts& k,
                                   StepCtl* ctl, double* partials, int* flags, long long step,
-                                  hipStream_t stream);
+                                  hipStream_t stream, bool split);
 template <typename T>
 hipError_t launch_pool2d_species(const PoolView& v, const Consts& k, int nblocks_lean, int nblocks, bool walls,
                                  hipStream_t stream);

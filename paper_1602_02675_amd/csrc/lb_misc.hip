@@ -82,6 +82,8 @@ __global__ void reset_ctl_kernel(StepCtl* ctl)
         ctl->redo_tiles = 0;
         ctl->keep[0] = 0;
         ctl->keep[1] = 0;
+        ctl->split_n[0] = 0;
+        ctl->split_n[1] = 0;
     }
 }
 

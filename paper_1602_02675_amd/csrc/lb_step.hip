@@ -168,6 +168,7 @@ finalize_kernel(const double* __restrict__ partials, int64_t nb, int64_t stride,
         for (int i = 0; i < 5; ++i) ctl->next[i] = 0;
         ctl->keep[1] = ctl->keep[0];
         ctl->keep[0] = 0;
+        ctl->split_n[(step + 1) & 1] = 0;  // the next step lists its tiles afresh
     }
     if (ctl->err_step < step) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
