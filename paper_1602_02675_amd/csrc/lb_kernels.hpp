@@ -26,6 +26,8 @@ struct StepCtl {
     double totals_sp;       // square lattice with two gases: interior sum of rho chi
     int split_n[2];         // square lattice: tiles listed for row chunks in the steps of each parity
                             // (finalize clears the next step's)
+    int full_n;             // square lattice: tiles the short pass listed for the full pass (finalize
+                            // clears it)
 };
 
 // Per-block partial results: 4 field sums, reach, error bits; the square
@@ -80,10 +82,11 @@ hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, 
 // (flags, flags_lean): two work words per tile (written in the steps of
 // each parity), one counter of finished chunks per tile (zero between
 // passes), two lists of tiles to cut (written in the steps of each parity),
-// then kSplitMax partial rows per tile (chunk p of tile t at row
-// p * tiles + t), 8-byte aligned.  The first 5 words per tile start at zero.
+// the list of tiles for the full pass, then kSplitMax partial rows per tile
+// (chunk p of tile t at row p * tiles + t), 8-byte aligned.  The first 5
+// words per tile start at zero.
 constexpr int kSplitMax = 4;
-__host__ __device__ inline int64_t split_slots_offset(int64_t ntiles) { return (7 * ntiles + 1) / 2 * 2; }
+__host__ __device__ inline int64_t split_slots_offset(int64_t ntiles) { return 8 * ntiles; }
 inline size_t march2d_flag_bytes(int64_t ntiles, bool split)
 {
     return split ? (size_t)split_slots_offset(ntiles) * 4 + (size_t)kSplitMax * ntiles * kPartialStride * 8

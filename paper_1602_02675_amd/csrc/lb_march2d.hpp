@@ -672,6 +672,8 @@ __device__ __forceinline__ void load_node(const T* __restrict__ Y, int64_t nn, i
 // cannot take (march_tile's kFlagNotLean), and the next step's lean pass
 // leaves those to it at once.
 constexpr int kFlagFar = 1, kFlagReach = 2, kFlagKeep = 4, kFlagNotLean = 8;
+// flags_lean: the tile is in this step's list for the full pass (row chunks)
+constexpr int kFlagFullListed = 16;
 
 // Work of one window of a wavefront on the paths of march_tile, in units of
 // about half a uniform window (the fast instances' packet classes: speeds x
@@ -1383,13 +1385,36 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
     int* __restrict__ done = flags + 4 * (int64_t)ntiles;
     const int* __restrict__ list_in = flags + (5 + ((step - 1) & 1)) * (int64_t)ntiles;
     int* __restrict__ list_out = flags + (5 + (step & 1)) * (int64_t)ntiles;
+    int* __restrict__ full_list = flags + 7 * (int64_t)ntiles;
     double* __restrict__ slots = reinterpret_cast<double*>(flags + split_slots_offset(ntiles));
-    // the short pass cuts the listed tiles (by their work); the full pass,
-    // which takes the flagged tiles and their row-chunk neighbours, cuts
-    // every tile alike
+    // the short pass cuts the listed tiles (by their work); the full pass
+    // takes the tiles the short pass listed for it (each flagged tile and
+    // the row chunks within two of one whose sources reach far: a superset
+    // of those needs_pass selects) and cuts them all alike
     const int nlist = (L < kLFull && split) ? ctl->split_n[(step - 1) & 1] : 0;
-    const int ns_full = min(nsx, max(1, (int)gridDim.x / (3 * nflag)));
-    const int nclaim = L < kLFull ? nlist * nsx + ntiles : ntiles * nsx;
+    const int nfull = (L == kLFull && split) ? ctl->full_n : 0;
+    const int ns_full = min(nsx, max(1, (int)gridDim.x / max(1, nfull)));
+    const int nclaim = L < kLFull ? nlist * nsx + ntiles : (split ? nfull * nsx : ntiles);
+    // short pass with row chunks: list tile tq for the full pass, once
+    auto list_full = [&](int64_t tq) {
+        if (!(atomicOr(&flags_lean[tq], kFlagFullListed) & kFlagFullListed))
+            full_list[atomicAdd(&ctl->full_n, 1)] = (int)tq;
+    };
+    // ... a tile with flag bits fb: itself if flagged, and the row chunks
+    // within two of it (same column strip, wrapped when y is periodic) if its
+    // sources reach far (those whose halo rows it may own)
+    auto list_for_full = [&](int64_t tq, int fb) {
+        if (fb & kFlagFar) list_full(tq);
+        if (fb & kFlagReach) {
+            const int64_t chunks = ntiles / tiles_x, cx = tq % tiles_x, cy = tq / tiles_x;
+            for (int d = -2; d <= 2; ++d) {
+                int64_t y2 = cy + d;
+                if (g.bc_y == kBcPeriodic) y2 = (y2 % chunks + chunks) % chunks;
+                else if (y2 < 0 || y2 >= chunks) continue;
+                list_full(y2 * tiles_x + cx);
+            }
+        }
+    };
     auto chunks_of = [&](int t) -> int {
         if (nsx == 1) return 1;
         if (L == kLFull) return ns_full;
@@ -1406,9 +1431,12 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
             const bool listed = c < nlist * nsx;
             t = listed ? list_in[c / nsx] : c - nlist * nsx;
             q = listed ? c % nsx : -1;
+        } else if (split) {
+            t = full_list[c / nsx];
+            q = c % nsx;
         } else {
-            q = c / ntiles;
-            t = c - q * ntiles;
+            q = 0;
+            t = c;
         }
         const int64_t tx = t % tiles_x, ty = t / tiles_x;
         const int64_t Y0 = ty * sy, ylast = min(Y0 + sy, g.ny);
@@ -1430,6 +1458,7 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
                 if (p == 0 && threadIdx.x == 0) {
                     flags[t] = kFlagFar | kFlagReach | kFlagKeep;
                     atomicAdd(&ctl->next[kNextShortFlagged], 1);
+                    if (split) list_for_full(t, kFlagFar | kFlagReach);
                 }
                 continue;
             }
@@ -1488,8 +1517,11 @@ march2d_kernel(const T* __restrict__ Y, T* __restrict__ Yn, Grid g, Consts k,
                 if (L < kLFull) {
                     flags[t] = tb & (kFlagFar | kFlagReach);
                     if (far) atomicAdd(&ctl->next[kNextShortFlagged], 1);
-                    // keep the lean pass's bits, which other blocks of this pass read
-                    flags_lean[t] = (flags_lean[t] & (kFlagFar | kFlagReach)) | ((tb & kFlagNotLean) ? kFlagKeep : 0);
+                    // keep the lean pass's bits, which other blocks of this
+                    // pass read, and the full pass's list mark, which they set
+                    atomicAnd(&flags_lean[t], kFlagFar | kFlagReach | kFlagFullListed);
+                    if (tb & kFlagNotLean) atomicOr(&flags_lean[t], kFlagKeep);
+                    if (split) list_for_full(t, tb);
                 } else {
                     // keep the short pass's bits, which other blocks of this pass read
                     flags[t] = (flags[t] & (kFlagFar | kFlagReach)) | (far ? kFlagKeep : 0);

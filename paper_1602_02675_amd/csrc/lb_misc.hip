@@ -84,6 +84,7 @@ __global__ void reset_ctl_kernel(StepCtl* ctl)
         ctl->keep[1] = 0;
         ctl->split_n[0] = 0;
         ctl->split_n[1] = 0;
+        ctl->full_n = 0;
     }
 }
 

@@ -169,6 +169,7 @@ finalize_kernel(const double* __restrict__ partials, int64_t nb, int64_t stride,
         ctl->keep[1] = ctl->keep[0];
         ctl->keep[0] = 0;
         ctl->split_n[(step + 1) & 1] = 0;  // the next step lists its tiles afresh
+        ctl->full_n = 0;
     }
     if (ctl->err_step < step) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
