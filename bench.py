@@ -71,7 +71,7 @@ SEED = 0
 BYTES_PER_NODE = {"fp64": 64, "fp32": 32}  # read 4 moment fields + write 4 (algorithmic)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_march2d_fp64_4096.json")
 KERNEL_SOURCES = ["paper_1602_02675_amd/csrc/lb_march2d.hpp", "paper_1602_02675_amd/csrc/lb_march2d.hip",
-                  "paper_1602_02675_amd/csrc/lb_device.hpp"]
+                  "paper_1602_02675_amd/csrc/lb_device.hpp", "paper_1602_02675_amd/csrc/lb_kernels.hpp"]
 
 
 def kernel_source_sha(sources=None) -> str:

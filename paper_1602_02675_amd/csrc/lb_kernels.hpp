@@ -85,7 +85,7 @@ hipError_t launch_march2d(const T* Y, T* Yn, const Grid& g, const MarchGeom& m, 
 // the list of tiles for the full pass, then kSplitMax partial rows per tile
 // (chunk p of tile t at row p * tiles + t), 8-byte aligned.  The first 5
 // words per tile start at zero.
-constexpr int kSplitMax = 4;
+constexpr int kSplitMax = 8;
 __host__ __device__ inline int64_t split_slots_offset(int64_t ntiles) { return 8 * ntiles; }
 inline size_t march2d_flag_bytes(int64_t ntiles, bool split)
 {
